@@ -1,0 +1,216 @@
+/*
+ * ndtm -- multi-shift solver for the non-degenerate (N_f = 1+1) twisted-mass
+ * Wilson operator on one MI355X (gfx950).
+ *
+ * Problem statement (paper: eq:shifted_linear with the operator of
+ * eq:non-degenerate, section 2): for a gauge field U, parameters
+ * (kappa, mubar, epsbar) and shifts sigma_i = m_i^2 > 0, compute for one right-hand
+ * side b all solutions x_i of
+ *
+ *     (Q^2 + sigma_i) x_i = b,      Q = (Gamma5 x tau1) S,
+ *     S = A - 1/4 H_oe A^-1 H_eo    (even-odd Schur complement on the odd sites),
+ *     A = a + i mubar Gamma5 x tau3 - epsbar tau1,   a = 1/(2 kappa),
+ *
+ * H the Wilson hopping sum of eq:Wilson (clover term off).  The solve uses
+ * multi-shift CG for the larger shifts and, for the smallest ones, a two-level
+ * aggregation multigrid (section 3) applied through the difference of single
+ * solves (eq:lindif) started from interpolated guesses (section 4.2).
+ *
+ * Conventions shared by every call:
+ *  - dims = {T, Lz, Ly, Lx}, all even and >= 2; site s = ((t*Lz+z)*Ly+y)*Lx+x;
+ *    parity (t+z+y+x) mod 2; direction mu = 0 time, 1 x, 2 y, 3 z.
+ *  - Gauge field: complex128 U[V][4][3][3] (row-major colour matrix, U_mu(x)
+ *    connects x to x+mu).  Boundaries periodic; bc_flags bit 0 makes time
+ *    antiperiodic for the fermion field.
+ *  - Odd-site doublet spinor (the space Q acts on): complex128
+ *    [V/2][2 flavour][4 spin][3 colour], half index h = s >> 1 over the odd
+ *    sites.  Full-lattice doublet spinor: complex128 [V][2][4][3].
+ *  - Gamma matrices in the chiral basis, gamma5 = diag(1,1,-1,-1).
+ *
+ * Ownership: every pointer argument is owned by the caller; device pointers
+ * must be device memory of the context's GPU, 16-byte aligned, and are only
+ * used during the call (asynchronously on `stream`, a hipStream_t, NULL for
+ * the default stream).  The library never keeps a caller pointer.  It owns
+ * its internal storage (repacked links, Krylov vectors, multigrid data),
+ * allocated with hipMalloc on demand and freed by ndtm_destroy.
+ *
+ * Errors: every call returns an ndtm_status; ndtm_last_error gives a
+ * per-context message.  No exception crosses the boundary.  A call made
+ * before its prerequisite (apply before set_gauge/set_params) returns
+ * NDTM_ESTATE.  Calls are asynchronous on `stream` unless stated otherwise.
+ */
+#ifndef NDTM_H
+#define NDTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ndtm_ctx ndtm_ctx;
+
+typedef enum {
+  NDTM_OK = 0,
+  NDTM_EINVAL = -1,      /* bad argument (dims, sizes, null pointers, op codes) */
+  NDTM_ENOMEM = -2,      /* device allocation failed */
+  NDTM_ENOCONV = -3,     /* a shift missed the tolerance within the iteration caps */
+  NDTM_EBREAKDOWN = -4,  /* non-finite values or a Krylov breakdown */
+  NDTM_ESTATE = -5,      /* prerequisite call missing */
+  NDTM_EHIP = -6         /* HIP runtime error */
+} ndtm_status;
+
+#define NDTM_MAX_SHIFTS 16
+
+/* Precision of the stencil / multigrid inner work. */
+enum { NDTM_PREC_F64 = 0, NDTM_PREC_F32 = 1, NDTM_PREC_F16 = 2 };
+
+/* Operators of ndtm_apply. */
+enum {
+  NDTM_OP_QHAT = 0,       /* y_o = Q x_o                                          */
+  NDTM_OP_QHAT2 = 1,      /* y_o = (Q^2 + param) x_o                              */
+  NDTM_OP_SHAT_SHIFT = 2, /* y_o = (S + i param Gamma5 tau1) x_o                  */
+  NDTM_OP_DFULL = 3,      /* y = (D_ND + i param (Gamma5 x tau1) P_odd) x, full lattice */
+  NDTM_OP_HOP_EO = 4,     /* y_e = H_eo x_o (even sites, same half layout)         */
+  NDTM_OP_HOP_OE = 5      /* y_o = H_oe x_e                                        */
+};
+
+/* Initial-guess modes for the multigrid shifts. */
+enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2 };
+
+/* Creates a context on HIP device `device` for a lattice of dims {T,Lz,Ly,Lx}.
+ * EINVAL if a dim is odd or < 2 or V exceeds 2^31. */
+int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out);
+void ndtm_destroy(ndtm_ctx* ctx);
+const char* ndtm_last_error(const ndtm_ctx* ctx);
+/* V/2 (the number of odd sites) and V. */
+long long ndtm_half_volume(const ndtm_ctx* ctx);
+
+/* Copies and repacks the gauge field (eq:Wilson's U_mu(x)) from U_dev
+ * (complex128 [V][4][3][3], device).  FP32 and FP16 copies for the mixed form
+ * are made at the same time.  Invalidates any multigrid setup. */
+int ndtm_set_gauge(ndtm_ctx* ctx, const void* U_dev, void* stream);
+
+/* kappa > 0, a = 1/(2 kappa); requires a^2 + mubar^2 - epsbar^2 != 0 (the
+ * closed-form inverse of the site block A).  Invalidates the coarse operator. */
+int ndtm_set_params(ndtm_ctx* ctx, double kappa, double mubar, double epsbar);
+
+/* n in [1, NDTM_MAX_SHIFTS] shifts sigma_i = m_i^2 > 0, any order, distinct
+ * (eq:shifted_linear).  The solve orders them descending internally
+ * (section 4.2: sigma_1 > sigma_2 > ...). */
+int ndtm_set_shifts(ndtm_ctx* ctx, int n, const double* sigma);
+
+/* Applies an operator (NDTM_OP_*) in precision prec (NDTM_PREC_*).  x_dev and
+ * y_dev are canonical complex128 device arrays (odd-site, even-site or full
+ * lattice as the op states); y_dev must not alias x_dev.  Lower precisions
+ * convert x to the internal storage format, apply, and convert back. */
+int ndtm_apply(ndtm_ctx* ctx, int op, int prec, void* y_dev, const void* x_dev,
+               double param, void* stream);
+
+/* ---- multigrid (section 3, section 3.2) -------------------------------- */
+typedef struct {
+  int block[4];        /* aggregate extents {bt,bz,by,bx}; each divides the dim */
+  int n_vec;           /* test vectors N_v (<= 32); coarse dof per flavour = 2 N_v */
+  int setup_iters;     /* inverse-iteration sweeps building the test vectors */
+  int setup_smooth;    /* smoother iterations per sweep */
+  int smooth_iters;    /* post-smoothing iterations per cycle (0 pre) */
+  int coarse_iters;    /* GMRES iterations of the coarse solve per cycle */
+  double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
+  unsigned long long seed; /* seed of the random initial test vectors */
+  int precision;       /* NDTM_PREC_F64 or NDTM_PREC_F32 for P, coarse ops and the cycle */
+} ndtm_mg_params;
+
+/* Fills *p with the defaults (4^4 aggregates, 24 vectors, ...). */
+void ndtm_mg_default_params(ndtm_mg_params* p);
+
+/* Builds P and the coarse operator.  If test_vectors_dev is not NULL it
+ * supplies the N_v test vectors (complex128 [N_v][V][4][3], device) and the
+ * inverse iteration is skipped; otherwise they come from inverse iteration on
+ * the single-flavour twisted-mass operator D_W + i mubar Gamma5 (section 3.2:
+ * the setup of the one-flavour operator is reused for the doublet).  Per
+ * aggregate and chirality the vectors are orthonormalised (Gram-Schmidt in
+ * vector order).  Synchronises the stream. */
+int ndtm_mg_setup(ndtm_ctx* ctx, const ndtm_mg_params* p, const void* test_vectors_dev, void* stream);
+
+/* Coarse vector layout: complex128 [Vc][2 flavour][2 N_v], dof = chi*N_v + k. */
+long long ndtm_mg_coarse_volume(const ndtm_ctx* ctx);
+/* vc = (P x I2)^dag v; v full-lattice canonical doublet. */
+int ndtm_mg_restrict(ndtm_ctx* ctx, void* vc_dev, const void* v_dev, void* stream);
+/* v = (P x I2) vc. */
+int ndtm_mg_prolong(ndtm_ctx* ctx, void* v_dev, const void* vc_dev, void* stream);
+/* yc = D'_c(m) xc = (D_W,c x I2 + i d mubar Gamma5_c x tau3 - epsbar tau1
+ *                     + i m C_o x tau1) xc   (eq:non-degenerate_coarse). */
+int ndtm_mg_coarse_apply(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, double m, void* stream);
+
+/* ---- solve ------------------------------------------------------------- */
+typedef struct {
+  double tol;          /* target true relative residual per shift (1e-10) */
+  int maxiter;         /* MMS-CG iteration cap */
+  int n_mmscg;         /* shifts solved by MMS-CG (the largest ones); the
+                          rest go to the multigrid; >= number of shifts means
+                          plain MMS-CG for all */
+  int guess;           /* NDTM_GUESS_* for the multigrid shifts */
+  int precision;       /* NDTM_PREC_F64, or NDTM_PREC_F32/F16 for the mixed form */
+  int poll_every;      /* MMS-CG iterations between host convergence polls */
+  double mg_tol;       /* relative residual of each single (Q +- i m) solve per round */
+  int fgmres_restart;  /* outer FGMRES restart length */
+  int fgmres_maxiter;  /* outer FGMRES iteration cap per single solve */
+  int max_rounds;      /* FP64 defect-correction rounds per multigrid shift */
+} ndtm_solve_params;
+
+void ndtm_solve_default_params(ndtm_solve_params* p);
+
+typedef struct {
+  int status;
+  int n_shifts;
+  int mms_iterations;               /* iterations of the shared Krylov space */
+  double sigma[NDTM_MAX_SHIFTS];    /* in solve order (descending) */
+  int input_index[NDTM_MAX_SHIFTS]; /* position of this shift in set_shifts */
+  int method[NDTM_MAX_SHIFTS];      /* 0 = MMS-CG, 1 = multigrid case C */
+  int iterations[NDTM_MAX_SHIFTS];  /* MMS-CG: iteration when frozen; MG: outer iterations */
+  int rounds[NDTM_MAX_SHIFTS];      /* MG: defect-correction rounds */
+  double true_res[NDTM_MAX_SHIFTS]; /* ||b - (Q^2+sigma) x|| / ||b||, FP64 */
+  double guess_res[NDTM_MAX_SHIFTS];/* relative residual of the chosen initial guess */
+  double lagrange_res[NDTM_MAX_SHIFTS]; /* predicted residual of the Lagrange guess */
+  double mlp_res[NDTM_MAX_SHIFTS];  /* predicted residual of the network's guess (or -1) */
+  int guess_kind[NDTM_MAX_SHIFTS];  /* NDTM_GUESS_* actually used */
+  double t_mms_ms, t_guess_ms, t_mg_ms, t_total_ms;
+  double hop_ms;                    /* summed duration of FP64 stencil launches (if profiling) */
+  long long hop_launches;
+} ndtm_solve_report;
+
+/* Solves all shifts for one b.  x_dev[i] receives the solution of the i-th
+ * shift as given to ndtm_set_shifts (odd-site canonical, device); b_dev is
+ * odd-site canonical.  Synchronises the stream at the end to fill the report.
+ * Returns ENOCONV (solutions and report still written) if a shift misses tol,
+ * EBREAKDOWN on non-finite input or a Krylov breakdown. */
+int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
+               const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
+
+/* Kernel timing.  When enabled, every launch of the kernel classes below made
+ * by later calls is bracketed by HIP events on its stream, and its algorithmic
+ * byte count (the bytes the operation must move, see NDTM_PROF_*) is added to
+ * the class.  ndtm_profile_read returns, for one class, the summed kernel
+ * milliseconds, the launch count and the algorithmic bytes since the last
+ * reset (it synchronises the recorded events). */
+enum {
+  NDTM_PROF_HOP_F64 = 0,  /* stencil pass, per output site 1920 B (+384 per extra site vector) */
+  NDTM_PROF_HOP_F32 = 1,  /* 960 B (+192) */
+  NDTM_PROF_HOP_F16 = 2,  /* 488 B (+100) */
+  NDTM_PROF_MMS_UPDATE = 3, /* fused shift update, (3 + 4 N_active) x 384 B per odd site */
+  NDTM_PROF_MMS_RESID = 4,  /* r -= alpha w with ||r||^2, 3 x 384 B per odd site */
+  NDTM_PROF_RESTRICT = 5,
+  NDTM_PROF_PROLONG = 6,
+  NDTM_PROF_COARSE = 7,
+  NDTM_PROF_NCLASS = 8
+};
+/* mask: bit k enables timing of kernel class k (NDTM_PROF_*); 0 disables. */
+int ndtm_profile_enable(ndtm_ctx* ctx, int mask);
+int ndtm_profile_read(ndtm_ctx* ctx, int kernel_class, double* total_ms, long long* launches,
+                      double* alg_bytes, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDTM_H */

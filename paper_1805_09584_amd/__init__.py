@@ -1,0 +1,28 @@
+"""Python binding of libndtm (the HIP multi-shift twisted-mass solver for gfx950).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (complex128 CUDA tensors) and the current
+stream.  Importing this package does not load the library; the first call
+does, and raises if the shared library has not been built.
+"""
+from __future__ import annotations
+
+from .binding import (  # noqa: F401
+    NDTM_GUESS_LAGRANGE,
+    NDTM_GUESS_MLP,
+    NDTM_GUESS_ZERO,
+    NDTM_OP_DFULL,
+    NDTM_OP_HOP_EO,
+    NDTM_OP_HOP_OE,
+    NDTM_OP_QHAT,
+    NDTM_OP_QHAT2,
+    NDTM_OP_SHAT_SHIFT,
+    NDTM_PREC_F16,
+    NDTM_PREC_F32,
+    NDTM_PREC_F64,
+    Context,
+    NdtmError,
+    PROF_CLASSES,
+    lib_path,
+    load_library,
+)

@@ -1,0 +1,242 @@
+"""ctypes binding of include/ndtm.h.  Same names as the C entry points."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+NDTM_OK = 0
+NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16 = 0, 1, 2
+(NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
+ NDTM_OP_HOP_OE) = range(6)
+NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP = 0, 1, 2
+PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
+                "coarse")
+MAX_SHIFTS = 16
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "ESTATE",
+           -6: "EHIP"}
+
+
+class NdtmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ndtm {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MGParams(C.Structure):
+    _fields_ = [("block", C.c_int * 4), ("n_vec", C.c_int), ("setup_iters", C.c_int),
+                ("setup_smooth", C.c_int), ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
+                ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("n_mmscg", C.c_int), ("guess", C.c_int),
+                ("precision", C.c_int), ("poll_every", C.c_int), ("mg_tol", C.c_double),
+                ("fgmres_restart", C.c_int), ("fgmres_maxiter", C.c_int), ("max_rounds", C.c_int)]
+
+
+_D16 = C.c_double * MAX_SHIFTS
+_I16 = C.c_int * MAX_SHIFTS
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("status", C.c_int), ("n_shifts", C.c_int), ("mms_iterations", C.c_int),
+                ("sigma", _D16), ("input_index", _I16), ("method", _I16), ("iterations", _I16),
+                ("rounds", _I16), ("true_res", _D16), ("guess_res", _D16), ("lagrange_res", _D16),
+                ("mlp_res", _D16), ("guess_kind", _I16), ("t_mms_ms", C.c_double),
+                ("t_guess_ms", C.c_double), ("t_mg_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("hop_ms", C.c_double), ("hop_launches", C.c_longlong)]
+
+    def to_dict(self):
+        n = self.n_shifts
+        d = {k: getattr(self, k) for k in ("status", "n_shifts", "mms_iterations", "t_mms_ms", "t_guess_ms",
+                                          "t_mg_ms", "t_total_ms", "hop_ms", "hop_launches")}
+        for k in ("sigma", "input_index", "method", "iterations", "rounds", "true_res", "guess_res",
+                  "lagrange_res", "mlp_res", "guess_kind"):
+            d[k] = list(getattr(self, k)[:n])
+        return d
+
+
+def lib_path():
+    return os.path.join(_HERE, "libndtm.so")
+
+
+def load_library():
+    """Loads libndtm.so; raises if it is missing (there is no fallback path)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or "
+                           "python paper_1805_09584_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "ndtm_create": (i, [C.POINTER(C.c_int), i, i, C.POINTER(vp)]),
+        "ndtm_destroy": (None, [vp]),
+        "ndtm_last_error": (C.c_char_p, [vp]),
+        "ndtm_half_volume": (C.c_longlong, [vp]),
+        "ndtm_set_gauge": (i, [vp, vp, vp]),
+        "ndtm_set_params": (i, [vp, d, d, d]),
+        "ndtm_set_shifts": (i, [vp, i, C.POINTER(C.c_double)]),
+        "ndtm_apply": (i, [vp, i, i, vp, vp, d, vp]),
+        "ndtm_mg_default_params": (None, [C.POINTER(MGParams)]),
+        "ndtm_mg_setup": (i, [vp, C.POINTER(MGParams), vp, vp]),
+        "ndtm_mg_coarse_volume": (C.c_longlong, [vp]),
+        "ndtm_mg_restrict": (i, [vp, vp, vp, vp]),
+        "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
+        "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
+        "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
+        "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
+        "ndtm_profile_enable": (i, [vp, i]),
+        "ndtm_profile_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                  C.POINTER(C.c_double), i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    assert t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous(), "need a contiguous complex128 CUDA tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One lattice on one GPU (ndtm_create .. ndtm_destroy)."""
+
+    def __init__(self, dims, bc_flags=0, device=0):
+        self.lib = load_library()
+        self.dims = tuple(int(x) for x in dims)
+        self.device = device
+        h = C.c_void_p()
+        arr = (C.c_int * 4)(*self.dims)
+        rc = self.lib.ndtm_create(arr, bc_flags, device, C.byref(h))
+        if rc != NDTM_OK:
+            raise NdtmError(rc, "ndtm_create failed")
+        self.h = h
+        self.V = 1
+        for x in self.dims:
+            self.V *= x
+        self.vh = self.V // 2
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ndtm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != NDTM_OK:
+            msg = self.lib.ndtm_last_error(self.h)
+            raise NdtmError(rc, msg.decode() if msg else "")
+        return rc
+
+    # -- setup ----------------------------------------------------------------
+    def ndtm_set_gauge(self, U):
+        """U: complex128 CUDA tensor (V, 4, 3, 3)."""
+        assert U.numel() == self.V * 36
+        self._check(self.lib.ndtm_set_gauge(self.h, _ptr(U), _stream()))
+
+    def ndtm_set_params(self, kappa, mubar, epsbar):
+        self._check(self.lib.ndtm_set_params(self.h, kappa, mubar, epsbar))
+
+    def ndtm_set_shifts(self, sigma):
+        arr = (C.c_double * len(sigma))(*[float(s) for s in sigma])
+        self._check(self.lib.ndtm_set_shifts(self.h, len(sigma), arr))
+        self.n_shifts = len(sigma)
+
+    # -- operators ------------------------------------------------------------
+    def ndtm_apply(self, op, x, param=0.0, prec=NDTM_PREC_F64, out=None):
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(self.lib.ndtm_apply(self.h, op, prec, _ptr(out), _ptr(x), float(param), _stream()))
+        return out
+
+    # -- multigrid ------------------------------------------------------------
+    @staticmethod
+    def mg_params(**kw):
+        p = MGParams()
+        load_library().ndtm_mg_default_params(C.byref(p))
+        for k, v in kw.items():
+            if k == "block":
+                p.block = (C.c_int * 4)(*v)
+            else:
+                setattr(p, k, v)
+        return p
+
+    def ndtm_mg_setup(self, params=None, test_vectors=None):
+        p = params if params is not None else self.mg_params()
+        tv = _ptr(test_vectors) if test_vectors is not None else None
+        self._check(self.lib.ndtm_mg_setup(self.h, C.byref(p), tv, _stream()))
+        self.Vc = int(self.lib.ndtm_mg_coarse_volume(self.h))
+        self.n_vec = p.n_vec
+
+    def ndtm_mg_restrict(self, v):
+        out = torch.empty((self.Vc, 2, 2 * self.n_vec), dtype=torch.complex128, device=v.device)
+        self._check(self.lib.ndtm_mg_restrict(self.h, _ptr(out), _ptr(v), _stream()))
+        return out
+
+    def ndtm_mg_prolong(self, vc):
+        out = torch.empty((self.V, 2, 4, 3), dtype=torch.complex128, device=vc.device)
+        self._check(self.lib.ndtm_mg_prolong(self.h, _ptr(out), _ptr(vc), _stream()))
+        return out
+
+    def ndtm_mg_coarse_apply(self, xc, m=0.0):
+        out = torch.empty_like(xc)
+        self._check(self.lib.ndtm_mg_coarse_apply(self.h, _ptr(out), _ptr(xc), float(m), _stream()))
+        return out
+
+    # -- solve ----------------------------------------------------------------
+    @staticmethod
+    def solve_params(**kw):
+        p = SolveParams()
+        load_library().ndtm_solve_default_params(C.byref(p))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    def ndtm_solve(self, b, params=None, xs=None, check=True):
+        """Solves all shifts for b (complex128 CUDA (V/2,2,4,3)); returns (xs, report dict)."""
+        p = params if params is not None else self.solve_params()
+        if xs is None:
+            xs = [torch.empty_like(b) for _ in range(self.n_shifts)]
+        arr = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        rep = SolveReport()
+        rc = self.lib.ndtm_solve(self.h, arr, _ptr(b), C.byref(p), C.byref(rep), _stream())
+        if check:
+            self._check(rc)
+        d = rep.to_dict()
+        d["rc"] = rc
+        return xs, d
+
+    # -- profiling --------------------------------------------------------------
+    def ndtm_profile_enable(self, on=True):
+        self._check(self.lib.ndtm_profile_enable(self.h, 1 if on else 0))
+
+    def ndtm_profile_read(self, kernel_class=0, reset=False):
+        """(milliseconds, launches, algorithmic bytes) of one kernel class since the last reset."""
+        ms = C.c_double()
+        n = C.c_longlong()
+        by = C.c_double()
+        self._check(self.lib.ndtm_profile_read(self.h, kernel_class, C.byref(ms), C.byref(n), C.byref(by),
+                                               1 if reset else 0))
+        return ms.value, n.value, by.value

@@ -1,0 +1,347 @@
+// C-ABI entry points (context, gauge field, parameters, operator application,
+// profiling) and the internal operator helpers.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ctx.h"
+
+namespace ndtm {
+
+int fail(ndtm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_check(ndtm_ctx* c, hipError_t e, const char* what) {
+  return fail(c, NDTM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes) {
+  DevBuf& b = c->bufs[name];
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
+    return nullptr;
+  }
+  (void)hipMemset(b.p, 0, bytes);
+  b.bytes = bytes;
+  return b.p;
+}
+
+size_t half_elems(const ndtm_ctx* c) { return (size_t)24 * c->g.stride; }
+
+HalfField half_field(ndtm_ctx* c, const std::string& name, int prec) {
+  HalfField f;
+  f.prec = prec;
+  const size_t n = half_elems(c);
+  const size_t esz = prec == P64 ? 16 : (prec == P32 ? 8 : 4);
+  f.v = ws_get(c, name + (prec == P64 ? "#64" : prec == P32 ? "#32" : "#16"), n * esz);
+  if (prec == P16) f.sc = static_cast<float*>(ws_get(c, name + "#sc", (size_t)c->g.stride * 4));
+  return f;
+}
+
+static std::pair<hipEvent_t, hipEvent_t> take_events(ndtm_ctx* c) {
+  if (!c->ev_free.empty()) {
+    auto e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+  }
+  std::pair<hipEvent_t, hipEvent_t> e;
+  (void)hipEventCreate(&e.first);
+  (void)hipEventCreate(&e.second);
+  return e;
+}
+
+ProfScope::ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_) : c(c_), cls(cls_), st(st_) {
+  if (!((c->prof_mask >> cls) & 1)) return;
+  ev = take_events(c);
+  (void)hipEventRecord(ev.first, st);
+  c->prof_bytes[cls] += bytes;
+}
+
+ProfScope::~ProfScope() {
+  if (!((c->prof_mask >> cls) & 1)) return;
+  (void)hipEventRecord(ev.second, st);
+  c->ev_used[cls].push_back(ev);
+}
+
+// algorithmic bytes per output site of one stencil pass
+static double hop_site_bytes(int prec, int epi) {
+  const double base[3] = {1920.0, 960.0, 488.0}, vec[3] = {384.0, 192.0, 100.0};
+  int extra = 0;
+  if (epi == EPI_QHAT || epi == EPI_SITE) extra = 1;
+  if (epi == EPI_QHAT_SIG) extra = 2;
+  return base[prec] + extra * vec[prec];
+}
+
+void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& in, const HalfField& out,
+         const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
+         double* partials, hipStream_t st) {
+  ProfScope ps(c, NDTM_PROF_HOP_F64 + prec, hop_site_bytes(prec, epi) * c->g.vh, st);
+  launch_hop(prec, epi, red, c->g, parity, c->op, c->U[prec][parity], c->U[prec][1 - parity], in, out,
+             xs, zs, ms, hop_coef, sigma, partials, st);
+}
+
+void apply_qhat(ndtm_ctx* c, int prec, const HalfField& y, const HalfField& x, const HalfField& tmp_e,
+                hipStream_t st) {
+  hop(c, prec, EPI_AINV, RED_NONE, 0, x, tmp_e, nullptr, nullptr, 0, 0, 0, nullptr, st);
+  hop(c, prec, EPI_QHAT, RED_NONE, 1, tmp_e, y, &x, nullptr, 0, 0, 0, nullptr, st);
+}
+
+void apply_qhat2(ndtm_ctx* c, int prec, const HalfField& w, const HalfField& p, const HalfField& u,
+                 const HalfField& tmp_e, double sigma, double* partials, hipStream_t st) {
+  apply_qhat(c, prec, u, p, tmp_e, st);
+  hop(c, prec, EPI_AINV, RED_NONE, 0, u, tmp_e, nullptr, nullptr, 0, 0, 0, nullptr, st);
+  hop(c, prec, EPI_QHAT_SIG, partials ? RED_REDOT : RED_NONE, 1, tmp_e, w, &u, &p, 0, 0, sigma, partials,
+      st);
+}
+
+void apply_sshift(ndtm_ctx* c, int prec, const HalfField& y, const HalfField& x, const HalfField& tmp_e,
+                  double m, hipStream_t st) {
+  hop(c, prec, EPI_AINV, RED_NONE, 0, x, tmp_e, nullptr, nullptr, 0, 0, 0, nullptr, st);
+  hop(c, prec, EPI_SITE, RED_NONE, 1, tmp_e, y, &x, nullptr, m, -0.25, 0, nullptr, st);
+}
+
+void apply_dfull(ndtm_ctx* c, int prec, const HalfField& ye, const HalfField& yo, const HalfField& xe,
+                 const HalfField& xo, double m, hipStream_t st) {
+  hop(c, prec, EPI_SITE, RED_NONE, 0, xo, ye, &xe, nullptr, 0.0, -0.5, 0, nullptr, st);
+  hop(c, prec, EPI_SITE, RED_NONE, 1, xe, yo, &xo, nullptr, m, -0.5, 0, nullptr, st);
+}
+
+double norm2_host(ndtm_ctx* c, const double2* x, size_t n, hipStream_t st) {
+  const int g = blas_norm2_partials(x, n, c->partials, st);
+  blas_finalize(c->partials, g, 1, c->dscal, st);
+  (void)hipMemcpyAsync(c->hscal, c->dscal, sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  return c->hscal[0];
+}
+
+double2 dot_host(ndtm_ctx* c, const double2* x, const double2* y, size_t n, hipStream_t st) {
+  const int g = blas_dot_partials(x, y, n, c->partials, st);
+  blas_finalize(c->partials, g, 2, c->dscal, st);
+  (void)hipMemcpyAsync(c->hscal, c->dscal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  return make_double2(c->hscal[0], c->hscal[1]);
+}
+
+}  // namespace ndtm
+
+using namespace ndtm;
+
+extern "C" {
+
+int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
+  if (!dims || !out) return NDTM_EINVAL;
+  *out = nullptr;
+  long long V = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 2 || (dims[i] & 1)) return NDTM_EINVAL;
+    V *= dims[i];
+  }
+  if (V > (1LL << 31)) return NDTM_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NDTM_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return NDTM_EHIP;
+  ndtm_ctx* c = new (std::nothrow) ndtm_ctx();
+  if (!c) return NDTM_ENOMEM;
+  c->device = device;
+  c->V = V;
+  c->g.T = dims[0];
+  c->g.Lz = dims[1];
+  c->g.Ly = dims[2];
+  c->g.Lx = dims[3];
+  c->g.vh = (int)(V / 2);
+  c->g.stride = (int)((V / 2 + 255) / 256 * 256);
+  c->g.antiperiodic = bc_flags & 1;
+  c->partials_n = (size_t)hop_grid(c->g) * 4 + 4096 * 80;
+  if (hipMalloc(&c->partials, c->partials_n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->dscal, kScalN * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->mms_S, MS_SIZE * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&c->hscal, kScalN * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    ndtm_destroy(c);
+    return NDTM_ENOMEM;
+  }
+  *out = c;
+  return NDTM_OK;
+}
+
+void ndtm_mg_free(ndtm_ctx* c);
+void ndtm_mlp_free(ndtm_ctx* c);
+
+void ndtm_destroy(ndtm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  ndtm_mg_free(c);
+  ndtm_mlp_free(c);
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 2; ++q)
+      if (c->U[p][q]) (void)hipFree(c->U[p][q]);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->dscal) (void)hipFree(c->dscal);
+  if (c->mms_S) (void)hipFree(c->mms_S);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  for (int p = 0; p < NDTM_PROF_NCLASS; ++p)
+    for (auto& e : c->ev_used[p]) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  for (auto& e : c->ev_free) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete c;
+}
+
+const char* ndtm_last_error(const ndtm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+long long ndtm_half_volume(const ndtm_ctx* c) { return c ? c->V / 2 : 0; }
+
+int ndtm_set_gauge(ndtm_ctx* c, const void* U_dev, void* stream) {
+  if (!c || !U_dev) return fail(c, NDTM_EINVAL, "set_gauge: null argument");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)36 * c->g.stride;
+  const size_t esz[3] = {16, 8, 4};
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 2; ++q) {
+      if (!c->U[p][q]) {
+        if (hipMalloc(&c->U[p][q], n * esz[p]) != hipSuccess) {
+          c->U[p][q] = nullptr;
+          return fail(c, NDTM_ENOMEM, "set_gauge: link storage");
+        }
+        NDTM_HIP(c, hipMemsetAsync(c->U[p][q], 0, n * esz[p], st));
+      }
+    }
+  launch_pack_gauge(c->g, static_cast<const double2*>(U_dev), (double2*)c->U[0][0], (double2*)c->U[0][1],
+                    (float2*)c->U[1][0], (float2*)c->U[1][1], (__half2*)c->U[2][0], (__half2*)c->U[2][1],
+                    st);
+  NDTM_HIP(c, hipGetLastError());
+  c->have_gauge = true;
+  ndtm_mg_free(c);
+  return NDTM_OK;
+}
+
+int ndtm_set_params(ndtm_ctx* c, double kappa, double mubar, double epsbar) {
+  if (!c) return NDTM_EINVAL;
+  if (!(kappa > 0) || !std::isfinite(mubar) || !std::isfinite(epsbar))
+    return fail(c, NDTM_EINVAL, "set_params: kappa must be > 0 and mubar, epsbar finite");
+  const double a = 1.0 / (2.0 * kappa);
+  const double den = a * a + mubar * mubar - epsbar * epsbar;
+  if (den == 0.0) return fail(c, NDTM_EINVAL, "set_params: a^2 + mubar^2 - epsbar^2 == 0");
+  c->kappa = kappa;
+  c->mubar = mubar;
+  c->epsbar = epsbar;
+  c->op.a = a;
+  c->op.mubar = mubar;
+  c->op.epsbar = epsbar;
+  c->op.inv_den = 1.0 / den;
+  c->have_params = true;
+  ndtm_mg_free(c);
+  return NDTM_OK;
+}
+
+int ndtm_set_shifts(ndtm_ctx* c, int n, const double* sigma) {
+  if (!c) return NDTM_EINVAL;
+  if (n < 1 || n > NDTM_MAX_SHIFTS || !sigma) return fail(c, NDTM_EINVAL, "set_shifts: 1..16 shifts");
+  for (int i = 0; i < n; ++i) {
+    if (!(sigma[i] > 0) || !std::isfinite(sigma[i])) return fail(c, NDTM_EINVAL, "set_shifts: sigma > 0");
+    for (int j = 0; j < i; ++j)
+      if (sigma[j] == sigma[i]) return fail(c, NDTM_EINVAL, "set_shifts: shifts must be distinct");
+  }
+  c->shifts.assign(sigma, sigma + n);
+  return NDTM_OK;
+}
+
+int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, double param, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!y_dev || !x_dev || y_dev == x_dev) return fail(c, NDTM_EINVAL, "apply: null or aliased pointers");
+  if (prec < 0 || prec > 2) return fail(c, NDTM_EINVAL, "apply: bad precision");
+  if (!c->have_gauge || !c->have_params) return fail(c, NDTM_ESTATE, "apply: set_gauge and set_params first");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double2* x = static_cast<const double2*>(x_dev);
+  double2* y = static_cast<double2*>(y_dev);
+  HalfField X = half_field(c, "ap_x", prec), Y = half_field(c, "ap_y", prec), T = half_field(c, "ap_t", prec);
+  if (!X.v || !Y.v || !T.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
+  switch (op) {
+    case NDTM_OP_QHAT:
+      launch_pack_half(c->g, x, X, st);
+      apply_qhat(c, prec, Y, X, T, st);
+      launch_unpack_half(c->g, Y, y, st);
+      break;
+    case NDTM_OP_QHAT2: {
+      HalfField U = half_field(c, "ap_u", prec);
+      if (!U.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
+      launch_pack_half(c->g, x, X, st);
+      apply_qhat2(c, prec, Y, X, U, T, param, nullptr, st);
+      launch_unpack_half(c->g, Y, y, st);
+      break;
+    }
+    case NDTM_OP_SHAT_SHIFT:
+      launch_pack_half(c->g, x, X, st);
+      apply_sshift(c, prec, Y, X, T, param, st);
+      launch_unpack_half(c->g, Y, y, st);
+      break;
+    case NDTM_OP_DFULL: {
+      HalfField Ye = half_field(c, "ap_ye", prec);
+      if (!Ye.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
+      launch_pack_full(c->g, x, T, X, st);
+      apply_dfull(c, prec, Ye, Y, T, X, param, st);
+      launch_unpack_full(c->g, Ye, Y, y, st);
+      break;
+    }
+    case NDTM_OP_HOP_EO:
+      launch_pack_half(c->g, x, X, st);
+      hop(c, prec, EPI_PLAIN, RED_NONE, 0, X, Y, nullptr, nullptr, 0, 0, 0, nullptr, st);
+      launch_unpack_half(c->g, Y, y, st);
+      break;
+    case NDTM_OP_HOP_OE:
+      launch_pack_half(c->g, x, X, st);
+      hop(c, prec, EPI_PLAIN, RED_NONE, 1, X, Y, nullptr, nullptr, 0, 0, 0, nullptr, st);
+      launch_unpack_half(c->g, Y, y, st);
+      break;
+    default:
+      return fail(c, NDTM_EINVAL, "apply: unknown operator");
+  }
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_profile_enable(ndtm_ctx* c, int on) {
+  if (!c) return NDTM_EINVAL;
+  c->prof_mask = on;
+  return NDTM_OK;
+}
+
+int ndtm_profile_read(ndtm_ctx* c, int cls, double* total_ms, long long* launches, double* alg_bytes,
+                      int reset) {
+  if (!c || cls < 0 || cls >= NDTM_PROF_NCLASS) return NDTM_EINVAL;
+  NDTM_HIP(c, hipSetDevice(c->device));
+  for (auto& e : c->ev_used[cls]) {
+    NDTM_HIP(c, hipEventSynchronize(e.second));
+    float ms = 0;
+    NDTM_HIP(c, hipEventElapsedTime(&ms, e.first, e.second));
+    c->prof_ms[cls] += ms;
+    c->prof_n[cls] += 1;
+    c->ev_free.push_back(e);
+  }
+  c->ev_used[cls].clear();
+  if (total_ms) *total_ms = c->prof_ms[cls];
+  if (launches) *launches = c->prof_n[cls];
+  if (alg_bytes) *alg_bytes = c->prof_bytes[cls];
+  if (reset) {
+    c->prof_ms[cls] = 0;
+    c->prof_n[cls] = 0;
+    c->prof_bytes[cls] = 0;
+  }
+  return NDTM_OK;
+}
+
+}  // extern "C"

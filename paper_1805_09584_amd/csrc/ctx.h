@@ -1,0 +1,117 @@
+// The library context and the internal operator helpers shared by the
+// drivers (MMS-CG, multigrid, hybrid).  Not part of the C-ABI.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ndtm.h"
+#include "ndtm_internal.h"
+
+namespace ndtm {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct MGData;  // multigrid state (mg.cpp)
+struct MLPData; // learned proposer state (mlp.cpp)
+
+}  // namespace ndtm
+
+struct ndtm_ctx {
+  int device = 0;
+  ndtm::Geom g{};
+  long long V = 0;
+  std::string err;
+  bool have_gauge = false, have_params = false;
+  double kappa = 0, mubar = 0, epsbar = 0;
+  ndtm::OpParams op{};
+  std::vector<double> shifts;
+  void* U[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
+  double* partials = nullptr;
+  size_t partials_n = 0;
+  double* dscal = nullptr;  // device scalar scratch (kScalN doubles)
+  double* hscal = nullptr;  // pinned host mirror
+  double* mms_S = nullptr;
+  std::map<std::string, ndtm::DevBuf> bufs;
+  int prof_mask = 0;  // bit k: time kernel class k
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[NDTM_PROF_NCLASS];
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+  double prof_ms[NDTM_PROF_NCLASS] = {};
+  long long prof_n[NDTM_PROF_NCLASS] = {};
+  double prof_bytes[NDTM_PROF_NCLASS] = {};
+  ndtm::MGData* mg = nullptr;
+  ndtm::MLPData* mlp = nullptr;
+};
+
+namespace ndtm {
+
+constexpr int kScalN = 8192;
+
+// status helpers
+int fail(ndtm_ctx* c, int code, const std::string& msg);
+int hip_check(ndtm_ctx* c, hipError_t e, const char* what);
+#define NDTM_HIP(ctx, call)                                   \
+  do {                                                        \
+    hipError_t _e = (call);                                   \
+    if (_e != hipSuccess) return ndtm::hip_check(ctx, _e, #call); \
+  } while (0)
+
+// named workspace (grown on demand, zero-filled when (re)allocated)
+void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes);
+HalfField half_field(ndtm_ctx* c, const std::string& name, int prec);
+size_t half_elems(const ndtm_ctx* c);  // complex elements of a half field (24*stride)
+
+// event timing of one launch of a kernel class (no-ops when profiling is off)
+struct ProfScope {
+  ndtm_ctx* c;
+  int cls;
+  hipStream_t st;
+  std::pair<hipEvent_t, hipEvent_t> ev{};
+  ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_);
+  ~ProfScope();
+};
+
+// stencil launch with optional event timing
+void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& in, const HalfField& out,
+         const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
+         double* partials, hipStream_t st);
+
+// y = Q x (odd), using tmp_e (even)
+void apply_qhat(ndtm_ctx* c, int prec, const HalfField& y, const HalfField& x, const HalfField& tmp_e,
+                hipStream_t st);
+// w = (Q^2 + sigma) p using u (odd) and tmp_e; partials receive Re<p, w> per block
+void apply_qhat2(ndtm_ctx* c, int prec, const HalfField& w, const HalfField& p, const HalfField& u,
+                 const HalfField& tmp_e, double sigma, double* partials, hipStream_t st);
+// y = (S + i m Gamma5 tau1) x (odd)
+void apply_sshift(ndtm_ctx* c, int prec, const HalfField& y, const HalfField& x, const HalfField& tmp_e,
+                  double m, hipStream_t st);
+// full lattice: (ye, yo) = D'(m) (xe, xo)
+void apply_dfull(ndtm_ctx* c, int prec, const HalfField& ye, const HalfField& yo, const HalfField& xe,
+                 const HalfField& xo, double m, hipStream_t st);
+
+// reductions returning host values (synchronise the stream)
+double norm2_host(ndtm_ctx* c, const double2* x, size_t n, hipStream_t st);
+double2 dot_host(ndtm_ctx* c, const double2* x, const double2* y, size_t n, hipStream_t st);
+
+int red_grid(size_t n);
+void mms_seed(double* S, const double* src, hipStream_t st);
+
+// drivers
+struct MmsResult {
+  int iterations = 0;
+  std::vector<int> iters;
+  bool breakdown = false;
+};
+// MMS-CG for (Q^2 + sigma_s) x_s = b on internal FP64 fields; sigmas any order.
+int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
+              const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
+              hipStream_t st);
+// true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
+double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma,
+                     const HalfField& r, hipStream_t st);
+
+}  // namespace ndtm

@@ -1,0 +1,430 @@
+// Even-odd hopping stencil of the non-degenerate twisted-mass doublet with its
+// site terms fused into the epilogue.
+//
+// Operator (section 2, eq:Wilson and eq:non-degenerate): per flavour,
+//   (H psi)(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu),
+// one output parity per launch.  Site block A = a + i mubar gamma5 tau3 - epsbar tau1
+// and its closed-form inverse (a - i mubar gamma5 tau3 + epsbar tau1)/(a^2+mubar^2-epsbar^2)
+// are applied in the epilogue, as is Gamma5 x tau1 for Q = Gamma5 tau1 (A - H_oe A^-1 H_eo/4).
+//
+// Work decomposition: two threads per output site, one per flavour; both read
+// the same link (one cache line), each reads only its flavour of the
+// neighbour spinors, and the flavour-mixing site terms exchange values with
+// the partner lane (lane ^ 1).  The spin projection (1 -+ gamma_mu) halves the
+// colour matrix-vector work (chiral basis, gamma_0 = [[0,-1],[-1,0]],
+// gamma_k = [[0,-i s_k],[i s_k,0]]).  Blocks are remapped so that each of the 8
+// XCDs (block b runs on XCD b mod 8) sweeps one contiguous slab of the lattice,
+// which keeps neighbour re-reads inside that XCD's L2.
+#include <type_traits>
+
+#include "ndtm_internal.h"
+
+namespace ndtm {
+namespace {
+
+template <class R>
+struct cx {
+  R x, y;
+};
+template <class R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.x, s * a.y}; }
+template <class R>
+__device__ __forceinline__ cx<R> mul(cx<R> a, cx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class R>
+__device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {  // conj(a) * b
+  return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+template <class R>
+__device__ __forceinline__ cx<R> ipl(cx<R> a) { return {-a.y, a.x}; }  // i a
+template <class R>
+__device__ __forceinline__ cx<R> imi(cx<R> a) { return {a.y, -a.x}; }  // -i a
+template <class R>
+__device__ __forceinline__ cx<R> shfl1(cx<R> v) {
+  return {__shfl_xor(v.x, 1), __shfl_xor(v.y, 1)};
+}
+
+template <class S>
+struct RealOf;
+template <>
+struct RealOf<double2> { using T = double; };
+template <>
+struct RealOf<float2> { using T = float; };
+template <>
+struct RealOf<__half2> { using T = float; };
+template <class S>
+constexpr bool kHalf = std::is_same<S, __half2>::value;
+
+__device__ __forceinline__ cx<double> ldc(const double2* p, long i) {
+  double2 v = p[i];
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ldc(const float2* p, long i) {
+  float2 v = p[i];
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cx<float> ldc(const __half2* p, long i) {
+  float2 v = __half22float2(p[i]);
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void stc(double2* p, long i, cx<double> v) { p[i] = make_double2(v.x, v.y); }
+__device__ __forceinline__ void stc(float2* p, long i, cx<float> v) { p[i] = make_float2(v.x, v.y); }
+__device__ __forceinline__ void stc(__half2* p, long i, cx<float> v) {
+  p[i] = __float22half2_rn(make_float2(v.x, v.y));
+}
+
+template <class S, class L>
+struct HopArgs {
+  const S* in;
+  const float* in_sc;
+  const L* Uo;
+  const L* Ui;
+  S* out;
+  float* out_sc;
+  const S* xs;
+  const float* xs_sc;
+  const S* zs;
+  const float* zs_sc;
+  double* partials;
+  int T, Lz, Ly, Lx, vh, stride, parity, antiperiodic;
+  double a, mubar, epsbar, inv_den, ms, hop_coef, sigma;
+};
+
+// Loads the 12 components (4 spins x 3 colours) of flavour f at site h.
+template <class S, class R>
+__device__ __forceinline__ void load_flav(cx<R> (&v)[4][3], const S* p, const float* sc, int f,
+                                          int stride, int h) {
+  R s = 1;
+  if constexpr (kHalf<S>) s = sc[h];
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<R> t = ldc(p, (long)(f * 12 + sp * 3 + c) * stride + h);
+      if constexpr (kHalf<S>) t = s * t;
+      v[sp][c] = t;
+    }
+}
+
+// One of the eight hops: project, colour-multiply, reconstruct, accumulate.
+template <int MU, bool FWD, class S, class L, class R>
+__device__ __forceinline__ void hop_dir(cx<R> (&acc)[4][3], const HopArgs<S, L>& A, int f, int hn,
+                                        const L* U, int hl, R sg) {
+  cx<R> p[4][3];
+  load_flav<S, R>(p, A.in, A.in_sc, f, A.stride, hn);
+  cx<R> h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if constexpr (MU == 0) {
+      h0[c] = FWD ? p[0][c] + p[2][c] : p[0][c] - p[2][c];
+      h1[c] = FWD ? p[1][c] + p[3][c] : p[1][c] - p[3][c];
+    } else if constexpr (MU == 1) {
+      h0[c] = FWD ? p[0][c] + ipl(p[3][c]) : p[0][c] - ipl(p[3][c]);
+      h1[c] = FWD ? p[1][c] + ipl(p[2][c]) : p[1][c] - ipl(p[2][c]);
+    } else if constexpr (MU == 2) {
+      h0[c] = FWD ? p[0][c] + p[3][c] : p[0][c] - p[3][c];
+      h1[c] = FWD ? p[1][c] - p[2][c] : p[1][c] + p[2][c];
+    } else {
+      h0[c] = FWD ? p[0][c] + ipl(p[2][c]) : p[0][c] - ipl(p[2][c]);
+      h1[c] = FWD ? p[1][c] - ipl(p[3][c]) : p[1][c] + ipl(p[3][c]);
+    }
+  }
+  cx<R> u[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[r][c] = ldc(U, (long)(MU * 9 + r * 3 + c) * A.stride + hl);
+  cx<R> g0[3], g1[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    cx<R> s0 = {0, 0}, s1 = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (FWD) {
+        s0 = s0 + mul(u[r][c], h0[c]);
+        s1 = s1 + mul(u[r][c], h1[c]);
+      } else {
+        s0 = s0 + mulc(u[c][r], h0[c]);
+        s1 = s1 + mulc(u[c][r], h1[c]);
+      }
+    }
+    g0[r] = sg * s0;
+    g1[r] = sg * s1;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[0][c] = acc[0][c] + g0[c];
+    acc[1][c] = acc[1][c] + g1[c];
+    if constexpr (MU == 0) {
+      acc[2][c] = FWD ? acc[2][c] + g0[c] : acc[2][c] - g0[c];
+      acc[3][c] = FWD ? acc[3][c] + g1[c] : acc[3][c] - g1[c];
+    } else if constexpr (MU == 1) {
+      acc[2][c] = FWD ? acc[2][c] + imi(g1[c]) : acc[2][c] + ipl(g1[c]);
+      acc[3][c] = FWD ? acc[3][c] + imi(g0[c]) : acc[3][c] + ipl(g0[c]);
+    } else if constexpr (MU == 2) {
+      acc[2][c] = FWD ? acc[2][c] - g1[c] : acc[2][c] + g1[c];
+      acc[3][c] = FWD ? acc[3][c] + g0[c] : acc[3][c] - g0[c];
+    } else {
+      acc[2][c] = FWD ? acc[2][c] + imi(g0[c]) : acc[2][c] + ipl(g0[c]);
+      acc[3][c] = FWD ? acc[3][c] + ipl(g1[c]) : acc[3][c] + imi(g1[c]);
+    }
+  }
+}
+
+__device__ __forceinline__ void block_reduce_store(double v, double* partials) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  __shared__ double ws[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += ws[i];
+    partials[blockIdx.x] = s;
+  }
+}
+
+template <class S, class L, int EPI, int RED>
+__global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
+  using R = typename RealOf<S>::T;
+  // XCD-aware block order: XCD k = b % 8 gets one contiguous range of logical blocks.
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, rem = nb & 7, xcd = b & 7, loc = b >> 3;
+  const int lb = xcd * q + min(xcd, rem) + loc;
+  const int f = threadIdx.x & 1;
+  const int h = lb * kSitesPerBlock + (threadIdx.x >> 1);
+  const bool valid = h < A.vh;
+  double red = 0.0;
+
+  cx<R> acc[4][3];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[s][c] = {0, 0};
+
+  if (valid) {
+    const int Lxh = A.Lx >> 1;
+    const int row = h / Lxh;
+    const int xh = h - row * Lxh;
+    const int y = row % A.Ly;
+    const int tz = row / A.Ly;
+    const int z = tz % A.Lz;
+    const int t = tz / A.Lz;
+    const int x = 2 * xh + ((A.parity + t + z + y) & 1);
+    // neighbour half indices
+    const int xp = (x + 1 == A.Lx) ? 0 : x + 1;
+    const int xm = (x == 0) ? A.Lx - 1 : x - 1;
+    const int yp = (y + 1 == A.Ly) ? 0 : y + 1;
+    const int ym = (y == 0) ? A.Ly - 1 : y - 1;
+    const int zp = (z + 1 == A.Lz) ? 0 : z + 1;
+    const int zm = (z == 0) ? A.Lz - 1 : z - 1;
+    const int tp = (t + 1 == A.T) ? 0 : t + 1;
+    const int tm = (t == 0) ? A.T - 1 : t - 1;
+    const int hx_p = row * Lxh + (xp >> 1);
+    const int hx_m = row * Lxh + (xm >> 1);
+    const int hy_p = (tz * A.Ly + yp) * Lxh + xh;
+    const int hy_m = (tz * A.Ly + ym) * Lxh + xh;
+    const int hz_p = ((t * A.Lz + zp) * A.Ly + y) * Lxh + xh;
+    const int hz_m = ((t * A.Lz + zm) * A.Ly + y) * Lxh + xh;
+    const int ht_p = ((tp * A.Lz + z) * A.Ly + y) * Lxh + xh;
+    const int ht_m = ((tm * A.Lz + z) * A.Ly + y) * Lxh + xh;
+    const R sg_tp = (A.antiperiodic && t == A.T - 1) ? R(-1) : R(1);
+    const R sg_tm = (A.antiperiodic && t == 0) ? R(-1) : R(1);
+    hop_dir<0, true>(acc, A, f, ht_p, A.Uo, h, sg_tp);
+    hop_dir<0, false>(acc, A, f, ht_m, A.Ui, ht_m, sg_tm);
+    hop_dir<1, true>(acc, A, f, hx_p, A.Uo, h, R(1));
+    hop_dir<1, false>(acc, A, f, hx_m, A.Ui, hx_m, R(1));
+    hop_dir<2, true>(acc, A, f, hy_p, A.Uo, h, R(1));
+    hop_dir<2, false>(acc, A, f, hy_m, A.Ui, hy_m, R(1));
+    hop_dir<3, true>(acc, A, f, hz_p, A.Uo, h, R(1));
+    hop_dir<3, false>(acc, A, f, hz_m, A.Ui, hz_m, R(1));
+  }
+
+  // ---- epilogue (both lanes of a site are valid or invalid together) ----
+  const R a = R(A.a), mub = R(A.mubar), eps = R(A.epsbar);
+  const R t3 = f == 0 ? R(1) : R(-1);
+  cx<R> out[4][3];
+  if constexpr (EPI == EPI_PLAIN) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[s][c] = acc[s][c];
+  } else if constexpr (EPI == EPI_AINV) {
+    const R id = R(A.inv_den);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const R g5 = s < 2 ? R(1) : R(-1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<R> o = shfl1(acc[s][c]);
+        // (a - i mubar g5 tau3) acc_f + epsbar acc_{1-f}
+        out[s][c] = id * (a * acc[s][c] - (mub * g5 * t3) * ipl(acc[s][c]) + eps * o);
+      }
+    }
+  } else {
+    cx<R> xv[4][3];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xv[s][c] = {0, 0};
+    if (valid) load_flav<S, R>(xv, A.xs, A.xs_sc, f, A.stride, h);
+    const R hc = (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) ? R(-0.25) : R(A.hop_coef);
+    const R ms = R(A.ms);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const R g5 = s < 2 ? R(1) : R(-1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<R> xo = shfl1(xv[s][c]);
+        // y_f = a x_f + i mubar g5 tau3 x_f - epsbar x_{1-f} + hc acc_f (+ i ms g5 x_{1-f})
+        cx<R> y = a * xv[s][c] + (mub * g5 * t3) * ipl(xv[s][c]) - eps * xo + hc * acc[s][c];
+        if constexpr (EPI == EPI_SITE) y = y + (ms * g5) * ipl(xo);
+        out[s][c] = y;
+      }
+    }
+    if constexpr (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) {
+      // Gamma5 tau1: out_f = g5 y_{1-f}
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const R g5 = s < 2 ? R(1) : R(-1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[s][c] = g5 * shfl1(out[s][c]);
+      }
+    }
+    if constexpr (EPI == EPI_QHAT_SIG) {
+      cx<R> zv[4][3];
+      if (valid) {
+        load_flav<S, R>(zv, A.zs, A.zs_sc, f, A.stride, h);
+        const R sgm = R(A.sigma);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[s][c] = out[s][c] + sgm * zv[s][c];
+        if constexpr (RED == RED_REDOT) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+              red += double(zv[s][c].x) * double(out[s][c].x) + double(zv[s][c].y) * double(out[s][c].y);
+        }
+      }
+    }
+  }
+
+  if constexpr (RED == RED_NORM) {
+    if (valid) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          red += double(out[s][c].x) * double(out[s][c].x) + double(out[s][c].y) * double(out[s][c].y);
+    }
+  }
+
+  // ---- store ----
+  R inv_sc = 1;
+  if constexpr (kHalf<S>) {
+    R mx = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mx = fmaxf(mx, fmaxf(fabsf(out[s][c].x), fabsf(out[s][c].y)));
+    mx = fmaxf(mx, __shfl_xor(mx, 1));
+    inv_sc = mx > 0 ? R(1) / mx : R(0);
+    if (valid && f == 0) A.out_sc[h] = mx;
+  }
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<R> o = out[s][c];
+        if constexpr (kHalf<S>) o = inv_sc * o;
+        stc(A.out, (long)(f * 12 + s * 3 + c) * A.stride + h, o);
+      }
+  }
+  if constexpr (RED != RED_NONE) block_reduce_store(red, A.partials);
+}
+
+template <class S, class L>
+void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& op, const void* Uo,
+                  const void* Ui, const HalfField& in, const HalfField& out, const HalfField* xs,
+                  const HalfField* zs, double ms, double hop_coef, double sigma, double* partials,
+                  hipStream_t st) {
+  HopArgs<S, L> A;
+  A.in = static_cast<const S*>(in.v);
+  A.in_sc = in.sc;
+  A.Uo = static_cast<const L*>(Uo);
+  A.Ui = static_cast<const L*>(Ui);
+  A.out = static_cast<S*>(out.v);
+  A.out_sc = out.sc;
+  A.xs = xs ? static_cast<const S*>(xs->v) : nullptr;
+  A.xs_sc = xs ? xs->sc : nullptr;
+  A.zs = zs ? static_cast<const S*>(zs->v) : nullptr;
+  A.zs_sc = zs ? zs->sc : nullptr;
+  A.partials = partials;
+  A.T = g.T;
+  A.Lz = g.Lz;
+  A.Ly = g.Ly;
+  A.Lx = g.Lx;
+  A.vh = g.vh;
+  A.stride = g.stride;
+  A.parity = parity;
+  A.antiperiodic = g.antiperiodic;
+  A.a = op.a;
+  A.mubar = op.mubar;
+  A.epsbar = op.epsbar;
+  A.inv_den = op.inv_den;
+  A.ms = ms;
+  A.hop_coef = hop_coef;
+  A.sigma = sigma;
+  const dim3 grid(hop_grid(g)), block(kBlock);
+#define NDTM_HOP(E, RD) hipLaunchKernelGGL((hop_kernel<S, L, E, RD>), grid, block, 0, st, A)
+  switch (epi) {
+    case EPI_PLAIN: NDTM_HOP(EPI_PLAIN, RED_NONE); break;
+    case EPI_AINV: NDTM_HOP(EPI_AINV, RED_NONE); break;
+    case EPI_QHAT:
+      if (red == RED_NORM) NDTM_HOP(EPI_QHAT, RED_NORM);
+      else NDTM_HOP(EPI_QHAT, RED_NONE);
+      break;
+    case EPI_QHAT_SIG:
+      if (red == RED_REDOT) NDTM_HOP(EPI_QHAT_SIG, RED_REDOT);
+      else NDTM_HOP(EPI_QHAT_SIG, RED_NONE);
+      break;
+    case EPI_SITE: NDTM_HOP(EPI_SITE, RED_NONE); break;
+  }
+#undef NDTM_HOP
+}
+
+}  // namespace
+
+int hop_grid(const Geom& g) { return (g.vh + kSitesPerBlock - 1) / kSitesPerBlock; }
+
+void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpParams& op,
+                const void* Uo, const void* Ui, const HalfField& in, const HalfField& out,
+                const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
+                double* partials, hipStream_t st) {
+  switch (prec) {
+    case P64:
+      launch_typed<double2, double2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
+                                     sigma, partials, st);
+      break;
+    case P32:
+      launch_typed<float2, float2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
+                                   sigma, partials, st);
+      break;
+    default:
+      launch_typed<__half2, __half2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
+                                     sigma, partials, st);
+      break;
+  }
+}
+
+}  // namespace ndtm

@@ -1,0 +1,145 @@
+// Conversions between the canonical complex128 layouts of the C-ABI and the
+// internal structure-of-arrays even-odd storage in FP64, FP32 and FP16 (with
+// one FP32 scale per site: the largest |real| or |imag| part of the site's
+// 48 reals, values stored as binary16 of x/scale, round to nearest even).
+#include "ndtm_internal.h"
+
+namespace ndtm {
+namespace {
+
+__device__ __forceinline__ int site_parity(long s, int T, int Lz, int Ly, int Lx) {
+  const int x = s % Lx;
+  const long r = s / Lx;
+  const int y = r % Ly;
+  const long r2 = r / Ly;
+  const int z = r2 % Lz;
+  const int t = r2 / Lz;
+  return (t + z + y + x) & 1;
+}
+
+__global__ void pack_gauge_k(Geom g, const double2* U, double2* U64e, double2* U64o, float2* U32e,
+                             float2* U32o, __half2* U16e, __half2* U16o) {
+  const long V = 2L * g.vh;
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  const int p = site_parity(s, g.T, g.Lz, g.Ly, g.Lx);
+  const long h = s >> 1;
+  double2* d64 = p ? U64o : U64e;
+  float2* d32 = p ? U32o : U32e;
+  __half2* d16 = p ? U16o : U16e;
+  for (int k = 0; k < 36; ++k) {
+    const double2 u = U[s * 36 + k];
+    const long o = (long)k * g.stride + h;
+    d64[o] = u;
+    d32[o] = make_float2((float)u.x, (float)u.y);
+    d16[o] = __floats2half2_rn((float)u.x, (float)u.y);
+  }
+}
+
+// store one site's 24 complex values into a half field of any precision
+__device__ __forceinline__ void put_site(const HalfField& f, int stride, long h, const double2* v) {
+  if (f.prec == P64) {
+    double2* d = static_cast<double2*>(f.v);
+    for (int c = 0; c < 24; ++c) d[(long)c * stride + h] = v[c];
+  } else if (f.prec == P32) {
+    float2* d = static_cast<float2*>(f.v);
+    for (int c = 0; c < 24; ++c) d[(long)c * stride + h] = make_float2((float)v[c].x, (float)v[c].y);
+  } else {
+    double mx = 0;
+    for (int c = 0; c < 24; ++c) mx = fmax(mx, fmax(fabs(v[c].x), fabs(v[c].y)));
+    const float sc = (float)mx;
+    const double inv = sc > 0 ? 1.0 / (double)sc : 0.0;
+    __half2* d = static_cast<__half2*>(f.v);
+    for (int c = 0; c < 24; ++c)
+      d[(long)c * stride + h] = __floats2half2_rn((float)(v[c].x * inv), (float)(v[c].y * inv));
+    f.sc[h] = sc;
+  }
+}
+
+__device__ __forceinline__ void get_site(const HalfField& f, int stride, long h, double2* v) {
+  if (f.prec == P64) {
+    const double2* d = static_cast<const double2*>(f.v);
+    for (int c = 0; c < 24; ++c) v[c] = d[(long)c * stride + h];
+  } else if (f.prec == P32) {
+    const float2* d = static_cast<const float2*>(f.v);
+    for (int c = 0; c < 24; ++c) v[c] = make_double2(d[(long)c * stride + h].x, d[(long)c * stride + h].y);
+  } else {
+    const __half2* d = static_cast<const __half2*>(f.v);
+    const double sc = f.sc[h];
+    for (int c = 0; c < 24; ++c) {
+      const float2 t = __half22float2(d[(long)c * stride + h]);
+      v[c] = make_double2(t.x * sc, t.y * sc);
+    }
+  }
+}
+
+__global__ void pack_half_k(Geom g, const double2* canon, HalfField f) {
+  const long h = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (h >= g.vh) return;
+  double2 v[24];
+  for (int c = 0; c < 24; ++c) v[c] = canon[h * 24 + c];
+  put_site(f, g.stride, h, v);
+}
+
+__global__ void unpack_half_k(Geom g, HalfField f, double2* canon) {
+  const long h = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (h >= g.vh) return;
+  double2 v[24];
+  get_site(f, g.stride, h, v);
+  for (int c = 0; c < 24; ++c) canon[h * 24 + c] = v[c];
+}
+
+__global__ void pack_full_k(Geom g, const double2* canon, HalfField fe, HalfField fo) {
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= 2L * g.vh) return;
+  const int p = site_parity(s, g.T, g.Lz, g.Ly, g.Lx);
+  double2 v[24];
+  for (int c = 0; c < 24; ++c) v[c] = canon[s * 24 + c];
+  put_site(p ? fo : fe, g.stride, s >> 1, v);
+}
+
+__global__ void unpack_full_k(Geom g, HalfField fe, HalfField fo, double2* canon) {
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= 2L * g.vh) return;
+  const int p = site_parity(s, g.T, g.Lz, g.Ly, g.Lx);
+  double2 v[24];
+  get_site(p ? fo : fe, g.stride, s >> 1, v);
+  for (int c = 0; c < 24; ++c) canon[s * 24 + c] = v[c];
+}
+
+__global__ void convert_half_k(Geom g, HalfField src, HalfField dst) {
+  const long h = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (h >= g.vh) return;
+  double2 v[24];
+  get_site(src, g.stride, h, v);
+  put_site(dst, g.stride, h, v);
+}
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* U64o, float2* U32e,
+                       float2* U32o, __half2* U16e, __half2* U16o, hipStream_t st) {
+  hipLaunchKernelGGL(pack_gauge_k, dim3(nblk(2L * g.vh, 256)), dim3(256), 0, st, g, U, U64e, U64o,
+                     U32e, U32o, U16e, U16o);
+}
+void launch_pack_half(const Geom& g, const double2* canon, const HalfField& f, hipStream_t st) {
+  hipLaunchKernelGGL(pack_half_k, dim3(nblk(g.vh, 256)), dim3(256), 0, st, g, canon, f);
+}
+void launch_unpack_half(const Geom& g, const HalfField& f, double2* canon, hipStream_t st) {
+  hipLaunchKernelGGL(unpack_half_k, dim3(nblk(g.vh, 256)), dim3(256), 0, st, g, f, canon);
+}
+void launch_pack_full(const Geom& g, const double2* canon, const HalfField& fe, const HalfField& fo,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(pack_full_k, dim3(nblk(2L * g.vh, 256)), dim3(256), 0, st, g, canon, fe, fo);
+}
+void launch_unpack_full(const Geom& g, const HalfField& fe, const HalfField& fo, double2* canon,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(unpack_full_k, dim3(nblk(2L * g.vh, 256)), dim3(256), 0, st, g, fe, fo, canon);
+}
+void launch_convert_half(const Geom& g, const HalfField& src, const HalfField& dst, hipStream_t st) {
+  hipLaunchKernelGGL(convert_half_k, dim3(nblk(g.vh, 256)), dim3(256), 0, st, g, src, dst);
+}
+
+}  // namespace ndtm

@@ -1,0 +1,124 @@
+// Internal declarations of the ndtm library (not part of the C-ABI).
+//
+// Internal storage layouts (all per parity, structure of arrays so that a
+// wavefront reads 64 consecutive sites of one component):
+//   half spinor field: component c = f*12 + spin*3 + colour, site h:
+//       element [c * stride + h], 24 components; FP16 fields carry one FP32
+//       scale per site, sc[h].
+//   links of parity p: element [(mu*9 + row*3 + col) * stride + h] is U_mu(x)
+//       of the site x with half index h and parity p.
+//   full-lattice vector: even half field followed by the odd half field.
+//   stride = vh rounded up to a multiple of 256; padding stays zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ndtm {
+
+constexpr int kBlock = 256;         // threads per block of the lattice kernels
+constexpr int kSitesPerBlock = 128; // two threads (one per flavour) per site
+constexpr int kMaxShifts = 16;
+constexpr int kMaxPartials = 8192;  // reduction partials per scalar
+
+struct Geom {
+  int T, Lz, Ly, Lx;
+  int vh;      // V/2
+  int stride;  // padded vh
+  int antiperiodic;
+};
+
+enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+// Epilogues of the hopping kernel.
+enum Epi {
+  EPI_PLAIN = 0,   // out = H in
+  EPI_AINV = 1,    // out = A^-1 H in
+  EPI_QHAT = 2,    // out = Gamma5 tau1 (A xs - 1/4 H in)
+  EPI_QHAT_SIG = 3,// out = Gamma5 tau1 (A xs - 1/4 H in) + sigma zs
+  EPI_SITE = 4     // out = (A + i ms Gamma5 tau1) xs + hop_coef H in
+};
+enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2 };
+
+struct OpParams {
+  double a, mubar, epsbar, inv_den;
+};
+
+// A precision-tagged half field (device pointers).
+struct HalfField {
+  void* v = nullptr;    // double2 / float2 / __half2
+  float* sc = nullptr;  // per-site scale (FP16 only)
+  int prec = P64;
+};
+
+// Launch the hopping kernel: out (parity `parity`) from in (parity 1-parity).
+// Uo: links of the output parity, Ui: links of the input parity (same precision
+// as the fields: FP64 links for P64, FP32 for P32, FP16 for P16).
+void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpParams& op,
+                const void* Uo, const void* Ui, const HalfField& in, const HalfField& out,
+                const HalfField* xs, const HalfField* zs, double ms, double hop_coef,
+                double sigma, double* partials, hipStream_t st);
+int hop_grid(const Geom& g);
+
+// ---- layout conversion -------------------------------------------------
+void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* U64o, float2* U32e,
+                       float2* U32o, __half2* U16e, __half2* U16o, hipStream_t st);
+// canonical [V/2][24] (complex128) <-> internal half field (any precision)
+void launch_pack_half(const Geom& g, const double2* canon, const HalfField& f, hipStream_t st);
+void launch_unpack_half(const Geom& g, const HalfField& f, double2* canon, hipStream_t st);
+// canonical full lattice [V][24] <-> even + odd half fields
+void launch_pack_full(const Geom& g, const double2* canon, const HalfField& fe, const HalfField& fo,
+                      hipStream_t st);
+void launch_unpack_full(const Geom& g, const HalfField& fe, const HalfField& fo, double2* canon,
+                        hipStream_t st);
+// precision conversion between internal half fields of the same geometry
+void launch_convert_half(const Geom& g, const HalfField& src, const HalfField& dst, hipStream_t st);
+
+// ---- BLAS on FP64 complex arrays of n elements ------------------------------
+void blas_zero(void* p, size_t bytes, hipStream_t st);
+void blas_copy(double2* y, const double2* x, size_t n, hipStream_t st);
+void blas_axpy(double2* y, double2 a, const double2* x, size_t n, hipStream_t st);      // y += a x
+void blas_xpay(double2* y, const double2* x, double2 a, size_t n, hipStream_t st);      // y = x + a y
+void blas_axpby(double2* y, double2 a, const double2* x, double2 b, size_t n, hipStream_t st); // y = a x + b y
+void blas_scale(double2* y, double2 a, size_t n, hipStream_t st);
+// partial sums, then finalize into dst (device) in a fixed order
+int blas_norm2_partials(const double2* x, size_t n, double* partials, hipStream_t st);
+int blas_dot_partials(const double2* x, const double2* y, size_t n, double* partials, hipStream_t st);  // <x,y>, 2 doubles
+void blas_finalize(const double* partials, int nparts, int width, double* dst, hipStream_t st);
+// multi-dot: dst[2i..2i+1] = <V_i, w> for i < k (V_i = base + i*ld)
+void blas_multidot(const double2* const* V, int k, const double2* w, size_t n, double* partials,
+                   double* dst, hipStream_t st);
+// w -= sum_i coef[i] V_i, coef read from device memory (complex, 2 doubles each), scaled by sgn
+void blas_multi_axpy_dev(double2* w, const double2* const* V, int k, const double* coef, double sgn,
+                         size_t n, hipStream_t st);
+// y = sum_i c_i V_i (host coefficients)
+void blas_lincomb(double2* y, const double2* const* V, const double2* c, int k, size_t n,
+                  hipStream_t st);
+// Gram matrix M_ij = <V_i, V_j> (upper triangle incl. diagonal) into dst[(i*k+j)*2]
+void blas_gram(const double2* const* V, int k, size_t n, double* partials, double* dst, hipStream_t st);
+
+// ---- MMS-CG -----------------------------------------------------------------
+struct MmsState;  // device-side scalars, see kern_cg.hip
+void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st);
+void mms_update_r(double2* r, const double2* w, const double* S, size_t n, double* partials,
+                  hipStream_t st);
+void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st);
+void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh,
+                  const double* S, size_t n, hipStream_t st);
+void mms_init(double* S, int nsh, const double* deltas_host, double tol, hipStream_t st);
+// Layout of the scalar block S (doubles).
+enum MmsIdx {
+  MS_RR = 0, MS_PW, MS_ALPHA, MS_ALPHA_PREV, MS_BETA, MS_BB, MS_TOL2, MS_IT, MS_NSH, MS_DONE,
+  MS_BREAK, MS_HDR = 16,
+  // per-shift arrays of length kMaxShifts follow
+  MS_ZETA = MS_HDR, MS_ZETA_PREV = MS_ZETA + kMaxShifts, MS_ZETA_NEXT = MS_ZETA_PREV + kMaxShifts,
+  MS_ALPHA_S = MS_ZETA_NEXT + kMaxShifts, MS_BETA_S = MS_ALPHA_S + kMaxShifts,
+  MS_DELTA = MS_BETA_S + kMaxShifts, MS_ACT = MS_DELTA + kMaxShifts,
+  MS_ACT_NEXT = MS_ACT + kMaxShifts, MS_ITERS = MS_ACT_NEXT + kMaxShifts,
+  MS_SIZE = MS_ITERS + kMaxShifts
+};
+
+}  // namespace ndtm

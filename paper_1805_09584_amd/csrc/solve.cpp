@@ -1,0 +1,262 @@
+// Solve drivers: multi-shift CG (MMS-CG) with device-side recurrences, the
+// FP64 true-residual check with single-shift CG polish, and ndtm_solve.
+//
+// MMS-CG follows the multi-mass-shift scheme the paper takes as its standard
+// solver (sections 1 and 4.2): one CG Krylov space built for the smallest shift
+// of the set iterates all shifted systems (Q^2 + sigma_s) x_s = b through
+// r_s = zeta_s r.  Each iteration is
+//   w = (Q^2 + sigma_base) p        two Q applications, Re<p,w> fused in the last epilogue
+//   scalars (alpha, zeta_s, alpha_s) one-block kernel
+//   r -= alpha w, ||r||^2            fused
+//   scalars (beta, beta_s, freeze)   one-block kernel
+//   x_s += alpha_s p_s, p_s = zeta_s r + beta_s p_s, p = r + beta p   fused over active shifts
+// with a host poll of the done flag every poll_every iterations.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ctx.h"
+
+namespace ndtm {
+
+int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
+              const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
+              hipStream_t st) {
+  const int nsh = (int)sigmas.size();
+  const size_t n = half_elems(c);
+  const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
+  HalfField r = half_field(c, "cg_r", P64), p = half_field(c, "cg_p", P64), w = half_field(c, "cg_w", P64);
+  HalfField u = half_field(c, "cg_u", P64), te = half_field(c, "cg_te", P64);
+  std::vector<double2*> ps(nsh), xv(nsh);
+  for (int s = 0; s < nsh; ++s) {
+    HalfField f = half_field(c, "cg_ps" + std::to_string(s), P64);
+    if (!f.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
+    ps[s] = static_cast<double2*>(f.v);
+    xv[s] = static_cast<double2*>(xs[s].v);
+  }
+  if (!r.v || !p.v || !w.v || !u.v || !te.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
+  const double2* bv = static_cast<const double2*>(b.v);
+  blas_copy((double2*)r.v, bv, n, st);
+  blas_copy((double2*)p.v, bv, n, st);
+  for (int s = 0; s < nsh; ++s) {
+    blas_copy(ps[s], bv, n, st);
+    blas_zero(xv[s], n * sizeof(double2), st);
+  }
+  std::vector<double> S(MS_SIZE, 0.0);
+  S[MS_ALPHA_PREV] = 1.0;
+  S[MS_BETA] = 0.0;
+  S[MS_TOL2] = tol * tol;
+  S[MS_NSH] = nsh;
+  for (int s = 0; s < nsh; ++s) {
+    S[MS_ZETA + s] = S[MS_ZETA_PREV + s] = 1.0;
+    S[MS_DELTA + s] = sigmas[s] - sig_base;
+    S[MS_ACT_NEXT + s] = 1.0;
+  }
+  NDTM_HIP(c, hipMemcpyAsync(c->mms_S, S.data(), MS_SIZE * sizeof(double), hipMemcpyHostToDevice, st));
+  {
+    const int g = blas_norm2_partials(bv, n, c->partials, st);
+    blas_finalize(c->partials, g, 1, c->dscal, st);
+    mms_seed(c->mms_S, c->dscal, st);
+  }
+  const int hg = hop_grid(c->g);
+  const int rg = red_grid(n);
+  int it = 0;
+  if (poll_every < 1) poll_every = 1;
+  while (it < maxiter) {
+    apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
+    mms_scal1(c->mms_S, c->partials, hg, st);
+    {
+      ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
+      mms_update_r((double2*)r.v, (const double2*)w.v, c->mms_S, n, c->partials, st);
+    }
+    mms_scal2(c->mms_S, c->partials, rg, st);
+    {
+      // bytes of this class are added after the loop, once the active counts are known
+      ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
+      mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, c->mms_S, n, st);
+    }
+    ++it;
+    if (it % poll_every == 0 || it == maxiter) {
+      NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S + MS_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
+      NDTM_HIP(c, hipStreamSynchronize(st));
+      if (c->hscal[0] != 0.0) break;
+    }
+  }
+  NDTM_HIP(c, hipGetLastError());
+  NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
+  NDTM_HIP(c, hipStreamSynchronize(st));
+  res->iterations = (int)c->hscal[MS_IT];
+  res->breakdown = c->hscal[MS_BREAK] != 0.0;
+  res->iters.resize(nsh);
+  for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
+  bool done = c->hscal[MS_DONE] != 0.0;
+  if ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1) {
+    // every launch moves r, p (read, p written) and x_s, p_s (read and written) of each active shift;
+    // a shift is active in exactly iters[s] launches, and all `it` launches ran
+    double active_launches = 0;
+    for (int s = 0; s < nsh; ++s) active_launches += res->iters[s];
+    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += (3.0 * it + 4.0 * active_launches) * 384.0 * c->g.vh;
+  }
+  if (res->breakdown) return fail(c, NDTM_EBREAKDOWN, "mmscg: breakdown (non-finite or p.Ap <= 0)");
+  return done ? NDTM_OK : NDTM_ENOCONV;
+}
+
+double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, const HalfField& r,
+                     hipStream_t st) {
+  const size_t n = half_elems(c);
+  HalfField u = half_field(c, "tr_u", P64), te = half_field(c, "tr_te", P64);
+  apply_qhat2(c, P64, r, x, u, te, sigma, nullptr, st);
+  // r = b - (Q^2 + sigma) x
+  blas_axpby((double2*)r.v, make_double2(1, 0), (const double2*)b.v, make_double2(-1, 0), n, st);
+  const double rr = norm2_host(c, (const double2*)r.v, n, st);
+  const double bb = norm2_host(c, (const double2*)b.v, n, st);
+  return std::sqrt(rr / bb);
+}
+
+// x += CG((Q^2 + sigma) e = r) until the true residual of x meets tol (up to `rounds` restarts).
+static int polish_cg(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
+                     double* res_out, int* iters_out, hipStream_t st) {
+  const size_t n = half_elems(c);
+  HalfField r = half_field(c, "pol_r", P64), e = half_field(c, "pol_e", P64);
+  if (!r.v || !e.v) return fail(c, NDTM_ENOMEM, "polish: workspace");
+  double res = true_residual(c, x, b, sigma, r, st);
+  int total = 0;
+  for (int round = 0; round < 4 && res > tol; ++round) {
+    MmsResult mr;
+    std::vector<HalfField> es{e};
+    const double inner = std::min(0.5, 0.5 * tol / res);
+    int rc = run_mmscg(c, {sigma}, es, r, inner, maxiter, 8, &mr, st);
+    total += mr.iterations;
+    if (rc == NDTM_EBREAKDOWN) return rc;
+    blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e.v, n, st);
+    res = true_residual(c, x, b, sigma, r, st);
+  }
+  *res_out = res;
+  *iters_out = total;
+  return res <= tol ? NDTM_OK : NDTM_ENOCONV;
+}
+
+// The hybrid part (multigrid shifts) lives in mg.cpp.
+int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig_desc, int n_mms, std::vector<HalfField>& xs,
+                    const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st);
+
+}  // namespace ndtm
+
+using namespace ndtm;
+
+extern "C" {
+
+void ndtm_solve_default_params(ndtm_solve_params* p) {
+  if (!p) return;
+  p->tol = 1e-10;
+  p->maxiter = 20000;
+  p->n_mmscg = NDTM_MAX_SHIFTS;
+  p->guess = NDTM_GUESS_LAGRANGE;
+  p->precision = NDTM_PREC_F64;
+  p->poll_every = 8;
+  p->mg_tol = 1e-9;
+  p->fgmres_restart = 16;
+  p->fgmres_maxiter = 400;
+  p->max_rounds = 6;
+}
+
+int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_solve_params* p,
+               ndtm_solve_report* rep, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!x_dev || !b_dev || !p || !rep) return fail(c, NDTM_EINVAL, "solve: null argument");
+  if (!c->have_gauge || !c->have_params || c->shifts.empty())
+    return fail(c, NDTM_ESTATE, "solve: set_gauge, set_params and set_shifts first");
+  if (!(p->tol > 0) || p->maxiter < 1) return fail(c, NDTM_EINVAL, "solve: tol > 0 and maxiter >= 1");
+  const int nsh = (int)c->shifts.size();
+  for (int i = 0; i < nsh; ++i)
+    if (!x_dev[i]) return fail(c, NDTM_EINVAL, "solve: null solution pointer");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  std::memset(rep, 0, sizeof(*rep));
+  rep->n_shifts = nsh;
+  // descending order (section 4.2: solve sigma_1 > sigma_2 > ...)
+  std::vector<int> order(nsh);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return c->shifts[a] > c->shifts[b]; });
+  std::vector<double> sig(nsh);
+  for (int i = 0; i < nsh; ++i) {
+    sig[i] = c->shifts[order[i]];
+    rep->sigma[i] = sig[i];
+    rep->input_index[i] = order[i];
+    rep->mlp_res[i] = -1.0;
+  }
+  const size_t n = half_elems(c);
+  HalfField B = half_field(c, "sv_b", P64);
+  if (!B.v) return fail(c, NDTM_ENOMEM, "solve: workspace");
+  launch_pack_half(c->g, static_cast<const double2*>(b_dev), B, st);
+  const double bb = norm2_host(c, (const double2*)B.v, n, st);
+  if (!std::isfinite(bb)) {
+    rep->status = NDTM_EBREAKDOWN;
+    return fail(c, NDTM_EBREAKDOWN, "solve: b is not finite");
+  }
+  std::vector<HalfField> xs(nsh);
+  for (int i = 0; i < nsh; ++i) {
+    xs[i] = half_field(c, "sv_x" + std::to_string(i), P64);
+    if (!xs[i].v) return fail(c, NDTM_ENOMEM, "solve: workspace");
+  }
+  if (bb == 0.0) {
+    for (int i = 0; i < nsh; ++i) blas_zero(xs[i].v, n * sizeof(double2), st);
+    for (int i = 0; i < nsh; ++i) launch_unpack_half(c->g, xs[i], static_cast<double2*>(x_dev[order[i]]), st);
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    return NDTM_OK;
+  }
+  const int n_mms = std::max(1, std::min(p->n_mmscg, nsh));
+  int status = NDTM_OK;
+  // ---- MMS-CG for the n_mms largest shifts ----
+  {
+    std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
+    std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms);
+    MmsResult mr;
+    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, &mr, st);
+    rep->mms_iterations = mr.iterations;
+    if (rc == NDTM_EBREAKDOWN) {
+      rep->status = rc;
+      return rc;
+    }
+    HalfField R = half_field(c, "sv_r", P64);
+    for (int i = 0; i < n_mms; ++i) {
+      rep->method[i] = 0;
+      rep->iterations[i] = mr.iters[i];
+      double res = true_residual(c, xs[i], B, sig[i], R, st);
+      if (res > p->tol) {
+        int extra = 0;
+        int prc = polish_cg(c, xs[i], B, sig[i], p->tol, p->maxiter, &res, &extra, st);
+        rep->iterations[i] += extra;
+        if (prc != NDTM_OK) status = prc;
+      }
+      rep->true_res[i] = res;
+    }
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  rep->t_mms_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  // ---- multigrid (case C) for the remaining shifts ----
+  if (n_mms < nsh) {
+    int rc = solve_mg_shifts(c, sig, n_mms, xs, B, p, rep, st);
+    if (rc != NDTM_OK && status == NDTM_OK) status = rc;
+  }
+  for (int i = 0; i < nsh; ++i) launch_unpack_half(c->g, xs[i], static_cast<double2*>(x_dev[order[i]]), st);
+  NDTM_HIP(c, hipStreamSynchronize(st));
+  NDTM_HIP(c, hipGetLastError());
+  auto t2 = std::chrono::steady_clock::now();
+  rep->t_total_ms = std::chrono::duration<double, std::milli>(t2 - t0).count();
+  if ((c->prof_mask >> NDTM_PROF_HOP_F64) & 1) {
+    double ms = 0;
+    long long nl = 0;
+    ndtm_profile_read(c, NDTM_PROF_HOP_F64, &ms, &nl, nullptr, 0);
+    rep->hop_ms = ms;
+    rep->hop_launches = nl;
+  }
+  rep->status = status;
+  if (status == NDTM_ENOCONV) c->err = "solve: a shift missed the tolerance";
+  return status;
+}
+
+}  // extern "C"

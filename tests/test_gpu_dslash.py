@@ -1,0 +1,101 @@
+"""GPU parity of the stencil operators against the FP64 oracle (through the C-ABI).
+
+Bar: FP64 applications match to 1e-12 relative (norm-wise and per-site max);
+FP32 to 2e-6; FP16 storage (per-site scale, FP32 arithmetic) to 5e-3.
+Lattices: 2^4 (neighbours alias), a ragged one (V/2 not a multiple of the
+128-site block), the 4^4 config and the 16^3x32 config (several hundred blocks).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.lattice import Lattice, NDOperator
+from tests.gpu_util import dev, host, rel_err, site_err
+
+pytestmark = pytest.mark.gpu
+
+K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
+TOL = {0: 1e-12, 1: 2e-6, 2: 5e-3}
+
+CASES = [((2, 2, 2, 2), False), ((2, 2, 2, 2), True), ((6, 4, 2, 10), True), ((4, 4, 4, 4), False),
+         ((32, 16, 16, 16), False)]
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1805_09584_amd as nd
+    return nd
+
+
+def _setup(nd, dims, ap, seed=11):
+    U = synth.gauge_field(dims, seed, 0.3)
+    lat = Lattice(dims, U, antiperiodic_t=ap)
+    op = NDOperator(lat, K, MB, EB)
+    ctx = nd.Context(dims, bc_flags=1 if ap else 0)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    return lat, op, ctx
+
+
+@pytest.mark.parametrize("dims,ap", CASES)
+def test_hop_and_qhat_fp64(nd, dims, ap):
+    print(f"case dims={dims} antiperiodic={ap}", flush=True)
+    lat, op, ctx = _setup(nd, dims, ap)
+    x = synth.gaussian_spinor(dims, 5)
+    xd = dev(x)
+    got = host(ctx.ndtm_apply(nd.NDTM_OP_HOP_EO, xd))
+    want = op.H_eo(x)
+    assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
+    got = host(ctx.ndtm_apply(nd.NDTM_OP_HOP_OE, xd))
+    want = op.H_oe(x)
+    assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
+    got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT, xd))
+    want = op.Q_hat(x)
+    assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
+    if dims != (32, 16, 16, 16):
+        got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.0123))
+        want = op.Q_hat2(x, 0.0123)
+        assert rel_err(got, want) < 1e-12
+        got = host(ctx.ndtm_apply(nd.NDTM_OP_SHAT_SHIFT, xd, -0.0316))
+        want = op.S_shift(x, -0.0316)
+        assert rel_err(got, want) < 1e-12
+        xf = synth.gaussian_spinor(dims, 6, "full")
+        got = host(ctx.ndtm_apply(nd.NDTM_OP_DFULL, dev(xf), 0.05))
+        want = op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=0.05).reshape(xf.shape)
+        assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 10)])
+def test_low_precision_operators(nd, dims, prec):
+    print(f"case dims={dims} prec={prec}", flush=True)
+    lat, op, ctx = _setup(nd, dims, False)
+    x = synth.gaussian_spinor(dims, 7)
+    xd = dev(x)
+    for opcode, ref, par in ((nd.NDTM_OP_QHAT, lambda v: op.Q_hat(v), 0.0),
+                             (nd.NDTM_OP_SHAT_SHIFT, lambda v: op.S_shift(v, 0.02), 0.02),
+                             (nd.NDTM_OP_HOP_EO, lambda v: op.H_eo(v), 0.0)):
+        got = host(ctx.ndtm_apply(opcode, xd, par, prec=prec))
+        want = ref(x)
+        assert rel_err(got, want) < TOL[prec], (opcode, rel_err(got, want))
+    xf = synth.gaussian_spinor(dims, 8, "full")
+    got = host(ctx.ndtm_apply(nd.NDTM_OP_DFULL, dev(xf), 0.03, prec=prec))
+    want = op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=0.03).reshape(xf.shape)
+    assert rel_err(got, want) < TOL[prec]
+    ctx.close()
+
+
+def test_errors_and_state(nd):
+    ctx = nd.Context((4, 4, 4, 4))
+    x = dev(synth.gaussian_spinor((4, 4, 4, 4), 1))
+    with pytest.raises(nd.NdtmError) as e:
+        ctx.ndtm_apply(nd.NDTM_OP_QHAT, x)
+    assert e.value.code == -5  # ESTATE before set_gauge
+    with pytest.raises(nd.NdtmError):
+        ctx.ndtm_set_params(-1.0, MB, EB)
+    with pytest.raises(nd.NdtmError):
+        ctx.ndtm_set_shifts([0.1, 0.1])
+    with pytest.raises(nd.NdtmError):
+        nd.Context((3, 4, 4, 4))
+    ctx.close()

@@ -1,0 +1,81 @@
+"""GPU multi-shift CG against the FP64 oracle.
+
+* 4^4 config (10 shifts, 1e-4..1): every shift's true relative residual,
+  recomputed by the oracle, is <= 1e-10; each solution lies within the
+  appendix A bound ||x - x*|| <= ||r|| / (lambda_min + sigma) of the oracle's
+  own MMS-CG solution (both within the tolerance, so within twice the bound).
+* 16^3x32 config, all 12 shifts by MMS-CG: sampled shifts checked by the
+  oracle's true residual.
+* zero and non-finite right-hand sides.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import solvers
+from oracle.lattice import Lattice, NDOperator, norm2, rel_residual
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1805_09584_amd as nd
+    return nd
+
+
+def _ctx(nd, cfg):
+    c = synth.CONFIGS[cfg]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_shifts(list(c["shifts"]))
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    return ctx, op, b, c["shifts"]
+
+
+def test_mmscg_config1(nd):
+    print("case c1 plain MMS-CG", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c1")
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=1e-10))
+    xo, it, _ = solvers.mms_cg(lambda v: op.Q_hat2(v, sig[-1]), b, sig - sig[-1], tol=1e-10)
+    bn = np.sqrt(norm2(b))
+    lmin_lb = 0.0  # lambda_min >= 0; the bound below uses sigma only (weaker, still a bound)
+    for i, s in enumerate(sig):
+        x = host(xs[i])
+        r = rel_residual(op, x, b, s)
+        assert r <= 1e-10, (i, r)
+        assert rep["true_res"][rep["input_index"].index(i)] <= 1e-10
+        assert np.linalg.norm(x - xo[i]) <= 2e-10 * bn / (lmin_lb + s)
+    assert abs(rep["mms_iterations"] - it) <= 8  # same Krylov space; polls every 8 iterations
+    ctx.close()
+
+
+def test_mmscg_config2_sampled(nd):
+    print("case c2 plain MMS-CG", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c2")
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=1e-10))
+    for i in (0, 6, 11):
+        r = rel_residual(op, host(xs[i]), b, sig[i])
+        assert r <= 1e-10, (i, r)
+    print("c2 report", rep["mms_iterations"], rep["iterations"], rep["t_total_ms"], flush=True)
+    ctx.close()
+
+
+def test_zero_and_nonfinite_rhs(nd):
+    ctx, op, b, sig = _ctx(nd, "c1")
+    z = np.zeros_like(b)
+    xs, rep = ctx.ndtm_solve(dev(z))
+    assert all(np.abs(host(x)).max() == 0 for x in xs)
+    bad = b.copy()
+    bad[3, 0, 0, 0] = np.nan
+    with pytest.raises(nd.NdtmError) as e:
+        ctx.ndtm_solve(dev(bad))
+    assert e.value.code == -4
+    ctx.close()
