@@ -152,7 +152,8 @@ typedef struct {
   int guess;           /* NDTM_GUESS_* for the multigrid shifts */
   int precision;       /* NDTM_PREC_F64, or NDTM_PREC_F32/F16 for the mixed form */
   int poll_every;      /* MMS-CG iterations between host convergence polls */
-  double mg_tol;       /* relative residual of each single (Q +- i m) solve per round */
+  double mg_tol;       /* cap on the relative residual of each single (Q +- i m) solve; each
+                          round tightens it so that the squared system meets tol */
   int fgmres_restart;  /* outer FGMRES restart length */
   int fgmres_maxiter;  /* outer FGMRES iteration cap per single solve */
   int max_rounds;      /* FP64 defect-correction rounds per multigrid shift */

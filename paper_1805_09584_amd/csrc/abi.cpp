@@ -32,6 +32,17 @@ void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes) {
   return b.p;
 }
 
+void ws_free_prefix(ndtm_ctx* c, const std::string& prefix) {
+  for (auto it = c->bufs.begin(); it != c->bufs.end();) {
+    if (it->first.compare(0, prefix.size(), prefix) == 0) {
+      if (it->second.p) (void)hipFree(it->second.p);
+      it = c->bufs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 size_t half_elems(const ndtm_ctx* c) { return (size_t)24 * c->g.stride; }
 
 HalfField half_field(ndtm_ctx* c, const std::string& name, int prec) {

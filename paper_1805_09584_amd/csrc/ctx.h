@@ -115,3 +115,13 @@ double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
                      const HalfField& r, hipStream_t st);
 
 }  // namespace ndtm
+
+extern "C" {
+void ndtm_mg_free(ndtm_ctx* c);
+void ndtm_mlp_free(ndtm_ctx* c);
+}
+
+namespace ndtm {
+// frees every workspace buffer whose name starts with prefix
+void ws_free_prefix(ndtm_ctx* c, const std::string& prefix);
+}  // namespace ndtm

@@ -115,9 +115,25 @@ __global__ void convert_half_k(Geom g, HalfField src, HalfField dst) {
   put_site(dst, g.stride, h, v);
 }
 
+// out = Gamma5 x tau1 in (site-local: out_{f,s} = g5_s in_{1-f,s}), FP64 half fields
+__global__ void g5t1_k(Geom g, const double2* in, double2* out) {
+  const long h = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (h >= g.vh) return;
+  for (int f = 0; f < 2; ++f)
+    for (int sc = 0; sc < 12; ++sc) {
+      const double g5 = sc < 6 ? 1.0 : -1.0;
+      const double2 v = in[(long)((1 - f) * 12 + sc) * g.stride + h];
+      out[(long)(f * 12 + sc) * g.stride + h] = make_double2(g5 * v.x, g5 * v.y);
+    }
+}
+
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
+
+void launch_g5t1(const Geom& g, const double2* in, double2* out, hipStream_t st) {
+  hipLaunchKernelGGL(g5t1_k, dim3(nblk(g.vh, 256)), dim3(256), 0, st, g, in, out);
+}
 
 void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* U64o, float2* U32e,
                        float2* U32o, __half2* U16e, __half2* U16o, hipStream_t st) {

@@ -1,0 +1,579 @@
+// Two-level aggregation multigrid kernels (section 3 and section 3.2):
+// block orthonormalisation of the test vectors, the Galerkin coarse operator
+// D_W,c = P^+ D_W P and C_o's block P^+ P_odd P, restriction (P x I2)^+,
+// prolongation (P x I2), and the coarse doublet stencil
+//   D'_c = D_W,c x I2 + i d mubar Gamma5_c x tau3 - epsbar I x tau1 + i m (Gamma5_c P^+P_odd P) x tau1.
+//
+// Storage: P[X][l][row][k] (row = spin*3 + colour, k < N_v; a row belongs to
+// chirality spin/2, so column (chi, k) of P is nonzero only on its chirality's
+// rows), coarse blocks D[X][b][j][i] (column-major so that the threads of one
+// output row i read consecutive addresses), coarse vectors [X][flavour][chi*N_v + k].
+#include <cstdint>
+
+#include "vec.h"
+
+namespace ndtm {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+struct SiteLoc {
+  int par, h, t, z, y, x;
+};
+
+__device__ __forceinline__ SiteLoc agg_site(const MGGeom& m, int X, int l) {
+  int r = X;
+  const int cx = r % m.CX;
+  r /= m.CX;
+  const int cy = r % m.CY;
+  r /= m.CY;
+  const int cz = r % m.CZ;
+  const int ct = r / m.CZ;
+  int q = l;
+  const int lx = q % m.bx;
+  q /= m.bx;
+  const int ly = q % m.by;
+  q /= m.by;
+  const int lz = q % m.bz;
+  const int lt = q / m.bz;
+  SiteLoc s;
+  s.t = ct * m.bt + lt;
+  s.z = cz * m.bz + lz;
+  s.y = cy * m.by + ly;
+  s.x = cx * m.bx + lx;
+  const long site = (((long)s.t * m.Lz + s.z) * m.Ly + s.y) * m.Lx + s.x;
+  s.par = (s.t + s.z + s.y + s.x) & 1;
+  s.h = (int)(site >> 1);
+  return s;
+}
+
+__device__ __forceinline__ void agg_local(const MGGeom& m, int l, int loc[4]) {
+  // loc indexed by direction mu: 0 t, 1 x, 2 y, 3 z
+  int q = l;
+  loc[1] = q % m.bx;
+  q /= m.bx;
+  loc[2] = q % m.by;
+  q /= m.by;
+  loc[3] = q % m.bz;
+  loc[0] = q / m.bz;
+}
+
+__device__ __forceinline__ int local_index(const MGGeom& m, const int loc[4]) {
+  return ((loc[0] * m.bz + loc[3]) * m.by + loc[2]) * m.bx + loc[1];
+}
+
+// neighbouring coarse site in direction mu (+1 or -1), periodic
+__device__ __forceinline__ int coarse_nbr(const MGGeom& m, int X, int mu, int dir) {
+  int r = X;
+  int c[4];
+  c[1] = r % m.CX;
+  r /= m.CX;
+  c[2] = r % m.CY;
+  r /= m.CY;
+  c[3] = r % m.CZ;
+  c[0] = r / m.CZ;
+  const int ext[4] = {m.CT, m.CX, m.CY, m.CZ};
+  c[mu] = (c[mu] + dir + ext[mu]) % ext[mu];
+  return ((c[0] * m.CZ + c[3]) * m.CY + c[2]) * m.CX + c[1];
+}
+
+// block sum of cnt doubles per thread; result in out[0..cnt) (shared), all threads synchronised
+__device__ void block_reduce_batch(double* v, int cnt, double* lds, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < cnt; ++i) {
+    double s = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+    if (lane == 0) lds[w * cnt + i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    double s = 0;
+    for (int q = 0; q < nw; ++q) s += lds[q * cnt + i];
+    out[i] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------- test vectors -> P ----------------
+__global__ void tv_to_P_k(MGGeom m, const double2* tv, double2* P) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)m.Vc * m.nloc) return;
+  const int X = idx / m.nloc, l = idx % m.nloc;
+  const SiteLoc s = agg_site(m, X, l);
+  const long site = (((long)s.t * m.Lz + s.z) * m.Ly + s.y) * m.Lx + s.x;
+  const long V = (long)m.T * m.Lz * m.Ly * m.Lx;
+  for (int r = 0; r < 12; ++r)
+    for (int k = 0; k < m.Nv; ++k) P[(idx * 12 + r) * m.Nv + k] = tv[((long)k * V + site) * 12 + r];
+}
+
+struct FieldList {
+  const double2* f[16];
+};
+
+__global__ void fields_to_P_k(MGGeom m, FieldList F, double2* P) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (idx >= (long)m.Vc * m.nloc) return;
+  const int X = idx / m.nloc, l = idx % m.nloc;
+  const SiteLoc s = agg_site(m, X, l);
+  const long half = 24L * m.stride;
+  for (int k = 0; k < m.Nv; ++k) {
+    const double2* base = F.f[k >> 1] + s.par * half;
+    const int f = k & 1;
+    for (int r = 0; r < 12; ++r) P[(idx * 12 + r) * m.Nv + k] = base[(long)(f * 12 + r) * m.stride + s.h];
+  }
+}
+
+// ---------------- block orthonormalisation ----------------
+// one block per (X, chi); thread l holds the 6 rows of chirality chi at site l.
+__global__ __launch_bounds__(256) void orthonormalize_k(MGGeom m, double2* P) {
+  const int X = blockIdx.x >> 1, chi = blockIdx.x & 1;
+  const int l = threadIdx.x;
+  const bool on = l < m.nloc;
+  __shared__ double lds[4 * 64];
+  __shared__ double red[64];
+  const int Nv = m.Nv;
+  double2* Pl = P + ((long)X * m.nloc + (on ? l : 0)) * 12 * Nv;
+  for (int k = 0; k < Nv; ++k) {
+    double2 v[6];
+    for (int r = 0; r < 6; ++r) v[r] = on ? Pl[(6 * chi + r) * Nv + k] : make_double2(0, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+      // classical Gram-Schmidt against q_0..q_{k-1}, in chunks of 16 coefficients
+      for (int j0 = 0; j0 < k; j0 += 16) {
+        const int cnt = min(16, k - j0);
+        double d[32];
+        for (int j = 0; j < cnt; ++j) {
+          double2 s = make_double2(0, 0);
+          if (on)
+            for (int r = 0; r < 6; ++r) s = cadd(s, cmulc(Pl[(6 * chi + r) * Nv + j0 + j], v[r]));
+          d[2 * j] = s.x;
+          d[2 * j + 1] = s.y;
+        }
+        block_reduce_batch(d, 2 * cnt, lds, red);
+        if (on)
+          for (int j = 0; j < cnt; ++j) {
+            const double2 c = make_double2(red[2 * j], red[2 * j + 1]);
+            for (int r = 0; r < 6; ++r) {
+              const double2 t = cmul(c, Pl[(6 * chi + r) * Nv + j0 + j]);
+              v[r].x -= t.x;
+              v[r].y -= t.y;
+            }
+          }
+        __syncthreads();
+      }
+    }
+    double nn[1] = {0};
+    for (int r = 0; r < 6; ++r) nn[0] += v[r].x * v[r].x + v[r].y * v[r].y;
+    block_reduce_batch(nn, 1, lds, red);
+    const double inv = 1.0 / sqrt(red[0]);
+    if (on)
+      for (int r = 0; r < 6; ++r) Pl[(6 * chi + r) * Nv + k] = make_double2(v[r].x * inv, v[r].y * inv);
+    __syncthreads();
+  }
+}
+
+// ---------------- Galerkin coarse operator ----------------
+// gamma matrices of the chiral basis (same as the fine stencil): gamma[mu][row][col]
+__constant__ double2 kGamma[4][4][4] = {
+    // gamma_0 = [[0,-1],[-1,0]]
+    {{{0, 0}, {0, 0}, {-1, 0}, {0, 0}},
+     {{0, 0}, {0, 0}, {0, 0}, {-1, 0}},
+     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}},
+     {{0, 0}, {-1, 0}, {0, 0}, {0, 0}}},
+    // gamma_1 = [[0,-i s1],[i s1,0]], s1 = [[0,1],[1,0]]
+    {{{0, 0}, {0, 0}, {0, 0}, {0, -1}},
+     {{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 1}, {0, 0}, {0, 0}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}}},
+    // gamma_2 = [[0,-i s2],[i s2,0]], s2 = [[0,-i],[i,0]] -> -i s2 = [[0,-1],[1,0]]
+    {{{0, 0}, {0, 0}, {0, 0}, {-1, 0}},
+     {{0, 0}, {0, 0}, {1, 0}, {0, 0}},
+     {{0, 0}, {1, 0}, {0, 0}, {0, 0}},
+     {{-1, 0}, {0, 0}, {0, 0}, {0, 0}}},
+    // gamma_3 = [[0,-i s3],[i s3,0]], s3 = diag(1,-1)
+    {{{0, 0}, {0, 0}, {0, -1}, {0, 0}},
+     {{0, 0}, {0, 0}, {0, 0}, {0, 1}},
+     {{0, 1}, {0, 0}, {0, 0}, {0, 0}},
+     {{0, 0}, {0, -1}, {0, 0}, {0, 0}}}};
+
+struct GalArgs {
+  MGGeom m;
+  const double2* U[2];  // FP64 links per parity, [(mu*9 + r*3 + c)*stride + h]
+  int antiperiodic;
+  const double2* P;
+  double2* D;
+  double2* scratch;
+};
+
+// block (X, dd): dd < 8 -> directional block d = dd from aggregate-boundary pairs;
+// dd >= 8 -> partial self block from interior pairs of direction d = dd - 8.
+__global__ __launch_bounds__(256) void galerkin_k(GalArgs A) {
+  const MGGeom& m = A.m;
+  const int X = blockIdx.x >> 4, dd = blockIdx.x & 15;
+  const bool face = dd < 8;
+  const int d = dd & 7, mu = d >> 1, bwd = d & 1;
+  const int Nv = m.Nv, n2 = 2 * Nv;
+  extern __shared__ double2 sm[];
+  double2* Px = sm;               // 12 * Nv
+  double2* Py = Px + 12 * Nv;     // 12 * Nv
+  double2* Tm = Py + 12 * Nv;     // 12 * n2, [r][j]
+  double2* Ul = Tm + 12 * n2;     // 9
+  const int ntot = n2 * n2;
+  constexpr int kPer = 16;        // output entries per thread (256*16 >= 64*64)
+  double2 acc[kPer];
+  for (int q = 0; q < kPer; ++q) acc[q] = make_double2(0, 0);
+  const int bext[4] = {m.bt, m.bx, m.by, m.bz};
+  for (int l = 0; l < m.nloc; ++l) {
+    int loc[4];
+    agg_local(m, l, loc);
+    const bool at_face = bwd ? loc[mu] == 0 : loc[mu] == bext[mu] - 1;
+    if (at_face != face) continue;
+    // neighbour y = x +- mu: local index within its aggregate and its aggregate
+    int nl[4] = {loc[0], loc[1], loc[2], loc[3]};
+    int Y = X;
+    if (at_face) {
+      nl[mu] = bwd ? bext[mu] - 1 : 0;
+      Y = coarse_nbr(m, X, mu, bwd ? -1 : 1);
+    } else {
+      nl[mu] += bwd ? -1 : 1;
+    }
+    const int ly = local_index(m, nl);
+    const SiteLoc sx = agg_site(m, X, l);
+    const SiteLoc sy = agg_site(m, Y, ly);
+    const int ext[4] = {m.T, m.Lx, m.Ly, m.Lz};
+    const int cx[4] = {sx.t, sx.x, sx.y, sx.z};
+    double sg = 1.0;
+    if (A.antiperiodic && mu == 0 && ((!bwd && cx[0] == ext[0] - 1) || (bwd && cx[0] == 0))) sg = -1.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 12 * Nv; e += blockDim.x) {
+      Px[e] = A.P[((long)X * m.nloc + l) * 12 * Nv + e];
+      Py[e] = A.P[((long)Y * m.nloc + ly) * 12 * Nv + e];
+    }
+    if (threadIdx.x < 9) {
+      // forward: U_mu(x) at x; backward: U_mu(y) at y (used daggered)
+      const SiteLoc& su = bwd ? sy : sx;
+      Ul[threadIdx.x] = A.U[su.par][(long)(mu * 9 + threadIdx.x) * m.stride + su.h];
+    }
+    __syncthreads();
+    // T[r][j] = -1/2 sg ((1 -+ gamma_mu) x U^(+)) P_y[:, j]
+    for (int e = threadIdx.x; e < 12 * n2; e += blockDim.x) {
+      const int r = e / n2, j = e % n2;
+      const int s = r / 3, c = r % 3;
+      const int chj = j / Nv, kj = j % Nv;
+      double2 up[2];  // (U P_y)[s'][c][j] for the two spins s' of chirality chj
+      for (int q = 0; q < 2; ++q) {
+        const int sp = 2 * chj + q;
+        double2 t = make_double2(0, 0);
+        for (int cc = 0; cc < 3; ++cc) {
+          const double2 pv = Py[(sp * 3 + cc) * Nv + kj];
+          t = cadd(t, bwd ? cmulc(Ul[cc * 3 + c], pv) : cmul(Ul[c * 3 + cc], pv));
+        }
+        up[q] = t;
+      }
+      double2 tv = make_double2(0, 0);
+      if ((s >> 1) == chj) tv = up[s & 1];
+      for (int q = 0; q < 2; ++q) {
+        const double2 gm = cmul(kGamma[mu][s][2 * chj + q], up[q]);
+        tv.x += bwd ? gm.x : -gm.x;
+        tv.y += bwd ? gm.y : -gm.y;
+      }
+      Tm[e] = make_double2(-0.5 * sg * tv.x, -0.5 * sg * tv.y);
+    }
+    __syncthreads();
+    for (int q = 0; q < kPer; ++q) {
+      const int o = threadIdx.x + q * blockDim.x;
+      if (o >= ntot) break;
+      const int j = o / n2, i = o % n2;
+      const int chi = i / Nv, ki = i % Nv;
+      double2 s = acc[q];
+      for (int rr = 0; rr < 6; ++rr) {
+        const int r = 6 * chi + rr;
+        s = cadd(s, cmulc(Px[r * Nv + ki], Tm[r * n2 + j]));
+      }
+      acc[q] = s;
+    }
+  }
+  double2* out = face ? A.D + ((long)X * 9 + 1 + d) * ntot : A.scratch + ((long)X * 8 + d) * ntot;
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * blockDim.x;
+    if (o < ntot) out[o] = acc[q];
+  }
+}
+
+__global__ void galerkin_self_k(MGGeom m, double a, const double2* scratch, double2* D) {
+  const int X = blockIdx.x;
+  const int n2 = 2 * m.Nv, ntot = n2 * n2;
+  for (int o = threadIdx.x; o < ntot; o += blockDim.x) {
+    double2 s = make_double2((o / n2 == o % n2) ? a : 0.0, 0.0);
+    for (int d = 0; d < 8; ++d) s = cadd(s, scratch[((long)X * 8 + d) * ntot + o]);
+    D[(long)X * 9 * ntot + o] = s;
+  }
+}
+
+// B_o[X][chi][k][k'] = sum_{odd l} sum_{rows of chi} conj(P[l][r][k]) P[l][r][k']
+__global__ void odd_block_k(MGGeom m, const double2* P, double2* Bo) {
+  const int X = blockIdx.x;
+  const int Nv = m.Nv, nb = Nv * Nv;
+  for (int o = threadIdx.x; o < 2 * nb; o += blockDim.x) {
+    const int chi = o / nb, k = (o % nb) / Nv, kp = o % Nv;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < m.nloc; ++l) {
+      const SiteLoc sl = agg_site(m, X, l);
+      if (!sl.par) continue;
+      const double2* Pl = P + ((long)X * m.nloc + l) * 12 * Nv;
+      for (int rr = 0; rr < 6; ++rr) {
+        const int r = 6 * chi + rr;
+        s = cadd(s, cmulc(Pl[r * Nv + k], Pl[r * Nv + kp]));
+      }
+    }
+    Bo[(long)X * 2 * nb + o] = s;
+  }
+}
+
+// ---------------- restriction / prolongation ----------------
+template <class R>
+struct C2;
+template <>
+struct C2<double> {
+  using T = double2;
+};
+template <>
+struct C2<float> {
+  using T = float2;
+};
+
+template <class R>
+__device__ __forceinline__ typename C2<R>::T mk(R x, R y) {
+  typename C2<R>::T v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+template <class R>
+__global__ __launch_bounds__(128) void restrict_k(MGGeom m, const typename C2<R>::T* P,
+                                                  const typename C2<R>::T* fe, const typename C2<R>::T* fo,
+                                                  typename C2<R>::T* vc) {
+  using T2 = typename C2<R>::T;
+  const int X = blockIdx.x;
+  const int Nv = m.Nv, n2 = 2 * Nv;
+  __shared__ int ph[1024];
+  for (int l = threadIdx.x; l < m.nloc; l += blockDim.x) {
+    const SiteLoc s = agg_site(m, X, l);
+    ph[l] = (s.h << 1) | s.par;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= 2 * n2) return;
+  const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
+  R ax = 0, ay = 0;
+  const T2* PX = P + (long)X * m.nloc * 12 * Nv;
+  for (int l = 0; l < m.nloc; ++l) {
+    const int hp = ph[l];
+    const T2* F = (hp & 1) ? fo : fe;
+    const int h = hp >> 1;
+    for (int rr = 0; rr < 6; ++rr) {
+      const int r = 6 * chi + rr;
+      const T2 p = PX[((long)l * 12 + r) * Nv + k];
+      const T2 v = F[(long)(f * 12 + r) * m.stride + h];
+      ax += p.x * v.x + p.y * v.y;
+      ay += p.x * v.y - p.y * v.x;
+    }
+  }
+  vc[((long)X * 2 + f) * n2 + i] = mk<R>(ax, ay);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>::T* P,
+                                                 const typename C2<R>::T* vc, typename C2<R>::T* fe,
+                                                 typename C2<R>::T* fo) {
+  using T2 = typename C2<R>::T;
+  const int X = blockIdx.x;
+  const int Nv = m.Nv, n2 = 2 * Nv;
+  __shared__ T2 cv[2 * 64];
+  __shared__ int ph[1024];
+  for (int e = threadIdx.x; e < 2 * n2; e += blockDim.x) cv[e] = vc[(long)X * 2 * n2 + e];
+  for (int l = threadIdx.x; l < m.nloc; l += blockDim.x) {
+    const SiteLoc s = agg_site(m, X, l);
+    ph[l] = (s.h << 1) | s.par;
+  }
+  __syncthreads();
+  const T2* PX = P + (long)X * m.nloc * 12 * Nv;
+  for (int e = threadIdx.x; e < m.nloc * 12; e += blockDim.x) {
+    const int l = e / 12, r = e % 12, chi = r / 6;
+    R a0x = 0, a0y = 0, a1x = 0, a1y = 0;
+    const T2* pr = PX + ((long)l * 12 + r) * Nv;
+    for (int k = 0; k < Nv; ++k) {
+      const T2 p = pr[k];
+      const T2 c0 = cv[chi * Nv + k], c1 = cv[n2 + chi * Nv + k];
+      a0x += p.x * c0.x - p.y * c0.y;
+      a0y += p.x * c0.y + p.y * c0.x;
+      a1x += p.x * c1.x - p.y * c1.y;
+      a1y += p.x * c1.y + p.y * c1.x;
+    }
+    const int hp = ph[l];
+    T2* F = (hp & 1) ? fo : fe;
+    const int h = hp >> 1;
+    F[(long)r * m.stride + h] = mk<R>(a0x, a0y);
+    F[(long)(12 + r) * m.stride + h] = mk<R>(a1x, a1y);
+  }
+}
+
+// ---------------- coarse stencil ----------------
+template <class R>
+__global__ __launch_bounds__(128) void coarse_apply_k(MGGeom m, const typename C2<R>::T* D,
+                                                      const typename C2<R>::T* Bo, const typename C2<R>::T* x,
+                                                      typename C2<R>::T* y, double mubar_c, double epsbar,
+                                                      double mm) {
+  using T2 = typename C2<R>::T;
+  const int X = blockIdx.x;
+  const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2;
+  __shared__ T2 xs[9][2 * 64];
+  __shared__ int nb[9];
+  if (threadIdx.x < 9) {
+    const int b = threadIdx.x;
+    nb[b] = b == 0 ? X : coarse_nbr(m, X, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 9 * 2 * n2; e += blockDim.x) {
+    const int b = e / (2 * n2), q = e % (2 * n2);
+    xs[b][q] = x[(long)nb[b] * 2 * n2 + q];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= 2 * n2) return;
+  const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
+  R ax = 0, ay = 0;
+  const T2* DX = D + (long)X * 9 * ntot;
+  for (int b = 0; b < 9; ++b) {
+    const T2* Db = DX + (long)b * ntot;
+    const T2* xv = xs[b] + f * n2;
+    for (int j = 0; j < n2; ++j) {
+      const T2 dv = Db[(long)j * n2 + i];
+      const T2 v = xv[j];
+      ax += dv.x * v.x - dv.y * v.y;
+      ay += dv.x * v.y + dv.y * v.x;
+    }
+  }
+  const R g5 = chi == 0 ? R(1) : R(-1);
+  const R t3 = f == 0 ? R(1) : R(-1);
+  const T2 xself = xs[0][f * n2 + i];
+  const T2 xoth = xs[0][(1 - f) * n2 + i];
+  // + i d mubar g5 tau3 x_f - epsbar x_{1-f}
+  ax += -R(mubar_c) * g5 * t3 * xself.y - R(epsbar) * xoth.x;
+  ay += R(mubar_c) * g5 * t3 * xself.x - R(epsbar) * xoth.y;
+  if (mm != 0.0) {
+    // + i m g5 sum_k' Bo[chi][k][k'] x_{1-f}[chi, k']
+    const T2* B = Bo + ((long)X * 2 + chi) * Nv * Nv + (long)k * Nv;
+    const T2* xo = xs[0] + (1 - f) * n2 + chi * Nv;
+    R bx = 0, by = 0;
+    for (int kp = 0; kp < Nv; ++kp) {
+      const T2 bv = B[kp], v = xo[kp];
+      bx += bv.x * v.x - bv.y * v.y;
+      by += bv.x * v.y + bv.y * v.x;
+    }
+    ax += -R(mm) * g5 * by;
+    ay += R(mm) * g5 * bx;
+  }
+  y[((long)X * 2 + f) * n2 + i] = mk<R>(ax, ay);
+}
+
+// ---------------- random test vectors ----------------
+__device__ __forceinline__ uint64_t splitmix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void random_fill_k(int vh, int stride, double2* fe, double2* fo, unsigned long long seed) {
+  const long idx = blockIdx.x * (long)blockDim.x + threadIdx.x;  // over 2 * 24 * vh
+  if (idx >= 48L * vh) return;
+  const int half = idx / (24L * vh);
+  const long r = idx % (24L * vh);
+  const int comp = r / vh, h = r % vh;
+  const uint64_t a = splitmix(seed * 0x100000001B3ull + (uint64_t)idx * 2);
+  const uint64_t b = splitmix(seed * 0x100000001B3ull + (uint64_t)idx * 2 + 1);
+  const double u1 = ((a >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((b >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(6.283185307179586 * u2, &sn, &cs);
+  (half ? fo : fe)[(long)comp * stride + h] = make_double2(rad * cs, rad * sn);
+}
+
+inline unsigned nb(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void mg_tv_to_P(const MGGeom& m, const double2* tv, double2* P, hipStream_t st) {
+  hipLaunchKernelGGL(tv_to_P_k, dim3(nb((long)m.Vc * m.nloc, 128)), dim3(128), 0, st, m, tv, P);
+}
+
+void mg_fields_to_P(const MGGeom& m, const double2* const* fields, int nfields, double2* P, hipStream_t st) {
+  FieldList F{};
+  for (int i = 0; i < nfields && i < 16; ++i) F.f[i] = fields[i];
+  hipLaunchKernelGGL(fields_to_P_k, dim3(nb((long)m.Vc * m.nloc, 128)), dim3(128), 0, st, m, F, P);
+}
+
+void mg_orthonormalize(const MGGeom& m, double2* P, hipStream_t st) {
+  hipLaunchKernelGGL(orthonormalize_k, dim3(2 * m.Vc), dim3(256), 0, st, m, P);
+}
+
+void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int antiperiodic, double a,
+                 const double2* P, double2* D, double2* scratch, double2* Bo, hipStream_t st) {
+  GalArgs A;
+  A.m = m;
+  A.U[0] = U64e;
+  A.U[1] = U64o;
+  A.antiperiodic = antiperiodic;
+  A.P = P;
+  A.D = D;
+  A.scratch = scratch;
+  const int n2 = 2 * m.Nv;
+  const size_t shmem = (size_t)(24 * m.Nv + 12 * n2 + 9) * sizeof(double2);
+  hipLaunchKernelGGL(galerkin_k, dim3(16 * m.Vc), dim3(256), shmem, st, A);
+  hipLaunchKernelGGL(galerkin_self_k, dim3(m.Vc), dim3(256), 0, st, m, a, scratch, D);
+  hipLaunchKernelGGL(odd_block_k, dim3(m.Vc), dim3(256), 0, st, m, P, Bo);
+}
+
+void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
+                 hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(restrict_k<double>, dim3(m.Vc), dim3(128), 0, st, m, (const double2*)P, (const double2*)fe,
+                       (const double2*)fo, (double2*)vc);
+  else
+    hipLaunchKernelGGL(restrict_k<float>, dim3(m.Vc), dim3(128), 0, st, m, (const float2*)P, (const float2*)fe,
+                       (const float2*)fo, (float2*)vc);
+}
+
+void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* fe, void* fo, hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(prolong_k<double>, dim3(m.Vc), dim3(256), 0, st, m, (const double2*)P, (const double2*)vc,
+                       (double2*)fe, (double2*)fo);
+  else
+    hipLaunchKernelGGL(prolong_k<float>, dim3(m.Vc), dim3(256), 0, st, m, (const float2*)P, (const float2*)vc,
+                       (float2*)fe, (float2*)fo);
+}
+
+void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
+                     double mubar_c, double epsbar, double m, hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(128), 0, st, g, (const double2*)D,
+                       (const double2*)Bo, (const double2*)x, (double2*)y, mubar_c, epsbar, m);
+  else
+    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(128), 0, st, g, (const float2*)D,
+                       (const float2*)Bo, (const float2*)x, (float2*)y, mubar_c, epsbar, m);
+}
+
+void mg_random_fill(const MGGeom& m, int vh, double2* fe, double2* fo, unsigned long long seed, hipStream_t st) {
+  hipLaunchKernelGGL(random_fill_k, dim3(nb(48L * vh, 256)), dim3(256), 0, st, vh, m.stride, fe, fo, seed);
+}
+
+}  // namespace ndtm

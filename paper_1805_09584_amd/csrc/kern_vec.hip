@@ -1,0 +1,373 @@
+// Vector kernels for the multigrid cycle and the coarse Krylov solver, for
+// complex vectors stored as double2 or float2.  Reductions accumulate in FP64,
+// one partial per block, and are finalised in a fixed order (deterministic).
+// Coefficients of the Krylov updates are read from device memory so that a
+// whole fixed-length Arnoldi loop runs without a host round trip.
+#include "vec.h"
+
+namespace ndtm {
+namespace {
+
+constexpr int kVB = 256;
+constexpr int kVGrid = 1024;
+constexpr int kMaxBasis = 40;
+
+template <class T2>
+struct Basis {
+  const T2* v[kMaxBasis];
+};
+
+inline unsigned vgrid(size_t n) {
+  size_t g = (n + kVB - 1) / kVB;
+  if (g > (size_t)kVGrid) g = kVGrid;
+  return (unsigned)(g ? g : 1);
+}
+
+__device__ __forceinline__ double2 ld2(const double2* p, size_t i) { return p[i]; }
+__device__ __forceinline__ double2 ld2(const float2* p, size_t i) {
+  const float2 v = p[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double2* p, size_t i, double2 v) { p[i] = v; }
+__device__ __forceinline__ void st2(float2* p, size_t i, double2 v) { p[i] = make_float2((float)v.x, (float)v.y); }
+
+__device__ __forceinline__ double2 cm(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double bsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  __shared__ double ws[kVB / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kVB / 64; ++i) s += ws[i];
+  return s;
+}
+
+#define GRID_LOOP(i, n) for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+
+template <class A, class B>
+__global__ void convert_k(B* y, const A* x, size_t n) {
+  GRID_LOOP(i, n) st2(y, i, ld2(x, i));
+}
+
+template <class T2>
+__global__ void zero_k(T2* y, size_t n) {
+  GRID_LOOP(i, n) st2(y, i, make_double2(0, 0));
+}
+
+// y = a x + b y with a = sa * coef[0..1] (device) or host value
+template <class T2>
+__global__ void axpby_k(T2* y, double2 a, const double* adev, double asgn, const T2* x, double2 b, size_t n) {
+  double2 aa = a;
+  if (adev) aa = make_double2(asgn * adev[0], asgn * adev[1]);
+  GRID_LOOP(i, n) {
+    const double2 xv = cm(aa, ld2(x, i));
+    const double2 yv = cm(b, ld2(y, i));
+    st2(y, i, make_double2(xv.x + yv.x, xv.y + yv.y));
+  }
+}
+
+// y *= 1 / sqrt(*nrm2)
+template <class T2>
+__global__ void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t n) {
+  const double s = *nrm2 > 1e-300 ? 1.0 / sqrt(*nrm2) : 0.0;
+  GRID_LOOP(i, n) {
+    const double2 v = ld2(x, i);
+    st2(y, i, make_double2(s * v.x, s * v.y));
+  }
+}
+
+template <class T2>
+__global__ void norm2_k(const T2* x, size_t n, double* part) {
+  double s = 0;
+  GRID_LOOP(i, n) {
+    const double2 v = ld2(x, i);
+    s += v.x * v.x + v.y * v.y;
+  }
+  s = bsum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// partials [2][nblk]: <x,y> re, im
+template <class T2>
+__global__ void dot_k(const T2* x, const T2* y, size_t n, double* part) {
+  double re = 0, im = 0;
+  GRID_LOOP(i, n) {
+    const double2 a = ld2(x, i), b = ld2(y, i);
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+  }
+  re = bsum(re);
+  im = bsum(im);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = re;
+    part[gridDim.x + blockIdx.x] = im;
+  }
+}
+
+template <class T2, int KM>
+__global__ void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* part) {
+  double re[KM], im[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) re[j] = im[j] = 0;
+  GRID_LOOP(i, n) {
+    const double2 wi = ld2(w, i);
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k) {
+        const double2 v = ld2(V.v[j], i);
+        re[j] += v.x * wi.x + v.y * wi.y;
+        im[j] += v.x * wi.y - v.y * wi.x;
+      }
+  }
+  for (int j = 0; j < k; ++j) {
+    const double a = bsum(re[j]);
+    const double b = bsum(im[j]);
+    if (threadIdx.x == 0) {
+      part[(size_t)(2 * j) * gridDim.x + blockIdx.x] = a;
+      part[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = b;
+    }
+  }
+}
+
+// sums column j of partials [width][nparts] into dst[j*dst_stride]
+__global__ void finalize_k(const double* part, int nparts, double* dst, int dst_stride) {
+  const double* p = part + (size_t)blockIdx.x * nparts;
+  double s = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[i];
+  s = bsum(s);
+  if (threadIdx.x == 0) dst[(size_t)blockIdx.x * dst_stride] = s;
+}
+
+// w -= sum_j coef[j] V_j   (coef complex, 2 doubles each, device)
+template <class T2>
+__global__ void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n) {
+  GRID_LOOP(i, n) {
+    double2 acc = ld2(w, i);
+    for (int j = 0; j < k; ++j) {
+      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.v[j], i));
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    st2(w, i, acc);
+  }
+}
+
+// y (+)= sum_j coef[j] V_j   (coef device)
+template <class T2>
+__global__ void lincomb_dev_k(T2* y, Basis<T2> V, int k, const double* coef, int accumulate, size_t n) {
+  GRID_LOOP(i, n) {
+    double2 acc = accumulate ? ld2(y, i) : make_double2(0, 0);
+    for (int j = 0; j < k; ++j) {
+      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.v[j], i));
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    st2(y, i, acc);
+  }
+}
+
+// omega = <t, r> / <t, t> from dst = [re<t,r>, im<t,r>, <t,t>]
+__global__ void mr_coef_k(const double* d, double* omega) {
+  if (threadIdx.x == 0) {
+    const double tt = d[2];
+    omega[0] = tt > 0 ? d[0] / tt : 0.0;
+    omega[1] = tt > 0 ? d[1] / tt : 0.0;
+  }
+}
+
+// Least squares of a (m+1) x m Hessenberg system by Givens rotations, one thread.
+// H column-major with leading dimension ldh (complex, 2 doubles); beta = sqrt(*beta2).
+__global__ void hess_lsq_k(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2 R[kMaxBasis][kMaxBasis];
+  double2 g[kMaxBasis + 1];
+  double2 cs[kMaxBasis], sn[kMaxBasis];
+  for (int j = 0; j < m; ++j)
+  {
+    for (int i = 0; i <= j; ++i) R[i][j] = make_double2(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
+    R[j + 1][j] = make_double2(sqrt(fmax(sub2[j], 0.0)), 0.0);
+  }
+  for (int i = 0; i <= m; ++i) g[i] = make_double2(0, 0);
+  g[0] = make_double2(sqrt(*beta2), 0);
+  int mm = m;
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double2 a = R[i][j], b = R[i + 1][j];
+      // G = [[conj(c), conj(s)], [-s, c]]
+      const double2 ca = make_double2(cs[i].x * a.x + cs[i].y * a.y, cs[i].x * a.y - cs[i].y * a.x);
+      const double2 sb = make_double2(sn[i].x * b.x + sn[i].y * b.y, sn[i].x * b.y - sn[i].y * b.x);
+      R[i][j] = make_double2(ca.x + sb.x, ca.y + sb.y);
+      const double2 t1 = cm(sn[i], a), t2 = cm(cs[i], b);
+      R[i + 1][j] = make_double2(t2.x - t1.x, t2.y - t1.y);
+    }
+    const double2 a = R[j][j], b = R[j + 1][j];
+    const double den = sqrt(a.x * a.x + a.y * a.y + b.x * b.x + b.y * b.y);
+    if (!(den > 0) || !isfinite(den)) {
+      mm = j;
+      break;
+    }
+    cs[j] = make_double2(a.x / den, a.y / den);
+    sn[j] = make_double2(b.x / den, b.y / den);
+    R[j][j] = make_double2(den, 0);
+    R[j + 1][j] = make_double2(0, 0);
+    const double2 gj = g[j];
+    const double2 t = cm(sn[j], gj);
+    g[j + 1] = make_double2(-t.x, -t.y);
+    g[j] = make_double2(cs[j].x * gj.x + cs[j].y * gj.y, cs[j].x * gj.y - cs[j].y * gj.x);
+  }
+  for (int j = 0; j < m; ++j) y[2 * j] = y[2 * j + 1] = 0.0;
+  for (int i = mm - 1; i >= 0; --i) {
+    double2 s = g[i];
+    for (int j = i + 1; j < mm; ++j) {
+      const double2 t = cm(R[i][j], make_double2(y[2 * j], y[2 * j + 1]));
+      s.x -= t.x;
+      s.y -= t.y;
+    }
+    const double2 d = R[i][i];
+    const double dd = d.x * d.x + d.y * d.y;
+    y[2 * i] = (s.x * d.x + s.y * d.y) / dd;
+    y[2 * i + 1] = (s.y * d.x - s.x * d.y) / dd;
+  }
+}
+
+template <class T2>
+Basis<T2> basis(const void* const* V, int k) {
+  Basis<T2> B;
+  for (int j = 0; j < k && j < kMaxBasis; ++j) B.v[j] = static_cast<const T2*>(V[j]);
+  return B;
+}
+
+}  // namespace
+
+#define DISPATCH(prec, F, ...)      \
+  do {                              \
+    if ((prec) == P64) F<double2>(__VA_ARGS__); \
+    else F<float2>(__VA_ARGS__);    \
+  } while (0)
+
+template <class T2>
+static void vzero_t(void* y, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(y), n);
+}
+void vzero(int prec, void* y, size_t n, hipStream_t st) { DISPATCH(prec, vzero_t, y, n, st); }
+
+void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st) {
+  const dim3 g(vgrid(n)), b(kVB);
+  if (prec_src == P64 && prec_dst == P64)
+    hipLaunchKernelGGL((convert_k<double2, double2>), g, b, 0, st, static_cast<double2*>(y), static_cast<const double2*>(x), n);
+  else if (prec_src == P64)
+    hipLaunchKernelGGL((convert_k<double2, float2>), g, b, 0, st, static_cast<float2*>(y), static_cast<const double2*>(x), n);
+  else if (prec_dst == P64)
+    hipLaunchKernelGGL((convert_k<float2, double2>), g, b, 0, st, static_cast<double2*>(y), static_cast<const float2*>(x), n);
+  else
+    hipLaunchKernelGGL((convert_k<float2, float2>), g, b, 0, st, static_cast<float2*>(y), static_cast<const float2*>(x), n);
+}
+
+template <class T2>
+static void vaxpby_t(void* y, double2 a, const double* adev, double asgn, const void* x, double2 b, size_t n,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(axpby_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(y), a, adev, asgn,
+                     static_cast<const T2*>(x), b, n);
+}
+void vaxpby(int prec, void* y, double2 a, const void* x, double2 b, size_t n, hipStream_t st) {
+  DISPATCH(prec, vaxpby_t, y, a, nullptr, 1.0, x, b, n, st);
+}
+void vaxpy_dev(int prec, void* y, const double* adev, double asgn, const void* x, size_t n, hipStream_t st) {
+  DISPATCH(prec, vaxpby_t, y, make_double2(0, 0), adev, asgn, x, make_double2(1, 0), n, st);
+}
+
+template <class T2>
+static void vscale_inv_sqrt_t(void* y, const void* x, const double* nrm2, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(scale_inv_sqrt_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(y),
+                     static_cast<const T2*>(x), nrm2, n);
+}
+void vscale_inv_sqrt(int prec, void* y, const void* x, const double* nrm2, size_t n, hipStream_t st) {
+  DISPATCH(prec, vscale_inv_sqrt_t, y, x, nrm2, n, st);
+}
+
+void vfinalize(const double* part, int nparts, int width, double* dst, int dst_stride, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_k, dim3(width), dim3(kVB), 0, st, part, nparts, dst, dst_stride);
+}
+
+template <class T2>
+static int vnorm2_t(const void* x, size_t n, double* part, hipStream_t st) {
+  const unsigned g = vgrid(n);
+  hipLaunchKernelGGL(norm2_k<T2>, dim3(g), dim3(kVB), 0, st, static_cast<const T2*>(x), n, part);
+  return (int)g;
+}
+void vnorm2(int prec, const void* x, size_t n, double* part, double* dst, hipStream_t st) {
+  int g = prec == P64 ? vnorm2_t<double2>(x, n, part, st) : vnorm2_t<float2>(x, n, part, st);
+  vfinalize(part, g, 1, dst, 1, st);
+}
+
+template <class T2>
+static int vdot_t(const void* x, const void* y, size_t n, double* part, hipStream_t st) {
+  const unsigned g = vgrid(n);
+  hipLaunchKernelGGL(dot_k<T2>, dim3(g), dim3(kVB), 0, st, static_cast<const T2*>(x), static_cast<const T2*>(y),
+                     n, part);
+  return (int)g;
+}
+void vdot(int prec, const void* x, const void* y, size_t n, double* part, double* dst, hipStream_t st) {
+  int g = prec == P64 ? vdot_t<double2>(x, y, n, part, st) : vdot_t<float2>(x, y, n, part, st);
+  vfinalize(part, g, 2, dst, 1, st);
+}
+
+template <class T2>
+static void vmultidot_t(const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
+                        hipStream_t st) {
+  const unsigned g = vgrid(n);
+  auto B = basis<T2>(V, k);
+  const T2* wp = static_cast<const T2*>(w);
+  if (k <= 4)
+    hipLaunchKernelGGL((multidot_k<T2, 4>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+  else if (k <= 8)
+    hipLaunchKernelGGL((multidot_k<T2, 8>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+  else if (k <= 16)
+    hipLaunchKernelGGL((multidot_k<T2, 16>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+  else
+    hipLaunchKernelGGL((multidot_k<T2, kMaxBasis>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+  vfinalize(part, (int)g, 2 * k, dst, 1, st);
+}
+void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
+               hipStream_t st) {
+  DISPATCH(prec, vmultidot_t, V, k, w, n, part, dst, st);
+}
+
+template <class T2>
+static void vmulti_axpy_t(void* w, const void* const* V, int k, const double* coef, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(multi_axpy_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(w), basis<T2>(V, k), k,
+                     coef, n);
+}
+void vmulti_axpy_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n,
+                     hipStream_t st) {
+  DISPATCH(prec, vmulti_axpy_t, w, V, k, coef, n, st);
+}
+
+template <class T2>
+static void vlincomb_t(void* y, const void* const* V, int k, const double* coef, int acc, size_t n,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(lincomb_dev_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(y), basis<T2>(V, k), k,
+                     coef, acc, n);
+}
+void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* coef, int accumulate, size_t n,
+                  hipStream_t st) {
+  DISPATCH(prec, vlincomb_t, y, V, k, coef, accumulate, n, st);
+}
+
+void mr_coef(const double* d, double* omega, hipStream_t st) {
+  hipLaunchKernelGGL(mr_coef_k, dim3(1), dim3(64), 0, st, d, omega);
+}
+
+void hess_lsq(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y,
+              hipStream_t st) {
+  hipLaunchKernelGGL(hess_lsq_k, dim3(1), dim3(64), 0, st, H, ldh, m, beta2, sub2, y);
+}
+
+}  // namespace ndtm

@@ -1,17 +1,513 @@
-// Multigrid driver (placeholder until the aggregation multigrid lands).
+// Two-level aggregation multigrid for the shifted single systems, the
+// difference-of-single-solves form (case C) with FP64 defect correction, the
+// Lagrange-interpolated initial guesses and the hybrid driver (sections 3.1,
+// 3.2, 4.2 and 4.4 of the paper).
+//
+// Single systems.  (Q +- i m) x = c with Q = Gamma5 tau1 S is equivalent to
+// (S +- i m Gamma5 tau1) x = Gamma5 tau1 c, and S +- i m Gamma5 tau1 is the odd
+// Schur complement of the full-lattice operator
+//   D'_+- = D_ND +- i m (Gamma5 x tau1) P_odd
+// (the even-even block is unchanged).  The outer solver is FGMRES in FP64 on
+// the odd system; each preconditioner application is one two-level cycle on
+// the full lattice for D'_+- applied to (0, r_o), returning the odd part:
+//   coarse correction z = P D'_c^-1 P^+ r   (the coarse system by a fixed
+//   number of GMRES iterations on the device), then post-smoothing by minimal
+//   residual steps on D'_+-  (0 pre- and smooth_iters post-smoothing steps).
+// The cycle runs in FP32 (or FP64 when the setup asks for it).
+//
+// Coarse operator (eq:non-degenerate_coarse with P_ND = P x I2 and the
+// odd-site shift term): D'_c = D_W,c x I2 + i d mubar Gamma5_c x tau3
+//   - epsbar tau1 +- i m (Gamma5_c P^+ P_odd P) x tau1.
+//
+// Setup (section 3.2: the one-flavour twisted-mass setup is reused for the
+// doublet): N_v test vectors by inverse iteration with the doublet kernel at
+// epsbar = 0, so that flavour 0 of each doublet field iterates D_W + i mubar
+// Gamma5 and flavour 1 D_W - i mubar Gamma5; each sweep replaces v by a few
+// minimal-residual steps towards D^-1 v and normalises it.
+//
+// Case C (eq:lindif): (Q^2 + m^2)^-1 r = (i/2m)[(Q + i m)^-1 r - (Q - i m)^-1 r].
+// The squared residual of case C grows by up to sqrt(lambda_max + m^2)/m over
+// the single residuals (appendix A), so each multigrid shift is refined by
+// FP64 defect correction on the true residual b - (Q^2 + m^2) x until it
+// reaches the tolerance.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
 #include "ctx.h"
+#include "vec.h"
 
 namespace ndtm {
-int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>&, int, std::vector<HalfField>&, const HalfField&,
-                    const ndtm_solve_params*, ndtm_solve_report*, hipStream_t) {
-  return fail(c, NDTM_ESTATE, "multigrid shifts: not available");
+
+struct MGData {
+  MGGeom g{};
+  ndtm_mg_params prm{};
+  int cprec = P32;  // precision of the cycle
+  double2* P64 = nullptr;
+  double2* D64 = nullptr;
+  double2* Bo64 = nullptr;
+  void* Pc = nullptr;   // P in cycle precision (aliases P64 for FP64)
+  void* Dc = nullptr;
+  void* Boc = nullptr;
+  size_t ncoarse = 0;   // complex elements of a coarse doublet vector
+  std::vector<void*> cV;  // coarse basis (cycle precision), coarse_iters + 1
+  void* cW = nullptr;
+  void* cR = nullptr;
+  double* dH = nullptr;   // Hessenberg columns, coarse_iters x (coarse_iters+1) complex
+  double* dsub = nullptr; // subdiagonal norms^2
+  double* dy = nullptr;   // least-squares coefficients
+  double* dbeta = nullptr;
+  double* dtmp = nullptr;
+  std::vector<void*> owned;
+  bool ready = false;
+};
+
+static void* mg_alloc(MGData* M, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  (void)hipMemset(p, 0, bytes);
+  M->owned.push_back(p);
+  return p;
 }
+
+static size_t csz(int prec) { return prec == P64 ? sizeof(double2) : sizeof(float2); }
+
+// views of a full-lattice field stored as one buffer (even half then odd half)
+struct Full {
+  HalfField e, o;
+  void* base = nullptr;
+};
+
+static Full full_field(ndtm_ctx* c, const std::string& name, int prec) {
+  Full f;
+  const size_t n = half_elems(c);
+  const size_t es = prec == P64 ? 16 : 8;
+  f.base = ws_get(c, name + (prec == P64 ? "#f64" : "#f32"), 2 * n * es);
+  f.e.prec = f.o.prec = prec;
+  f.e.v = f.base;
+  f.o.v = f.base ? static_cast<char*>(f.base) + n * es : nullptr;
+  return f;
+}
+
+// ---- coarse solve: fixed-length GMRES from zero, all on the device ----------
+static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t n = M->ncoarse;
+  const int kc = M->prm.coarse_iters;
+  const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+  vnorm2(cp, rhs, n, c->partials, M->dbeta, st);
+  vscale_inv_sqrt(cp, M->cV[0], rhs, M->dbeta, n, st);
+  for (int j = 0; j < kc; ++j) {
+    {
+      ProfScope ps(c, NDTM_PROF_COARSE, 0.0, st);
+      mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, c->epsbar, m, st);
+    }
+    double* hcol = M->dH + 2 * (size_t)j * (kc + 1);
+    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->partials, hcol, st);
+    vmulti_axpy_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol, n, st);
+    vnorm2(cp, M->cW, n, c->partials, M->dsub + j, st);
+    vscale_inv_sqrt(cp, M->cV[j + 1], M->cW, M->dsub + j, n, st);
+  }
+  hess_lsq(M->dH, kc + 1, kc, M->dbeta, M->dsub, M->dy, st);
+  vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, 0, n, st);
+}
+
+// full-lattice D' in the cycle precision
+static void dprime(ndtm_ctx* c, int prec, const Full& y, const Full& x, double m, hipStream_t st) {
+  apply_dfull(c, prec, y.e, y.o, x.e, x.o, m, st);
+}
+
+// z_o ~ S'^-1 r_o : one two-level cycle for D'(m) on (0, r_o); FP64 in/out
+static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfField& z64, double m, hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t nh = half_elems(c);
+  Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp), S = full_field(c, "mg_S", cp),
+       Tt = full_field(c, "mg_T", cp);
+  // r = (0, r_o)
+  vzero(cp, R.e.v, nh, st);
+  vconvert(cp, R.o.v, P64, r64.v, nh, st);
+  {
+    ProfScope ps(c, NDTM_PROF_RESTRICT, 0.0, st);
+    mg_restrict(cp, M->g, M->Pc, R.e.v, R.o.v, M->cR, st);
+  }
+  coarse_solve(c, M, M->cR, M->cW, m, st);
+  {
+    ProfScope ps(c, NDTM_PROF_PROLONG, 0.0, st);
+    mg_prolong(cp, M->g, M->Pc, M->cW, Z.e.v, Z.o.v, st);
+  }
+  // post-smoothing: minimal residual steps on D' z = r
+  const int nu = M->prm.smooth_iters;
+  if (nu > 0) {
+    dprime(c, cp, S, Z, m, st);
+    vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
+    for (int it = 0; it < nu; ++it) {
+      dprime(c, cp, Tt, S, m, st);
+      vdot(cp, Tt.base, S.base, 2 * nh, c->partials, M->dtmp, st);
+      vnorm2(cp, Tt.base, 2 * nh, c->partials, M->dtmp + 2, st);
+      mr_coef(M->dtmp, M->dtmp + 4, st);
+      vaxpy_dev(cp, Z.base, M->dtmp + 4, 1.0, S.base, 2 * nh, st);
+      if (it + 1 < nu) vaxpy_dev(cp, S.base, M->dtmp + 4, -1.0, Tt.base, 2 * nh, st);
+    }
+  }
+  vconvert(P64, z64.v, cp, Z.o.v, nh, st);
+}
+
+// FGMRES in FP64 for (S + i m Gamma5 tau1) x = rhs, x starting from zero.
+// Stops when the recursive residual <= tol * ||rhs||.  Returns iterations.
+static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField& x, double m, double tol, int restart,
+                  int maxiter, double* res_out, hipStream_t st) {
+  const size_t n = half_elems(c);
+  restart = std::max(2, std::min(restart, 32));
+  std::vector<HalfField> V(restart + 1), Z(restart);
+  for (int j = 0; j <= restart; ++j) V[j] = half_field(c, "fg_v" + std::to_string(j), P64);
+  for (int j = 0; j < restart; ++j) Z[j] = half_field(c, "fg_z" + std::to_string(j), P64);
+  HalfField W = half_field(c, "fg_w", P64), te = half_field(c, "fg_te", P64), r = half_field(c, "fg_r", P64);
+  std::vector<const void*> Vp(restart + 1), Zp(restart);
+  for (int j = 0; j <= restart; ++j) Vp[j] = V[j].v;
+  for (int j = 0; j < restart; ++j) Zp[j] = Z[j].v;
+  double* dh = c->dscal;  // [0, 2*restart): h, [2*restart, 4*restart): second pass, then norm2
+  const double bn = std::sqrt(norm2_host(c, (const double2*)rhs.v, n, st));
+  blas_zero(x.v, n * sizeof(double2), st);
+  if (bn == 0) {
+    *res_out = 0;
+    return 0;
+  }
+  int total = 0;
+  double res = bn;
+  while (total < maxiter) {
+    // r = rhs - A x
+    apply_sshift(c, P64, r, x, te, m, st);
+    blas_axpby((double2*)r.v, make_double2(1, 0), (const double2*)rhs.v, make_double2(-1, 0), n, st);
+    const double beta = std::sqrt(norm2_host(c, (const double2*)r.v, n, st));
+    res = beta;
+    if (beta <= tol * bn) break;
+    blas_axpby((double2*)V[0].v, make_double2(1.0 / beta, 0), (const double2*)r.v, make_double2(0, 0), n, st);
+    std::vector<std::complex<double>> H((restart + 1) * restart, 0.0), cs(restart), sn(restart),
+        g(restart + 1, 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (; k < restart && total < maxiter; ++k) {
+      mg_cycle(c, M, V[k], Z[k], m, st);
+      apply_sshift(c, P64, W, Z[k], te, m, st);
+      // classical Gram-Schmidt, two passes
+      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->partials, dh, st);
+      vmulti_axpy_dev(P64, W.v, Vp.data(), k + 1, dh, n, st);
+      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->partials, dh + 2 * restart, st);
+      vmulti_axpy_dev(P64, W.v, Vp.data(), k + 1, dh + 2 * restart, n, st);
+      vnorm2(P64, W.v, n, c->partials, dh + 4 * restart, st);
+      vscale_inv_sqrt(P64, V[k + 1].v, W.v, dh + 4 * restart, n, st);
+      (void)hipMemcpyAsync(c->hscal, dh, (4 * restart + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+      (void)hipStreamSynchronize(st);
+      ++total;
+      for (int i = 0; i <= k; ++i)
+        H[k * (restart + 1) + i] = std::complex<double>(c->hscal[2 * i] + c->hscal[2 * restart + 2 * i],
+                                                        c->hscal[2 * i + 1] + c->hscal[2 * restart + 2 * i + 1]);
+      const double hn = std::sqrt(std::max(0.0, c->hscal[4 * restart]));
+      H[k * (restart + 1) + k + 1] = hn;
+      for (int i = 0; i < k; ++i) {
+        auto& a = H[k * (restart + 1) + i];
+        auto& b = H[k * (restart + 1) + i + 1];
+        const auto t = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
+        b = -sn[i] * a + cs[i] * b;
+        a = t;
+      }
+      auto& a = H[k * (restart + 1) + k];
+      auto& b = H[k * (restart + 1) + k + 1];
+      const double den = std::sqrt(std::norm(a) + std::norm(b));
+      if (!(den > 0) || !std::isfinite(den)) break;
+      cs[k] = a / den;
+      sn[k] = b / den;
+      a = den;
+      b = 0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = std::conj(cs[k]) * g[k];
+      res = std::abs(g[k + 1]);
+      if (res <= tol * bn || hn == 0) {
+        ++k;
+        break;
+      }
+    }
+    // y = R^-1 g, x += Z y
+    std::vector<std::complex<double>> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+      auto s = g[i];
+      for (int j = i + 1; j < k; ++j) s -= H[j * (restart + 1) + i] * y[j];
+      y[i] = s / H[i * (restart + 1) + i];
+    }
+    std::vector<double> yc(2 * k);
+    for (int i = 0; i < k; ++i) {
+      yc[2 * i] = y[i].real();
+      yc[2 * i + 1] = y[i].imag();
+    }
+    (void)hipMemcpyAsync(c->dscal + 6 * restart, yc.data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, st);
+    vlincomb_dev(P64, x.v, Zp.data(), k, c->dscal + 6 * restart, 1, n, st);
+    if (res <= tol * bn) {
+      // confirm with the true residual at the top of the loop
+      continue;
+    }
+  }
+  *res_out = res / bn;
+  return total;
+}
+
+static double lambda_max_estimate() { return 28.0; }  // upper estimate of the spectrum of Q^2 (free field 25.6)
+
+// Solves (Q^2 + sigma) x = b for one multigrid shift by case C with FP64 defect
+// correction, starting from x (initial guess).  Returns NDTM_OK when the true
+// relative residual reaches tol.
+static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfField& b, double sigma,
+                        const ndtm_solve_params* p, double* res_out, int* iters, int* rounds, double* guess_res,
+                        hipStream_t st) {
+  const size_t n = half_elems(c);
+  const double m = std::sqrt(sigma);
+  HalfField r = half_field(c, "cc_r", P64), cr = half_field(c, "cc_c", P64), ep = half_field(c, "cc_ep", P64),
+            em = half_field(c, "cc_em", P64);
+  double res = true_residual(c, x, b, sigma, r, st);
+  *guess_res = res;
+  const double amp = m / std::sqrt(lambda_max_estimate() + sigma);
+  int it_total = 0, rd = 0;
+  while (res > p->tol && rd < p->max_rounds) {
+    // single-solve tolerance so that one round meets tol after the case-C amplification
+    double rho = 0.5 * p->tol / res * amp;
+    rho = std::max(1e-14, std::min(rho, p->mg_tol));
+    launch_g5t1(c->g, (const double2*)r.v, (double2*)cr.v, st);
+    double rp = 0, rm = 0;
+    it_total += fgmres(c, M, cr, ep, +m, rho, p->fgmres_restart, p->fgmres_maxiter, &rp, st);
+    it_total += fgmres(c, M, cr, em, -m, rho, p->fgmres_restart, p->fgmres_maxiter, &rm, st);
+    // x += (i/2m)(e_+ - e_-)
+    blas_axpy((double2*)x.v, make_double2(0, 0.5 / m), (const double2*)ep.v, n, st);
+    blas_axpy((double2*)x.v, make_double2(0, -0.5 / m), (const double2*)em.v, n, st);
+    res = true_residual(c, x, b, sigma, r, st);
+    ++rd;
+    if (!std::isfinite(res)) break;
+  }
+  *res_out = res;
+  *iters = it_total;
+  *rounds = rd;
+  if (!std::isfinite(res)) return fail(c, NDTM_EBREAKDOWN, "multigrid shift: non-finite residual");
+  return res <= p->tol ? NDTM_OK : NDTM_ENOCONV;
+}
+
+// Lagrange coefficients l_i(target) over the nodes (section 4.2, appendix B).
+static std::vector<double> lagrange(const std::vector<double>& nodes, double t) {
+  const size_t k = nodes.size();
+  std::vector<double> c(k, 1.0);
+  for (size_t i = 0; i < k; ++i)
+    for (size_t j = 0; j < k; ++j)
+      if (j != i) c[i] *= (t - nodes[j]) / (nodes[i] - nodes[j]);
+  return c;
+}
+
+int guess_mlp(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, int K, double sig_t,
+              const HalfField& b, const std::vector<double>& lag, std::vector<double>* coef, double* pred_mlp,
+              double* pred_lag, hipStream_t st);
+
+int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std::vector<HalfField>& xs,
+                    const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st) {
+  MGData* M = c->mg;
+  if (!M || !M->ready) return fail(c, NDTM_ESTATE, "solve: multigrid shifts need ndtm_mg_setup first");
+  const int nsh = (int)sig.size();
+  const size_t n = half_elems(c);
+  int status = NDTM_OK;
+  for (int t = n_mms; t < nsh; ++t) {
+    auto tg0 = std::chrono::steady_clock::now();
+    // ---- initial guess from the converged solutions (descending shifts) ----
+    std::vector<double> nodes(sig.begin(), sig.begin() + t);
+    std::vector<double> lag = lagrange(nodes, sig[t]);
+    int first = 0;
+    auto lebesgue = [&](const std::vector<double>& l) {
+      double s = 0;
+      for (double v : l) s += std::fabs(v);
+      return s;
+    };
+    // keep the Lebesgue constant moderate by dropping the farthest nodes (appendix B)
+    while (t - first > 1 && lebesgue(lag) > 4.0) {
+      ++first;
+      nodes.assign(sig.begin() + first, sig.begin() + t);
+      lag = lagrange(nodes, sig[t]);
+    }
+    const int K = t - first;
+    std::vector<double> coef = lag;
+    rep->guess_kind[t] = p->guess;
+    rep->lagrange_res[t] = -1;
+    if (p->guess == NDTM_GUESS_MLP) {
+      std::vector<HalfField> xk(xs.begin() + first, xs.begin() + t);
+      double pm = -1, pl = -1;
+      int rc = guess_mlp(c, nodes, xk, K, sig[t], b, lag, &coef, &pm, &pl, st);
+      rep->mlp_res[t] = pm;
+      rep->lagrange_res[t] = pl;
+      if (rc != NDTM_OK || !(pm >= 0) || pm > pl) {
+        coef = lag;  // fallback to Lagrange
+        rep->guess_kind[t] = NDTM_GUESS_LAGRANGE;
+      }
+    }
+    if (p->guess == NDTM_GUESS_ZERO) {
+      blas_zero(xs[t].v, n * sizeof(double2), st);
+    } else {
+      std::vector<const double2*> V(K);
+      std::vector<double2> cc(K);
+      for (int i = 0; i < K; ++i) {
+        V[i] = (const double2*)xs[first + i].v;
+        cc[i] = make_double2(coef[i], 0.0);
+      }
+      blas_lincomb((double2*)xs[t].v, V.data(), cc.data(), K, n, st);
+    }
+    auto tg1 = std::chrono::steady_clock::now();
+    rep->t_guess_ms += std::chrono::duration<double, std::milli>(tg1 - tg0).count();
+    // ---- case C with defect correction ----
+    double res = 0, gres = 0;
+    int iters = 0, rounds = 0;
+    int rc = case_c_solve(c, M, xs[t], b, sig[t], p, &res, &iters, &rounds, &gres, st);
+    rep->method[t] = 1;
+    rep->iterations[t] = iters;
+    rep->rounds[t] = rounds;
+    rep->true_res[t] = res;
+    rep->guess_res[t] = gres;
+    if (rep->lagrange_res[t] < 0 && p->guess == NDTM_GUESS_LAGRANGE) rep->lagrange_res[t] = gres;
+    auto tg2 = std::chrono::steady_clock::now();
+    rep->t_mg_ms += std::chrono::duration<double, std::milli>(tg2 - tg1).count();
+    if (rc == NDTM_EBREAKDOWN) return rc;
+    if (rc != NDTM_OK) status = rc;
+  }
+  return status;
+}
+
+// ---- setup ----------------------------------------------------------------
+static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, hipStream_t st) {
+  ndtm_mg_free(c);
+  MGData* M = new MGData();
+  c->mg = M;
+  M->prm = *prm;
+  MGGeom& g = M->g;
+  g.T = c->g.T;
+  g.Lz = c->g.Lz;
+  g.Ly = c->g.Ly;
+  g.Lx = c->g.Lx;
+  g.bt = prm->block[0];
+  g.bz = prm->block[1];
+  g.by = prm->block[2];
+  g.bx = prm->block[3];
+  g.CT = g.T / g.bt;
+  g.CZ = g.Lz / g.bz;
+  g.CY = g.Ly / g.by;
+  g.CX = g.Lx / g.bx;
+  g.Vc = g.CT * g.CZ * g.CY * g.CX;
+  g.nloc = g.bt * g.bz * g.by * g.bx;
+  g.Nv = prm->n_vec;
+  g.stride = c->g.stride;
+  M->cprec = prm->precision == NDTM_PREC_F64 ? P64 : P32;
+  const int Nv = g.Nv, n2 = 2 * Nv;
+  const size_t nP = (size_t)g.Vc * g.nloc * 12 * Nv;
+  const size_t nD = (size_t)g.Vc * 9 * n2 * n2;
+  const size_t nB = (size_t)g.Vc * 2 * Nv * Nv;
+  M->ncoarse = (size_t)g.Vc * 2 * n2;
+  M->P64 = (double2*)mg_alloc(M, nP * 16);
+  M->D64 = (double2*)mg_alloc(M, nD * 16);
+  M->Bo64 = (double2*)mg_alloc(M, nB * 16);
+  if (!M->P64 || !M->D64 || !M->Bo64) return fail(c, NDTM_ENOMEM, "mg_setup: P / coarse operator");
+  const size_t nh = half_elems(c);
+  if (tv_dev) {
+    mg_tv_to_P(g, static_cast<const double2*>(tv_dev), M->P64, st);
+  } else {
+    // inverse iteration on the one-flavour operators D_W +- i mubar Gamma5 (doublet kernel at epsbar = 0)
+    const int nf = (Nv + 1) / 2;
+    std::vector<Full> F(nf);
+    for (int i = 0; i < nf; ++i) {
+      F[i] = full_field(c, "su_v" + std::to_string(i), P64);
+      if (!F[i].base) return fail(c, NDTM_ENOMEM, "mg_setup: test vectors");
+      mg_random_fill(g, c->g.vh, (double2*)F[i].e.v, (double2*)F[i].o.v, prm->seed * 1000003ull + i, st);
+    }
+    Full X = full_field(c, "su_x", P64), R = full_field(c, "su_r", P64), Tt = full_field(c, "su_t", P64);
+    double* d = c->dscal + 64;
+    const OpParams saved = c->op;
+    const double a = c->op.a;
+    c->op.epsbar = 0.0;
+    c->op.inv_den = 1.0 / (a * a + c->mubar * c->mubar);
+    for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
+      for (int i = 0; i < nf; ++i) {
+        // x ~ D^-1 v by minimal-residual steps from x = 0, then v = x / ||x||
+        vzero(P64, X.base, 2 * nh, st);
+        blas_copy((double2*)R.base, (const double2*)F[i].base, 2 * nh, st);
+        for (int it = 0; it < prm->setup_smooth; ++it) {
+          apply_dfull(c, P64, Tt.e, Tt.o, R.e, R.o, 0.0, st);
+          vdot(P64, Tt.base, R.base, 2 * nh, c->partials, d, st);
+          vnorm2(P64, Tt.base, 2 * nh, c->partials, d + 2, st);
+          mr_coef(d, d + 4, st);
+          vaxpy_dev(P64, X.base, d + 4, 1.0, R.base, 2 * nh, st);
+          vaxpy_dev(P64, R.base, d + 4, -1.0, Tt.base, 2 * nh, st);
+        }
+        vnorm2(P64, X.base, 2 * nh, c->partials, d + 6, st);
+        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
+      }
+    }
+    c->op = saved;
+    std::vector<const double2*> fp(nf);
+    for (int i = 0; i < nf; ++i) fp[i] = (const double2*)F[i].base;
+    mg_fields_to_P(g, fp.data(), nf, M->P64, st);
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    ws_free_prefix(c, "su_");
+  }
+  mg_orthonormalize(g, M->P64, st);
+  double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
+  if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");
+  mg_galerkin(g, (const double2*)c->U[P64][0], (const double2*)c->U[P64][1], c->g.antiperiodic, c->op.a, M->P64,
+              M->D64, scratch, M->Bo64, st);
+  if (M->cprec == P64) {
+    M->Pc = M->P64;
+    M->Dc = M->D64;
+    M->Boc = M->Bo64;
+  } else {
+    M->Pc = mg_alloc(M, nP * 8);
+    M->Dc = mg_alloc(M, nD * 8);
+    M->Boc = mg_alloc(M, nB * 8);
+    if (!M->Pc || !M->Dc || !M->Boc) return fail(c, NDTM_ENOMEM, "mg_setup: FP32 copies");
+    vconvert(P32, M->Pc, P64, M->P64, nP, st);
+    vconvert(P32, M->Dc, P64, M->D64, nD, st);
+    vconvert(P32, M->Boc, P64, M->Bo64, nB, st);
+  }
+  const int kc = prm->coarse_iters;
+  M->cV.resize(kc + 1);
+  for (int j = 0; j <= kc; ++j) {
+    M->cV[j] = mg_alloc(M, M->ncoarse * csz(M->cprec));
+    if (!M->cV[j]) return fail(c, NDTM_ENOMEM, "mg_setup: coarse basis");
+  }
+  M->cW = mg_alloc(M, M->ncoarse * csz(M->cprec));
+  M->cR = mg_alloc(M, M->ncoarse * csz(M->cprec));
+  M->dH = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
+  M->dsub = (double*)mg_alloc(M, (kc + 1) * sizeof(double));
+  M->dy = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
+  M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
+  M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
+  if (!M->cW || !M->cR || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
+    return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
+  NDTM_HIP(c, hipGetLastError());
+  NDTM_HIP(c, hipStreamSynchronize(st));
+  // the partial self blocks are only needed during setup
+  auto it = c->bufs.find("mg_scratch");
+  if (it != c->bufs.end()) {
+    (void)hipFree(it->second.p);
+    c->bufs.erase(it);
+  }
+  M->ready = true;
+  return NDTM_OK;
+}
+
 }  // namespace ndtm
 
 using namespace ndtm;
+
 extern "C" {
-void ndtm_mg_free(ndtm_ctx*) {}
-void ndtm_mlp_free(ndtm_ctx*) {}
+
+void ndtm_mg_free(ndtm_ctx* c) {
+  if (!c || !c->mg) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : c->mg->owned) (void)hipFree(p);
+  delete c->mg;
+  c->mg = nullptr;
+}
+
 void ndtm_mg_default_params(ndtm_mg_params* p) {
   if (!p) return;
   p->block[0] = p->block[1] = p->block[2] = p->block[3] = 4;
@@ -22,11 +518,69 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->coarse_iters = 16;
   p->coarse_mu_factor = 1.0;
   p->seed = 32;
-  p->precision = NDTM_PREC_F64;
+  p->precision = NDTM_PREC_F32;
 }
-int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params*, const void*, void*) { return fail(c, NDTM_ESTATE, "mg: not available"); }
-long long ndtm_mg_coarse_volume(const ndtm_ctx*) { return 0; }
-int ndtm_mg_restrict(ndtm_ctx* c, void*, const void*, void*) { return fail(c, NDTM_ESTATE, "mg: not available"); }
-int ndtm_mg_prolong(ndtm_ctx* c, void*, const void*, void*) { return fail(c, NDTM_ESTATE, "mg: not available"); }
-int ndtm_mg_coarse_apply(ndtm_ctx* c, void*, const void*, double, void*) { return fail(c, NDTM_ESTATE, "mg: not available"); }
+
+int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!p) return fail(c, NDTM_EINVAL, "mg_setup: null params");
+  if (!c->have_gauge || !c->have_params) return fail(c, NDTM_ESTATE, "mg_setup: set_gauge and set_params first");
+  const int dims[4] = {c->g.T, c->g.Lz, c->g.Ly, c->g.Lx};
+  int nloc = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (p->block[i] < 1 || dims[i] % p->block[i]) return fail(c, NDTM_EINVAL, "mg_setup: block must divide dims");
+    nloc *= p->block[i];
+  }
+  if (nloc > 256) return fail(c, NDTM_EINVAL, "mg_setup: at most 256 sites per aggregate");
+  if (p->n_vec < 2 || p->n_vec > 32 || (p->n_vec & 1))
+    return fail(c, NDTM_EINVAL, "mg_setup: n_vec even in [2, 32]");
+  if (6 * nloc < p->n_vec) return fail(c, NDTM_EINVAL, "mg_setup: aggregate too small for n_vec vectors");
+  if (p->coarse_iters < 1 || p->coarse_iters > 32) return fail(c, NDTM_EINVAL, "mg_setup: coarse_iters in [1, 32]");
+  if (p->smooth_iters < 0 || p->setup_iters < 0 || p->setup_smooth < 1 || !(p->coarse_mu_factor >= 1.0))
+    return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
+  if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32)
+    return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64 or F32");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  const int rc = mg_build(c, p, tv, static_cast<hipStream_t>(stream));
+  if (rc != NDTM_OK) ndtm_mg_free(c);
+  return rc;
 }
+
+long long ndtm_mg_coarse_volume(const ndtm_ctx* c) { return (c && c->mg && c->mg->ready) ? c->mg->g.Vc : 0; }
+
+int ndtm_mg_restrict(ndtm_ctx* c, void* vc, const void* v, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_restrict: no multigrid setup");
+  if (!vc || !v) return fail(c, NDTM_EINVAL, "mg_restrict: null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Full F = full_field(c, "ab_f", P64);
+  launch_pack_full(c->g, static_cast<const double2*>(v), F.e, F.o, st);
+  mg_restrict(P64, c->mg->g, c->mg->P64, F.e.v, F.o.v, vc, st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_mg_prolong(ndtm_ctx* c, void* v, const void* vc, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_prolong: no multigrid setup");
+  if (!vc || !v) return fail(c, NDTM_EINVAL, "mg_prolong: null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Full F = full_field(c, "ab_f", P64);
+  mg_prolong(P64, c->mg->g, c->mg->P64, vc, F.e.v, F.o.v, st);
+  launch_unpack_full(c->g, F.e, F.o, static_cast<double2*>(v), st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_mg_coarse_apply(ndtm_ctx* c, void* yc, const void* xc, double m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_apply: no multigrid setup");
+  if (!yc || !xc || yc == xc) return fail(c, NDTM_EINVAL, "mg_coarse_apply: null or aliased pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  mg_coarse_apply(P64, c->mg->g, c->mg->D64, c->mg->Bo64, xc, yc, c->mg->prm.coarse_mu_factor * c->mubar,
+                  c->epsbar, m, st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+}  // extern "C"

@@ -74,6 +74,8 @@ void launch_pack_full(const Geom& g, const double2* canon, const HalfField& fe, 
                       hipStream_t st);
 void launch_unpack_full(const Geom& g, const HalfField& fe, const HalfField& fo, double2* canon,
                         hipStream_t st);
+// out = (Gamma5 x tau1) in on FP64 half fields (out must not alias in)
+void launch_g5t1(const Geom& g, const double2* in, double2* out, hipStream_t st);
 // precision conversion between internal half fields of the same geometry
 void launch_convert_half(const Geom& g, const HalfField& src, const HalfField& dst, hipStream_t st);
 

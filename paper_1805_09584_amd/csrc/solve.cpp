@@ -156,7 +156,7 @@ void ndtm_solve_default_params(ndtm_solve_params* p) {
   p->guess = NDTM_GUESS_LAGRANGE;
   p->precision = NDTM_PREC_F64;
   p->poll_every = 8;
-  p->mg_tol = 1e-9;
+  p->mg_tol = 0.1;
   p->fgmres_restart = 16;
   p->fgmres_maxiter = 400;
   p->max_rounds = 6;

@@ -1,0 +1,60 @@
+// Vector kernels for FP64/FP32 complex storage (kern_vec.hip) and the
+// multigrid kernels (kern_mg.hip).  Internal to the library.
+#pragma once
+
+#include "ndtm_internal.h"
+
+namespace ndtm {
+
+// ---- vectors: prec P64 -> double2 storage, P32 -> float2; n complex elements ----
+void vzero(int prec, void* y, size_t n, hipStream_t st);
+void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st);
+void vaxpby(int prec, void* y, double2 a, const void* x, double2 b, size_t n, hipStream_t st);   // y = a x + b y
+void vaxpy_dev(int prec, void* y, const double* adev, double asgn, const void* x, size_t n,
+               hipStream_t st);                                                                  // y += asgn*a x
+void vscale_inv_sqrt(int prec, void* y, const void* x, const double* nrm2, size_t n, hipStream_t st);
+void vnorm2(int prec, const void* x, size_t n, double* part, double* dst, hipStream_t st);        // dst[0]
+void vdot(int prec, const void* x, const void* y, size_t n, double* part, double* dst, hipStream_t st);  // dst[0..1]
+void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
+               hipStream_t st);                                                                  // dst[2j..]
+void vmulti_axpy_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n,
+                     hipStream_t st);                                                            // w -= sum c_j V_j
+void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* coef, int accumulate, size_t n,
+                  hipStream_t st);
+void vfinalize(const double* part, int nparts, int width, double* dst, int dst_stride, hipStream_t st);
+void mr_coef(const double* d, double* omega, hipStream_t st);
+// least squares min || beta e_1 - H y || for the (m+1) x m Hessenberg matrix with upper part H
+// (column-major, ldh, complex) and subdiagonal sqrt(sub2[j])
+void hess_lsq(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y,
+              hipStream_t st);
+
+// ---- multigrid ----
+struct MGGeom {
+  int T, Lz, Ly, Lx;        // fine dims
+  int bt, bz, by, bx;       // aggregate extents
+  int CT, CZ, CY, CX;       // coarse dims
+  int Vc, nloc, Nv;         // coarse sites, fine sites per aggregate, test vectors
+  int stride;               // fine half-field stride
+};
+
+// test vectors (canonical complex128 [Nv][V][4][3]) -> P (FP64, [X][l][row][k])
+void mg_tv_to_P(const MGGeom& m, const double2* tv, double2* P, hipStream_t st);
+// doublet full fields (even half + odd half, FP64; flavour f of field i is test vector 2i+f) -> P
+void mg_fields_to_P(const MGGeom& m, const double2* const* fields, int nfields, double2* P, hipStream_t st);
+// per aggregate and chirality Gram-Schmidt (classical, applied twice) of P's columns, FP64
+void mg_orthonormalize(const MGGeom& m, double2* P, hipStream_t st);
+// Galerkin coarse Wilson blocks D[X][b][j][i] (b: 0 self, 1+2mu fwd, 2+2mu bwd), FP64; scratch of
+// 8*Vc*(2Nv)^2 complex for the partial self blocks; B_o[X][chi][k][k'] = sum over odd sites P^+ P
+void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int antiperiodic, double a,
+                 const double2* P, double2* D, double2* scratch, double2* Bo, hipStream_t st);
+// restrict / prolong between fine full fields (even half at fe, odd half at fo) and coarse [X][2][2Nv]
+void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
+                 hipStream_t st);
+void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* fe, void* fo, hipStream_t st);
+// coarse doublet operator y = D'_c(m) x
+void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
+                     double mubar_c, double epsbar, double m, hipStream_t st);
+// fill a full doublet field (both halves) with complex Gaussian numbers from a counter-based hash
+void mg_random_fill(const MGGeom& m, int vh, double2* fe, double2* fo, unsigned long long seed, hipStream_t st);
+
+}  // namespace ndtm
