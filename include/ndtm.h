@@ -112,7 +112,12 @@ typedef struct {
   int block[4];        /* aggregate extents {bt,bz,by,bx}; each divides the dim */
   int n_vec;           /* test vectors N_v (<= 32); coarse dof per flavour = 2 N_v */
   int setup_iters;     /* inverse-iteration sweeps building the test vectors */
-  int setup_smooth;    /* smoother iterations per sweep */
+  int setup_smooth;    /* minimal-residual steps per inverse-iteration sweep */
+  int setup_refine;    /* refinement sweeps: each replaces every test vector by one
+                          two-level cycle applied to it, then rebuilds P and D_c */
+  int setup_nd;        /* 0: iterate the one-flavour operators D_W +- i mubar Gamma5
+                          (section 3.2's reuse of the twisted-mass setup); 1: iterate the
+                          doublet operator D_ND itself and use both flavour components */
   int smooth_iters;    /* post-smoothing iterations per cycle (0 pre) */
   int coarse_iters;    /* GMRES iterations of the coarse solve per cycle */
   double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
@@ -142,6 +147,10 @@ int ndtm_mg_prolong(ndtm_ctx* ctx, void* v_dev, const void* vc_dev, void* stream
  *                     + i m C_o x tau1) xc   (eq:non-degenerate_coarse). */
 int ndtm_mg_coarse_apply(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, double m, void* stream);
 
+/* xc ~ D'_c(m)^-1 bc by the coarse solver the cycle uses (coarse_iters GMRES
+ * iterations from zero in the cycle precision; no convergence test). */
+int ndtm_mg_coarse_solve(ndtm_ctx* ctx, void* xc_dev, const void* bc_dev, double m, void* stream);
+
 /* ---- solve ------------------------------------------------------------- */
 typedef struct {
   double tol;          /* target true relative residual per shift (1e-10) */
@@ -157,6 +166,8 @@ typedef struct {
   int fgmres_restart;  /* outer FGMRES restart length */
   int fgmres_maxiter;  /* outer FGMRES iteration cap per single solve */
   int max_rounds;      /* FP64 defect-correction rounds per multigrid shift */
+  int use_graphs;      /* 1: replay the multigrid cycle from a captured HIP graph (one per
+                          shift sign, cached until the next setup); 0: launch eagerly */
 } ndtm_solve_params;
 
 void ndtm_solve_default_params(ndtm_solve_params* p);

@@ -30,14 +30,16 @@ class NdtmError(RuntimeError):
 
 class MGParams(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("n_vec", C.c_int), ("setup_iters", C.c_int),
-                ("setup_smooth", C.c_int), ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
+                ("setup_smooth", C.c_int), ("setup_refine", C.c_int), ("setup_nd", C.c_int),
+                ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
                 ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int)]
 
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("n_mmscg", C.c_int), ("guess", C.c_int),
                 ("precision", C.c_int), ("poll_every", C.c_int), ("mg_tol", C.c_double),
-                ("fgmres_restart", C.c_int), ("fgmres_maxiter", C.c_int), ("max_rounds", C.c_int)]
+                ("fgmres_restart", C.c_int), ("fgmres_maxiter", C.c_int), ("max_rounds", C.c_int),
+                ("use_graphs", C.c_int)]
 
 
 _D16 = C.c_double * MAX_SHIFTS
@@ -92,6 +94,7 @@ def load_library():
         "ndtm_mg_restrict": (i, [vp, vp, vp, vp]),
         "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
+        "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_profile_enable": (i, [vp, i]),
@@ -203,6 +206,11 @@ class Context:
     def ndtm_mg_coarse_apply(self, xc, m=0.0):
         out = torch.empty_like(xc)
         self._check(self.lib.ndtm_mg_coarse_apply(self.h, _ptr(out), _ptr(xc), float(m), _stream()))
+        return out
+
+    def ndtm_mg_coarse_solve(self, bc, m=0.0):
+        out = torch.empty_like(bc)
+        self._check(self.lib.ndtm_mg_coarse_solve(self.h, _ptr(out), _ptr(bc), float(m), _stream()))
         return out
 
     # -- solve ----------------------------------------------------------------

@@ -32,6 +32,7 @@ struct ndtm_ctx {
   std::vector<double> shifts;
   void* U[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
   double* partials = nullptr;
+  double* vred = nullptr;  // single-launch reduction workspace: [counter][partials]
   size_t partials_n = 0;
   double* dscal = nullptr;  // device scalar scratch (kScalN doubles)
   double* hscal = nullptr;  // pinned host mirror
@@ -50,6 +51,7 @@ struct ndtm_ctx {
 namespace ndtm {
 
 constexpr int kScalN = 8192;
+constexpr size_t kVredN = 8 + 96 * 1024;  // counter + partials of up to 48 complex sums over 1024 blocks
 
 // status helpers
 int fail(ndtm_ctx* c, int code, const std::string& msg);

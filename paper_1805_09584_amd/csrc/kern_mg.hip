@@ -356,37 +356,52 @@ __device__ __forceinline__ typename C2<R>::T mk(R x, R y) {
   return v;
 }
 
+constexpr int kGroups = 4;  // thread groups per coarse site in restrict / coarse apply
+
 template <class R>
-__global__ __launch_bounds__(128) void restrict_k(MGGeom m, const typename C2<R>::T* P,
+__global__ __launch_bounds__(512) void restrict_k(MGGeom m, const typename C2<R>::T* P,
                                                   const typename C2<R>::T* fe, const typename C2<R>::T* fo,
                                                   typename C2<R>::T* vc) {
   using T2 = typename C2<R>::T;
   const int X = blockIdx.x;
-  const int Nv = m.Nv, n2 = 2 * Nv;
+  const int Nv = m.Nv, n2 = 2 * Nv, nout = 2 * n2;
   __shared__ int ph[1024];
+  __shared__ R red[kGroups][2][128];
   for (int l = threadIdx.x; l < m.nloc; l += blockDim.x) {
     const SiteLoc s = agg_site(m, X, l);
     ph[l] = (s.h << 1) | s.par;
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  if (t >= 2 * n2) return;
-  const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
+  const int t = threadIdx.x % nout, q = threadIdx.x / nout;
   R ax = 0, ay = 0;
-  const T2* PX = P + (long)X * m.nloc * 12 * Nv;
-  for (int l = 0; l < m.nloc; ++l) {
-    const int hp = ph[l];
-    const T2* F = (hp & 1) ? fo : fe;
-    const int h = hp >> 1;
-    for (int rr = 0; rr < 6; ++rr) {
-      const int r = 6 * chi + rr;
-      const T2 p = PX[((long)l * 12 + r) * Nv + k];
-      const T2 v = F[(long)(f * 12 + r) * m.stride + h];
-      ax += p.x * v.x + p.y * v.y;
-      ay += p.x * v.y - p.y * v.x;
+  if (q < kGroups) {
+    const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
+    const T2* PX = P + (long)X * m.nloc * 12 * Nv;
+    for (int l = q; l < m.nloc; l += kGroups) {
+      const int hp = ph[l];
+      const T2* F = (hp & 1) ? fo : fe;
+      const int h = hp >> 1;
+#pragma unroll
+      for (int rr = 0; rr < 6; ++rr) {
+        const int r = 6 * chi + rr;
+        const T2 p = PX[((long)l * 12 + r) * Nv + k];
+        const T2 v = F[(long)(f * 12 + r) * m.stride + h];
+        ax += p.x * v.x + p.y * v.y;
+        ay += p.x * v.y - p.y * v.x;
+      }
     }
+    red[q][0][t] = ax;
+    red[q][1][t] = ay;
   }
-  vc[((long)X * 2 + f) * n2 + i] = mk<R>(ax, ay);
+  __syncthreads();
+  if (threadIdx.x < nout) {
+    R sx = 0, sy = 0;
+    for (int g = 0; g < kGroups; ++g) {
+      sx += red[g][0][threadIdx.x];
+      sy += red[g][1][threadIdx.x];
+    }
+    vc[(long)X * nout + threadIdx.x] = mk<R>(sx, sy);
+  }
 }
 
 template <class R>
@@ -427,40 +442,50 @@ __global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>:
 
 // ---------------- coarse stencil ----------------
 template <class R>
-__global__ __launch_bounds__(128) void coarse_apply_k(MGGeom m, const typename C2<R>::T* D,
+__global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C2<R>::T* D,
                                                       const typename C2<R>::T* Bo, const typename C2<R>::T* x,
                                                       typename C2<R>::T* y, double mubar_c, double epsbar,
                                                       double mm) {
   using T2 = typename C2<R>::T;
   const int X = blockIdx.x;
-  const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2;
+  const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2, nout = 2 * n2;
   __shared__ T2 xs[9][2 * 64];
   __shared__ int nb[9];
+  __shared__ R red[kGroups][2][128];
   if (threadIdx.x < 9) {
     const int b = threadIdx.x;
     nb[b] = b == 0 ? X : coarse_nbr(m, X, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 9 * 2 * n2; e += blockDim.x) {
-    const int b = e / (2 * n2), q = e % (2 * n2);
-    xs[b][q] = x[(long)nb[b] * 2 * n2 + q];
+  for (int e = threadIdx.x; e < 9 * nout; e += blockDim.x) {
+    const int b = e / nout, q = e % nout;
+    xs[b][q] = x[(long)nb[b] * nout + q];
   }
   __syncthreads();
-  const int t = threadIdx.x;
-  if (t >= 2 * n2) return;
-  const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
-  R ax = 0, ay = 0;
-  const T2* DX = D + (long)X * 9 * ntot;
-  for (int b = 0; b < 9; ++b) {
-    const T2* Db = DX + (long)b * ntot;
-    const T2* xv = xs[b] + f * n2;
-    for (int j = 0; j < n2; ++j) {
-      const T2 dv = Db[(long)j * n2 + i];
-      const T2 v = xv[j];
+  const int t = threadIdx.x % nout, q = threadIdx.x / nout;
+  const int f = t / n2, i = t % n2;
+  if (q < kGroups) {
+    // the 9 * n2 products of row i are split over the groups: pair p = b * n2 + j
+    R ax = 0, ay = 0;
+    const T2* DX = D + (long)X * 9 * ntot;
+    for (int pidx = q; pidx < 9 * n2; pidx += kGroups) {
+      const int b = pidx / n2, j = pidx % n2;
+      const T2 dv = DX[(long)b * ntot + (long)j * n2 + i];
+      const T2 v = xs[b][f * n2 + j];
       ax += dv.x * v.x - dv.y * v.y;
       ay += dv.x * v.y + dv.y * v.x;
     }
+    red[q][0][t] = ax;
+    red[q][1][t] = ay;
   }
+  __syncthreads();
+  if (threadIdx.x >= nout) return;
+  R ax = 0, ay = 0;
+  for (int g = 0; g < kGroups; ++g) {
+    ax += red[g][0][t];
+    ay += red[g][1][t];
+  }
+  const int chi = i / Nv, k = i % Nv;
   const R g5 = chi == 0 ? R(1) : R(-1);
   const R t3 = f == 0 ? R(1) : R(-1);
   const T2 xself = xs[0][f * n2 + i];
@@ -546,10 +571,10 @@ void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int 
 void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
                  hipStream_t st) {
   if (prec == P64)
-    hipLaunchKernelGGL(restrict_k<double>, dim3(m.Vc), dim3(128), 0, st, m, (const double2*)P, (const double2*)fe,
+    hipLaunchKernelGGL(restrict_k<double>, dim3(m.Vc), dim3(4 * m.Nv * kGroups), 0, st, m, (const double2*)P, (const double2*)fe,
                        (const double2*)fo, (double2*)vc);
   else
-    hipLaunchKernelGGL(restrict_k<float>, dim3(m.Vc), dim3(128), 0, st, m, (const float2*)P, (const float2*)fe,
+    hipLaunchKernelGGL(restrict_k<float>, dim3(m.Vc), dim3(4 * m.Nv * kGroups), 0, st, m, (const float2*)P, (const float2*)fe,
                        (const float2*)fo, (float2*)vc);
 }
 
@@ -565,10 +590,10 @@ void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* 
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
                      double mubar_c, double epsbar, double m, hipStream_t st) {
   if (prec == P64)
-    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(128), 0, st, g, (const double2*)D,
+    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(4 * g.Nv * kGroups), 0, st, g, (const double2*)D,
                        (const double2*)Bo, (const double2*)x, (double2*)y, mubar_c, epsbar, m);
   else
-    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(128), 0, st, g, (const float2*)D,
+    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(4 * g.Nv * kGroups), 0, st, g, (const float2*)D,
                        (const float2*)Bo, (const float2*)x, (float2*)y, mubar_c, epsbar, m);
 }
 

@@ -17,6 +17,13 @@ struct Basis {
   const T2* v[kMaxBasis];
 };
 
+// reductions: at most 256 blocks so that the completion counter sees few atomics
+inline unsigned rgrid(size_t n) {
+  size_t g = (n + 4 * kVB - 1) / (4 * kVB);
+  if (g > 256) g = 256;
+  return (unsigned)(g ? g : 1);
+}
+
 inline unsigned vgrid(size_t n) {
   size_t g = (n + kVB - 1) / kVB;
   if (g > (size_t)kVGrid) g = kVGrid;
@@ -83,20 +90,53 @@ __global__ void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t 
   }
 }
 
+// Single-launch deterministic reduction: every block writes its partial(s);
+// the last block to finish (counted with a device-scope atomic) sums the
+// partials of each of the `width` scalars in block order and writes dst, then
+// resets the counter.  ws = [counter (8 doubles)][partials width x gridDim].
+__device__ bool last_block_sum(double* ws, int width, double* dst) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* cnt = reinterpret_cast<unsigned*>(ws);
+    last = atomicAdd(cnt, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  const double* part = ws + 8;
+  // one wavefront per scalar: lanes stride over the block partials in a fixed
+  // order, then a fixed-shape shuffle tree
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = w; j < width; j += nw) {
+    double s = 0;
+    for (int i = lane; i < (int)gridDim.x; i += 64) s += part[(size_t)j * gridDim.x + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+    if (lane == 0) dst[j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *reinterpret_cast<unsigned*>(ws) = 0u;
+  return true;
+}
+
 template <class T2>
-__global__ void norm2_k(const T2* x, size_t n, double* part) {
+__global__ void norm2_k(const T2* x, size_t n, double* ws, double* dst) {
   double s = 0;
   GRID_LOOP(i, n) {
     const double2 v = ld2(x, i);
     s += v.x * v.x + v.y * v.y;
   }
   s = bsum(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) ws[8 + blockIdx.x] = s;
+  last_block_sum(ws, 1, dst);
 }
 
 // partials [2][nblk]: <x,y> re, im
 template <class T2>
-__global__ void dot_k(const T2* x, const T2* y, size_t n, double* part) {
+__global__ void dot_k(const T2* x, const T2* y, size_t n, double* ws, double* dst) {
+  double* part = ws + 8;
   double re = 0, im = 0;
   GRID_LOOP(i, n) {
     const double2 a = ld2(x, i), b = ld2(y, i);
@@ -109,10 +149,12 @@ __global__ void dot_k(const T2* x, const T2* y, size_t n, double* part) {
     part[blockIdx.x] = re;
     part[gridDim.x + blockIdx.x] = im;
   }
+  last_block_sum(ws, 2, dst);
 }
 
 template <class T2, int KM>
-__global__ void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* part) {
+__global__ void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* ws, double* dst) {
+  double* part = ws + 8;
   double re[KM], im[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j) re[j] = im[j] = 0;
@@ -134,6 +176,7 @@ __global__ void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* pa
       part[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = b;
     }
   }
+  last_block_sum(ws, 2 * k, dst);
 }
 
 // sums column j of partials [width][nparts] into dst[j*dst_stride]
@@ -159,6 +202,70 @@ __global__ void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size
   }
 }
 
+// w -= sum_j coef[j] V_j and ||w||^2 into dst (single launch)
+template <class T2>
+__global__ void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n, double* ws,
+                                  double* dst) {
+  double s = 0;
+  GRID_LOOP(i, n) {
+    double2 acc = ld2(w, i);
+    for (int j = 0; j < k; ++j) {
+      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.v[j], i));
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    st2(w, i, acc);
+    const double2 r = ld2(w, i);  // the stored (rounded) value
+    s += r.x * r.x + r.y * r.y;
+  }
+  s = bsum(s);
+  if (threadIdx.x == 0) ws[8 + blockIdx.x] = s;
+  last_block_sum(ws, 1, dst);
+}
+
+// minimal-residual coefficient omega = <t, s> / <t, t> (single launch; dst[0..1] = omega,
+// dst[2..4] = re<t,s>, im<t,s>, <t,t>)
+template <class T2>
+__global__ void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws, double* dst) {
+  double re = 0, im = 0, tt = 0;
+  GRID_LOOP(i, n) {
+    const double2 a = ld2(t, i), b = ld2(sv, i);
+    re += a.x * b.x + a.y * b.y;
+    im += a.x * b.y - a.y * b.x;
+    tt += a.x * a.x + a.y * a.y;
+  }
+  re = bsum(re);
+  im = bsum(im);
+  tt = bsum(tt);
+  double* part = ws + 8;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = re;
+    part[gridDim.x + blockIdx.x] = im;
+    part[2 * gridDim.x + blockIdx.x] = tt;
+  }
+  if (last_block_sum(ws, 3, dst + 2) && threadIdx.x == 0) {
+    const double tts = dst[4];
+    dst[0] = tts > 0 ? dst[2] / tts : 0.0;
+    dst[1] = tts > 0 ? dst[3] / tts : 0.0;
+  }
+}
+
+// z += omega s ; s -= omega t  (omega complex at dev[0..1])
+template <class T2>
+__global__ void mr_update_k(T2* z, T2* sv, const T2* t, const double* om, int update_s, size_t n) {
+  const double2 w = make_double2(om[0], om[1]);
+  GRID_LOOP(i, n) {
+    const double2 sval = ld2(sv, i);
+    const double2 zs = cm(w, sval);
+    const double2 zv = ld2(z, i);
+    st2(z, i, make_double2(zv.x + zs.x, zv.y + zs.y));
+    if (update_s) {
+      const double2 tw = cm(w, ld2(t, i));
+      st2(sv, i, make_double2(sval.x - tw.x, sval.y - tw.y));
+    }
+  }
+}
+
 // y (+)= sum_j coef[j] V_j   (coef device)
 template <class T2>
 __global__ void lincomb_dev_k(T2* y, Basis<T2> V, int k, const double* coef, int accumulate, size_t n) {
@@ -173,7 +280,11 @@ __global__ void lincomb_dev_k(T2* y, Basis<T2> V, int k, const double* coef, int
   }
 }
 
-// omega = <t, r> / <t, t> from dst = [re<t,r>, im<t,r>, <t,t>]
+__global__ void vadd_k(double* a, const double* b, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] += b[i];
+}
+
+// omega = <t, r> / <t, t> from d = [re<t,r>, im<t,r>, <t,t>]
 __global__ void mr_coef_k(const double* d, double* omega) {
   if (threadIdx.x == 0) {
     const double tt = d[2];
@@ -185,10 +296,11 @@ __global__ void mr_coef_k(const double* d, double* omega) {
 // Least squares of a (m+1) x m Hessenberg system by Givens rotations, one thread.
 // H column-major with leading dimension ldh (complex, 2 doubles); beta = sqrt(*beta2).
 __global__ void hess_lsq_k(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y) {
+  // small dense work in LDS (a private array would live in scratch memory)
+  __shared__ double2 R[kMaxBasis + 1][kMaxBasis];
+  __shared__ double2 g[kMaxBasis + 1];
+  __shared__ double2 cs[kMaxBasis], sn[kMaxBasis];
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double2 R[kMaxBasis][kMaxBasis];
-  double2 g[kMaxBasis + 1];
-  double2 cs[kMaxBasis], sn[kMaxBasis];
   for (int j = 0; j < m; ++j)
   {
     for (int i = 0; i <= j; ++i) R[i][j] = make_double2(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
@@ -297,43 +409,36 @@ void vfinalize(const double* part, int nparts, int width, double* dst, int dst_s
 }
 
 template <class T2>
-static int vnorm2_t(const void* x, size_t n, double* part, hipStream_t st) {
-  const unsigned g = vgrid(n);
-  hipLaunchKernelGGL(norm2_k<T2>, dim3(g), dim3(kVB), 0, st, static_cast<const T2*>(x), n, part);
-  return (int)g;
+static void vnorm2_t(const void* x, size_t n, double* ws, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(norm2_k<T2>, dim3(rgrid(n)), dim3(kVB), 0, st, static_cast<const T2*>(x), n, ws, dst);
 }
-void vnorm2(int prec, const void* x, size_t n, double* part, double* dst, hipStream_t st) {
-  int g = prec == P64 ? vnorm2_t<double2>(x, n, part, st) : vnorm2_t<float2>(x, n, part, st);
-  vfinalize(part, g, 1, dst, 1, st);
+void vnorm2(int prec, const void* x, size_t n, double* ws, double* dst, hipStream_t st) {
+  DISPATCH(prec, vnorm2_t, x, n, ws, dst, st);
 }
 
 template <class T2>
-static int vdot_t(const void* x, const void* y, size_t n, double* part, hipStream_t st) {
-  const unsigned g = vgrid(n);
-  hipLaunchKernelGGL(dot_k<T2>, dim3(g), dim3(kVB), 0, st, static_cast<const T2*>(x), static_cast<const T2*>(y),
-                     n, part);
-  return (int)g;
+static void vdot_t(const void* x, const void* y, size_t n, double* ws, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(dot_k<T2>, dim3(rgrid(n)), dim3(kVB), 0, st, static_cast<const T2*>(x),
+                     static_cast<const T2*>(y), n, ws, dst);
 }
-void vdot(int prec, const void* x, const void* y, size_t n, double* part, double* dst, hipStream_t st) {
-  int g = prec == P64 ? vdot_t<double2>(x, y, n, part, st) : vdot_t<float2>(x, y, n, part, st);
-  vfinalize(part, g, 2, dst, 1, st);
+void vdot(int prec, const void* x, const void* y, size_t n, double* ws, double* dst, hipStream_t st) {
+  DISPATCH(prec, vdot_t, x, y, n, ws, dst, st);
 }
 
 template <class T2>
 static void vmultidot_t(const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
                         hipStream_t st) {
-  const unsigned g = vgrid(n);
+  const unsigned g = rgrid(n);
   auto B = basis<T2>(V, k);
   const T2* wp = static_cast<const T2*>(w);
   if (k <= 4)
-    hipLaunchKernelGGL((multidot_k<T2, 4>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+    hipLaunchKernelGGL((multidot_k<T2, 4>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
   else if (k <= 8)
-    hipLaunchKernelGGL((multidot_k<T2, 8>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+    hipLaunchKernelGGL((multidot_k<T2, 8>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
   else if (k <= 16)
-    hipLaunchKernelGGL((multidot_k<T2, 16>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
+    hipLaunchKernelGGL((multidot_k<T2, 16>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
   else
-    hipLaunchKernelGGL((multidot_k<T2, kMaxBasis>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part);
-  vfinalize(part, (int)g, 2 * k, dst, 1, st);
+    hipLaunchKernelGGL((multidot_k<T2, kMaxBasis>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
 }
 void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
                hipStream_t st) {
@@ -359,6 +464,41 @@ static void vlincomb_t(void* y, const void* const* V, int k, const double* coef,
 void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* coef, int accumulate, size_t n,
                   hipStream_t st) {
   DISPATCH(prec, vlincomb_t, y, V, k, coef, accumulate, n, st);
+}
+
+template <class T2>
+static void vmulti_axpy_norm_t(void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
+                               double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(multi_axpy_norm_k<T2>, dim3(rgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(w), basis<T2>(V, k),
+                     k, coef, n, ws, dst);
+}
+void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
+                          double* dst, hipStream_t st) {
+  DISPATCH(prec, vmulti_axpy_norm_t, w, V, k, coef, n, ws, dst, st);
+}
+
+template <class T2>
+static void vmr_coef_t(const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(mr_coef_fused_k<T2>, dim3(rgrid(n)), dim3(kVB), 0, st, static_cast<const T2*>(t),
+                     static_cast<const T2*>(s), n, ws, dst);
+}
+void vmr_coef(int prec, const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st) {
+  DISPATCH(prec, vmr_coef_t, t, s, n, ws, dst, st);
+}
+
+template <class T2>
+static void vmr_update_t(void* z, void* s, const void* t, const double* om, int update_s, size_t n,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(mr_update_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(z), static_cast<T2*>(s),
+                     static_cast<const T2*>(t), om, update_s, n);
+}
+void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int update_s, size_t n,
+                hipStream_t st) {
+  DISPATCH(prec, vmr_update_t, z, s, t, om, update_s, n, st);
+}
+
+void vadd_dev(double* a, const double* b, int n, hipStream_t st) {
+  hipLaunchKernelGGL(vadd_k, dim3(1), dim3(128), 0, st, a, b, n);
 }
 
 void mr_coef(const double* d, double* omega, hipStream_t st) {

@@ -60,8 +60,13 @@ struct MGData {
   double* dy = nullptr;   // least-squares coefficients
   double* dbeta = nullptr;
   double* dtmp = nullptr;
+  double* dh2 = nullptr;  // second Gram-Schmidt pass coefficients
   std::vector<void*> owned;
   bool ready = false;
+  // cycle graphs: one per value of the odd-site shift m, replayed on the caller's stream
+  hipStream_t cap = nullptr;
+  std::vector<std::pair<double, hipGraphExec_t>> graphs;
+  bool use_graphs = true;
 };
 
 static void* mg_alloc(MGData* M, size_t bytes) {
@@ -92,22 +97,27 @@ static Full full_field(ndtm_ctx* c, const std::string& name, int prec) {
 }
 
 // ---- coarse solve: fixed-length GMRES from zero, all on the device ----------
-static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, hipStream_t st) {
+static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
+                         hipStream_t st) {
   const int cp = M->cprec;
   const size_t n = M->ncoarse;
   const int kc = M->prm.coarse_iters;
   const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
-  vnorm2(cp, rhs, n, c->partials, M->dbeta, st);
+  vnorm2(cp, rhs, n, c->vred, M->dbeta, st);
   vscale_inv_sqrt(cp, M->cV[0], rhs, M->dbeta, n, st);
   for (int j = 0; j < kc; ++j) {
     {
       ProfScope ps(c, NDTM_PROF_COARSE, 0.0, st);
-      mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, c->epsbar, m, st);
+      mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, eps, m, st);
     }
+    // classical Gram-Schmidt with one reorthogonalisation; the second pass's
+    // coefficients are added into the Hessenberg column on the device
     double* hcol = M->dH + 2 * (size_t)j * (kc + 1);
-    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->partials, hcol, st);
+    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->vred, hcol, st);
     vmulti_axpy_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol, n, st);
-    vnorm2(cp, M->cW, n, c->partials, M->dsub + j, st);
+    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->vred, M->dh2, st);
+    vmulti_axpy_norm_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, M->dh2, n, c->vred, M->dsub + j, st);
+    vadd_dev(hcol, M->dh2, 2 * (j + 1), st);
     vscale_inv_sqrt(cp, M->cV[j + 1], M->cW, M->dsub + j, n, st);
   }
   hess_lsq(M->dH, kc + 1, kc, M->dbeta, M->dsub, M->dy, st);
@@ -119,20 +129,18 @@ static void dprime(ndtm_ctx* c, int prec, const Full& y, const Full& x, double m
   apply_dfull(c, prec, y.e, y.o, x.e, x.o, m, st);
 }
 
-// z_o ~ S'^-1 r_o : one two-level cycle for D'(m) on (0, r_o); FP64 in/out
-static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfField& z64, double m, hipStream_t st) {
+// Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
+// smooth_iters minimal-residual steps.  The fine operator is the one in c->op
+// (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
+static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, double eps, hipStream_t st) {
   const int cp = M->cprec;
   const size_t nh = half_elems(c);
-  Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp), S = full_field(c, "mg_S", cp),
-       Tt = full_field(c, "mg_T", cp);
-  // r = (0, r_o)
-  vzero(cp, R.e.v, nh, st);
-  vconvert(cp, R.o.v, P64, r64.v, nh, st);
+  Full S = full_field(c, "mg_S", cp), Tt = full_field(c, "mg_T", cp);
   {
     ProfScope ps(c, NDTM_PROF_RESTRICT, 0.0, st);
     mg_restrict(cp, M->g, M->Pc, R.e.v, R.o.v, M->cR, st);
   }
-  coarse_solve(c, M, M->cR, M->cW, m, st);
+  coarse_solve(c, M, M->cR, M->cW, m, eps, st);
   {
     ProfScope ps(c, NDTM_PROF_PROLONG, 0.0, st);
     mg_prolong(cp, M->g, M->Pc, M->cW, Z.e.v, Z.o.v, st);
@@ -144,13 +152,50 @@ static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfFie
     vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
     for (int it = 0; it < nu; ++it) {
       dprime(c, cp, Tt, S, m, st);
-      vdot(cp, Tt.base, S.base, 2 * nh, c->partials, M->dtmp, st);
-      vnorm2(cp, Tt.base, 2 * nh, c->partials, M->dtmp + 2, st);
-      mr_coef(M->dtmp, M->dtmp + 4, st);
-      vaxpy_dev(cp, Z.base, M->dtmp + 4, 1.0, S.base, 2 * nh, st);
-      if (it + 1 < nu) vaxpy_dev(cp, S.base, M->dtmp + 4, -1.0, Tt.base, 2 * nh, st);
+      vmr_coef(cp, Tt.base, S.base, 2 * nh, c->vred, M->dtmp, st);
+      vmr_update(cp, Z.base, S.base, Tt.base, M->dtmp, it + 1 < nu, 2 * nh, st);
     }
   }
+}
+
+// z_o ~ S'^-1 r_o : the cycle for D'(m) applied to (0, r_o), odd part; FP64 in/out
+// The cycle between fixed buffers (mg_R with a zero even half, mg_Z) is a fixed
+// sequence of about a hundred small launches for a given m; it is captured once
+// per m into a HIP graph (on the context's own stream, with timing events off)
+// and replayed on the caller's stream.  Every buffer it touches is allocated at
+// setup, so nothing is allocated or cleared by memset inside the capture.
+static hipGraphExec_t cycle_graph(ndtm_ctx* c, MGData* M, double m) {
+  for (auto& g : M->graphs)
+    if (g.first == m) return g.second;
+  const int cp = M->cprec;
+  Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp);
+  if (!M->cap && hipStreamCreateWithFlags(&M->cap, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  const int mask = c->prof_mask;
+  c->prof_mask = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (hipStreamBeginCapture(M->cap, hipStreamCaptureModeRelaxed) == hipSuccess) {
+    mg_vcycle(c, M, R, Z, m, c->epsbar, M->cap);
+    if (hipStreamEndCapture(M->cap, &graph) == hipSuccess && graph) {
+      if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+      (void)hipGraphDestroy(graph);
+    }
+  }
+  c->prof_mask = mask;
+  if (exec) M->graphs.push_back({m, exec});
+  return exec;
+}
+
+static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfField& z64, double m, hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t nh = half_elems(c);
+  Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp);
+  vconvert(cp, R.o.v, P64, r64.v, nh, st);
+  hipGraphExec_t g = M->use_graphs ? cycle_graph(c, M, m) : nullptr;
+  if (g)
+    (void)hipGraphLaunch(g, st);
+  else
+    mg_vcycle(c, M, R, Z, m, c->epsbar, st);
   vconvert(P64, z64.v, cp, Z.o.v, nh, st);
 }
 
@@ -192,11 +237,10 @@ static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField&
       mg_cycle(c, M, V[k], Z[k], m, st);
       apply_sshift(c, P64, W, Z[k], te, m, st);
       // classical Gram-Schmidt, two passes
-      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->partials, dh, st);
+      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->vred, dh, st);
       vmulti_axpy_dev(P64, W.v, Vp.data(), k + 1, dh, n, st);
-      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->partials, dh + 2 * restart, st);
-      vmulti_axpy_dev(P64, W.v, Vp.data(), k + 1, dh + 2 * restart, n, st);
-      vnorm2(P64, W.v, n, c->partials, dh + 4 * restart, st);
+      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->vred, dh + 2 * restart, st);
+      vmulti_axpy_norm_dev(P64, W.v, Vp.data(), k + 1, dh + 2 * restart, n, c->vred, dh + 4 * restart, st);
       vscale_inv_sqrt(P64, V[k + 1].v, W.v, dh + 4 * restart, n, st);
       (void)hipMemcpyAsync(c->hscal, dh, (4 * restart + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
       (void)hipStreamSynchronize(st);
@@ -308,6 +352,7 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
                     const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st) {
   MGData* M = c->mg;
   if (!M || !M->ready) return fail(c, NDTM_ESTATE, "solve: multigrid shifts need ndtm_mg_setup first");
+  M->use_graphs = p->use_graphs != 0;
   const int nsh = (int)sig.size();
   const size_t n = half_elems(c);
   int status = NDTM_OK;
@@ -408,52 +453,6 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->Bo64 = (double2*)mg_alloc(M, nB * 16);
   if (!M->P64 || !M->D64 || !M->Bo64) return fail(c, NDTM_ENOMEM, "mg_setup: P / coarse operator");
   const size_t nh = half_elems(c);
-  if (tv_dev) {
-    mg_tv_to_P(g, static_cast<const double2*>(tv_dev), M->P64, st);
-  } else {
-    // inverse iteration on the one-flavour operators D_W +- i mubar Gamma5 (doublet kernel at epsbar = 0)
-    const int nf = (Nv + 1) / 2;
-    std::vector<Full> F(nf);
-    for (int i = 0; i < nf; ++i) {
-      F[i] = full_field(c, "su_v" + std::to_string(i), P64);
-      if (!F[i].base) return fail(c, NDTM_ENOMEM, "mg_setup: test vectors");
-      mg_random_fill(g, c->g.vh, (double2*)F[i].e.v, (double2*)F[i].o.v, prm->seed * 1000003ull + i, st);
-    }
-    Full X = full_field(c, "su_x", P64), R = full_field(c, "su_r", P64), Tt = full_field(c, "su_t", P64);
-    double* d = c->dscal + 64;
-    const OpParams saved = c->op;
-    const double a = c->op.a;
-    c->op.epsbar = 0.0;
-    c->op.inv_den = 1.0 / (a * a + c->mubar * c->mubar);
-    for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
-      for (int i = 0; i < nf; ++i) {
-        // x ~ D^-1 v by minimal-residual steps from x = 0, then v = x / ||x||
-        vzero(P64, X.base, 2 * nh, st);
-        blas_copy((double2*)R.base, (const double2*)F[i].base, 2 * nh, st);
-        for (int it = 0; it < prm->setup_smooth; ++it) {
-          apply_dfull(c, P64, Tt.e, Tt.o, R.e, R.o, 0.0, st);
-          vdot(P64, Tt.base, R.base, 2 * nh, c->partials, d, st);
-          vnorm2(P64, Tt.base, 2 * nh, c->partials, d + 2, st);
-          mr_coef(d, d + 4, st);
-          vaxpy_dev(P64, X.base, d + 4, 1.0, R.base, 2 * nh, st);
-          vaxpy_dev(P64, R.base, d + 4, -1.0, Tt.base, 2 * nh, st);
-        }
-        vnorm2(P64, X.base, 2 * nh, c->partials, d + 6, st);
-        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
-      }
-    }
-    c->op = saved;
-    std::vector<const double2*> fp(nf);
-    for (int i = 0; i < nf; ++i) fp[i] = (const double2*)F[i].base;
-    mg_fields_to_P(g, fp.data(), nf, M->P64, st);
-    NDTM_HIP(c, hipStreamSynchronize(st));
-    ws_free_prefix(c, "su_");
-  }
-  mg_orthonormalize(g, M->P64, st);
-  double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
-  if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");
-  mg_galerkin(g, (const double2*)c->U[P64][0], (const double2*)c->U[P64][1], c->g.antiperiodic, c->op.a, M->P64,
-              M->D64, scratch, M->Bo64, st);
   if (M->cprec == P64) {
     M->Pc = M->P64;
     M->Dc = M->D64;
@@ -463,9 +462,6 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     M->Dc = mg_alloc(M, nD * 8);
     M->Boc = mg_alloc(M, nB * 8);
     if (!M->Pc || !M->Dc || !M->Boc) return fail(c, NDTM_ENOMEM, "mg_setup: FP32 copies");
-    vconvert(P32, M->Pc, P64, M->P64, nP, st);
-    vconvert(P32, M->Dc, P64, M->D64, nD, st);
-    vconvert(P32, M->Boc, P64, M->Bo64, nB, st);
   }
   const int kc = prm->coarse_iters;
   M->cV.resize(kc + 1);
@@ -480,15 +476,95 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->dy = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
   M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
   M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
-  if (!M->cW || !M->cR || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
+  M->dh2 = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
+  if (!M->dh2 || !M->cW || !M->cR || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
+  double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
+  if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");
+  // P from the vectors currently in M->P64: orthonormalise, Galerkin products, cycle-precision copies
+  auto rebuild = [&]() {
+    mg_orthonormalize(g, M->P64, st);
+    mg_galerkin(g, (const double2*)c->U[P64][0], (const double2*)c->U[P64][1], c->g.antiperiodic, c->op.a, M->P64,
+                M->D64, scratch, M->Bo64, st);
+    if (M->cprec != P64) {
+      vconvert(P32, M->Pc, P64, M->P64, nP, st);
+      vconvert(P32, M->Dc, P64, M->D64, nD, st);
+      vconvert(P32, M->Boc, P64, M->Bo64, nB, st);
+    }
+  };
+  if (tv_dev) {
+    mg_tv_to_P(g, static_cast<const double2*>(tv_dev), M->P64, st);
+    rebuild();
+  } else {
+    // inverse iteration on the one-flavour operators D_W +- i mubar Gamma5 (doublet kernel at epsbar = 0)
+    const int nf = (Nv + 1) / 2;
+    std::vector<Full> F(nf);
+    for (int i = 0; i < nf; ++i) {
+      F[i] = full_field(c, "su_v" + std::to_string(i), P64);
+      if (!F[i].base) return fail(c, NDTM_ENOMEM, "mg_setup: test vectors");
+      mg_random_fill(g, c->g.vh, (double2*)F[i].e.v, (double2*)F[i].o.v, prm->seed * 1000003ull + i, st);
+    }
+    Full X = full_field(c, "su_x", P64), R = full_field(c, "su_r", P64), Tt = full_field(c, "su_t", P64);
+    if (!X.base || !R.base || !Tt.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
+    double* d = c->dscal + 64;
+    const OpParams saved = c->op;
+    const double a = c->op.a;
+    const double eps_setup = prm->setup_nd ? c->epsbar : 0.0;
+    auto setup_op = [&]() {
+      c->op.epsbar = eps_setup;
+      c->op.inv_den = 1.0 / (a * a + c->mubar * c->mubar - eps_setup * eps_setup);
+    };
+    setup_op();
+    for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
+      for (int i = 0; i < nf; ++i) {
+        // x ~ D^-1 v by minimal-residual steps from x = 0, then v = x / ||x||
+        vzero(P64, X.base, 2 * nh, st);
+        blas_copy((double2*)R.base, (const double2*)F[i].base, 2 * nh, st);
+        for (int it = 0; it < prm->setup_smooth; ++it) {
+          apply_dfull(c, P64, Tt.e, Tt.o, R.e, R.o, 0.0, st);
+          vmr_coef(P64, Tt.base, R.base, 2 * nh, c->vred, d, st);
+          vmr_update(P64, X.base, R.base, Tt.base, d, 1, 2 * nh, st);
+        }
+        vnorm2(P64, X.base, 2 * nh, c->vred, d + 6, st);
+        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
+      }
+    }
+    std::vector<const double2*> fp(nf);
+    for (int i = 0; i < nf; ++i) fp[i] = (const double2*)F[i].base;
+    c->op = saved;
+    mg_fields_to_P(g, fp.data(), nf, M->P64, st);
+    rebuild();
+    // refinement: v <- (two-level cycle of the setup operator) v, then rebuild P and D_c
+    Full Rc = full_field(c, "su_rc", M->cprec), Zc = full_field(c, "su_zc", M->cprec);
+    if (!Rc.base || !Zc.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
+    for (int r = 0; r < prm->setup_refine; ++r) {
+      setup_op();
+      for (int i = 0; i < nf; ++i) {
+        vconvert(M->cprec, Rc.base, P64, F[i].base, 2 * nh, st);
+        mg_vcycle(c, M, Rc, Zc, 0.0, eps_setup, st);
+        vconvert(P64, X.base, M->cprec, Zc.base, 2 * nh, st);
+        vnorm2(P64, X.base, 2 * nh, c->vred, d + 6, st);
+        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
+      }
+      c->op = saved;
+      mg_fields_to_P(g, fp.data(), nf, M->P64, st);
+      rebuild();
+    }
+    c->op = saved;
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    ws_free_prefix(c, "su_");
+  }
   NDTM_HIP(c, hipGetLastError());
   NDTM_HIP(c, hipStreamSynchronize(st));
   // the partial self blocks are only needed during setup
-  auto it = c->bufs.find("mg_scratch");
-  if (it != c->bufs.end()) {
-    (void)hipFree(it->second.p);
-    c->bufs.erase(it);
+  ws_free_prefix(c, "mg_scratch");
+  {
+    // cycle buffers exist before any graph capture; the even half of mg_R stays zero
+    Full R = full_field(c, "mg_R", M->cprec), Z = full_field(c, "mg_Z", M->cprec);
+    Full S = full_field(c, "mg_S", M->cprec), Tt = full_field(c, "mg_T", M->cprec);
+    if (!R.base || !Z.base || !S.base || !Tt.base) return fail(c, NDTM_ENOMEM, "mg_setup: cycle workspace");
+    vzero(M->cprec, R.base, 2 * nh, st);
+    NDTM_HIP(c, hipStreamSynchronize(st));
   }
   M->ready = true;
   return NDTM_OK;
@@ -503,6 +579,8 @@ extern "C" {
 void ndtm_mg_free(ndtm_ctx* c) {
   if (!c || !c->mg) return;
   (void)hipDeviceSynchronize();
+  for (auto& g : c->mg->graphs) (void)hipGraphExecDestroy(g.second);
+  if (c->mg->cap) (void)hipStreamDestroy(c->mg->cap);
   for (void* p : c->mg->owned) (void)hipFree(p);
   delete c->mg;
   c->mg = nullptr;
@@ -514,8 +592,10 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->n_vec = 24;
   p->setup_iters = 6;
   p->setup_smooth = 4;
-  p->smooth_iters = 2;
-  p->coarse_iters = 16;
+  p->setup_refine = 4;
+  p->setup_nd = 1;
+  p->smooth_iters = 8;
+  p->coarse_iters = 8;
   p->coarse_mu_factor = 1.0;
   p->seed = 32;
   p->precision = NDTM_PREC_F32;
@@ -536,7 +616,7 @@ int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* st
     return fail(c, NDTM_EINVAL, "mg_setup: n_vec even in [2, 32]");
   if (6 * nloc < p->n_vec) return fail(c, NDTM_EINVAL, "mg_setup: aggregate too small for n_vec vectors");
   if (p->coarse_iters < 1 || p->coarse_iters > 32) return fail(c, NDTM_EINVAL, "mg_setup: coarse_iters in [1, 32]");
-  if (p->smooth_iters < 0 || p->setup_iters < 0 || p->setup_smooth < 1 || !(p->coarse_mu_factor >= 1.0))
+  if (p->smooth_iters < 0 || p->setup_iters < 0 || p->setup_smooth < 1 || p->setup_refine < 0 || !(p->coarse_mu_factor >= 1.0))
     return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
   if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32)
     return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64 or F32");
@@ -568,6 +648,19 @@ int ndtm_mg_prolong(ndtm_ctx* c, void* v, const void* vc, void* stream) {
   Full F = full_field(c, "ab_f", P64);
   mg_prolong(P64, c->mg->g, c->mg->P64, vc, F.e.v, F.o.v, st);
   launch_unpack_full(c->g, F.e, F.o, static_cast<double2*>(v), st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_mg_coarse_solve(ndtm_ctx* c, void* xc, const void* bc, double m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_solve: no multigrid setup");
+  if (!xc || !bc || xc == bc) return fail(c, NDTM_EINVAL, "mg_coarse_solve: null or aliased pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MGData* M = c->mg;
+  vconvert(M->cprec, M->cR, P64, bc, M->ncoarse, st);
+  coarse_solve(c, M, M->cR, M->cW, m, c->epsbar, st);
+  vconvert(P64, xc, M->cprec, M->cW, M->ncoarse, st);
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }

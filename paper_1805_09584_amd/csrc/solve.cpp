@@ -160,6 +160,7 @@ void ndtm_solve_default_params(ndtm_solve_params* p) {
   p->fgmres_restart = 16;
   p->fgmres_maxiter = 400;
   p->max_rounds = 6;
+  p->use_graphs = 1;
 }
 
 int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_solve_params* p,

@@ -7,6 +7,10 @@
 namespace ndtm {
 
 // ---- vectors: prec P64 -> double2 storage, P32 -> float2; n complex elements ----
+// Reductions (vnorm2, vdot, vmultidot) are single launches: `ws` is a reduction
+// workspace [counter (8 doubles, zero between calls)][partials], of at least
+// 8 + 2*k*1024 doubles; dst receives the sums (device).  Calls sharing a ws must
+// be ordered on one stream.
 void vzero(int prec, void* y, size_t n, hipStream_t st);
 void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st);
 void vaxpby(int prec, void* y, double2 a, const void* x, double2 b, size_t n, hipStream_t st);   // y = a x + b y
@@ -21,8 +25,18 @@ void vmulti_axpy_dev(int prec, void* w, const void* const* V, int k, const doubl
                      hipStream_t st);                                                            // w -= sum c_j V_j
 void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* coef, int accumulate, size_t n,
                   hipStream_t st);
+// w -= sum_j coef[j] V_j, then ||w||^2 into dst[0] (one launch)
+void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
+                          double* dst, hipStream_t st);
+// minimal-residual step: dst[0..1] = <t,s>/<t,t>, dst[2..4] scratch
+void vmr_coef(int prec, const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st);
+// z += omega s, and s -= omega t if update_s (omega at om[0..1], device)
+void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int update_s, size_t n,
+                hipStream_t st);
 void vfinalize(const double* part, int nparts, int width, double* dst, int dst_stride, hipStream_t st);
 void mr_coef(const double* d, double* omega, hipStream_t st);
+// a[i] += b[i], i < n (device scalars)
+void vadd_dev(double* a, const double* b, int n, hipStream_t st);
 // least squares min || beta e_1 - H y || for the (m+1) x m Hessenberg matrix with upper part H
 // (column-major, ldh, complex) and subdiagonal sqrt(sub2[j])
 void hess_lsq(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y,
