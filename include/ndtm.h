@@ -159,7 +159,12 @@ typedef struct {
                           rest go to the multigrid; >= number of shifts means
                           plain MMS-CG for all */
   int guess;           /* NDTM_GUESS_* for the multigrid shifts */
-  int precision;       /* NDTM_PREC_F64, or NDTM_PREC_F32/F16 for the mixed form */
+  int precision;       /* NDTM_PREC_F64: FP64 throughout.  NDTM_PREC_F16: mixed form, the
+                          multi-shift CG runs on FP16 stencil storage (one FP32 scale per
+                          site, FP32 arithmetic) with FP32 Krylov vectors and FP64 scalar
+                          recurrences, then each shift is refined by FP64 defect correction
+                          (FP64 true residual and solution, mixed-precision inner CG).
+                          Other values select the FP64 form. */
   int poll_every;      /* MMS-CG iterations between host convergence polls */
   double mg_tol;       /* cap on the relative residual of each single (Q +- i m) solve; each
                           round tightens it so that the squared system meets tol */
@@ -198,6 +203,45 @@ typedef struct {
  * EBREAKDOWN on non-finite input or a Krylov breakdown. */
 int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
                const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
+
+/* ---- learned initial-guess proposer ------------------------------------ */
+/* A 3-layer tanh network (59 -> 64 -> 64 -> 11) proposes the correction y to the
+ * Lagrange coefficients over the converged solutions, c = l + tau y with
+ * tau = ||r_L|| / ||b|| (r_L the Lagrange guess's residual), a generalisation of
+ * the interpolated guesses of section 4.2.  Its relative loss
+ * L = 1 + 2 h.y + y.G.y is exact from the Gram form of appendix B (see
+ * ndtm_mlp_sample).  Weights: NDTM_MLP_NPARAM floats, W1 (64x59), b1, W2 (64x64),
+ * b2, W3 (11x64), b3, row-major; FP32 for training, a BF16 copy for inference.
+ * All arrays of these calls are host memory; the calls synchronise the device. */
+#define NDTM_MLP_NFEAT 59
+#define NDTM_MLP_KMAX 11
+#define NDTM_MLP_NPARAM 8715
+/* Loads weights and resets the Adam state (initial or trained weights). */
+int ndtm_mlp_set_weights(ndtm_ctx* ctx, const float* w, size_t n);
+int ndtm_mlp_get_weights(ndtm_ctx* ctx, float* w, size_t n);
+/* Outputs y (B x 11) for features (B x 59); bf16 != 0 uses the BF16 inference
+ * kernel, else the FP32 one, which also returns the per-sample loss when mask,
+ * G (B x 11 x 11) and h (B x 11) are given (NULL = zeros). */
+int ndtm_mlp_forward(ndtm_ctx* ctx, int B, const float* feat, const float* mask, const float* G, const float* h,
+                     int bf16, float* y, float* loss);
+/* Gradient of the batch-mean loss w.r.t. the flat parameters, and the mean loss. */
+int ndtm_mlp_grad(ndtm_ctx* ctx, int B, const float* feat, const float* mask, const float* G, const float* h,
+                  float* grad, float* mean_loss);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) on the device;
+ * loss_hist (optional, steps floats) receives the mean loss before each step. */
+int ndtm_mlp_train(ndtm_ctx* ctx, int B, const float* feat, const float* mask, const float* G, const float* h,
+                   int steps, float lr, float* loss_hist);
+/* One training sample from solved vectors: x_dev[0..K) are the converged
+ * solutions (odd-site canonical, device) of the shifts nodes[0..K), descending
+ * and all above sig_t; b_dev the right-hand side (same layout).  Computes x_L, r_L = b - (Q^2 + sig_t) x_L, the Gram
+ * matrix of [b, x_1..x_K] and the overlaps with r_L on the GPU, then the
+ * features (59), mask (11), G (11 x 11) and h (11) in slot order (slot 0 = the
+ * nearest node).  The solver's node selection applies first: the farthest
+ * nodes are dropped while the Lebesgue constant of the Lagrange coefficients
+ * exceeds 4, and the sample covers nodes[first..K).  info (optional, 4 doubles):
+ * [tau, ||r_L||^2, ||b||^2, first]. */
+int ndtm_mlp_sample(ndtm_ctx* ctx, int K, void* const* x_dev, const double* nodes, double sig_t, const void* b_dev,
+                    float* feat, float* mask, float* G, float* h, double* info, void* stream);
 
 /* Kernel timing.  When enabled, every launch of the kernel classes below made
  * by later calls is bracketed by HIP events on its stream, and its algorithmic

@@ -1,23 +1,26 @@
 """FP64 reference of the learned initial-guess proposer.
 
 The paper builds the guess for the next shifted system as a Lagrange
-interpolation of the converged solutions, x_t = sum_i l_i(sigma_t) x_i
-(section 4.2), and appendix B shows that its residual is the same
-combination of w_i = r_i - b + (sigma_i - sigma_t) x_i added to b:
-r_t = b + sum_i c_i w_i for any real coefficients c.  The learned form keeps
-that structure and lets a small network propose a correction dc to the
-Lagrange coefficients, c = l(sigma_t) + dc, so the proposal is still a mix of
-converged solutions.
+interpolation of the converged solutions, x_L = sum_i l_i(sigma_t) x_i
+(section 4.2), and appendix B shows that the residual of any combination of
+converged solutions is the same combination of w_i = r_i - b + (sigma_i -
+sigma_t) x_i added to b.  The learned form keeps that structure: a small
+network proposes a correction to the Lagrange coefficients, c = l + tau * y,
+tau = ||r_L|| / ||b||, so the proposal is still a mix of converged solutions
+and y is O(1).  With w_i = -b + (sigma_i - sigma_t) x_i (node residuals below
+the solver tolerance neglected) the exact relative loss is
+
+    L(y) = ||r_L + W tau y||^2 / ||r_L||^2 = 1 + 2 hh.y + y.Gh.y,
+    Gh_ij = Re<w_i, w_j> / ||b||^2,  hh_i = Re<w_i, r_L> / (||r_L|| ||b||),
+
+computed from the Gram matrix of [b, x_1..x_K], the vector r_L = b - (Q^2 +
+sigma_t) x_L and its overlaps with b and the x_i.  L = 1 is the Lagrange guess;
+the least-squares optimum over the span is 1 - hh.Gh^+.hh.
 
 Network: 3 dense layers, tanh after the first two, width 64:
-    h1 = tanh(W1 f + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3, dc = mask * y.
-Loss per sample (exact, from the Gram matrix of the w_i, relative to the
-Lagrange residual r_L = b + W l):
-    L(dc) = ||r_L + W dc||^2 / ||r_L||^2 = c0 + ||R dc + q||^2,
-with G = W^T W / ||r_L||^2 = V diag(lam) V^T, R = diag(sqrt(lam)) V^T,
-q = diag(1/sqrt(lam)) V^T h, h = W^T r_L / ||r_L||^2 (real parts),
-c0 = 1 - ||q||^2 (eigen-directions with lam <= 1e-12 lam_max are dropped).
-L = 1 at dc = 0 (Lagrange) and c0 is the least-squares optimum over the span.
+    h1 = tanh(W1 f + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3, masked to the
+    filled slots.  Trained in FP32 with Adam; inference stores weights and
+    activations in BF16 with FP32 accumulation.
 """
 from __future__ import annotations
 
@@ -26,8 +29,9 @@ import numpy as np
 WIDTH = 64
 K_MAX = 11
 N_FEAT_SLOT = 5
-N_FEAT_GLOBAL = 3
-N_FEAT = K_MAX * N_FEAT_SLOT + N_FEAT_GLOBAL  # 58
+N_FEAT_GLOBAL = 4
+N_FEAT = K_MAX * N_FEAT_SLOT + N_FEAT_GLOBAL  # 59
+N_PARAM = WIDTH * N_FEAT + WIDTH + WIDTH * WIDTH + WIDTH + K_MAX * WIDTH + K_MAX
 
 
 def init_params(seed, n_in=N_FEAT, width=WIDTH, n_out=K_MAX, out_scale=1e-3):
@@ -48,13 +52,13 @@ def forward(p, F):
     return y, (F, h1, h2)
 
 
-def loss(y, mask, R, q, c0):
-    """Mean over the batch of c0 + ||R (mask*y) + q||^2; returns (loss, dL/dy)."""
-    dc = mask * y
-    u = np.einsum("bij,bj->bi", R, dc) + q
-    L = c0 + np.einsum("bi,bi->b", u, u)
+def loss(y, mask, G, h):
+    """Mean over the batch of 1 + 2 h.(m*y) + (m*y).G.(m*y); returns (loss, dL/dy, per-sample L)."""
+    ym = mask * y
+    u = h + np.einsum("bij,bj->bi", G, ym)
+    L = 1.0 + np.einsum("bi,bi->b", 2.0 * h + np.einsum("bij,bj->bi", G, ym), ym)
     B = y.shape[0]
-    dy = mask * (2.0 * np.einsum("bij,bi->bj", R, u)) / B
+    dy = mask * (2.0 * u) / B
     return float(L.mean()), dy, L
 
 
@@ -89,35 +93,124 @@ def adam_step(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p
 
 
-def w_gram(M, K, sig_nodes, sig_t):
-    """Gram of w_i = r_i - b + (sigma_i - sigma_t) x_i from the Gram M of the vector set
-    [b, x_1..x_K, r_1..r_K] (Hermitian, complex).  Returns (Gw (K,K) real, gb (K,) real, bb)."""
-    n = 1 + 2 * K
-    assert M.shape == (n, n)
-    # coefficient matrix expressing w_i in the basis [b, x, r]
-    C = np.zeros((K, n))
-    for i in range(K):
-        C[i, 0] = -1.0
-        C[i, 1 + i] = sig_nodes[i] - sig_t
-        C[i, 1 + K + i] = 1.0
-    Gw = (C @ M @ C.T).real
-    gb = (M[0, :] @ C.T).real  # <b, w_i>
+def bf16_round(x):
+    """Round to bfloat16 (8 significant bits, round to nearest, ties to even), returned as float64.
+
+    bfloat16 is the upper half of an IEEE binary32: the value is first rounded to
+    binary32, then its low 16 bits are rounded away.
+    """
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF
+    hi = u >> 16
+    up = (low > 0x8000) | ((low == 0x8000) & ((hi & 1) == 1))
+    hi = hi + up.astype(np.uint64)
+    return (hi << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(p, F):
+    """Inference as the BF16 form defines it: weights, inputs and the two hidden
+    activations rounded to bfloat16, sums and tanh exact (FP64 here)."""
+    q = {k: bf16_round(v) for k, v in p.items()}
+    h1 = bf16_round(np.tanh(bf16_round(F) @ q["W1"].T + q["b1"]))
+    h2 = bf16_round(np.tanh(h1 @ q["W2"].T + q["b2"]))
+    return h2 @ q["W3"].T + q["b3"]
+
+
+def flatten(p):
+    """Parameter dict -> flat vector in the order W1, b1, W2, b2, W3, b3 (row-major)."""
+    return np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def unflatten(v, n_in=N_FEAT, width=WIDTH, n_out=K_MAX):
+    shapes = (("W1", (width, n_in)), ("b1", (width,)), ("W2", (width, width)), ("b2", (width,)),
+              ("W3", (n_out, width)), ("b3", (n_out,)))
+    out, o = {}, 0
+    for k, sh in shapes:
+        n = int(np.prod(sh))
+        out[k] = np.asarray(v[o:o + n], dtype=np.float64).reshape(sh)
+        o += n
+    return out
+
+
+# ---- sample preparation: features and loss form for one target shift ----------
+#
+# Nodes are the converged shifts sigma_1 > ... > sigma_K (K <= K_MAX) with
+# solutions x_i; the target is sigma_t < sigma_K.  Slots are filled from the
+# nearest node outwards (slot 0 = sigma_K, the last solved), so a slot means the
+# same thing for every K.
+#
+# Per slot j (node i): [log10(sigma_i/sigma_t)/5, l_i/gamma, |x_i|/|x_K|,
+#                       log10(max(1 - cos(x_i, x_K), 1e-12))/12, 1]
+# Global: [log10(sigma_t)/5, K/K_MAX, log10(gamma), log10(||r_L||/||b||)/10],
+# gamma = sum |l_i|.
+
+def sample(M, hv, rL2, nodes, sig_t):
+    """Features, mask, Gh, hh (slot order), the slot of each node, l and tau.
+
+    M: Gram of [b, x_1..x_K] (complex, (K+1)^2); hv: [<b, r_L>, <x_1, r_L>, ..]
+    (complex, K+1); rL2 = ||r_L||^2.
+    """
+    from .solvers import lagrange_coefficients
+
+    nodes = np.asarray(nodes, dtype=np.float64)
+    K = len(nodes)
+    lag = lagrange_coefficients(nodes, sig_t)
+    gamma = float(np.abs(lag).sum())
     bb = float(M[0, 0].real)
-    return Gw, gb, bb
+    tau = np.sqrt(rL2 / bb)
+    G = M.real
+    nx = np.sqrt(np.maximum(np.diag(G)[1:], 0.0))
+    near = K - 1
+    f = np.zeros(N_FEAT)
+    mask = np.zeros(K_MAX)
+    slot = np.zeros(K, dtype=int)
+    d = nodes - sig_t
+    for i in range(K):
+        j = near - i
+        slot[i] = j
+        cosv = G[1 + i, 1 + near] / (nx[i] * nx[near])
+        f[j * N_FEAT_SLOT + 0] = np.log10(nodes[i] / sig_t) / 5.0
+        f[j * N_FEAT_SLOT + 1] = lag[i] / gamma
+        f[j * N_FEAT_SLOT + 2] = nx[i] / nx[near]
+        f[j * N_FEAT_SLOT + 3] = np.log10(max(1.0 - cosv, 1e-12)) / 12.0
+        f[j * N_FEAT_SLOT + 4] = 1.0
+        mask[j] = 1.0
+    g0 = K_MAX * N_FEAT_SLOT
+    f[g0 + 0] = np.log10(sig_t) / 5.0
+    f[g0 + 1] = K / K_MAX
+    f[g0 + 2] = np.log10(gamma)
+    f[g0 + 3] = np.log10(tau) / 10.0
+    # w_i = -b + d_i x_i
+    Gw = np.zeros((K, K))
+    hw = np.zeros(K)
+    for i in range(K):
+        hw[i] = (-hv[0] + d[i] * hv[1 + i]).real
+        for j in range(K):
+            Gw[i, j] = (M[0, 0] - d[j] * M[0, 1 + j] - d[i] * M[1 + i, 0] + d[i] * d[j] * M[1 + i, 1 + j]).real
+    Gs = np.zeros((K_MAX, K_MAX))
+    hs = np.zeros(K_MAX)
+    Gs[np.ix_(slot, slot)] = Gw / bb
+    hs[slot] = hw / np.sqrt(rL2 * bb)
+    return f, mask, Gs, hs, slot, lag, tau
 
 
-def quad_form(Gw, gb, bb, lag, drop=1e-12):
-    """(R, q, c0, rL2) of the loss above from the w-Gram and the Lagrange coefficients."""
-    K = len(lag)
-    rL2 = bb + 2.0 * gb @ lag + lag @ Gw @ lag
-    h = (gb + Gw @ lag) / rL2
-    G = Gw / rL2
-    lam, Vm = np.linalg.eigh(G)
-    keep = lam > drop * max(lam.max(), 0.0)
-    R = np.zeros((K, K))
-    q = np.zeros(K)
-    nk = int(keep.sum())
-    R[:nk] = (np.sqrt(lam[keep])[:, None] * Vm[:, keep].T)
-    q[:nk] = (Vm[:, keep].T @ h) / np.sqrt(lam[keep])
-    c0 = 1.0 - float(q @ q)
-    return R, q, c0, rL2
+def ls_optimum(Gs, hs, mask):
+    """Least-squares optimum of the loss over the span: returns (L*, y*)."""
+    idx = np.nonzero(mask)[0]
+    G = Gs[np.ix_(idx, idx)]
+    h = hs[idx]
+    y, *_ = np.linalg.lstsq(G, -h, rcond=1e-13)
+    yf = np.zeros(K_MAX)
+    yf[idx] = y
+    return float(1.0 + 2.0 * h @ y + y @ G @ y), yf
+
+
+def gram_of(vectors):
+    """Gram matrix <v_i, v_j> of a list of arrays (complex)."""
+    V = [np.asarray(v).reshape(-1) for v in vectors]
+    n = len(V)
+    M = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        for j in range(n):
+            M[i, j] = np.vdot(V[i], V[j])
+    return M

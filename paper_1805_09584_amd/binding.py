@@ -4,6 +4,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -17,6 +18,7 @@ NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP = 0, 1, 2
 PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
                 "coarse")
 MAX_SHIFTS = 16
+MLP_NFEAT, MLP_KMAX, MLP_NPARAM = 59, 11, 8715
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOCONV", -4: "EBREAKDOWN", -5: "ESTATE",
            -6: "EHIP"}
@@ -79,6 +81,7 @@ def load_library():
                            "python paper_1805_09584_amd/build.py")
     lib = C.CDLL(path)
     vp, i, d = C.c_void_p, C.c_int, C.c_double
+    fp = C.POINTER(C.c_float)
     sig = {
         "ndtm_create": (i, [C.POINTER(C.c_int), i, i, C.POINTER(vp)]),
         "ndtm_destroy": (None, [vp]),
@@ -97,6 +100,13 @@ def load_library():
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
+        "ndtm_mlp_set_weights": (i, [vp, fp, C.c_size_t]),
+        "ndtm_mlp_get_weights": (i, [vp, fp, C.c_size_t]),
+        "ndtm_mlp_forward": (i, [vp, i, fp, fp, fp, fp, i, fp, fp]),
+        "ndtm_mlp_grad": (i, [vp, i, fp, fp, fp, fp, fp, fp]),
+        "ndtm_mlp_train": (i, [vp, i, fp, fp, fp, fp, i, C.c_float, fp]),
+        "ndtm_mlp_sample": (i, [vp, i, C.POINTER(vp), C.POINTER(C.c_double), d, vp, fp, fp, fp, fp,
+                                C.POINTER(C.c_double), vp]),
         "ndtm_profile_enable": (i, [vp, i]),
         "ndtm_profile_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_double), i]),
@@ -107,6 +117,10 @@ def load_library():
         f.argtypes = args
     _LIB = lib
     return lib
+
+
+def _fp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_float))
 
 
 def _stream():
@@ -235,6 +249,53 @@ class Context:
         d = rep.to_dict()
         d["rc"] = rc
         return xs, d
+
+    # -- learned guess proposer -----------------------------------------------
+    def ndtm_mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._check(self.lib.ndtm_mlp_set_weights(self.h, _fp(w), w.size))
+
+    def ndtm_mlp_get_weights(self):
+        w = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(self.lib.ndtm_mlp_get_weights(self.h, _fp(w), w.size))
+        return w
+
+    def ndtm_mlp_forward(self, feat, mask=None, G=None, h=None, bf16=False):
+        feat = np.ascontiguousarray(feat, dtype=np.float32)
+        B = feat.shape[0]
+        y = np.zeros((B, MLP_KMAX), dtype=np.float32)
+        loss = np.zeros(B, dtype=np.float32)
+        arr = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in (mask, G, h)]
+        self._check(self.lib.ndtm_mlp_forward(self.h, B, _fp(feat), *[_fp(a) for a in arr], 1 if bf16 else 0,
+                                              _fp(y), _fp(loss)))
+        return y, loss
+
+    def ndtm_mlp_grad(self, feat, mask, G, h):
+        arr = [np.ascontiguousarray(a, dtype=np.float32) for a in (feat, mask, G, h)]
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        m = np.zeros(1, dtype=np.float32)
+        self._check(self.lib.ndtm_mlp_grad(self.h, arr[0].shape[0], *[_fp(a) for a in arr], _fp(g), _fp(m)))
+        return g, float(m[0])
+
+    def ndtm_mlp_train(self, feat, mask, G, h, steps, lr):
+        arr = [np.ascontiguousarray(a, dtype=np.float32) for a in (feat, mask, G, h)]
+        hist = np.zeros(steps, dtype=np.float32)
+        self._check(self.lib.ndtm_mlp_train(self.h, arr[0].shape[0], *[_fp(a) for a in arr], steps, float(lr),
+                                            _fp(hist)))
+        return hist
+
+    def ndtm_mlp_sample(self, xs, nodes, sig_t, b):
+        K = len(xs)
+        ptrs = (C.c_void_p * K)(*[x.data_ptr() for x in xs])
+        nd_ = (C.c_double * K)(*[float(s) for s in nodes])
+        feat = np.zeros(MLP_NFEAT, dtype=np.float32)
+        mask = np.zeros(MLP_KMAX, dtype=np.float32)
+        G = np.zeros((MLP_KMAX, MLP_KMAX), dtype=np.float32)
+        h = np.zeros(MLP_KMAX, dtype=np.float32)
+        info = (C.c_double * 4)()
+        self._check(self.lib.ndtm_mlp_sample(self.h, K, ptrs, nd_, float(sig_t), _ptr(b), _fp(feat), _fp(mask),
+                                             _fp(G), _fp(h), info, _stream()))
+        return feat, mask, G, h, list(info)
 
     # -- profiling --------------------------------------------------------------
     def ndtm_profile_enable(self, on=True):

@@ -303,6 +303,73 @@ __global__ void mms_seed_k(double* S, const double* src) {
   }
 }
 
+// ---------------- MMS-CG, mixed form ----------------
+// Krylov vectors in FP32 half-field layout [24][stride]; the stencil runs on
+// FP16 copies with one FP32 scale per site (w16 produced by the stencil, p16
+// written here).  All scalars stay FP64 in S.
+struct ShiftPtrs32 {
+  float2* x[kMaxShifts];
+  float2* p[kMaxShifts];
+};
+
+__global__ void mms_update_r_mx_k(float2* r, const __half2* w16, const float* wsc, const double* S, int vh,
+                                  int stride, double* partials) {
+  const double alpha = S[MS_ALPHA];
+  double acc = 0;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < vh; h += gridDim.x * blockDim.x) {
+    const double sc = wsc[h];
+    for (int c = 0; c < 24; ++c) {
+      const size_t i = (size_t)c * stride + h;
+      const float2 w = __half22float2(w16[i]);
+      float2 v = r[i];
+      v.x = (float)((double)v.x - alpha * sc * (double)w.x);
+      v.y = (float)((double)v.y - alpha * sc * (double)w.y);
+      r[i] = v;
+      acc += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ void mms_update_p_mx_k(const float2* r, float2* p, __half2* p16, float* p16sc, ShiftPtrs32 P, int nsh,
+                                  const double* S, int vh, int stride) {
+  const double beta = S[MS_BETA];
+  const bool any_before = S[MS_ALPHA] != 0.0;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < vh; h += gridDim.x * blockDim.x) {
+    float2 pn[24];
+    float mx = 0.f;
+    for (int c = 0; c < 24; ++c) {
+      const size_t i = (size_t)c * stride + h;
+      const float2 ri = r[i];
+      for (int s = 0; s < nsh; ++s) {
+        if (S[MS_ACT + s] == 0.0) continue;
+        const double as = S[MS_ALPHA_S + s], bs = S[MS_BETA_S + s], z = S[MS_ZETA + s];
+        float2 ps = P.p[s][i];
+        float2 xs = P.x[s][i];
+        xs.x = (float)(xs.x + as * ps.x);
+        xs.y = (float)(xs.y + as * ps.y);
+        ps.x = (float)(z * ri.x + bs * ps.x);
+        ps.y = (float)(z * ri.y + bs * ps.y);
+        P.x[s][i] = xs;
+        P.p[s][i] = ps;
+      }
+      float2 pv = p[i];
+      if (any_before) {
+        pv.x = (float)(ri.x + beta * pv.x);
+        pv.y = (float)(ri.y + beta * pv.y);
+        p[i] = pv;
+      }
+      pn[c] = pv;
+      mx = fmaxf(mx, fmaxf(fabsf(pv.x), fabsf(pv.y)));
+    }
+    const float inv = mx > 0.f ? 1.0f / mx : 0.f;
+    for (int c = 0; c < 24; ++c)
+      p16[(size_t)c * stride + h] = __floats2half2_rn(pn[c].x * inv, pn[c].y * inv);
+    p16sc[h] = mx;
+  }
+}
+
 }  // namespace
 
 void blas_zero(void* p, size_t bytes, hipStream_t st) {
@@ -388,14 +455,20 @@ void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps
   }
   hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, S, n);
 }
-void mms_init(double* S, int nsh, const double* deltas_host, double tol, hipStream_t st) {
-  (void)S;
-  (void)nsh;
-  (void)deltas_host;
-  (void)tol;
-  (void)st;
-}
 int red_grid(size_t n) { return (int)grid_for(n); }
+void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
+                     double* partials, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_r_mx_k, dim3(nblk), dim3(256), 0, st, r, w16, wsc, S, vh, stride, partials);
+}
+void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
+                     int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st) {
+  ShiftPtrs32 P;
+  for (int s = 0; s < nsh; ++s) {
+    P.x[s] = xs[s];
+    P.p[s] = ps[s];
+  }
+  hipLaunchKernelGGL(mms_update_p_mx_k, dim3(nblk), dim3(256), 0, st, r, p, p16, p16sc, P, nsh, S, vh, stride);
+}
 void mms_seed(double* S, const double* src, hipStream_t st) {
   hipLaunchKernelGGL(mms_seed_k, dim3(1), dim3(64), 0, st, S, src);
 }

@@ -344,6 +344,22 @@ static std::vector<double> lagrange(const std::vector<double>& nodes, double t) 
   return c;
 }
 
+// First node used for the guess of sig_t from the descending nodes: the
+// farthest nodes are dropped while the Lebesgue constant sum |l_i| exceeds 4,
+// which bounds the growth of the node residuals in the guess (appendix B).
+int guess_first_node(const std::vector<double>& nodes, double sig_t) {
+  const int t = (int)nodes.size();
+  int first = 0;
+  for (;;) {
+    if (t - first <= 1) return first;
+    std::vector<double> sub(nodes.begin() + first, nodes.end());
+    double s = 0;
+    for (double v : lagrange(sub, sig_t)) s += std::fabs(v);
+    if (s <= 4.0) return first;
+    ++first;
+  }
+}
+
 int guess_mlp(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, int K, double sig_t,
               const HalfField& b, const std::vector<double>& lag, std::vector<double>* coef, double* pred_mlp,
               double* pred_lag, hipStream_t st);
@@ -359,20 +375,9 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
   for (int t = n_mms; t < nsh; ++t) {
     auto tg0 = std::chrono::steady_clock::now();
     // ---- initial guess from the converged solutions (descending shifts) ----
-    std::vector<double> nodes(sig.begin(), sig.begin() + t);
+    const int first = guess_first_node(std::vector<double>(sig.begin(), sig.begin() + t), sig[t]);
+    std::vector<double> nodes(sig.begin() + first, sig.begin() + t);
     std::vector<double> lag = lagrange(nodes, sig[t]);
-    int first = 0;
-    auto lebesgue = [&](const std::vector<double>& l) {
-      double s = 0;
-      for (double v : l) s += std::fabs(v);
-      return s;
-    };
-    // keep the Lebesgue constant moderate by dropping the farthest nodes (appendix B)
-    while (t - first > 1 && lebesgue(lag) > 4.0) {
-      ++first;
-      nodes.assign(sig.begin() + first, sig.begin() + t);
-      lag = lagrange(nodes, sig[t]);
-    }
     const int K = t - first;
     std::vector<double> coef = lag;
     rep->guess_kind[t] = p->guess;

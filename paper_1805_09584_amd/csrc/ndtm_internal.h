@@ -110,7 +110,11 @@ void mms_update_r(double2* r, const double2* w, const double* S, size_t n, doubl
 void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st);
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh,
                   const double* S, size_t n, hipStream_t st);
-void mms_init(double* S, int nsh, const double* deltas_host, double tol, hipStream_t st);
+// mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
+void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
+                     double* partials, int nblk, hipStream_t st);
+void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
+                     int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st);
 // Layout of the scalar block S (doubles).
 enum MmsIdx {
   MS_RR = 0, MS_PW, MS_ALPHA, MS_ALPHA_PREV, MS_BETA, MS_BB, MS_TOL2, MS_IT, MS_NSH, MS_DONE,

@@ -18,6 +18,7 @@
 #include <numeric>
 
 #include "ctx.h"
+#include "vec.h"
 
 namespace ndtm {
 
@@ -103,6 +104,87 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   return done ? NDTM_OK : NDTM_ENOCONV;
 }
 
+// Mixed form of the same iteration: Krylov vectors in FP32, the stencil on
+// FP16 copies (per-site scale, FP32 arithmetic), every scalar recurrence in
+// FP64 on the device.  Solves (Q^2 + sigma_s) x_s = b for FP32 fields x_s, b.
+int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
+                    const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res, hipStream_t st) {
+  const int nsh = (int)sigmas.size();
+  const size_t n = half_elems(c);
+  const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
+  HalfField r = half_field(c, "mx_r", P32), p = half_field(c, "mx_p", P32);
+  HalfField p16 = half_field(c, "mx_p16", P16), w16 = half_field(c, "mx_w16", P16), u16 = half_field(c, "mx_u16", P16),
+            te16 = half_field(c, "mx_te16", P16);
+  std::vector<float2*> ps(nsh), xv(nsh);
+  for (int s = 0; s < nsh; ++s) {
+    HalfField f = half_field(c, "mx_ps" + std::to_string(s), P32);
+    if (!f.v) return fail(c, NDTM_ENOMEM, "mixed mmscg: workspace");
+    ps[s] = static_cast<float2*>(f.v);
+    xv[s] = static_cast<float2*>(xs[s].v);
+  }
+  if (!r.v || !p.v || !p16.v || !w16.v || !u16.v || !te16.v) return fail(c, NDTM_ENOMEM, "mixed mmscg: workspace");
+  vconvert(P32, r.v, P32, b.v, n, st);
+  vconvert(P32, p.v, P32, b.v, n, st);
+  launch_convert_half(c->g, b, p16, st);
+  for (int s = 0; s < nsh; ++s) {
+    vconvert(P32, ps[s], P32, b.v, n, st);
+    vzero(P32, xv[s], n, st);
+  }
+  std::vector<double> S(MS_SIZE, 0.0);
+  S[MS_ALPHA_PREV] = 1.0;
+  S[MS_TOL2] = tol * tol;
+  S[MS_NSH] = nsh;
+  for (int s = 0; s < nsh; ++s) {
+    S[MS_ZETA + s] = S[MS_ZETA_PREV + s] = 1.0;
+    S[MS_DELTA + s] = sigmas[s] - sig_base;
+    S[MS_ACT_NEXT + s] = 1.0;
+  }
+  NDTM_HIP(c, hipMemcpyAsync(c->mms_S, S.data(), MS_SIZE * sizeof(double), hipMemcpyHostToDevice, st));
+  vnorm2(P32, b.v, n, c->vred, c->dscal, st);
+  mms_seed(c->mms_S, c->dscal, st);
+  const int hg = hop_grid(c->g);
+  const int nb = std::min(1024, (c->g.vh + 255) / 256);
+  int it = 0;
+  if (poll_every < 1) poll_every = 1;
+  while (it < maxiter) {
+    apply_qhat2(c, P16, w16, p16, u16, te16, sig_base, c->partials, st);
+    mms_scal1(c->mms_S, c->partials, hg, st);
+    {
+      ProfScope pr(c, NDTM_PROF_MMS_RESID, (192.0 * 2 + 100.0) * c->g.vh, st);
+      mms_update_r_mx((float2*)r.v, (const __half2*)w16.v, w16.sc, c->mms_S, c->g.vh, c->g.stride, c->partials, nb,
+                      st);
+    }
+    mms_scal2(c->mms_S, c->partials, nb, st);
+    {
+      ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
+      mms_update_p_mx((const float2*)r.v, (float2*)p.v, (__half2*)p16.v, p16.sc, xv.data(), ps.data(), nsh, c->mms_S,
+                      c->g.vh, c->g.stride, nb, st);
+    }
+    ++it;
+    if (it % poll_every == 0 || it == maxiter) {
+      NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S + MS_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
+      NDTM_HIP(c, hipStreamSynchronize(st));
+      if (c->hscal[0] != 0.0) break;
+    }
+  }
+  NDTM_HIP(c, hipGetLastError());
+  NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
+  NDTM_HIP(c, hipStreamSynchronize(st));
+  res->iterations = (int)c->hscal[MS_IT];
+  res->breakdown = c->hscal[MS_BREAK] != 0.0;
+  res->iters.resize(nsh);
+  for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
+  const bool done = c->hscal[MS_DONE] != 0.0;
+  if ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1) {
+    // r (read), p (read, written) and its FP16 copy (written), x_s and p_s (read, written) in FP32
+    double active_launches = 0;
+    for (int s = 0; s < nsh; ++s) active_launches += res->iters[s];
+    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += ((3.0 * 192.0 + 100.0) * it + 4.0 * 192.0 * active_launches) * c->g.vh;
+  }
+  if (res->breakdown) return fail(c, NDTM_EBREAKDOWN, "mixed mmscg: breakdown (non-finite or p.Ap <= 0)");
+  return done ? NDTM_OK : NDTM_ENOCONV;
+}
+
 double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, const HalfField& r,
                      hipStream_t st) {
   const size_t n = half_elems(c);
@@ -136,6 +218,45 @@ static int polish_cg(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
   *res_out = res;
   *iters_out = total;
   return res <= tol ? NDTM_OK : NDTM_ENOCONV;
+}
+
+// FP64 defect correction of one shift with the mixed-precision CG as the inner
+// solver: r = b - (Q^2+sigma) x in FP64, e ~ (Q^2+sigma)^-1 r in the mixed form,
+// x += e in FP64, until the true residual meets tol.  Falls back to the FP64
+// polish when a round gains less than a factor 4.
+static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
+                        double* res_out, int* iters_out, int* rounds_out, hipStream_t st) {
+  const size_t n = half_elems(c);
+  HalfField r = half_field(c, "rf_r", P64), r32 = half_field(c, "rf_r32", P32), e32 = half_field(c, "rf_e32", P32),
+            e64 = half_field(c, "rf_e64", P64);
+  if (!r.v || !r32.v || !e32.v || !e64.v) return fail(c, NDTM_ENOMEM, "refine: workspace");
+  double res = true_residual(c, x, b, sigma, r, st);
+  int total = 0, rounds = 0;
+  while (res > tol && rounds < 12) {
+    vconvert(P32, r32.v, P64, r.v, n, st);
+    MmsResult mr;
+    std::vector<HalfField> es{e32};
+    const double inner = std::max(1e-4, std::min(0.5, 0.5 * tol / res));
+    int rc = run_mmscg_mixed(c, {sigma}, es, r32, inner, maxiter, 8, &mr, st);
+    total += mr.iterations;
+    ++rounds;
+    if (rc == NDTM_EBREAKDOWN) break;
+    vconvert(P64, e64.v, P32, e32.v, n, st);
+    blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e64.v, n, st);
+    const double prev = res;
+    res = true_residual(c, x, b, sigma, r, st);
+    if (!(res < 0.25 * prev)) break;
+  }
+  int rc = NDTM_OK;
+  if (res > tol) {
+    int extra = 0;
+    rc = polish_cg(c, x, b, sigma, tol, maxiter, &res, &extra, st);
+    total += extra;
+  }
+  *res_out = res;
+  *iters_out = total;
+  *rounds_out = rounds;
+  return res <= tol ? NDTM_OK : rc;
 }
 
 // The hybrid part (multigrid shifts) lives in mg.cpp.
@@ -212,7 +333,35 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   const int n_mms = std::max(1, std::min(p->n_mmscg, nsh));
   int status = NDTM_OK;
   // ---- MMS-CG for the n_mms largest shifts ----
-  {
+  if (p->precision == NDTM_PREC_F16) {
+    // mixed form: multi-shift CG on FP16 stencil storage, then FP64 defect correction per shift
+    std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
+    std::vector<HalfField> x32(n_mms);
+    for (int i = 0; i < n_mms; ++i) {
+      x32[i] = half_field(c, "sv_x32_" + std::to_string(i), P32);
+      if (!x32[i].v) return fail(c, NDTM_ENOMEM, "solve: workspace");
+    }
+    HalfField B32 = half_field(c, "sv_b32", P32);
+    vconvert(P32, B32.v, P64, B.v, n, st);
+    MmsResult mr;
+    int rc = run_mmscg_mixed(c, s_mms, x32, B32, std::max(p->tol, 1e-5), p->maxiter, p->poll_every, &mr, st);
+    rep->mms_iterations = mr.iterations;
+    if (rc == NDTM_EBREAKDOWN) {
+      rep->status = rc;
+      return rc;
+    }
+    for (int i = 0; i < n_mms; ++i) {
+      vconvert(P64, xs[i].v, P32, x32[i].v, n, st);
+      double res = 0;
+      int extra = 0, rounds = 0;
+      int prc = refine_mixed(c, xs[i], B, sig[i], p->tol, p->maxiter, &res, &extra, &rounds, st);
+      rep->method[i] = 0;
+      rep->iterations[i] = mr.iters[i] + extra;
+      rep->rounds[i] = rounds;
+      rep->true_res[i] = res;
+      if (prc != NDTM_OK) status = prc;
+    }
+  } else {
     std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
     std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms);
     MmsResult mr;

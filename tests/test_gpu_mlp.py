@@ -1,0 +1,211 @@
+"""Learned guess proposer on the GPU against the FP64 oracle.
+
+* FP32 forward (outputs, per-sample loss) and the batch gradient against the
+  oracle's forward, loss and manual backprop on a random batch;
+* one Adam step: parameters with a clear gradient move by lr*sign(g) (the
+  first bias-corrected Adam step), none moves by more than lr; a short training
+  run tracks the oracle's loss history;
+* BF16 inference against the oracle's BF16 forward (same rounding points);
+* sample preparation from solved vectors on the 4^4 config: features, mask,
+  G, h and tau against the oracle's sample() built from the oracle's own
+  solutions;
+* solve with the learned guess: a zero output layer reproduces the Lagrange
+  run bit for bit; a random net is rejected where its predicted residual is
+  worse; all shifts still meet the tolerance (residuals by the oracle).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp, solvers
+from oracle.lattice import Lattice, NDOperator, norm2, rel_residual
+from tests.gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1805_09584_amd as nd
+    return nd
+
+
+def _batch(B, seed):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((B, mlp.N_FEAT)) * 0.5
+    mask = np.zeros((B, mlp.K_MAX))
+    for s in range(B):
+        mask[s, : rng.integers(1, mlp.K_MAX + 1)] = 1.0
+    A = rng.standard_normal((B, mlp.K_MAX, mlp.K_MAX)) / np.sqrt(mlp.K_MAX)
+    G = np.einsum("bij,bkj->bik", A, A)
+    h = rng.standard_normal((B, mlp.K_MAX)) * 0.3
+    # values exactly representable in FP32 so both sides see the same inputs
+    return [np.float32(a).astype(np.float64) for a in (F, mask, G, h)]
+
+
+def _f32(p):
+    return {k: np.float32(v).astype(np.float64) for k, v in p.items()}
+
+
+def test_forward_and_gradient(nd):
+    print("mlp forward/grad B=37", flush=True)
+    ctx = nd.Context((4, 4, 4, 4))
+    p = _f32(mlp.init_params(7, out_scale=0.3))
+    F, mask, G, h = _batch(37, 1)
+    ctx.ndtm_mlp_set_weights(mlp.flatten(p))
+    assert np.array_equal(ctx.ndtm_mlp_get_weights(), np.float32(mlp.flatten(p)))
+    y, L = ctx.ndtm_mlp_forward(F, mask, G, h)
+    yw, cache = mlp.forward(p, F)
+    lw, dy, Lw = mlp.loss(yw, mask, G, h)
+    assert np.abs(y - yw).max() <= 1e-5 * np.abs(yw).max()
+    assert np.abs(L - Lw).max() <= 1e-5 * np.abs(Lw).max()
+    g, mean = ctx.ndtm_mlp_grad(F, mask, G, h)
+    gw = mlp.flatten(mlp.backward(p, cache, dy))
+    assert abs(mean - lw) <= 1e-5 * abs(lw)
+    assert np.abs(g - gw).max() <= 1e-4 * np.abs(gw).max()
+    # masked output slots get no gradient at all
+    dead = np.nonzero(mask.sum(axis=0) == 0)[0]
+    off_b3 = mlp.N_PARAM - mlp.K_MAX
+    for j in dead:
+        assert g[off_b3 + j] == 0.0
+    ctx.close()
+
+
+def test_adam_step_and_training(nd):
+    print("mlp adam/train B=64", flush=True)
+    ctx = nd.Context((4, 4, 4, 4))
+    p0 = _f32(mlp.init_params(8, out_scale=0.3))
+    F, mask, G, h = _batch(64, 2)
+    lr = 1e-3
+    ctx.ndtm_mlp_set_weights(mlp.flatten(p0))
+    hist = ctx.ndtm_mlp_train(F, mask, G, h, 1, lr)
+    w1 = ctx.ndtm_mlp_get_weights().astype(np.float64)
+    yw, cache = mlp.forward(p0, F)
+    l0, dy, _ = mlp.loss(yw, mask, G, h)
+    gw = mlp.flatten(mlp.backward(p0, cache, dy))
+    assert abs(hist[0] - l0) <= 1e-5 * abs(l0)
+    step = w1 - mlp.flatten(p0)
+    assert np.abs(step).max() <= lr * (1 + 1e-3) + 1e-7
+    clear = np.abs(gw) > 1e-3 * np.abs(gw).max()
+    assert np.allclose(step[clear], -lr * np.sign(gw[clear]), rtol=1e-3, atol=1e-7)
+    # 60 more steps on both sides
+    steps = 60
+    hist = ctx.ndtm_mlp_train(F, mask, G, h, steps, lr)
+    p, state = {k: v.copy() for k, v in p0.items()}, {}
+    want = []
+    for _ in range(steps + 1):
+        yw, cache = mlp.forward(p, F)
+        lw, dy, _ = mlp.loss(yw, mask, G, h)
+        want.append(lw)
+        p = mlp.adam_step(p, mlp.backward(p, cache, dy), state, lr)
+    want = np.array(want[1:])
+    print("loss gpu", hist[[0, -1]], "oracle", want[[0, -1]], flush=True)
+    assert np.abs(hist - want).max() <= 1e-3 * np.abs(want).max()
+    assert hist[-1] < hist[0]
+    ctx.close()
+
+
+def test_bf16_inference(nd):
+    print("mlp bf16 inference B=50", flush=True)
+    ctx = nd.Context((4, 4, 4, 4))
+    p = _f32(mlp.init_params(9, out_scale=0.3))
+    F, mask, G, h = _batch(50, 3)
+    ctx.ndtm_mlp_set_weights(mlp.flatten(p))
+    y16, _ = ctx.ndtm_mlp_forward(F, bf16=True)
+    want = mlp.forward_bf16(p, F)
+    y64, _ = mlp.forward(p, F)
+    scale = np.abs(y64).max()
+    # same rounding points: only FP32 accumulation and the odd flipped rounding of an activation differ
+    assert np.abs(y16 - want).max() <= 5e-3 * scale
+    # and the BF16 form stays within its own error budget of the FP32/FP64 output
+    assert np.abs(y16 - y64).max() <= 5e-2 * scale
+    ctx.close()
+
+
+def _c1_solutions():
+    c = synth.CONFIGS["c1"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    sig = np.array(c["shifts"])
+    xs = [solvers.cg(lambda v, s=s: op.Q_hat2(v, s), b, tol=1e-13)[0] for s in sig]
+    return dims, U, op, b, sig, xs
+
+
+def test_sample_preparation(nd):
+    print("mlp sample c1", flush=True)
+    dims, U, op, b, sig, xs = _c1_solutions()
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    xd = [dev(x) for x in xs]
+    for t in (5, 7, 9):
+        nodes = sig[:t]
+        f, mask, G, h, info = ctx.ndtm_mlp_sample(xd[:t], nodes, sig[t], dev(b))
+        first = int(info[3])
+        # the oracle's node selection: drop the farthest nodes while sum |l_i| > 4
+        f0 = 0
+        while t - f0 > 1 and np.abs(solvers.lagrange_coefficients(sig[f0:t], sig[t])).sum() > 4.0:
+            f0 += 1
+        assert first == f0
+        nodes = sig[first:t]
+        xk = xs[first:t]
+        lag = solvers.lagrange_coefficients(nodes, sig[t])
+        xL = sum(l * x for l, x in zip(lag, xk))
+        rL = b - op.Q_hat2(xL, sig[t])
+        M = mlp.gram_of([b] + xk)
+        hv = np.array([np.vdot(v, rL) for v in [b] + xk])
+        fw, mw, Gw, hw, slot, _, tau = mlp.sample(M, hv, norm2(rL), nodes, sig[t])
+        print("t", t, "first", first, "tau", info[0], tau, flush=True)
+        assert abs(info[0] - tau) <= 1e-8 * tau
+        assert np.array_equal(mask, mw)
+        assert np.abs(f - fw).max() <= 1e-5
+        assert np.abs(G - Gw).max() <= 1e-5 * np.abs(Gw).max()
+        assert np.abs(h - hw).max() <= 1e-4
+    ctx.close()
+
+
+def test_solve_with_learned_guess(nd):
+    print("mlp guess in hybrid solve c1", flush=True)
+    c = synth.CONFIGS["c1"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_shifts(list(c["shifts"]))
+    ctx.ndtm_mg_setup(ctx.mg_params(block=(2, 2, 2, 2), n_vec=8))
+    bd = dev(b)
+    xl, rl = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=1))
+    # zero output layer: y = 0, the proposal is the Lagrange guess itself
+    p = mlp.init_params(4, out_scale=0.0)
+    ctx.ndtm_mlp_set_weights(mlp.flatten(p))
+    xm, rm = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2))
+    print("lagrange", rl["guess_res"][7:], "mlp0", rm["guess_res"][7:], rm["guess_kind"][7:], flush=True)
+    assert rm["guess_kind"][7:] == [2, 2, 2]
+    assert rm["guess_res"][7:] == rl["guess_res"][7:]
+    assert rm["iterations"] == rl["iterations"]
+    for i in range(7, 10):
+        assert np.array_equal(host(xm[i]), host(xl[i]))
+    # a random net: whatever is chosen, the predicted residual of the chosen guess
+    # is no worse than Lagrange's, and every shift converges
+    ctx.ndtm_mlp_set_weights(mlp.flatten(mlp.init_params(5, out_scale=0.5)))
+    xr, rr = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2))
+    print("random net", rr["guess_kind"][7:], rr["mlp_res"][7:], rr["lagrange_res"][7:], rr["guess_res"][7:],
+          flush=True)
+    for t in range(7, 10):
+        if rr["guess_kind"][t] == 2:
+            assert rr["mlp_res"][t] <= rr["lagrange_res"][t]
+            # predicted (Gram form) and measured residual of the chosen guess agree
+            # (up to the node residuals, <= 1e-10 each, that the Gram form neglects)
+            assert abs(rr["guess_res"][t] - rr["mlp_res"][t]) <= 1e-3 * rr["guess_res"][t] + 2e-9
+        else:
+            assert rr["guess_kind"][t] == 1 and rr["guess_res"][t] == rl["guess_res"][t]
+    for i, s in enumerate(c["shifts"]):
+        assert rel_residual(op, host(xr[i]), b, s) <= 1e-10
+    ctx.close()
