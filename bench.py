@@ -3,13 +3,25 @@
 One step = one solve of all shifted systems (Q^2 + sigma_i) x_i = b for one
 synthetic right-hand side, to a true relative residual of 1e-10 per shift, on
 the 16^3x32 lattice with 12 shifts geometric in [1e-5, 1] (kappa = 0.1275,
-mubar = 0.1408, epsbar = 0.1521, links exp(0.3 i H)).  Inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+mubar = 0.1408, epsbar = 0.1521, links exp(0.3 i H)), by the hybrid solver:
+multi-shift CG for the 9 largest shifts, the two-level aggregation multigrid
+(case C, FGMRES, FP64 defect correction) for the 3 smallest from Lagrange
+guesses.  The multigrid setup (test vectors, prolongator, coarse operator) is
+done once before the timed region and reported separately, as it is reused
+across right-hand sides.  Inputs are resident in HBM before the timed region.
 
-Roofline: the dominant kernel class in the timed region is timed with HIP
-events on the launch stream; achieved GB/s = algorithmic bytes / summed kernel
-time.  cpu_baseline: the FP64 NumPy oracle timed on a bounded sample (a few
-multi-shift CG iterations) and extrapolated to the GPU's iteration count.
+Beside the headline (hybrid) the same K steps are timed for plain multi-shift
+CG over all 12 shifts (the speed-up reference), the mixed-precision form and,
+when trained weights are present, the learned-guess form.  A separate block
+times the even-odd stencil on a 32^3x64 lattice (the 16^3x32 field tiled 2x in
+every direction), where the working set is far above the 256 MB last-level
+cache.  Prints one JSON line.
+
+Roofline: kernel classes are timed with HIP events on the launch stream over
+the hybrid's timed region; the dominant class (largest summed time) gives
+achieved GB/s = its algorithmic bytes / its summed kernel time.
+cpu_baseline: the FP64 NumPy oracle timed on a bounded sample (a few
+multi-shift CG iterations on the same lattice) and scaled to one solve.
 """
 from __future__ import annotations
 
@@ -26,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "All-shift rational solve time at 1e-10 vs plain MMS-CG; Dslash HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+N_MMS = 9
 
 
 def parse():
@@ -34,9 +47,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--mode", default="plain", choices=["plain"])
+    ap.add_argument("--forms", default="hybrid,plain,mixed,learned",
+                    help="comma list; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dslash", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--dslash-reps", type=int, default=50)
     return ap.parse_args()
 
 
@@ -57,16 +73,99 @@ def cpu_baseline(cfg, U, b, gpu_iters, n_iter):
     per_iter = dt / n_iter
     est = per_iter * gpu_iters
     return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_iter} oracle multi-shift CG iterations on the same lattice "
-                      f"({per_iter:.2f} s each), extrapolated to the {gpu_iters} iterations of the "
-                      f"plain multi-shift CG solve ({est:.0f} s per solve)"}
+            "sample": f"{n_iter} oracle multi-shift CG iterations on the same lattice and shifts "
+                      f"({per_iter:.2f} s each), scaled to the {gpu_iters} iterations the plain "
+                      f"multi-shift CG takes for the whole solve ({est:.0f} s per solve)"}
+
+
+def form_params(ctx, nd, form):
+    if form == "plain":
+        return ctx.solve_params(tol=1e-10)
+    if form == "hybrid":
+        return ctx.solve_params(tol=1e-10, n_mmscg=N_MMS, guess=nd.NDTM_GUESS_LAGRANGE)
+    if form == "mixed":
+        return ctx.solve_params(tol=1e-10, n_mmscg=N_MMS, guess=nd.NDTM_GUESS_LAGRANGE,
+                                precision=nd.NDTM_PREC_F16)
+    if form == "learned":
+        return ctx.solve_params(tol=1e-10, n_mmscg=N_MMS, guess=nd.NDTM_GUESS_MLP)
+    raise ValueError(form)
+
+
+def run_form(ctx, nd, bd, xs, form, steps, warmup, profile):
+    import torch
+
+    params = form_params(ctx, nd, form)
+    for _ in range(warmup):
+        ctx.ndtm_solve(bd, params, xs=xs)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.ndtm_profile_enable((1 << len(nd.PROF_CLASSES)) - 1)
+        for k in range(len(nd.PROF_CLASSES)):
+            ctx.ndtm_profile_read(k, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(steps):
+        _, rep = ctx.ndtm_solve(bd, params, xs=xs)
+        reps.append(rep)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = None
+    if profile:
+        ctx.ndtm_profile_enable(0)
+        prof = {nd.PROF_CLASSES[k]: ctx.ndtm_profile_read(k) for k in range(len(nd.PROF_CLASSES))}
+    last = reps[-1]
+    return {
+        "ms_per_solve": 1000.0 * dt / steps,
+        "solves_per_s": steps / dt,
+        "worst_true_res": max(max(r["true_res"]) for r in reps),
+        "mms_iterations": last["mms_iterations"],
+        "mg_iterations": last["iterations"][N_MMS:] if form != "plain" else [],
+        "guess_res": last["guess_res"][N_MMS:] if form != "plain" else [],
+        "guess_kind": last["guess_kind"][N_MMS:] if form != "plain" else [],
+        "t_mms_ms": last["t_mms_ms"], "t_mg_ms": last["t_mg_ms"], "t_guess_ms": last["t_guess_ms"],
+    }, prof
+
+
+def dslash_block(nd, U_small, d0, reps):
+    """Q-hat applications on the lattice of twice the extent (the field tiled 2x per direction)."""
+    import torch
+
+    import synth
+
+    U = np.tile(U_small.reshape(tuple(d0) + U_small.shape[1:]), (2, 2, 2, 2, 1, 1, 1))
+    dims = U.shape[:4]
+    U = U.reshape((-1,) + U_small.shape[1:])
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(torch.from_numpy(U).to("cuda:0"))
+    del U
+    ctx.ndtm_set_params(synth.KAPPA, synth.MUBAR, synth.EPSBAR)
+    x = torch.from_numpy(synth.gaussian_spinor(dims, 99)).to("cuda:0")
+    y = torch.empty_like(x)
+    out = {"lattice": list(dims)}
+    for prec, name in ((nd.NDTM_PREC_F64, "f64"), (nd.NDTM_PREC_F32, "f32"), (nd.NDTM_PREC_F16, "f16")):
+        for _ in range(3):
+            ctx.ndtm_apply(nd.NDTM_OP_QHAT, x, prec=prec, out=y)
+        torch.cuda.synchronize()
+        ctx.ndtm_profile_enable(1 << prec)
+        ctx.ndtm_profile_read(prec, reset=True)
+        for _ in range(reps):
+            ctx.ndtm_apply(nd.NDTM_OP_QHAT, x, prec=prec, out=y)
+        torch.cuda.synchronize()
+        ctx.ndtm_profile_enable(0)
+        ms, n, by = ctx.ndtm_profile_read(prec, reset=True)
+        gbs = by / (ms * 1e-3) / 1e9
+        out[name] = {"gbs": gbs, "frac": gbs / HBM_PEAK_GBS, "avg_launch_us": 1000.0 * ms / n,
+                     "alg_bytes_per_launch": by / n, "launches": n}
+    ctx.close()
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(multi-GPU sharding is described in the design notes, not built)"}))
         sys.exit(2)
     import torch
 
@@ -84,60 +183,69 @@ def main():
     ctx.ndtm_set_shifts(list(cfg["shifts"]))
     bd = torch.from_numpy(b).to(dev)
     xs = [torch.empty_like(bd) for _ in cfg["shifts"]]
-    params = ctx.solve_params(tol=1e-10)
-    for _ in range(args.warmup):
-        ctx.ndtm_solve(bd, params, xs=xs)
-    torch.cuda.synchronize()
-    # kernel classes timed with events: stencil and fused shift update
-    ctx.ndtm_profile_enable((1 << 0) | (1 << 3))
-    for k in range(8):
-        ctx.ndtm_profile_read(k, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = []
-    for _ in range(args.steps):
-        _, rep = ctx.ndtm_solve(bd, params, xs=xs)
-        reps.append(rep)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ctx.ndtm_profile_enable(0)
-    prof = {nd.PROF_CLASSES[k]: ctx.ndtm_profile_read(k) for k in (0, 3)}
-    ms_step = 1000.0 * dt / args.steps
-    worst = max(max(r["true_res"]) for r in reps)
-    # dominant kernel = the class with the largest summed time
+
+    forms = [f for f in args.forms.split(",") if f]
+    setup_ms = None
+    if any(f != "plain" for f in forms):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.ndtm_mg_setup(ctx.mg_params())
+        torch.cuda.synchronize()
+        setup_ms = 1000.0 * (time.perf_counter() - t0)
+    weights = nd.trained_weights_path()
+    if "learned" in forms:
+        if weights and os.path.exists(weights):
+            ctx.ndtm_mlp_set_weights(np.load(weights)["w"])
+        else:
+            forms.remove("learned")
+
+    results, prof = {}, None
+    for i, f in enumerate(forms):
+        r, p = run_form(ctx, nd, bd, xs, f, args.steps, args.warmup, profile=(i == 0))
+        results[f] = r
+        if i == 0:
+            prof = p
+    head = results[forms[0]]
     dom = max(prof, key=lambda k: prof[k][0])
     ms, nl, by = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    hop_ms, hop_n, hop_by = prof["hop_f64"]
+    classes = {k: {"ms": v[0], "launches": v[1], "gbs": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else 0.0}
+               for k, v in prof.items() if v[1] > 0}
+    speedup = {f: results["plain"]["ms_per_solve"] / results[f]["ms_per_solve"]
+               for f in results if "plain" in results and f != "plain"}
     out = {
         "metric": METRIC,
-        "value": 1000.0 / ms_step,
+        "value": head["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_solve"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"ND twisted-mass multi-shift solve, {dims[0]}x{dims[1]}x{dims[2]}x{dims[3]} "
-                               f"(T,Lz,Ly,Lx), {len(cfg['shifts'])} shifts geometric in "
-                               f"[{cfg['shifts'][-1]:g},1], tol 1e-10, mode {args.mode}",
-                   "lattice": list(dims), "n_shifts": len(cfg["shifts"]), "mode": args.mode,
-                   "kappa": synth.KAPPA, "mubar": synth.MUBAR, "epsbar": synth.EPSBAR},
+        "config": {"workload": f"ND twisted-mass multi-shift solve, {'x'.join(map(str, dims))} (T,Lz,Ly,Lx), "
+                               f"{len(cfg['shifts'])} shifts geometric in [{cfg['shifts'][-1]:g},1], tol 1e-10, "
+                               f"{forms[0]} ({N_MMS} multi-shift CG + {len(cfg['shifts']) - N_MMS} multigrid)"
+                               if forms[0] != "plain" else "plain multi-shift CG",
+                   "lattice": list(dims), "n_shifts": len(cfg["shifts"]), "form": forms[0],
+                   "kappa": synth.KAPPA, "mubar": synth.MUBAR, "epsbar": synth.EPSBAR, "link_amp": cfg["amp"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches": nl, "avg_launch_us": 1000.0 * ms / max(nl, 1),
                      "alg_bytes_per_launch": by / max(nl, 1)},
-        "dslash_f64_gbs": hop_by / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0,
-        "mms_iterations": reps[-1]["mms_iterations"],
-        "worst_true_res": worst,
-        "report": {k: reps[-1][k] for k in ("iterations", "true_res", "t_mms_ms", "t_mg_ms", "t_total_ms")},
+        "kernel_classes": classes,
+        "forms": results,
+        "speedup_vs_plain": speedup,
+        "mg_setup_ms": setup_ms,
     }
+    if not args.no_dslash:
+        out["dslash_large"] = dslash_block(nd, U, dims, args.dslash_reps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, U, b, reps[-1]["mms_iterations"], args.cpu_iters)
+        it = results["plain"]["mms_iterations"] if "plain" in results else head["mms_iterations"]
+        out["cpu_baseline"] = cpu_baseline(cfg, U, b, it, args.cpu_iters)
     ctx.close()
     print(json.dumps(out))
 

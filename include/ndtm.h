@@ -255,9 +255,9 @@ enum {
   NDTM_PROF_HOP_F16 = 2,  /* 488 B (+100) */
   NDTM_PROF_MMS_UPDATE = 3, /* fused shift update, (3 + 4 N_active) x 384 B per odd site */
   NDTM_PROF_MMS_RESID = 4,  /* r -= alpha w with ||r||^2, 3 x 384 B per odd site */
-  NDTM_PROF_RESTRICT = 5,
-  NDTM_PROF_PROLONG = 6,
-  NDTM_PROF_COARSE = 7,
+  NDTM_PROF_RESTRICT = 5,   /* restriction, V x (12 Nv + 24) complex of the cycle precision */
+  NDTM_PROF_PROLONG = 6,    /* prolongation, same bytes as the restriction */
+  NDTM_PROF_COARSE = 7,     /* coarse stencil, Vc x 9.5 (2 Nv)^2 complex + 2 coarse vectors */
   NDTM_PROF_NCLASS = 8
 };
 /* mask: bit k enables timing of kernel class k (NDTM_PROF_*); 0 disables. */

@@ -26,3 +26,10 @@ from .binding import (  # noqa: F401
     lib_path,
     load_library,
 )
+
+
+def trained_weights_path():
+    """Path of the shipped weights of the learned guess proposer (flat FP32, key 'w')."""
+    import os
+
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "guess_mlp.npz")

@@ -298,8 +298,9 @@ class Context:
         return feat, mask, G, h, list(info)
 
     # -- profiling --------------------------------------------------------------
-    def ndtm_profile_enable(self, on=True):
-        self._check(self.lib.ndtm_profile_enable(self.h, 1 if on else 0))
+    def ndtm_profile_enable(self, mask=0xFF):
+        """Bit k of mask enables event timing of kernel class k (PROF_CLASSES); 0 disables."""
+        self._check(self.lib.ndtm_profile_enable(self.h, int(mask)))
 
     def ndtm_profile_read(self, kernel_class=0, reset=False):
         """(milliseconds, launches, algorithmic bytes) of one kernel class since the last reset."""

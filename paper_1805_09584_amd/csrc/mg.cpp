@@ -96,6 +96,21 @@ static Full full_field(ndtm_ctx* c, const std::string& name, int prec) {
   return f;
 }
 
+// Algorithmic bytes of the cycle's transfer and coarse kernels (element size es
+// of a complex number in the cycle precision): restriction and prolongation
+// stream P (V x 12 x Nv) and one full doublet field (V x 24) and touch one
+// coarse vector; the coarse stencil streams the 9 blocks (2Nv)^2 of every coarse
+// site and the odd-projector block (2 x Nv^2), and reads/writes a coarse vector.
+static double transfer_bytes(const MGData* M) {
+  const double es = (double)csz(M->cprec), Nv = M->g.Nv;
+  const double V = (double)M->g.Vc * M->g.nloc;
+  return V * (12.0 * Nv + 24.0) * es + (double)M->ncoarse * es;
+}
+static double coarse_bytes(const MGData* M) {
+  const double es = (double)csz(M->cprec), n2 = 2.0 * M->g.Nv;
+  return (double)M->g.Vc * (9.0 * n2 * n2 + 0.5 * n2 * n2) * es + 2.0 * (double)M->ncoarse * es;
+}
+
 // ---- coarse solve: fixed-length GMRES from zero, all on the device ----------
 static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
                          hipStream_t st) {
@@ -107,7 +122,7 @@ static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, dou
   vscale_inv_sqrt(cp, M->cV[0], rhs, M->dbeta, n, st);
   for (int j = 0; j < kc; ++j) {
     {
-      ProfScope ps(c, NDTM_PROF_COARSE, 0.0, st);
+      ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
       mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, eps, m, st);
     }
     // classical Gram-Schmidt with one reorthogonalisation; the second pass's
@@ -137,12 +152,12 @@ static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
   const size_t nh = half_elems(c);
   Full S = full_field(c, "mg_S", cp), Tt = full_field(c, "mg_T", cp);
   {
-    ProfScope ps(c, NDTM_PROF_RESTRICT, 0.0, st);
+    ProfScope ps(c, NDTM_PROF_RESTRICT, transfer_bytes(M), st);
     mg_restrict(cp, M->g, M->Pc, R.e.v, R.o.v, M->cR, st);
   }
   coarse_solve(c, M, M->cR, M->cW, m, eps, st);
   {
-    ProfScope ps(c, NDTM_PROF_PROLONG, 0.0, st);
+    ProfScope ps(c, NDTM_PROF_PROLONG, transfer_bytes(M), st);
     mg_prolong(cp, M->g, M->Pc, M->cW, Z.e.v, Z.o.v, st);
   }
   // post-smoothing: minimal residual steps on D' z = r

@@ -11,7 +11,8 @@
   solutions;
 * solve with the learned guess: a zero output layer reproduces the Lagrange
   run bit for bit; a random net is rejected where its predicted residual is
-  worse; all shifts still meet the tolerance (residuals by the oracle).
+  worse, and where it is kept the predicted (Gram form) and measured guess
+  residuals agree; all shifts still meet the tolerance (residuals by the oracle).
 """
 import numpy as np
 import pytest
@@ -205,7 +206,10 @@ def test_solve_with_learned_guess(nd):
             # (up to the node residuals, <= 1e-10 each, that the Gram form neglects)
             assert abs(rr["guess_res"][t] - rr["mlp_res"][t]) <= 1e-3 * rr["guess_res"][t] + 2e-9
         else:
-            assert rr["guess_kind"][t] == 1 and rr["guess_res"][t] == rl["guess_res"][t]
+            # fallback: the guess is this run's Lagrange guess (earlier shifts may have
+            # converged to slightly different solutions, so compare within the run)
+            assert rr["guess_kind"][t] == 1
+            assert abs(rr["guess_res"][t] - rr["lagrange_res"][t]) <= 1e-8 * rr["lagrange_res"][t]
     for i, s in enumerate(c["shifts"]):
         assert rel_residual(op, host(xr[i]), b, s) <= 1e-10
     ctx.close()

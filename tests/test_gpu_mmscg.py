@@ -79,3 +79,31 @@ def test_zero_and_nonfinite_rhs(nd):
         ctx.ndtm_solve(dev(bad))
     assert e.value.code == -4
     ctx.close()
+
+
+def test_profile_classes(nd):
+    """Event timing per kernel class: only enabled classes count; the byte count of
+    the stencil class is its per-site figure times the odd sites per launch."""
+    print("profile classes c1", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c1")
+    bd = dev(b)
+    mask = (1 << 0) | (1 << 3)
+    ctx.ndtm_profile_enable(mask)
+    for k in range(len(nd.PROF_CLASSES)):
+        ctx.ndtm_profile_read(k, reset=True)
+    _, rep = ctx.ndtm_solve(bd)
+    ctx.ndtm_profile_enable(0)
+    stats = [ctx.ndtm_profile_read(k) for k in range(len(nd.PROF_CLASSES))]
+    for k, (ms, n, by) in enumerate(stats):
+        if (mask >> k) & 1:
+            assert n > 0 and ms > 0, (k, stats[k])
+        else:
+            assert n == 0 and ms == 0.0, (k, stats[k])
+    ms, n, by = stats[0]
+    vh = int(np.prod(ctx.dims)) // 2
+    # every FP64 stencil pass of a Q^2 application moves 1920 B per site plus 384 B per extra vector
+    per = by / n / vh
+    assert 1920.0 <= per <= 1920.0 + 2 * 384.0
+    # the multi-shift CG applies Q^2 (two Q, four stencil passes) once per iteration
+    assert n >= 4 * rep["mms_iterations"]
+    ctx.close()
