@@ -158,6 +158,19 @@ def dslash_block(nd, U_small, d0, reps):
         out[name] = {"gbs": gbs, "frac": gbs / HBM_PEAK_GBS, "avg_launch_us": 1000.0 * ms / n,
                      "alg_bytes_per_launch": by / n, "launches": n}
     ctx.close()
+    # measured streaming ceiling: a device-to-device copy of 2 GiB (read + write)
+    a = torch.empty(1 << 29, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_ceiling_gbs"] = 10 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
     return out
 
 

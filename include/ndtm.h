@@ -79,7 +79,8 @@ enum {
 enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2 };
 
 /* Creates a context on HIP device `device` for a lattice of dims {T,Lz,Ly,Lx}.
- * EINVAL if a dim is odd or < 2 or V exceeds 2^31. */
+ * EINVAL if a dim is odd or < 2, or if V/2 exceeds about 20.6 million sites
+ * (the stencil's 32-bit per-field byte offsets; 128 x 64^3 fits). */
 int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out);
 void ndtm_destroy(ndtm_ctx* ctx);
 const char* ndtm_last_error(const ndtm_ctx* ctx);

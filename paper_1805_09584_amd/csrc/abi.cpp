@@ -153,7 +153,9 @@ int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
     if (dims[i] < 2 || (dims[i] & 1)) return NDTM_EINVAL;
     V *= dims[i];
   }
-  if (V > (1LL << 31)) return NDTM_EINVAL;
+  // the stencil addresses a field through 32-bit byte offsets from each
+  // component array: 13 x (V/2 + 512) x 16 bytes must stay below 4 GiB
+  if (13.0 * (double)(V / 2 + 512) * 16.0 >= 4294967296.0) return NDTM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NDTM_EHIP;
   if (hipSetDevice(device) != hipSuccess) return NDTM_EHIP;
@@ -166,7 +168,9 @@ int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
   c->g.Ly = dims[2];
   c->g.Lx = dims[3];
   c->g.vh = (int)(V / 2);
-  c->g.stride = (int)((V / 2 + 255) / 256 * 256);
+  // one extra 256-element block keeps the 24 component arrays (and the 36 link
+  // arrays) of a field off power-of-two spacings, which alias in the HBM channels
+  c->g.stride = (int)((V / 2 + 255) / 256 * 256) + 256;
   c->g.antiperiodic = bc_flags & 1;
   c->partials_n = (size_t)hop_grid(c->g) * 4 + 4096 * 80;
   if (hipMalloc(&c->partials, c->partials_n * sizeof(double)) != hipSuccess ||

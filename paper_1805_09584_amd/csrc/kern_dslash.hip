@@ -40,6 +40,17 @@ template <class R>
 __device__ __forceinline__ cx<R> mulc(cx<R> a, cx<R> b) {  // conj(a) * b
   return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
 }
+// s + a b and s + conj(a) b with explicit fused multiply-adds
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <class R>
+__device__ __forceinline__ cx<R> cmac(cx<R> s, cx<R> a, cx<R> b) {
+  return {fmad(-a.y, b.y, fmad(a.x, b.x, s.x)), fmad(a.y, b.x, fmad(a.x, b.y, s.y))};
+}
+template <class R>
+__device__ __forceinline__ cx<R> cmacc(cx<R> s, cx<R> a, cx<R> b) {
+  return {fmad(a.y, b.y, fmad(a.x, b.x, s.x)), fmad(-a.y, b.x, fmad(a.x, b.y, s.y))};
+}
 template <class R>
 __device__ __forceinline__ cx<R> ipl(cx<R> a) { return {-a.y, a.x}; }  // i a
 template <class R>
@@ -60,22 +71,26 @@ struct RealOf<__half2> { using T = float; };
 template <class S>
 constexpr bool kHalf = std::is_same<S, __half2>::value;
 
-__device__ __forceinline__ cx<double> ldc(const double2* p, long i) {
-  double2 v = p[i];
-  return {v.x, v.y};
+// Streaming accesses (links, the site's own vectors, the output): each element
+// is touched once per pass, so they are loaded/stored non-temporally and leave
+// the L2 to the neighbour spinors, which are read eight times.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void stc_nt(double2* p, cx<double> v) {
+  v2d w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p));
 }
-__device__ __forceinline__ cx<float> ldc(const float2* p, long i) {
-  float2 v = p[i];
-  return {v.x, v.y};
+__device__ __forceinline__ void stc_nt(float2* p, cx<float> v) {
+  v2f w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<v2f*>(p));
 }
-__device__ __forceinline__ cx<float> ldc(const __half2* p, long i) {
-  float2 v = __half22float2(p[i]);
-  return {v.x, v.y};
-}
-__device__ __forceinline__ void stc(double2* p, long i, cx<double> v) { p[i] = make_double2(v.x, v.y); }
-__device__ __forceinline__ void stc(float2* p, long i, cx<float> v) { p[i] = make_float2(v.x, v.y); }
-__device__ __forceinline__ void stc(__half2* p, long i, cx<float> v) {
-  p[i] = __float22half2_rn(make_float2(v.x, v.y));
+__device__ __forceinline__ void stc_nt(__half2* p, cx<float> v) {
+  union {
+    unsigned u;
+    __half2 h;
+  } w;
+  w.h = __float22half2_rn(make_float2(v.x, v.y));
+  __builtin_nontemporal_store(w.u, reinterpret_cast<unsigned*>(p));
 }
 
 template <class S, class L>
@@ -92,31 +107,103 @@ struct HopArgs {
   const float* zs_sc;
   double* partials;
   int T, Lz, Ly, Lx, vh, stride, parity, antiperiodic;
+  int bz;  // z-chunk of the traversal order (divides Lz)
   double a, mubar, epsbar, inv_den, ms, hop_coef, sigma;
 };
 
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+  const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+  const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ __half2 ld_nt(const __half2* p) {
+  union {
+    unsigned u;
+    __half2 h;
+  } w;
+  w.u = __builtin_nontemporal_load(reinterpret_cast<const unsigned*>(p));
+  return w.h;
+}
+__device__ __forceinline__ cx<double> cvt(double2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> cvt(float2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> cvt(__half2 v) {
+  const float2 f = __half22float2(v);
+  return {f.x, f.y};
+}
+
+// Address of component array k (a uniform base, kept in scalar registers)
+// plus a per-lane byte offset below 4 GiB: the loads then take the
+// scalar-base + 32-bit-offset form and need no per-load address arithmetic.
+template <class T>
+__device__ __forceinline__ const T* at(const T* base, long comp_elems, unsigned off_bytes) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + comp_elems) + off_bytes);
+}
+template <class T>
+__device__ __forceinline__ T* at(T* base, long comp_elems, unsigned off_bytes) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base + comp_elems) + off_bytes);
+}
+// byte offset of flavour f of half-site h in a [24][stride] field
+template <class S>
+__device__ __forceinline__ unsigned flav_off(int f, int stride, int h) {
+  return (unsigned)(f * 12 * stride + h) * (unsigned)sizeof(S);
+}
+
 // Loads the 12 components (4 spins x 3 colours) of flavour f at site h.
-template <class S, class R>
+template <class S, class R, bool NT = false>
 __device__ __forceinline__ void load_flav(cx<R> (&v)[4][3], const S* p, const float* sc, int f,
                                           int stride, int h) {
   R s = 1;
   if constexpr (kHalf<S>) s = sc[h];
+  const unsigned vo = flav_off<S>(f, stride, h);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<R> t = ldc(p, (long)(f * 12 + sp * 3 + c) * stride + h);
+      const S* q = at(p, (long)(sp * 3 + c) * stride, vo);
+      cx<R> t;
+      if constexpr (NT) t = cvt(ld_nt(q));
+      else t = cvt(*q);
       if constexpr (kHalf<S>) t = s * t;
       v[sp][c] = t;
     }
 }
 
+// Raw operands of one hop in storage precision: the neighbour spinor of the
+// lane's flavour (12 complex), its scale (FP16 only) and the link (9 complex).
+// Loading them is split from the arithmetic so that the loads of the next
+// hop are in flight while the current one is computed (two buffers).
+template <class S, class L>
+struct Raw {
+  S p[12];
+  L u[9];
+  float sc;
+};
+
+template <int MU, class S, class L>
+__device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
+                                         int hl) {
+  const unsigned vo = flav_off<S>(f, A.stride, hn);
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
+  if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
+  const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+}
+
 // One of the eight hops: project, colour-multiply, reconstruct, accumulate.
-template <int MU, bool FWD, class S, class L, class R>
-__device__ __forceinline__ void hop_dir(cx<R> (&acc)[4][3], const HopArgs<S, L>& A, int f, int hn,
-                                        const L* U, int hl, R sg) {
+// SIGN: the hop carries the sign sg of an antiperiodic time boundary; the
+// FP16 spinor scale and sg multiply the colour products once, at the end.
+template <int MU, bool FWD, bool SIGN, class S, class L, class R>
+__device__ __forceinline__ void hop_compute(cx<R> (&acc)[4][3], const Raw<S, L>& raw, R sg) {
   cx<R> p[4][3];
-  load_flav<S, R>(p, A.in, A.in_sc, f, A.stride, hn);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[sp][c] = cvt(raw.p[sp * 3 + c]);
   cx<R> h0[3], h1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -138,23 +225,37 @@ __device__ __forceinline__ void hop_dir(cx<R> (&acc)[4][3], const HopArgs<S, L>&
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[r][c] = ldc(U, (long)(MU * 9 + r * 3 + c) * A.stride + hl);
+    for (int c = 0; c < 3; ++c) u[r][c] = cvt(raw.u[r * 3 + c]);
   cx<R> g0[3], g1[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    cx<R> s0 = {0, 0}, s1 = {0, 0};
+    cx<R> s0, s1;
+    if constexpr (FWD) {
+      s0 = mul(u[r][0], h0[0]);
+      s1 = mul(u[r][0], h1[0]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if constexpr (FWD) {
-        s0 = s0 + mul(u[r][c], h0[c]);
-        s1 = s1 + mul(u[r][c], h1[c]);
-      } else {
-        s0 = s0 + mulc(u[c][r], h0[c]);
-        s1 = s1 + mulc(u[c][r], h1[c]);
+      for (int c = 1; c < 3; ++c) {
+        s0 = cmac(s0, u[r][c], h0[c]);
+        s1 = cmac(s1, u[r][c], h1[c]);
+      }
+    } else {
+      s0 = mulc(u[0][r], h0[0]);
+      s1 = mulc(u[0][r], h1[0]);
+#pragma unroll
+      for (int c = 1; c < 3; ++c) {
+        s0 = cmacc(s0, u[c][r], h0[c]);
+        s1 = cmacc(s1, u[c][r], h1[c]);
       }
     }
-    g0[r] = sg * s0;
-    g1[r] = sg * s1;
+    if constexpr (kHalf<S> || SIGN) {
+      R fac = 1;
+      if constexpr (kHalf<S>) fac = R(raw.sc);
+      if constexpr (SIGN) fac *= sg;
+      s0 = fac * s0;
+      s1 = fac * s1;
+    }
+    g0[r] = s0;
+    g1[r] = s1;
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -199,8 +300,22 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   const int q = nb >> 3, rem = nb & 7, xcd = b & 7, loc = b >> 3;
   const int lb = xcd * q + min(xcd, rem) + loc;
   const int f = threadIdx.x & 1;
-  const int h = lb * kSitesPerBlock + (threadIdx.x >> 1);
-  const bool valid = h < A.vh;
+  // traversal order: z-chunks of bz planes outermost, then t, z within the chunk,
+  // y, x; the reuse distance of the t-neighbours is bz planes instead of Lz
+  const int o = lb * kSitesPerBlock + (threadIdx.x >> 1);
+  const bool valid = o < A.vh;
+  const int Lxh = A.Lx >> 1;
+  const int plane = A.Ly * Lxh;
+  int h = 0, t = 0, z = 0, y = 0, xh = 0;
+  {
+    const int p = o / plane, r = o - p * plane;
+    const int zin = p % A.bz, q = p / A.bz;
+    t = q % A.T;
+    z = (q / A.T) * A.bz + zin;
+    y = r / Lxh;
+    xh = r - y * Lxh;
+    h = ((t * A.Lz + z) * A.Ly + y) * Lxh + xh;
+  }
   double red = 0.0;
 
   cx<R> acc[4][3];
@@ -210,13 +325,8 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     for (int c = 0; c < 3; ++c) acc[s][c] = {0, 0};
 
   if (valid) {
-    const int Lxh = A.Lx >> 1;
-    const int row = h / Lxh;
-    const int xh = h - row * Lxh;
-    const int y = row % A.Ly;
-    const int tz = row / A.Ly;
-    const int z = tz % A.Lz;
-    const int t = tz / A.Lz;
+    const int row = (t * A.Lz + z) * A.Ly + y;
+    const int tz = t * A.Lz + z;
     const int x = 2 * xh + ((A.parity + t + z + y) & 1);
     // neighbour half indices
     const int xp = (x + 1 == A.Lx) ? 0 : x + 1;
@@ -237,14 +347,45 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     const int ht_m = ((tm * A.Lz + z) * A.Ly + y) * Lxh + xh;
     const R sg_tp = (A.antiperiodic && t == A.T - 1) ? R(-1) : R(1);
     const R sg_tm = (A.antiperiodic && t == 0) ? R(-1) : R(1);
-    hop_dir<0, true>(acc, A, f, ht_p, A.Uo, h, sg_tp);
-    hop_dir<0, false>(acc, A, f, ht_m, A.Ui, ht_m, sg_tm);
-    hop_dir<1, true>(acc, A, f, hx_p, A.Uo, h, R(1));
-    hop_dir<1, false>(acc, A, f, hx_m, A.Ui, hx_m, R(1));
-    hop_dir<2, true>(acc, A, f, hy_p, A.Uo, h, R(1));
-    hop_dir<2, false>(acc, A, f, hy_m, A.Ui, hy_m, R(1));
-    hop_dir<3, true>(acc, A, f, hz_p, A.Uo, h, R(1));
-    hop_dir<3, false>(acc, A, f, hz_m, A.Ui, hz_m, R(1));
+    if constexpr (std::is_same<S, double2>::value) {
+      // FP64: the operands of one hop already take ~90 registers; a second
+      // buffer would leave one wave per SIMD, so hops are loaded one at a time
+      Raw<S, L> r;
+      load_raw<0>(r, A, f, ht_p, A.Uo, h);
+      hop_compute<0, true, true>(acc, r, sg_tp);
+      load_raw<0>(r, A, f, ht_m, A.Ui, ht_m);
+      hop_compute<0, false, true>(acc, r, sg_tm);
+      load_raw<1>(r, A, f, hx_p, A.Uo, h);
+      hop_compute<1, true, false>(acc, r, R(1));
+      load_raw<1>(r, A, f, hx_m, A.Ui, hx_m);
+      hop_compute<1, false, false>(acc, r, R(1));
+      load_raw<2>(r, A, f, hy_p, A.Uo, h);
+      hop_compute<2, true, false>(acc, r, R(1));
+      load_raw<2>(r, A, f, hy_m, A.Ui, hy_m);
+      hop_compute<2, false, false>(acc, r, R(1));
+      load_raw<3>(r, A, f, hz_p, A.Uo, h);
+      hop_compute<3, true, false>(acc, r, R(1));
+      load_raw<3>(r, A, f, hz_m, A.Ui, hz_m);
+      hop_compute<3, false, false>(acc, r, R(1));
+    } else {
+    Raw<S, L> ra, rb;
+    load_raw<0>(ra, A, f, ht_p, A.Uo, h);
+    load_raw<0>(rb, A, f, ht_m, A.Ui, ht_m);
+    hop_compute<0, true, true>(acc, ra, sg_tp);
+    load_raw<1>(ra, A, f, hx_p, A.Uo, h);
+    hop_compute<0, false, true>(acc, rb, sg_tm);
+    load_raw<1>(rb, A, f, hx_m, A.Ui, hx_m);
+    hop_compute<1, true, false>(acc, ra, R(1));
+    load_raw<2>(ra, A, f, hy_p, A.Uo, h);
+    hop_compute<1, false, false>(acc, rb, R(1));
+    load_raw<2>(rb, A, f, hy_m, A.Ui, hy_m);
+    hop_compute<2, true, false>(acc, ra, R(1));
+    load_raw<3>(ra, A, f, hz_p, A.Uo, h);
+    hop_compute<2, false, false>(acc, rb, R(1));
+    load_raw<3>(rb, A, f, hz_m, A.Ui, hz_m);
+    hop_compute<3, true, false>(acc, ra, R(1));
+    hop_compute<3, false, false>(acc, rb, R(1));
+    }
   }
 
   // ---- epilogue (both lanes of a site are valid or invalid together) ----
@@ -274,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) xv[s][c] = {0, 0};
-    if (valid) load_flav<S, R>(xv, A.xs, A.xs_sc, f, A.stride, h);
+    if (valid) load_flav<S, R, true>(xv, A.xs, A.xs_sc, f, A.stride, h);
     const R hc = (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) ? R(-0.25) : R(A.hop_coef);
     const R ms = R(A.ms);
 #pragma unroll
@@ -301,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     if constexpr (EPI == EPI_QHAT_SIG) {
       cx<R> zv[4][3];
       if (valid) {
-        load_flav<S, R>(zv, A.zs, A.zs_sc, f, A.stride, h);
+        load_flav<S, R, true>(zv, A.zs, A.zs_sc, f, A.stride, h);
         const R sgm = R(A.sigma);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -341,16 +482,27 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     if (valid && f == 0) A.out_sc[h] = mx;
   }
   if (valid) {
+    const unsigned vout = flav_off<S>(f, A.stride, h);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         cx<R> o = out[s][c];
         if constexpr (kHalf<S>) o = inv_sc * o;
-        stc(A.out, (long)(f * 12 + s * 3 + c) * A.stride + h, o);
+        stc_nt(at(A.out, (long)(s * 3 + c) * A.stride, vout), o);
       }
   }
   if constexpr (RED != RED_NONE) block_reduce_store(red, A.partials);
+}
+
+// Largest divisor bz of Lz whose bz-plane window of input spinors (the reuse
+// distance of the t-neighbours) stays within half of an XCD's 4 MB L2.
+int hop_chunk(const Geom& g, int site_bytes) {
+  const double plane = (double)g.Ly * (g.Lx / 2);
+  const double budget = 2.0 * 1024.0 * 1024.0;
+  int bz = g.Lz;
+  while (bz > 1 && (g.Lz % bz != 0 || bz * plane * site_bytes > budget)) --bz;
+  return bz;
 }
 
 template <class S, class L>
@@ -378,6 +530,7 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.stride = g.stride;
   A.parity = parity;
   A.antiperiodic = g.antiperiodic;
+  A.bz = hop_chunk(g, sizeof(S) * 24 + (kHalf<S> ? 4 : 0));
   A.a = op.a;
   A.mubar = op.mubar;
   A.epsbar = op.epsbar;

@@ -8,7 +8,7 @@
 //   links of parity p: element [(mu*9 + row*3 + col) * stride + h] is U_mu(x)
 //       of the site x with half index h and parity p.
 //   full-lattice vector: even half field followed by the odd half field.
-//   stride = vh rounded up to a multiple of 256; padding stays zero.
+//   stride = vh rounded up to a multiple of 256, plus 256; padding stays zero.
 #pragma once
 
 #include <hip/hip_runtime.h>
