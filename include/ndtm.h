@@ -75,8 +75,12 @@ enum {
   NDTM_OP_HOP_OE = 5      /* y_o = H_oe x_e                                        */
 };
 
-/* Initial-guess modes for the multigrid shifts. */
-enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2 };
+/* Initial-guess modes for the multigrid shifts.  LAGRANGE: interpolation over
+ * the converged solutions (section 4.2); MLP: the learned proposer with Lagrange
+ * as fallback; PROJECTION: the combination of all converged solutions with the
+ * smallest residual, from the Gram matrix of [b, x_1..x_K] and the identity of
+ * appendix B, refined on the true residual (a generalisation of section 4.2). */
+enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2, NDTM_GUESS_PROJECTION = 3 };
 
 /* Creates a context on HIP device `device` for a lattice of dims {T,Lz,Ly,Lx}.
  * EINVAL if a dim is odd or < 2, or if V/2 exceeds about 20.6 million sites
@@ -113,7 +117,8 @@ typedef struct {
   int block[4];        /* aggregate extents {bt,bz,by,bx}; each divides the dim */
   int n_vec;           /* test vectors N_v (<= 32); coarse dof per flavour = 2 N_v */
   int setup_iters;     /* inverse-iteration sweeps building the test vectors */
-  int setup_smooth;    /* minimal-residual steps per inverse-iteration sweep */
+  int setup_smooth;    /* CG steps on the normal equations D^+ D x = v per
+                          inverse-iteration sweep (D^+ = Gamma5 tau1 D Gamma5 tau1) */
   int setup_refine;    /* refinement sweeps: each replaces every test vector by one
                           two-level cycle applied to it, then rebuilds P and D_c */
   int setup_nd;        /* 0: iterate the one-flavour operators D_W +- i mubar Gamma5
@@ -184,7 +189,8 @@ typedef struct {
   int mms_iterations;               /* iterations of the shared Krylov space */
   double sigma[NDTM_MAX_SHIFTS];    /* in solve order (descending) */
   int input_index[NDTM_MAX_SHIFTS]; /* position of this shift in set_shifts */
-  int method[NDTM_MAX_SHIFTS];      /* 0 = MMS-CG, 1 = multigrid case C */
+  int method[NDTM_MAX_SHIFTS];      /* 0 = MMS-CG, 1 = multigrid case C, 2 = multigrid
+                                       did not converge, finished by FP64 CG */
   int iterations[NDTM_MAX_SHIFTS];  /* MMS-CG: iteration when frozen; MG: outer iterations */
   int rounds[NDTM_MAX_SHIFTS];      /* MG: defect-correction rounds */
   double true_res[NDTM_MAX_SHIFTS]; /* ||b - (Q^2+sigma) x|| / ||b||, FP64 */

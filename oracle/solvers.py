@@ -194,3 +194,14 @@ def case_c(solve_plus, solve_minus, b, m):
     xp = solve_plus(b)
     xm = solve_minus(b)
     return (1j / (2.0 * m)) * (xp - xm)
+
+
+def projection_guess(apply_At, xs, b):
+    """Minimal-residual combination of the converged solutions (generalises the
+    interpolated guesses of section 4.2): c = argmin || b - A_t sum_i c_i x_i ||
+    over complex c, with the products A_t x_i formed explicitly (the plain
+    definition; the appendix B identity is not used here).  Returns (x, c)."""
+    Y = np.stack([np.asarray(apply_At(x)).reshape(-1) for x in xs], axis=1)
+    c, *_ = np.linalg.lstsq(Y, np.asarray(b).reshape(-1), rcond=None)
+    x = sum(ci * xi for ci, xi in zip(c, xs))
+    return x, c

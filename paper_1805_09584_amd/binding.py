@@ -14,7 +14,7 @@ NDTM_OK = 0
 NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16 = 0, 1, 2
 (NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
  NDTM_OP_HOP_OE) = range(6)
-NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP = 0, 1, 2
+NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP, NDTM_GUESS_PROJECTION = 0, 1, 2, 3
 PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
                 "coarse")
 MAX_SHIFTS = 16

@@ -113,6 +113,9 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
               const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
               hipStream_t st);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
+// x += CG corrections on (Q^2 + sigma) until the true residual of x meets tol
+int cg_shift(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
+             double* res_out, int* iters_out, hipStream_t st);
 int guess_first_node(const std::vector<double>& nodes, double sig_t);
 double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma,
                      const HalfField& r, hipStream_t st);

@@ -323,11 +323,14 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
   const double m = std::sqrt(sigma);
   HalfField r = half_field(c, "cc_r", P64), cr = half_field(c, "cc_c", P64), ep = half_field(c, "cc_ep", P64),
             em = half_field(c, "cc_em", P64);
+  HalfField xb = half_field(c, "cc_xb", P64);
+  if (!r.v || !cr.v || !ep.v || !em.v || !xb.v) return fail(c, NDTM_ENOMEM, "multigrid shift: workspace");
   double res = true_residual(c, x, b, sigma, r, st);
   *guess_res = res;
   const double amp = m / std::sqrt(lambda_max_estimate() + sigma);
   int it_total = 0, rd = 0;
   while (res > p->tol && rd < p->max_rounds) {
+    blas_copy((double2*)xb.v, (const double2*)x.v, n, st);
     // single-solve tolerance so that one round meets tol after the case-C amplification
     double rho = 0.5 * p->tol / res * amp;
     rho = std::max(1e-14, std::min(rho, p->mg_tol));
@@ -338,14 +341,19 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
     // x += (i/2m)(e_+ - e_-)
     blas_axpy((double2*)x.v, make_double2(0, 0.5 / m), (const double2*)ep.v, n, st);
     blas_axpy((double2*)x.v, make_double2(0, -0.5 / m), (const double2*)em.v, n, st);
+    const double prev = res;
     res = true_residual(c, x, b, sigma, r, st);
     ++rd;
-    if (!std::isfinite(res)) break;
+    if (!std::isfinite(res) || res >= prev) {
+      // the round did not converge far enough to help: keep the previous iterate
+      blas_copy((double2*)x.v, (const double2*)xb.v, n, st);
+      res = prev;
+      break;
+    }
   }
   *res_out = res;
   *iters = it_total;
   *rounds = rd;
-  if (!std::isfinite(res)) return fail(c, NDTM_EBREAKDOWN, "multigrid shift: non-finite residual");
   return res <= p->tol ? NDTM_OK : NDTM_ENOCONV;
 }
 
@@ -378,6 +386,8 @@ int guess_first_node(const std::vector<double>& nodes, double sig_t) {
 int guess_mlp(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, int K, double sig_t,
               const HalfField& b, const std::vector<double>& lag, std::vector<double>* coef, double* pred_mlp,
               double* pred_lag, hipStream_t st);
+int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, double sig_t,
+                     const HalfField& b, const HalfField& x, double* lag_res, double* proj_res, hipStream_t st);
 
 int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std::vector<HalfField>& xs,
                     const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st) {
@@ -408,7 +418,14 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
         rep->guess_kind[t] = NDTM_GUESS_LAGRANGE;
       }
     }
-    if (p->guess == NDTM_GUESS_ZERO) {
+    if (p->guess == NDTM_GUESS_PROJECTION) {
+      std::vector<double> all(sig.begin(), sig.begin() + t);
+      std::vector<HalfField> xall(xs.begin(), xs.begin() + t);
+      double lres = -1, pres = -1;
+      const int grc = guess_projection(c, all, xall, sig[t], b, xs[t], &lres, &pres, st);
+      if (grc != NDTM_OK) return grc;
+      rep->lagrange_res[t] = lres;
+    } else if (p->guess == NDTM_GUESS_ZERO) {
       blas_zero(xs[t].v, n * sizeof(double2), st);
     } else {
       std::vector<const double2*> V(K);
@@ -433,8 +450,19 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
     if (rep->lagrange_res[t] < 0 && p->guess == NDTM_GUESS_LAGRANGE) rep->lagrange_res[t] = gres;
     auto tg2 = std::chrono::steady_clock::now();
     rep->t_mg_ms += std::chrono::duration<double, std::milli>(tg2 - tg1).count();
-    if (rc == NDTM_EBREAKDOWN) return rc;
-    if (rc != NDTM_OK) status = rc;
+    if (rc != NDTM_OK) {
+      // the multigrid did not reach the tolerance: finish this shift with FP64 CG
+      // from the best iterate, so that every shift still converges
+      double pres = 0;
+      int pits = 0;
+      const int prc = cg_shift(c, xs[t], b, sig[t], p->tol, p->maxiter, &pres, &pits, st);
+      rep->method[t] = 2;
+      rep->iterations[t] += pits;
+      rep->true_res[t] = pres;
+      rep->t_mg_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg2).count();
+      if (prc == NDTM_EBREAKDOWN) return prc;
+      if (prc != NDTM_OK) status = prc;
+    }
   }
   return status;
 }
@@ -535,18 +563,42 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
       c->op.inv_den = 1.0 / (a * a + c->mubar * c->mubar - eps_setup * eps_setup);
     };
     setup_op();
+    // x ~ (D^+ D)^-1 v by CG on the normal equations, D^+ = Gamma5 tau1 D Gamma5 tau1
+    // (eq:g5tau1-hermiticity), then v = x / ||x||: inverse iteration towards the
+    // smallest singular vectors, which span the near-null space the coarse grid
+    // has to represent
+    Full Pp = full_field(c, "su_p", P64), W = full_field(c, "su_w", P64), T2 = full_field(c, "su_t2", P64);
+    if (!Pp.base || !W.base || !T2.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
+    const size_t nf2 = 2 * nh;
+    auto g5t1_full = [&](const Full& y, const Full& x) {
+      launch_g5t1(c->g, (const double2*)x.e.v, (double2*)y.e.v, st);
+      launch_g5t1(c->g, (const double2*)x.o.v, (double2*)y.o.v, st);
+    };
+    auto apply_normal = [&](const Full& w, const Full& v) {
+      apply_dfull(c, P64, Tt.e, Tt.o, v.e, v.o, 0.0, st);
+      g5t1_full(T2, Tt);
+      apply_dfull(c, P64, Tt.e, Tt.o, T2.e, T2.o, 0.0, st);
+      g5t1_full(w, Tt);
+    };
     for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
       for (int i = 0; i < nf; ++i) {
-        // x ~ D^-1 v by minimal-residual steps from x = 0, then v = x / ||x||
-        vzero(P64, X.base, 2 * nh, st);
-        blas_copy((double2*)R.base, (const double2*)F[i].base, 2 * nh, st);
-        for (int it = 0; it < prm->setup_smooth; ++it) {
-          apply_dfull(c, P64, Tt.e, Tt.o, R.e, R.o, 0.0, st);
-          vmr_coef(P64, Tt.base, R.base, 2 * nh, c->vred, d, st);
-          vmr_update(P64, X.base, R.base, Tt.base, d, 1, 2 * nh, st);
+        vzero(P64, X.base, nf2, st);
+        blas_copy((double2*)R.base, (const double2*)F[i].base, nf2, st);
+        blas_copy((double2*)Pp.base, (const double2*)R.base, nf2, st);
+        double rr = norm2_host(c, (const double2*)R.base, nf2, st);
+        for (int it = 0; it < prm->setup_smooth && rr > 0; ++it) {
+          apply_normal(W, Pp);
+          const double pw = dot_host(c, (const double2*)Pp.base, (const double2*)W.base, nf2, st).x;
+          if (!(pw > 0)) break;
+          const double alpha = rr / pw;
+          blas_axpy((double2*)X.base, make_double2(alpha, 0), (const double2*)Pp.base, nf2, st);
+          blas_axpy((double2*)R.base, make_double2(-alpha, 0), (const double2*)W.base, nf2, st);
+          const double rn = norm2_host(c, (const double2*)R.base, nf2, st);
+          blas_axpby((double2*)Pp.base, make_double2(1, 0), (const double2*)R.base, make_double2(rn / rr, 0), nf2, st);
+          rr = rn;
         }
-        vnorm2(P64, X.base, 2 * nh, c->vred, d + 6, st);
-        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
+        vnorm2(P64, X.base, nf2, c->vred, d + 6, st);
+        vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, nf2, st);
       }
     }
     std::vector<const double2*> fp(nf);
@@ -611,8 +663,8 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->block[0] = p->block[1] = p->block[2] = p->block[3] = 4;
   p->n_vec = 24;
   p->setup_iters = 6;
-  p->setup_smooth = 4;
-  p->setup_refine = 4;
+  p->setup_smooth = 30;
+  p->setup_refine = 0;
   p->setup_nd = 1;
   p->smooth_iters = 8;
   p->coarse_iters = 8;

@@ -220,6 +220,14 @@ static int polish_cg(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
   return res <= tol ? NDTM_OK : NDTM_ENOCONV;
 }
 
+int cg_shift(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
+             double* res_out, int* iters_out, hipStream_t st) {
+  HalfField r = half_field(c, "pol_r", P64);
+  if (!r.v) return fail(c, NDTM_ENOMEM, "cg shift: workspace");
+  if (!std::isfinite(true_residual(c, x, b, sigma, r, st))) blas_zero(x.v, half_elems(c) * sizeof(double2), st);
+  return polish_cg(c, x, b, sigma, tol, maxiter, res_out, iters_out, st);
+}
+
 // FP64 defect correction of one shift with the mixed-precision CG as the inner
 // solver: r = b - (Q^2+sigma) x in FP64, e ~ (Q^2+sigma)^-1 r in the mixed form,
 // x += e in FP64, until the true residual meets tol.  Falls back to the FP64

@@ -164,3 +164,32 @@ def test_gmres_dense():
     b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     x, it = solvers.gmres(lambda v: A @ v, b, tol=1e-12, restart=15)
     assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b) * 1.01
+
+
+def test_projection_guess_pins():
+    """K = 1 closed form; the residual is orthogonal to every A_t x_i (first-order
+    optimality); it is no larger than the Lagrange guess's and than any perturbed
+    combination."""
+    dims = (2, 2, 2, 4)
+    U = synth.gauge_field(dims, 7, 0.3)
+    op = NDOperator(Lattice(dims, U), synth.KAPPA, synth.MUBAR, synth.EPSBAR)
+    b = synth.gaussian_spinor(dims, 8)
+    nodes = np.array([0.5, 0.1, 0.02, 0.004])
+    st = 0.001
+    xs = [solvers.cg(lambda v, s=s: op.Q_hat2(v, s), b, tol=1e-13)[0] for s in nodes]
+    At = lambda v: op.Q_hat2(v, st)
+    # K = 1: c = <A x, b> / <A x, A x>
+    x1, c1 = solvers.projection_guess(At, xs[-1:], b)
+    y = At(xs[-1])
+    assert abs(c1[0] - np.vdot(y, b) / np.vdot(y, y)) < 1e-12 * abs(c1[0])
+    x, c = solvers.projection_guess(At, xs, b)
+    r = b - At(x)
+    for xi in xs:
+        assert abs(np.vdot(At(xi), r)) <= 1e-9 * np.linalg.norm(At(xi)) * np.linalg.norm(b)
+    xl = solvers.lagrange_guess(xs, nodes, st)
+    assert norm2(r) <= norm2(b - At(xl))
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        dc = 1e-3 * (rng.standard_normal(len(c)) + 1j * rng.standard_normal(len(c)))
+        xp = sum((ci + di) * xi for ci, di, xi in zip(c, dc, xs))
+        assert norm2(b - At(xp)) >= norm2(r)
