@@ -320,7 +320,7 @@ __global__ void mms_update_r_mx_k(float2* r, const __half2* w16, const float* ws
     const double sc = wsc[h];
     for (int c = 0; c < 24; ++c) {
       const size_t i = (size_t)c * stride + h;
-      const float2 w = __half22float2(w16[i]);
+      const float2 w = __half22float2(w16[idx16(c, stride, h)]);
       float2 v = r[i];
       v.x = (float)((double)v.x - alpha * sc * (double)w.x);
       v.y = (float)((double)v.y - alpha * sc * (double)w.y);
@@ -365,7 +365,7 @@ __global__ void mms_update_p_mx_k(const float2* r, float2* p, __half2* p16, floa
     }
     const float inv = mx > 0.f ? 1.0f / mx : 0.f;
     for (int c = 0; c < 24; ++c)
-      p16[(size_t)c * stride + h] = __floats2half2_rn(pn[c].x * inv, pn[c].y * inv);
+      p16[idx16(c, stride, h)] = __floats2half2_rn(pn[c].x * inv, pn[c].y * inv);
     p16sc[h] = mx;
   }
 }

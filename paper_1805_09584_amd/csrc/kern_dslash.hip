@@ -151,24 +151,49 @@ __device__ __forceinline__ unsigned flav_off(int f, int stride, int h) {
   return (unsigned)(f * 12 * stride + h) * (unsigned)sizeof(S);
 }
 
+// FP16 fields: 4 components per 16-byte word (idx16 / lidx16 layout); group g
+// of flavour f at half-site h is word (f*3 + g)*stride + h.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+union H4 {
+  v4u w;
+  __half2 h[4];
+};
+template <bool NT>
+__device__ __forceinline__ H4 ld_group(const __half2* base, long group, int stride, unsigned off_bytes) {
+  const v4u* q = reinterpret_cast<const v4u*>(reinterpret_cast<const char*>(base + group * stride * 4) + off_bytes);
+  H4 u;
+  if constexpr (NT) u.w = __builtin_nontemporal_load(q);
+  else u.w = *q;
+  return u;
+}
+__device__ __forceinline__ unsigned group_off(int f, int stride, int h) {
+  return (unsigned)(f * 3 * stride + h) * 16u;
+}
+
 // Loads the 12 components (4 spins x 3 colours) of flavour f at site h.
 template <class S, class R, bool NT = false>
 __device__ __forceinline__ void load_flav(cx<R> (&v)[4][3], const S* p, const float* sc, int f,
                                           int stride, int h) {
-  R s = 1;
-  if constexpr (kHalf<S>) s = sc[h];
-  const unsigned vo = flav_off<S>(f, stride, h);
+  if constexpr (kHalf<S>) {
+    const R s = sc[h];
+    const unsigned vo = group_off(f, stride, h);
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
+    for (int g = 0; g < 3; ++g) {
+      const H4 u = ld_group<NT>(p, g, stride, vo);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const S* q = at(p, (long)(sp * 3 + c) * stride, vo);
-      cx<R> t;
-      if constexpr (NT) t = cvt(ld_nt(q));
-      else t = cvt(*q);
-      if constexpr (kHalf<S>) t = s * t;
-      v[sp][c] = t;
+      for (int q = 0; q < 4; ++q) v[(4 * g + q) / 3][(4 * g + q) % 3] = s * cvt(u.h[q]);
     }
+  } else {
+    const unsigned vo = flav_off<S>(f, stride, h);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const S* q = at(p, (long)(sp * 3 + c) * stride, vo);
+        if constexpr (NT) v[sp][c] = cvt(ld_nt(q));
+        else v[sp][c] = cvt(*q);
+      }
+  }
 }
 
 // Raw operands of one hop in storage precision: the neighbour spinor of the
@@ -185,13 +210,31 @@ struct Raw {
 template <int MU, class S, class L>
 __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
                                          int hl) {
-  const unsigned vo = flav_off<S>(f, A.stride, hn);
+  if constexpr (kHalf<S>) {
+    const unsigned vo = group_off(f, A.stride, hn);
 #pragma unroll
-  for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
-  if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
-  const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
+    for (int g = 0; g < 3; ++g) {
+      const H4 u = ld_group<false>(A.in, g, A.stride, vo);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+      for (int q = 0; q < 4; ++q) r.p[4 * g + q] = u.h[q];
+    }
+    r.sc = A.in_sc[hn];
+    const unsigned vl = (unsigned)hl * 16u;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const H4 u = ld_group<true>(U, 2 * MU + g, A.stride, vl);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r.u[4 * g + q] = u.h[q];
+    }
+    r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
+  } else {
+    const unsigned vo = flav_off<S>(f, A.stride, hn);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
+    const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+  }
 }
 
 // One of the eight hops: project, colour-multiply, reconstruct, accumulate.
@@ -482,15 +525,26 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     if (valid && f == 0) A.out_sc[h] = mx;
   }
   if (valid) {
-    const unsigned vout = flav_off<S>(f, A.stride, h);
+    if constexpr (kHalf<S>) {
+      const unsigned vout = group_off(f, A.stride, h);
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int g = 0; g < 3; ++g) {
+        H4 u;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cx<R> o = out[s][c];
-        if constexpr (kHalf<S>) o = inv_sc * o;
-        stc_nt(at(A.out, (long)(s * 3 + c) * A.stride, vout), o);
+        for (int q = 0; q < 4; ++q) {
+          const cx<R> o = inv_sc * out[(4 * g + q) / 3][(4 * g + q) % 3];
+          u.h[q] = __float22half2_rn(make_float2(o.x, o.y));
+        }
+        v4u* dst = reinterpret_cast<v4u*>(reinterpret_cast<char*>(A.out + (long)g * A.stride * 4) + vout);
+        __builtin_nontemporal_store(u.w, dst);
       }
+    } else {
+      const unsigned vout = flav_off<S>(f, A.stride, h);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) stc_nt(at(A.out, (long)(s * 3 + c) * A.stride, vout), out[s][c]);
+    }
   }
   if constexpr (RED != RED_NONE) block_reduce_store(red, A.partials);
 }

@@ -32,7 +32,7 @@ __global__ void pack_gauge_k(Geom g, const double2* U, double2* U64e, double2* U
     const long o = (long)k * g.stride + h;
     d64[o] = u;
     d32[o] = make_float2((float)u.x, (float)u.y);
-    d16[o] = __floats2half2_rn((float)u.x, (float)u.y);
+    d16[lidx16(k / 9, k % 9, g.stride, h)] = __floats2half2_rn((float)u.x, (float)u.y);
   }
 }
 
@@ -51,7 +51,7 @@ __device__ __forceinline__ void put_site(const HalfField& f, int stride, long h,
     const double inv = sc > 0 ? 1.0 / (double)sc : 0.0;
     __half2* d = static_cast<__half2*>(f.v);
     for (int c = 0; c < 24; ++c)
-      d[(long)c * stride + h] = __floats2half2_rn((float)(v[c].x * inv), (float)(v[c].y * inv));
+      d[idx16(c, stride, h)] = __floats2half2_rn((float)(v[c].x * inv), (float)(v[c].y * inv));
     f.sc[h] = sc;
   }
 }
@@ -67,7 +67,7 @@ __device__ __forceinline__ void get_site(const HalfField& f, int stride, long h,
     const __half2* d = static_cast<const __half2*>(f.v);
     const double sc = f.sc[h];
     for (int c = 0; c < 24; ++c) {
-      const float2 t = __half22float2(d[(long)c * stride + h]);
+      const float2 t = __half22float2(d[idx16(c, stride, h)]);
       v[c] = make_double2(t.x * sc, t.y * sc);
     }
   }

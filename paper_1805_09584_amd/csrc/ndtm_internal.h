@@ -9,6 +9,11 @@
 //       of the site x with half index h and parity p.
 //   full-lattice vector: even half field followed by the odd half field.
 //   stride = vh rounded up to a multiple of 256, plus 256; padding stays zero.
+//   FP16 fields and links group 4 components per 16-byte word so that the
+//   stencil loads a flavour's spinor in 3 and a link in 3 instructions:
+//   spinor element (c, h) at ((c/4)*stride + h)*4 + c%4 (idx16); link
+//   component k < 8 of direction mu at ((2*mu + k/4)*stride + h)*4 + k%4 and
+//   component 8 at 32*stride + mu*stride + h (lidx16).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,6 +37,13 @@ struct Geom {
 };
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+
+__host__ __device__ inline long idx16(int c, int stride, long h) {
+  return ((long)(c >> 2) * stride + h) * 4 + (c & 3);
+}
+__host__ __device__ inline long lidx16(int mu, int k, int stride, long h) {
+  return k < 8 ? ((long)(2 * mu + (k >> 2)) * stride + h) * 4 + (k & 3) : (long)(32 + mu) * stride + h;
+}
 
 // Epilogues of the hopping kernel.
 enum Epi {
