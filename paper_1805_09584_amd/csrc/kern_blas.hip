@@ -319,7 +319,7 @@ __global__ void mms_update_r_mx_k(float2* r, const __half2* w16, const float* ws
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < vh; h += gridDim.x * blockDim.x) {
     const double sc = wsc[h];
     for (int c = 0; c < 24; ++c) {
-      const size_t i = (size_t)c * stride + h;
+      const size_t i = idx32(c, stride, h);
       const float2 w = __half22float2(w16[idx16(c, stride, h)]);
       float2 v = r[i];
       v.x = (float)((double)v.x - alpha * sc * (double)w.x);
@@ -340,7 +340,7 @@ __global__ void mms_update_p_mx_k(const float2* r, float2* p, __half2* p16, floa
     float2 pn[24];
     float mx = 0.f;
     for (int c = 0; c < 24; ++c) {
-      const size_t i = (size_t)c * stride + h;
+      const size_t i = idx32(c, stride, h);
       const float2 ri = r[i];
       for (int s = 0; s < nsh; ++s) {
         if (S[MS_ACT + s] == 0.0) continue;

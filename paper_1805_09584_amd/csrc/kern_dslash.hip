@@ -151,37 +151,51 @@ __device__ __forceinline__ unsigned flav_off(int f, int stride, int h) {
   return (unsigned)(f * 12 * stride + h) * (unsigned)sizeof(S);
 }
 
-// FP16 fields: 4 components per 16-byte word (idx16 / lidx16 layout); group g
-// of flavour f at half-site h is word (f*3 + g)*stride + h.
+// FP32 and FP16 fields: G = 16/sizeof(S) components per 16-byte word
+// (idx32/idx16, lidx32/lidx16 layouts); group g of flavour f at half-site h is
+// word (f*NG + g)*stride + h with NG = 12/G groups per flavour.
+template <class S>
+constexpr bool kGrouped = !std::is_same<S, double2>::value;
+template <class S>
+constexpr int kG = 16 / (int)sizeof(S);
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
-union H4 {
+template <class S>
+union Grp {
   v4u w;
-  __half2 h[4];
+  S e[16 / sizeof(S)];
 };
-template <bool NT>
-__device__ __forceinline__ H4 ld_group(const __half2* base, long group, int stride, unsigned off_bytes) {
-  const v4u* q = reinterpret_cast<const v4u*>(reinterpret_cast<const char*>(base + group * stride * 4) + off_bytes);
-  H4 u;
+template <bool NT, class S>
+__device__ __forceinline__ Grp<S> ld_group(const S* base, long group, int stride, unsigned off_bytes) {
+  const v4u* q =
+      reinterpret_cast<const v4u*>(reinterpret_cast<const char*>(base + group * stride * kG<S>) + off_bytes);
+  Grp<S> u;
   if constexpr (NT) u.w = __builtin_nontemporal_load(q);
   else u.w = *q;
   return u;
 }
+template <class S>
 __device__ __forceinline__ unsigned group_off(int f, int stride, int h) {
-  return (unsigned)(f * 3 * stride + h) * 16u;
+  return (unsigned)(f * (12 / kG<S>)*stride + h) * 16u;
 }
 
 // Loads the 12 components (4 spins x 3 colours) of flavour f at site h.
 template <class S, class R, bool NT = false>
 __device__ __forceinline__ void load_flav(cx<R> (&v)[4][3], const S* p, const float* sc, int f,
                                           int stride, int h) {
-  if constexpr (kHalf<S>) {
-    const R s = sc[h];
-    const unsigned vo = group_off(f, stride, h);
+  if constexpr (kGrouped<S>) {
+    constexpr int G = kG<S>;
+    R s = 1;
+    if constexpr (kHalf<S>) s = sc[h];
+    const unsigned vo = group_off<S>(f, stride, h);
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
-      const H4 u = ld_group<NT>(p, g, stride, vo);
+    for (int g = 0; g < 12 / G; ++g) {
+      const Grp<S> u = ld_group<NT>(p, g, stride, vo);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[(4 * g + q) / 3][(4 * g + q) % 3] = s * cvt(u.h[q]);
+      for (int q = 0; q < G; ++q) {
+        cx<R> t = cvt(u.e[q]);
+        if constexpr (kHalf<S>) t = s * t;
+        v[(G * g + q) / 3][(G * g + q) % 3] = t;
+      }
     }
   } else {
     const unsigned vo = flav_off<S>(f, stride, h);
@@ -210,21 +224,22 @@ struct Raw {
 template <int MU, class S, class L>
 __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
                                          int hl) {
-  if constexpr (kHalf<S>) {
-    const unsigned vo = group_off(f, A.stride, hn);
+  if constexpr (kGrouped<S>) {
+    constexpr int G = kG<S>;
+    const unsigned vo = group_off<S>(f, A.stride, hn);
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
-      const H4 u = ld_group<false>(A.in, g, A.stride, vo);
+    for (int g = 0; g < 12 / G; ++g) {
+      const Grp<S> u = ld_group<false>(A.in, g, A.stride, vo);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) r.p[4 * g + q] = u.h[q];
+      for (int q = 0; q < G; ++q) r.p[G * g + q] = u.e[q];
     }
-    r.sc = A.in_sc[hn];
+    if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
     const unsigned vl = (unsigned)hl * 16u;
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const H4 u = ld_group<true>(U, 2 * MU + g, A.stride, vl);
+    for (int g = 0; g < 8 / G; ++g) {
+      const Grp<L> u = ld_group<true>(U, (8 / G) * MU + g, A.stride, vl);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) r.u[4 * g + q] = u.h[q];
+      for (int q = 0; q < G; ++q) r.u[G * g + q] = u.e[q];
     }
     r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
   } else {
@@ -525,17 +540,19 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     if (valid && f == 0) A.out_sc[h] = mx;
   }
   if (valid) {
-    if constexpr (kHalf<S>) {
-      const unsigned vout = group_off(f, A.stride, h);
+    if constexpr (kGrouped<S>) {
+      constexpr int G = kG<S>;
+      const unsigned vout = group_off<S>(f, A.stride, h);
 #pragma unroll
-      for (int g = 0; g < 3; ++g) {
-        H4 u;
+      for (int g = 0; g < 12 / G; ++g) {
+        Grp<S> u;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const cx<R> o = inv_sc * out[(4 * g + q) / 3][(4 * g + q) % 3];
-          u.h[q] = __float22half2_rn(make_float2(o.x, o.y));
+        for (int q = 0; q < G; ++q) {
+          const cx<R> o = inv_sc * out[(G * g + q) / 3][(G * g + q) % 3];
+          if constexpr (kHalf<S>) u.e[q] = __float22half2_rn(make_float2(o.x, o.y));
+          else u.e[q] = make_float2(o.x, o.y);
         }
-        v4u* dst = reinterpret_cast<v4u*>(reinterpret_cast<char*>(A.out + (long)g * A.stride * 4) + vout);
+        v4u* dst = reinterpret_cast<v4u*>(reinterpret_cast<char*>(A.out + (long)g * A.stride * G) + vout);
         __builtin_nontemporal_store(u.w, dst);
       }
     } else {

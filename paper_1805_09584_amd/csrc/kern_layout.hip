@@ -31,7 +31,7 @@ __global__ void pack_gauge_k(Geom g, const double2* U, double2* U64e, double2* U
     const double2 u = U[s * 36 + k];
     const long o = (long)k * g.stride + h;
     d64[o] = u;
-    d32[o] = make_float2((float)u.x, (float)u.y);
+    d32[lidx32(k / 9, k % 9, g.stride, h)] = make_float2((float)u.x, (float)u.y);
     d16[lidx16(k / 9, k % 9, g.stride, h)] = __floats2half2_rn((float)u.x, (float)u.y);
   }
 }
@@ -43,7 +43,7 @@ __device__ __forceinline__ void put_site(const HalfField& f, int stride, long h,
     for (int c = 0; c < 24; ++c) d[(long)c * stride + h] = v[c];
   } else if (f.prec == P32) {
     float2* d = static_cast<float2*>(f.v);
-    for (int c = 0; c < 24; ++c) d[(long)c * stride + h] = make_float2((float)v[c].x, (float)v[c].y);
+    for (int c = 0; c < 24; ++c) d[idx32(c, stride, h)] = make_float2((float)v[c].x, (float)v[c].y);
   } else {
     double mx = 0;
     for (int c = 0; c < 24; ++c) mx = fmax(mx, fmax(fabs(v[c].x), fabs(v[c].y)));
@@ -62,7 +62,7 @@ __device__ __forceinline__ void get_site(const HalfField& f, int stride, long h,
     for (int c = 0; c < 24; ++c) v[c] = d[(long)c * stride + h];
   } else if (f.prec == P32) {
     const float2* d = static_cast<const float2*>(f.v);
-    for (int c = 0; c < 24; ++c) v[c] = make_double2(d[(long)c * stride + h].x, d[(long)c * stride + h].y);
+    for (int c = 0; c < 24; ++c) v[c] = make_double2(d[idx32(c, stride, h)].x, d[idx32(c, stride, h)].y);
   } else {
     const __half2* d = static_cast<const __half2*>(f.v);
     const double sc = f.sc[h];

@@ -358,6 +358,13 @@ __device__ __forceinline__ typename C2<R>::T mk(R x, R y) {
 
 constexpr int kGroups = 4;  // thread groups per coarse site in restrict / coarse apply
 
+// element of component c at half-site h of a fine field in the cycle precision R
+template <class R>
+__device__ __forceinline__ long fine_idx(int c, int stride, long h) {
+  if constexpr (sizeof(R) == 8) return (long)c * stride + h;
+  else return idx32(c, stride, h);
+}
+
 template <class R>
 __global__ __launch_bounds__(512) void restrict_k(MGGeom m, const typename C2<R>::T* P,
                                                   const typename C2<R>::T* fe, const typename C2<R>::T* fo,
@@ -385,7 +392,7 @@ __global__ __launch_bounds__(512) void restrict_k(MGGeom m, const typename C2<R>
       for (int rr = 0; rr < 6; ++rr) {
         const int r = 6 * chi + rr;
         const T2 p = PX[((long)l * 12 + r) * Nv + k];
-        const T2 v = F[(long)(f * 12 + r) * m.stride + h];
+        const T2 v = F[fine_idx<R>(f * 12 + r, m.stride, h)];
         ax += p.x * v.x + p.y * v.y;
         ay += p.x * v.y - p.y * v.x;
       }
@@ -435,8 +442,8 @@ __global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>:
     const int hp = ph[l];
     T2* F = (hp & 1) ? fo : fe;
     const int h = hp >> 1;
-    F[(long)r * m.stride + h] = mk<R>(a0x, a0y);
-    F[(long)(12 + r) * m.stride + h] = mk<R>(a1x, a1y);
+    F[fine_idx<R>(r, m.stride, h)] = mk<R>(a0x, a0y);
+    F[fine_idx<R>(12 + r, m.stride, h)] = mk<R>(a1x, a1y);
   }
 }
 

@@ -370,6 +370,35 @@ static void vzero_t(void* y, size_t n, hipStream_t st) {
 }
 void vzero(int prec, void* y, size_t n, hipStream_t st) { DISPATCH(prec, vzero_t, y, n, st); }
 
+// per site and component: the two precisions order a half field's elements differently
+template <class TS, class TD>
+__global__ void convert_field_k(TD* y, int pd, const TS* x, int ps, int nhalves, int vh, int stride) {
+  const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (e >= (long)nhalves * vh) return;
+  const long k = e / vh, h = e - k * vh;
+  const long base = k * 24L * stride;
+  for (int c = 0; c < 24; ++c) {
+    const TS v = x[base + fidx(ps, c, stride, h)];
+    TD w;
+    w.x = v.x;
+    w.y = v.y;
+    y[base + fidx(pd, c, stride, h)] = w;
+  }
+}
+
+void vconvert_field(int prec_dst, void* y, int prec_src, const void* x, int nhalves, int vh, int stride,
+                    hipStream_t st) {
+  const dim3 g((unsigned)(((long)nhalves * vh + 255) / 256)), b(256);
+  if (prec_src == P64 && prec_dst == P32)
+    hipLaunchKernelGGL((convert_field_k<double2, float2>), g, b, 0, st, static_cast<float2*>(y), prec_dst,
+                       static_cast<const double2*>(x), prec_src, nhalves, vh, stride);
+  else if (prec_src == P32 && prec_dst == P64)
+    hipLaunchKernelGGL((convert_field_k<float2, double2>), g, b, 0, st, static_cast<double2*>(y), prec_dst,
+                       static_cast<const float2*>(x), prec_src, nhalves, vh, stride);
+  else
+    vconvert(prec_dst, y, prec_src, x, (size_t)nhalves * 24 * stride, st);  // same precision: same layout
+}
+
 void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st) {
   const dim3 g(vgrid(n)), b(kVB);
   if (prec_src == P64 && prec_dst == P64)

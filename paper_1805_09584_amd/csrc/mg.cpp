@@ -205,13 +205,13 @@ static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfFie
   const int cp = M->cprec;
   const size_t nh = half_elems(c);
   Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp);
-  vconvert(cp, R.o.v, P64, r64.v, nh, st);
+  vconvert_field(cp, R.o.v, P64, r64.v, 1, c->g.vh, c->g.stride, st);
   hipGraphExec_t g = M->use_graphs ? cycle_graph(c, M, m) : nullptr;
   if (g)
     (void)hipGraphLaunch(g, st);
   else
     mg_vcycle(c, M, R, Z, m, c->epsbar, st);
-  vconvert(P64, z64.v, cp, Z.o.v, nh, st);
+  vconvert_field(P64, z64.v, cp, Z.o.v, 1, c->g.vh, c->g.stride, st);
 }
 
 // FGMRES in FP64 for (S + i m Gamma5 tau1) x = rhs, x starting from zero.
@@ -612,9 +612,9 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     for (int r = 0; r < prm->setup_refine; ++r) {
       setup_op();
       for (int i = 0; i < nf; ++i) {
-        vconvert(M->cprec, Rc.base, P64, F[i].base, 2 * nh, st);
+        vconvert_field(M->cprec, Rc.base, P64, F[i].base, 2, c->g.vh, c->g.stride, st);
         mg_vcycle(c, M, Rc, Zc, 0.0, eps_setup, st);
-        vconvert(P64, X.base, M->cprec, Zc.base, 2 * nh, st);
+        vconvert_field(P64, X.base, M->cprec, Zc.base, 2, c->g.vh, c->g.stride, st);
         vnorm2(P64, X.base, 2 * nh, c->vred, d + 6, st);
         vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, 2 * nh, st);
       }

@@ -9,11 +9,12 @@
 //       of the site x with half index h and parity p.
 //   full-lattice vector: even half field followed by the odd half field.
 //   stride = vh rounded up to a multiple of 256, plus 256; padding stays zero.
-//   FP16 fields and links group 4 components per 16-byte word so that the
-//   stencil loads a flavour's spinor in 3 and a link in 3 instructions:
-//   spinor element (c, h) at ((c/4)*stride + h)*4 + c%4 (idx16); link
-//   component k < 8 of direction mu at ((2*mu + k/4)*stride + h)*4 + k%4 and
-//   component 8 at 32*stride + mu*stride + h (lidx16).
+//   FP32 and FP16 fields and links group G = 2 (FP32) or 4 (FP16) components
+//   per 16-byte word, so that the stencil loads a flavour's spinor in 6 or 3
+//   and a link in 5 or 3 instructions: spinor element (c, h) at
+//   ((c/G)*stride + h)*G + c%G (idx32, idx16); link component k < 8 of
+//   direction mu at (((8/G)*mu + k/G)*stride + h)*G + k%G and component 8 at
+//   (32 + mu)*stride + h (lidx32, lidx16).  FP64 keeps one component per array.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,11 +39,21 @@ struct Geom {
 
 enum Prec { P64 = 0, P32 = 1, P16 = 2 };
 
+__host__ __device__ inline long idx32(int c, int stride, long h) {
+  return ((long)(c >> 1) * stride + h) * 2 + (c & 1);
+}
+__host__ __device__ inline long lidx32(int mu, int k, int stride, long h) {
+  return k < 8 ? ((long)(4 * mu + (k >> 1)) * stride + h) * 2 + (k & 1) : (long)(32 + mu) * stride + h;
+}
 __host__ __device__ inline long idx16(int c, int stride, long h) {
   return ((long)(c >> 2) * stride + h) * 4 + (c & 3);
 }
 __host__ __device__ inline long lidx16(int mu, int k, int stride, long h) {
   return k < 8 ? ((long)(2 * mu + (k >> 2)) * stride + h) * 4 + (k & 3) : (long)(32 + mu) * stride + h;
+}
+// element of component c (0..23) at half-site h in a half field of precision prec
+__host__ __device__ inline long fidx(int prec, int c, int stride, long h) {
+  return prec == P64 ? (long)c * stride + h : prec == P32 ? idx32(c, stride, h) : idx16(c, stride, h);
 }
 
 // Epilogues of the hopping kernel.

@@ -241,7 +241,7 @@ static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, dou
   double res = true_residual(c, x, b, sigma, r, st);
   int total = 0, rounds = 0;
   while (res > tol && rounds < 12) {
-    vconvert(P32, r32.v, P64, r.v, n, st);
+    vconvert_field(P32, r32.v, P64, r.v, 1, c->g.vh, c->g.stride, st);
     MmsResult mr;
     std::vector<HalfField> es{e32};
     const double inner = std::max(1e-4, std::min(0.5, 0.5 * tol / res));
@@ -249,7 +249,7 @@ static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, dou
     total += mr.iterations;
     ++rounds;
     if (rc == NDTM_EBREAKDOWN) break;
-    vconvert(P64, e64.v, P32, e32.v, n, st);
+    vconvert_field(P64, e64.v, P32, e32.v, 1, c->g.vh, c->g.stride, st);
     blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e64.v, n, st);
     const double prev = res;
     res = true_residual(c, x, b, sigma, r, st);
@@ -350,7 +350,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       if (!x32[i].v) return fail(c, NDTM_ENOMEM, "solve: workspace");
     }
     HalfField B32 = half_field(c, "sv_b32", P32);
-    vconvert(P32, B32.v, P64, B.v, n, st);
+    vconvert_field(P32, B32.v, P64, B.v, 1, c->g.vh, c->g.stride, st);
     MmsResult mr;
     int rc = run_mmscg_mixed(c, s_mms, x32, B32, std::max(p->tol, 1e-5), p->maxiter, p->poll_every, &mr, st);
     rep->mms_iterations = mr.iterations;
@@ -359,7 +359,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       return rc;
     }
     for (int i = 0; i < n_mms; ++i) {
-      vconvert(P64, xs[i].v, P32, x32[i].v, n, st);
+      vconvert_field(P64, xs[i].v, P32, x32[i].v, 1, c->g.vh, c->g.stride, st);
       double res = 0;
       int extra = 0, rounds = 0;
       int prc = refine_mixed(c, xs[i], B, sig[i], p->tol, p->maxiter, &res, &extra, &rounds, st);

@@ -12,7 +12,10 @@ namespace ndtm {
 // 8 + 2*k*1024 doubles; dst receives the sums (device).  Calls sharing a ws must
 // be ordered on one stream.
 void vzero(int prec, void* y, size_t n, hipStream_t st);
-void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st);
+void vconvert(int prec_dst, void* y, int prec_src, const void* x, size_t n, hipStream_t st);  // flat arrays
+// half fields (nhalves consecutive [24][stride] fields) between FP64 and FP32 element orders
+void vconvert_field(int prec_dst, void* y, int prec_src, const void* x, int nhalves, int vh, int stride,
+                    hipStream_t st);
 void vaxpby(int prec, void* y, double2 a, const void* x, double2 b, size_t n, hipStream_t st);   // y = a x + b y
 void vaxpy_dev(int prec, void* y, const double* adev, double asgn, const void* x, size_t n,
                hipStream_t st);                                                                  // y += asgn*a x
