@@ -4,6 +4,7 @@
 
 #include <map>
 #include <string>
+#include <complex>
 #include <vector>
 
 #include "../../include/ndtm.h"
@@ -113,6 +114,12 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
               const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
               hipStream_t st);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
+// Gram matrix <B_i, B_j> of B = [b, x_1, x_2, ...] (row-major 17 x 17), filled
+// for the first `count` vectors; kept across the multigrid targets of one solve
+struct GramCache {
+  std::vector<std::complex<double>> M;
+  int count = 0;
+};
 // x += CG corrections on (Q^2 + sigma) until the true residual of x meets tol
 int cg_shift(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
              double* res_out, int* iters_out, hipStream_t st);

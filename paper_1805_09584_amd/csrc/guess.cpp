@@ -70,8 +70,34 @@ bool hpd_solve(std::vector<cd> A, std::vector<cd> rhs, int n, double rel_eps, st
 
 }  // namespace
 
+void gram_extend(ndtm_ctx* c, GramCache* g, const HalfField& b, const std::vector<HalfField>& xs, int K,
+                 hipStream_t st) {
+  const size_t n = half_elems(c);
+  if ((int)g->M.size() != 17 * 17) {
+    g->M.assign(17 * 17, 0.0);
+    g->count = 0;
+  }
+  double* d = c->dscal + 2048;
+  // vectors B_0 = b, B_j = x_{j-1}; each new column j holds <B_i, B_j> for i <= j
+  for (int j = g->count; j <= K; ++j) {
+    std::vector<const void*> B(j + 1);
+    B[0] = b.v;
+    for (int i = 1; i <= j; ++i) B[i] = xs[i - 1].v;
+    vmultidot(P64, B.data(), j + 1, B[j], n, c->vred, d, st);
+    (void)hipMemcpyAsync(c->hscal, d, 2 * (j + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    for (int i = 0; i <= j; ++i) {
+      const cd v(c->hscal[2 * i], c->hscal[2 * i + 1]);
+      g->M[i * 17 + j] = v;
+      g->M[j * 17 + i] = std::conj(v);
+    }
+  }
+  g->count = std::max(g->count, K + 1);
+}
+
 int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, double sig_t,
-                     const HalfField& b, const HalfField& x, double* lag_res, double* proj_res, hipStream_t st) {
+                     const HalfField& b, const HalfField& x, GramCache* gram, double* lag_res, double* proj_res,
+                     hipStream_t st) {
   const int K = (int)nodes.size();
   if (K < 1) return fail(c, NDTM_EINVAL, "projection guess: no converged solutions");
   if (K + 1 > 16) return fail(c, NDTM_EINVAL, "projection guess: at most 15 nodes");
@@ -96,25 +122,20 @@ int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::v
   }
   double res = true_residual(c, x, b, sig_t, r, st);
   *lag_res = res;
-  // Gram matrix of B = [b, x_1..x_K]; column j of M holds <B_i, B_j>
+  // Gram matrix of B = [b, x_1..x_K], kept across the targets of one solve
+  gram_extend(c, gram, b, xs, K, st);
+  auto M = [&](int i, int j) { return gram->M[i * 17 + j]; };
   std::vector<const void*> B(K + 1);
   B[0] = b.v;
   for (int i = 0; i < K; ++i) B[1 + i] = xs[i].v;
   double* d = c->dscal + 2048;
-  for (int j = 0; j <= K; ++j) vmultidot(P64, B.data(), K + 1, B[j], n, c->vred, d + 2 * (K + 1) * j, st);
-  NDTM_HIP(c, hipMemcpyAsync(c->hscal, d, 2 * (K + 1) * (K + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
-  NDTM_HIP(c, hipStreamSynchronize(st));
-  std::vector<cd> M((K + 1) * (K + 1));
-  for (int j = 0; j <= K; ++j)
-    for (int i = 0; i <= K; ++i) M[i * (K + 1) + j] = cd(c->hscal[2 * ((K + 1) * j + i)], c->hscal[2 * ((K + 1) * j + i) + 1]);
   std::vector<double> dl(K);
   for (int i = 0; i < K; ++i) dl[i] = nodes[i] - sig_t;
   // G_ij = <w_i, w_j>, w_i = dl_i x_i - b
   std::vector<cd> G(K * K);
   for (int i = 0; i < K; ++i)
     for (int j = 0; j < K; ++j)
-      G[i * K + j] = M[0] - dl[j] * M[j + 1] - dl[i] * M[(i + 1) * (K + 1)] +
-                     dl[i] * dl[j] * M[(i + 1) * (K + 1) + j + 1];
+      G[i * K + j] = M(0, 0) - dl[j] * M(0, j + 1) - dl[i] * M(i + 1, 0) + dl[i] * dl[j] * M(i + 1, j + 1);
   for (int step = 0; step < 3 && std::isfinite(res) && res > 0; ++step) {
     // g_i = <w_i, r> = dl_i <x_i, r> - <b, r>
     vmultidot(P64, B.data(), K + 1, r.v, n, c->vred, d, st);
@@ -126,8 +147,13 @@ int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::v
     std::vector<cd> y;
     if (!hpd_solve(G, g, K, 1e-13, &y)) break;
     blas_copy((double2*)xb.v, (const double2*)x.v, n, st);
-    for (int i = 0; i < K; ++i)
-      blas_axpy((double2*)x.v, make_double2(y[i].real(), y[i].imag()), (const double2*)xs[i].v, n, st);
+    // x += sum_i y_i x_i in one pass (coefficients staged through pinned memory)
+    for (int i = 0; i < K; ++i) {
+      c->hscal[2 * i] = y[i].real();
+      c->hscal[2 * i + 1] = y[i].imag();
+    }
+    NDTM_HIP(c, hipMemcpyAsync(d, c->hscal, 2 * K * sizeof(double), hipMemcpyHostToDevice, st));
+    vlincomb_dev(P64, x.v, B.data() + 1, K, d, 1, n, st);
     const double nres = true_residual(c, x, b, sig_t, r, st);
     if (!(nres < 0.9 * res)) {
       blas_copy((double2*)x.v, (const double2*)xb.v, n, st);

@@ -17,7 +17,8 @@ struct Basis {
   const T2* v[kMaxBasis];
 };
 
-// reductions: at most 256 blocks so that the completion counter sees few atomics
+// reductions: at most 256 blocks (the completion of each block costs a release
+// fence and an atomic on one counter, which grows with the block count)
 inline unsigned rgrid(size_t n) {
   size_t g = (n + 4 * kVB - 1) / (4 * kVB);
   if (g > 256) g = 256;
@@ -56,7 +57,9 @@ __device__ __forceinline__ double bsum(double v) {
   return s;
 }
 
-#define GRID_LOOP(i, n) for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
+// grid-stride loop, unrolled so that several independent loads per thread are in flight
+#define GRID_LOOP(i, n)  \
+  _Pragma("unroll 4") for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
 template <class A, class B>
 __global__ void convert_k(B* y, const A* x, size_t n) {
@@ -96,9 +99,11 @@ __global__ void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t 
 // resets the counter.  ws = [counter (8 doubles)][partials width x gridDim].
 __device__ bool last_block_sum(double* ws, int width, double* dst) {
   __shared__ bool last;
-  __threadfence();
+  // the block's partials are written by thread 0 (after the block sum), so
+  // only its wave needs the release fence before the counter
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     unsigned* cnt = reinterpret_cast<unsigned*>(ws);
     last = atomicAdd(cnt, 1u) == gridDim.x - 1;
   }

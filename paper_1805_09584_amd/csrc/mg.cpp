@@ -387,7 +387,8 @@ int guess_mlp(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<H
               const HalfField& b, const std::vector<double>& lag, std::vector<double>* coef, double* pred_mlp,
               double* pred_lag, hipStream_t st);
 int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::vector<HalfField>& xs, double sig_t,
-                     const HalfField& b, const HalfField& x, double* lag_res, double* proj_res, hipStream_t st);
+                     const HalfField& b, const HalfField& x, GramCache* gram, double* lag_res, double* proj_res,
+                     hipStream_t st);
 
 int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std::vector<HalfField>& xs,
                     const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st) {
@@ -397,6 +398,7 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
   const int nsh = (int)sig.size();
   const size_t n = half_elems(c);
   int status = NDTM_OK;
+  GramCache gram;
   for (int t = n_mms; t < nsh; ++t) {
     auto tg0 = std::chrono::steady_clock::now();
     // ---- initial guess from the converged solutions (descending shifts) ----
@@ -422,7 +424,7 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
       std::vector<double> all(sig.begin(), sig.begin() + t);
       std::vector<HalfField> xall(xs.begin(), xs.begin() + t);
       double lres = -1, pres = -1;
-      const int grc = guess_projection(c, all, xall, sig[t], b, xs[t], &lres, &pres, st);
+      const int grc = guess_projection(c, all, xall, sig[t], b, xs[t], &gram, &lres, &pres, st);
       if (grc != NDTM_OK) return grc;
       rep->lagrange_res[t] = lres;
     } else if (p->guess == NDTM_GUESS_ZERO) {
