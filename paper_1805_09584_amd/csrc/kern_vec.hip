@@ -62,18 +62,18 @@ __device__ __forceinline__ double bsum(double v) {
   _Pragma("unroll 4") for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
 template <class A, class B>
-__global__ void convert_k(B* y, const A* x, size_t n) {
+__global__ __launch_bounds__(256) void convert_k(B* y, const A* x, size_t n) {
   GRID_LOOP(i, n) st2(y, i, ld2(x, i));
 }
 
 template <class T2>
-__global__ void zero_k(T2* y, size_t n) {
+__global__ __launch_bounds__(256) void zero_k(T2* y, size_t n) {
   GRID_LOOP(i, n) st2(y, i, make_double2(0, 0));
 }
 
 // y = a x + b y with a = sa * coef[0..1] (device) or host value
 template <class T2>
-__global__ void axpby_k(T2* y, double2 a, const double* adev, double asgn, const T2* x, double2 b, size_t n) {
+__global__ __launch_bounds__(256) void axpby_k(T2* y, double2 a, const double* adev, double asgn, const T2* x, double2 b, size_t n) {
   double2 aa = a;
   if (adev) aa = make_double2(asgn * adev[0], asgn * adev[1]);
   GRID_LOOP(i, n) {
@@ -85,7 +85,7 @@ __global__ void axpby_k(T2* y, double2 a, const double* adev, double asgn, const
 
 // y *= 1 / sqrt(*nrm2)
 template <class T2>
-__global__ void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t n) {
+__global__ __launch_bounds__(256) void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t n) {
   const double s = *nrm2 > 1e-300 ? 1.0 / sqrt(*nrm2) : 0.0;
   GRID_LOOP(i, n) {
     const double2 v = ld2(x, i);
@@ -127,7 +127,7 @@ __device__ bool last_block_sum(double* ws, int width, double* dst) {
 }
 
 template <class T2>
-__global__ void norm2_k(const T2* x, size_t n, double* ws, double* dst) {
+__global__ __launch_bounds__(256) void norm2_k(const T2* x, size_t n, double* ws, double* dst) {
   double s = 0;
   GRID_LOOP(i, n) {
     const double2 v = ld2(x, i);
@@ -140,7 +140,7 @@ __global__ void norm2_k(const T2* x, size_t n, double* ws, double* dst) {
 
 // partials [2][nblk]: <x,y> re, im
 template <class T2>
-__global__ void dot_k(const T2* x, const T2* y, size_t n, double* ws, double* dst) {
+__global__ __launch_bounds__(256) void dot_k(const T2* x, const T2* y, size_t n, double* ws, double* dst) {
   double* part = ws + 8;
   double re = 0, im = 0;
   GRID_LOOP(i, n) {
@@ -158,12 +158,14 @@ __global__ void dot_k(const T2* x, const T2* y, size_t n, double* ws, double* ds
 }
 
 template <class T2, int KM>
-__global__ void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* ws, double* dst) {
+__global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* ws, double* dst) {
   double* part = ws + 8;
   double re[KM], im[KM];
 #pragma unroll
   for (int j = 0; j < KM; ++j) re[j] = im[j] = 0;
-  GRID_LOOP(i, n) {
+  // up to KM + 1 independent loads per element already; no further unrolling
+#pragma unroll 1
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const double2 wi = ld2(w, i);
 #pragma unroll
     for (int j = 0; j < KM; ++j)
@@ -195,7 +197,7 @@ __global__ void finalize_k(const double* part, int nparts, double* dst, int dst_
 
 // w -= sum_j coef[j] V_j   (coef complex, 2 doubles each, device)
 template <class T2>
-__global__ void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n) {
+__global__ __launch_bounds__(256) void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n) {
   GRID_LOOP(i, n) {
     double2 acc = ld2(w, i);
     for (int j = 0; j < k; ++j) {
@@ -209,7 +211,7 @@ __global__ void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size
 
 // w -= sum_j coef[j] V_j and ||w||^2 into dst (single launch)
 template <class T2>
-__global__ void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n, double* ws,
+__global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n, double* ws,
                                   double* dst) {
   double s = 0;
   GRID_LOOP(i, n) {
@@ -231,7 +233,7 @@ __global__ void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef,
 // minimal-residual coefficient omega = <t, s> / <t, t> (single launch; dst[0..1] = omega,
 // dst[2..4] = re<t,s>, im<t,s>, <t,t>)
 template <class T2>
-__global__ void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws, double* dst) {
+__global__ __launch_bounds__(256) void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws, double* dst) {
   double re = 0, im = 0, tt = 0;
   GRID_LOOP(i, n) {
     const double2 a = ld2(t, i), b = ld2(sv, i);
@@ -257,7 +259,7 @@ __global__ void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws,
 
 // z += omega s ; s -= omega t  (omega complex at dev[0..1])
 template <class T2>
-__global__ void mr_update_k(T2* z, T2* sv, const T2* t, const double* om, int update_s, size_t n) {
+__global__ __launch_bounds__(256) void mr_update_k(T2* z, T2* sv, const T2* t, const double* om, int update_s, size_t n) {
   const double2 w = make_double2(om[0], om[1]);
   GRID_LOOP(i, n) {
     const double2 sval = ld2(sv, i);
@@ -273,7 +275,7 @@ __global__ void mr_update_k(T2* z, T2* sv, const T2* t, const double* om, int up
 
 // y (+)= sum_j coef[j] V_j   (coef device)
 template <class T2>
-__global__ void lincomb_dev_k(T2* y, Basis<T2> V, int k, const double* coef, int accumulate, size_t n) {
+__global__ __launch_bounds__(256) void lincomb_dev_k(T2* y, Basis<T2> V, int k, const double* coef, int accumulate, size_t n) {
   GRID_LOOP(i, n) {
     double2 acc = accumulate ? ld2(y, i) : make_double2(0, 0);
     for (int j = 0; j < k; ++j) {
@@ -377,7 +379,7 @@ void vzero(int prec, void* y, size_t n, hipStream_t st) { DISPATCH(prec, vzero_t
 
 // per site and component: the two precisions order a half field's elements differently
 template <class TS, class TD>
-__global__ void convert_field_k(TD* y, int pd, const TS* x, int ps, int nhalves, int vh, int stride) {
+__global__ __launch_bounds__(256) void convert_field_k(TD* y, int pd, const TS* x, int ps, int nhalves, int vh, int stride) {
   const long e = blockIdx.x * (long)blockDim.x + threadIdx.x;
   if (e >= (long)nhalves * vh) return;
   const long k = e / vh, h = e - k * vh;
@@ -471,6 +473,8 @@ static void vmultidot_t(const void* const* V, int k, const void* w, size_t n, do
     hipLaunchKernelGGL((multidot_k<T2, 8>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
   else if (k <= 16)
     hipLaunchKernelGGL((multidot_k<T2, 16>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
+  else if (k <= 24)
+    hipLaunchKernelGGL((multidot_k<T2, 24>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
   else
     hipLaunchKernelGGL((multidot_k<T2, kMaxBasis>), dim3(g), dim3(kVB), 0, st, B, k, wp, n, part, dst);
 }
