@@ -293,6 +293,9 @@ def main():
         out["dslash_large"] = dslash_block(nd, U, dims, args.dslash_reps)
     if not args.no_copy:
         out["copy_ceiling_gbs"] = copy_ceiling()
+        cp, rd, wr = ctx.ndtm_stream_bandwidth(1 << 30, 10)
+        out["stream_ceiling_gbs"] = {"copy": cp, "read": rd, "write": wr,
+                                     "note": "library's 16-byte non-temporal streaming kernels, 1 GiB"}
     if not args.no_cpu_baseline:
         it = results["plain"]["mms_iterations"] if "plain" in results else head["mms_iterations"]
         out["cpu_baseline"] = cpu_baseline(cfg, U, b, it, args.cpu_iters)

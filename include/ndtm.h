@@ -93,7 +93,11 @@ long long ndtm_half_volume(const ndtm_ctx* ctx);
 
 /* Copies and repacks the gauge field (eq:Wilson's U_mu(x)) from U_dev
  * (complex128 [V][4][3][3], device).  FP32 and FP16 copies for the mixed form
- * are made at the same time.  Invalidates any multigrid setup. */
+ * are made at the same time.  If every link's third row equals
+ * conj(row 0 x row 1) to 1e-14 (SU(3) links), the stencil loads two rows per
+ * link and rebuilds the third; otherwise it loads all three.  Any complex 3x3
+ * links are accepted.  Synchronises the stream; invalidates any multigrid
+ * setup. */
 int ndtm_set_gauge(ndtm_ctx* ctx, const void* U_dev, void* stream);
 
 /* kappa > 0, a = 1/(2 kappa); requires a^2 + mubar^2 - epsbar^2 != 0 (the
@@ -267,6 +271,15 @@ enum {
   NDTM_PROF_COARSE = 7,     /* coarse stencil, Vc x 9.5 (2 Nv)^2 complex + 2 coarse vectors */
   NDTM_PROF_NCLASS = 8
 };
+/* Streaming reference on the context's device: a copy (read + write), a read
+ * and a write of `bytes` (>= 1 MiB, multiple of 16) with 16-byte non-temporal
+ * accesses per lane, each repeated `reps` times and timed with HIP events; the
+ * bandwidths in GB/s are written to the three host doubles.  Allocates and
+ * frees two device buffers of `bytes`; synchronises the device.  It gives the
+ * measured ceiling that the library's bandwidth-bound kernels are compared with. */
+int ndtm_stream_bandwidth(ndtm_ctx* ctx, size_t bytes, int reps, double* copy_gbs, double* read_gbs,
+                          double* write_gbs);
+
 /* mask: bit k enables timing of kernel class k (NDTM_PROF_*); 0 disables. */
 int ndtm_profile_enable(ndtm_ctx* ctx, int mask);
 int ndtm_profile_read(ndtm_ctx* ctx, int kernel_class, double* total_ms, long long* launches,

@@ -107,6 +107,8 @@ def load_library():
         "ndtm_mlp_train": (i, [vp, i, fp, fp, fp, fp, i, C.c_float, fp]),
         "ndtm_mlp_sample": (i, [vp, i, C.POINTER(vp), C.POINTER(C.c_double), d, vp, fp, fp, fp, fp,
                                 C.POINTER(C.c_double), vp]),
+        "ndtm_stream_bandwidth": (i, [vp, C.c_size_t, i, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
         "ndtm_profile_enable": (i, [vp, i]),
         "ndtm_profile_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_double), i]),
@@ -298,6 +300,12 @@ class Context:
         return feat, mask, G, h, list(info)
 
     # -- profiling --------------------------------------------------------------
+    def ndtm_stream_bandwidth(self, nbytes=1 << 30, reps=10):
+        """(copy, read, write) GB/s of the streaming reference kernels on this device."""
+        out = [C.c_double(), C.c_double(), C.c_double()]
+        self._check(self.lib.ndtm_stream_bandwidth(self.h, nbytes, reps, *[C.byref(o) for o in out]))
+        return tuple(o.value for o in out)
+
     def ndtm_profile_enable(self, mask=0xFF):
         """Bit k of mask enables event timing of kernel class k (PROF_CLASSES); 0 disables."""
         self._check(self.lib.ndtm_profile_enable(self.h, int(mask)))

@@ -1,5 +1,6 @@
 // C-ABI entry points (context, gauge field, parameters, operator application,
 // profiling) and the internal operator helpers.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -240,6 +241,18 @@ int ndtm_set_gauge(ndtm_ctx* c, const void* U_dev, void* stream) {
                     (float2*)c->U[1][0], (float2*)c->U[1][1], (__half2*)c->U[2][0], (__half2*)c->U[2][1],
                     st);
   NDTM_HIP(c, hipGetLastError());
+  // SU(3) check: the stencil rebuilds the third row of each link when every
+  // stored third row equals conj(row 0 x row 1) to 1e-14
+  {
+    const int nb = launch_su3_check(c->V, static_cast<const double2*>(U_dev), c->partials, st);
+    std::vector<double> part(nb);
+    NDTM_HIP(c, hipMemcpyAsync(part.data(), c->partials, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    double dev = 0;
+    for (double v : part) dev = std::isfinite(v) ? std::max(dev, v) : 1e300;
+    c->op.recon12 = dev <= 1e-14 ? 1 : 0;
+    c->su3_dev = dev;
+  }
   c->have_gauge = true;
   ndtm_mg_free(c);
   return NDTM_OK;
@@ -327,6 +340,45 @@ int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, do
     default:
       return fail(c, NDTM_EINVAL, "apply: unknown operator");
   }
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_stream_bandwidth(ndtm_ctx* c, size_t bytes, int reps, double* copy_gbs, double* read_gbs,
+                          double* write_gbs) {
+  if (!c) return NDTM_EINVAL;
+  if (bytes < (1u << 20) || (bytes & 15) || reps < 1 || !copy_gbs || !read_gbs || !write_gbs)
+    return fail(c, NDTM_EINVAL, "stream_bandwidth: bytes >= 1 MiB, multiple of 16; reps >= 1");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  void *a = nullptr, *b = nullptr;
+  unsigned* sink = nullptr;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess || hipMalloc(&sink, 64) != hipSuccess) {
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return fail(c, NDTM_ENOMEM, "stream_bandwidth: buffers");
+  }
+  (void)hipMemset(a, 0x5a, bytes);
+  (void)hipMemset(b, 0, bytes);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  double* out[3] = {copy_gbs, read_gbs, write_gbs};
+  for (int kind = 0; kind < 3; ++kind) {
+    for (int w = 0; w < 2; ++w) launch_stream(kind, a, b, bytes, sink, nullptr);
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps; ++r) launch_stream(kind, a, b, bytes, sink, nullptr);
+    (void)hipEventRecord(e1, nullptr);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double moved = (kind == 0 ? 2.0 : 1.0) * (double)bytes * reps;
+    *out[kind] = ms > 0 ? moved / (ms * 1e-3) / 1e9 : 0.0;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  (void)hipFree(sink);
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }

@@ -30,6 +30,7 @@ struct ndtm_ctx {
   bool have_gauge = false, have_params = false;
   double kappa = 0, mubar = 0, epsbar = 0;
   ndtm::OpParams op{};
+  double su3_dev = 0;  // max deviation of the stored links from SU(3) row structure
   std::vector<double> shifts;
   void* U[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
   double* partials = nullptr;

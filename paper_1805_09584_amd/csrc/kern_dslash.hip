@@ -221,7 +221,7 @@ struct Raw {
   float sc;
 };
 
-template <int MU, class S, class L>
+template <int MU, bool R12, class S, class L>
 __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
                                          int hl) {
   if constexpr (kGrouped<S>) {
@@ -235,27 +235,30 @@ __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, i
     }
     if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
     const unsigned vl = (unsigned)hl * 16u;
+    // rows 0-1 (components 0..5) always; with R12 row 2 is rebuilt in hop_compute
+    constexpr int NLG = R12 ? (6 + G - 1) / G : 8 / G;
 #pragma unroll
-    for (int g = 0; g < 8 / G; ++g) {
+    for (int g = 0; g < NLG; ++g) {
       const Grp<L> u = ld_group<true>(U, (8 / G) * MU + g, A.stride, vl);
 #pragma unroll
-      for (int q = 0; q < G; ++q) r.u[G * g + q] = u.e[q];
+      for (int q = 0; q < G; ++q)
+        if (G * g + q < 9) r.u[G * g + q] = u.e[q];
     }
-    r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
+    if constexpr (!R12) r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
   } else {
     const unsigned vo = flav_off<S>(f, A.stride, hn);
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
     const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+    for (int k = 0; k < (R12 ? 6 : 9); ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
   }
 }
 
 // One of the eight hops: project, colour-multiply, reconstruct, accumulate.
 // SIGN: the hop carries the sign sg of an antiperiodic time boundary; the
 // FP16 spinor scale and sg multiply the colour products once, at the end.
-template <int MU, bool FWD, bool SIGN, class S, class L, class R>
+template <int MU, bool FWD, bool SIGN, bool R12, class S, class L, class R>
 __device__ __forceinline__ void hop_compute(cx<R> (&acc)[4][3], const Raw<S, L>& raw, R sg) {
   cx<R> p[4][3];
 #pragma unroll
@@ -281,9 +284,18 @@ __device__ __forceinline__ void hop_compute(cx<R> (&acc)[4][3], const Raw<S, L>&
   }
   cx<R> u[3][3];
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+  for (int r = 0; r < (R12 ? 2 : 3); ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[r][c] = cvt(raw.u[r * 3 + c]);
+  if constexpr (R12) {
+    // SU(3): row 2 = conj(row 0 x row 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int a = (c + 1) % 3, b = (c + 2) % 3;
+      const cx<R> x = mul(u[0][a], u[1][b]) - mul(u[0][b], u[1][a]);
+      u[2][c] = {x.x, -x.y};
+    }
+  }
   cx<R> g0[3], g1[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -350,7 +362,7 @@ __device__ __forceinline__ void block_reduce_store(double v, double* partials) {
   }
 }
 
-template <class S, class L, int EPI, int RED>
+template <class S, class L, int EPI, int RED, bool R12>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   using R = typename RealOf<S>::T;
   // XCD-aware block order: XCD k = b % 8 gets one contiguous range of logical blocks.
@@ -409,40 +421,40 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
       // FP64: the operands of one hop already take ~90 registers; a second
       // buffer would leave one wave per SIMD, so hops are loaded one at a time
       Raw<S, L> r;
-      load_raw<0>(r, A, f, ht_p, A.Uo, h);
-      hop_compute<0, true, true>(acc, r, sg_tp);
-      load_raw<0>(r, A, f, ht_m, A.Ui, ht_m);
-      hop_compute<0, false, true>(acc, r, sg_tm);
-      load_raw<1>(r, A, f, hx_p, A.Uo, h);
-      hop_compute<1, true, false>(acc, r, R(1));
-      load_raw<1>(r, A, f, hx_m, A.Ui, hx_m);
-      hop_compute<1, false, false>(acc, r, R(1));
-      load_raw<2>(r, A, f, hy_p, A.Uo, h);
-      hop_compute<2, true, false>(acc, r, R(1));
-      load_raw<2>(r, A, f, hy_m, A.Ui, hy_m);
-      hop_compute<2, false, false>(acc, r, R(1));
-      load_raw<3>(r, A, f, hz_p, A.Uo, h);
-      hop_compute<3, true, false>(acc, r, R(1));
-      load_raw<3>(r, A, f, hz_m, A.Ui, hz_m);
-      hop_compute<3, false, false>(acc, r, R(1));
+      load_raw<0, R12>(r, A, f, ht_p, A.Uo, h);
+      hop_compute<0, true, true, R12>(acc, r, sg_tp);
+      load_raw<0, R12>(r, A, f, ht_m, A.Ui, ht_m);
+      hop_compute<0, false, true, R12>(acc, r, sg_tm);
+      load_raw<1, R12>(r, A, f, hx_p, A.Uo, h);
+      hop_compute<1, true, false, R12>(acc, r, R(1));
+      load_raw<1, R12>(r, A, f, hx_m, A.Ui, hx_m);
+      hop_compute<1, false, false, R12>(acc, r, R(1));
+      load_raw<2, R12>(r, A, f, hy_p, A.Uo, h);
+      hop_compute<2, true, false, R12>(acc, r, R(1));
+      load_raw<2, R12>(r, A, f, hy_m, A.Ui, hy_m);
+      hop_compute<2, false, false, R12>(acc, r, R(1));
+      load_raw<3, R12>(r, A, f, hz_p, A.Uo, h);
+      hop_compute<3, true, false, R12>(acc, r, R(1));
+      load_raw<3, R12>(r, A, f, hz_m, A.Ui, hz_m);
+      hop_compute<3, false, false, R12>(acc, r, R(1));
     } else {
     Raw<S, L> ra, rb;
-    load_raw<0>(ra, A, f, ht_p, A.Uo, h);
-    load_raw<0>(rb, A, f, ht_m, A.Ui, ht_m);
-    hop_compute<0, true, true>(acc, ra, sg_tp);
-    load_raw<1>(ra, A, f, hx_p, A.Uo, h);
-    hop_compute<0, false, true>(acc, rb, sg_tm);
-    load_raw<1>(rb, A, f, hx_m, A.Ui, hx_m);
-    hop_compute<1, true, false>(acc, ra, R(1));
-    load_raw<2>(ra, A, f, hy_p, A.Uo, h);
-    hop_compute<1, false, false>(acc, rb, R(1));
-    load_raw<2>(rb, A, f, hy_m, A.Ui, hy_m);
-    hop_compute<2, true, false>(acc, ra, R(1));
-    load_raw<3>(ra, A, f, hz_p, A.Uo, h);
-    hop_compute<2, false, false>(acc, rb, R(1));
-    load_raw<3>(rb, A, f, hz_m, A.Ui, hz_m);
-    hop_compute<3, true, false>(acc, ra, R(1));
-    hop_compute<3, false, false>(acc, rb, R(1));
+    load_raw<0, R12>(ra, A, f, ht_p, A.Uo, h);
+    load_raw<0, R12>(rb, A, f, ht_m, A.Ui, ht_m);
+    hop_compute<0, true, true, R12>(acc, ra, sg_tp);
+    load_raw<1, R12>(ra, A, f, hx_p, A.Uo, h);
+    hop_compute<0, false, true, R12>(acc, rb, sg_tm);
+    load_raw<1, R12>(rb, A, f, hx_m, A.Ui, hx_m);
+    hop_compute<1, true, false, R12>(acc, ra, R(1));
+    load_raw<2, R12>(ra, A, f, hy_p, A.Uo, h);
+    hop_compute<1, false, false, R12>(acc, rb, R(1));
+    load_raw<2, R12>(rb, A, f, hy_m, A.Ui, hy_m);
+    hop_compute<2, true, false, R12>(acc, ra, R(1));
+    load_raw<3, R12>(ra, A, f, hz_p, A.Uo, h);
+    hop_compute<2, false, false, R12>(acc, rb, R(1));
+    load_raw<3, R12>(rb, A, f, hz_m, A.Ui, hz_m);
+    hop_compute<3, true, false, R12>(acc, ra, R(1));
+    hop_compute<3, false, false, R12>(acc, rb, R(1));
     }
   }
 
@@ -610,7 +622,11 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.hop_coef = hop_coef;
   A.sigma = sigma;
   const dim3 grid(hop_grid(g)), block(kBlock);
-#define NDTM_HOP(E, RD) hipLaunchKernelGGL((hop_kernel<S, L, E, RD>), grid, block, 0, st, A)
+#define NDTM_HOP(E, RD)                                                            \
+  do {                                                                             \
+    if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true>), grid, block, 0, st, A); \
+    else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false>), grid, block, 0, st, A);           \
+  } while (0)
   switch (epi) {
     case EPI_PLAIN: NDTM_HOP(EPI_PLAIN, RED_NONE); break;
     case EPI_AINV: NDTM_HOP(EPI_AINV, RED_NONE); break;

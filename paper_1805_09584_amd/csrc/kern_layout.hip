@@ -129,7 +129,35 @@ __global__ void g5t1_k(Geom g, const double2* in, double2* out) {
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// SU(3) links satisfy row 2 = conj(row 0 x row 1); the deviation decides
+// whether the stencil may rebuild the third row instead of loading it
+__global__ __launch_bounds__(256) void su3_check_k(long nlinks, const double2* U, double* part) {
+  double dev = 0;
+  for (long l = blockIdx.x * (long)blockDim.x + threadIdx.x; l < nlinks; l += (long)gridDim.x * blockDim.x) {
+    const double2* u = U + l * 9;
+    for (int c = 0; c < 3; ++c) {
+      const int a = (c + 1) % 3, b = (c + 2) % 3;
+      // (row0 x row1)_c = u0a u1b - u0b u1a
+      const double2 p = u[a], q = u[3 + b], r = u[b], t = u[3 + a];
+      const double xr = p.x * q.x - p.y * q.y - (r.x * t.x - r.y * t.y);
+      const double xi = p.x * q.y + p.y * q.x - (r.x * t.y + r.y * t.x);
+      const double2 w = u[6 + c];
+      dev = fmax(dev, fmax(fabs(w.x - xr), fabs(w.y + xi)));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_down(dev, off));
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(ws[0], ws[1]), fmax(ws[2], ws[3]));
+}
+
 }  // namespace
+
+int launch_su3_check(long V, const double2* U, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(su3_check_k, dim3(1024), dim3(256), 0, st, 4 * V, U, part);
+  return 1024;
+}
 
 void launch_g5t1(const Geom& g, const double2* in, double2* out, hipStream_t st) {
   hipLaunchKernelGGL(g5t1_k, dim3(nblk(g.vh, 256)), dim3(256), 0, st, g, in, out);

@@ -68,6 +68,7 @@ enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2 };
 
 struct OpParams {
   double a, mubar, epsbar, inv_den;
+  int recon12;  // links are SU(3): the stencil loads two rows and rebuilds the third
 };
 
 // A precision-tagged half field (device pointers).
@@ -90,6 +91,11 @@ int hop_grid(const Geom& g);
 void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* U64o, float2* U32e,
                        float2* U32o, __half2* U16e, __half2* U16o, hipStream_t st);
 // canonical [V/2][24] (complex128) <-> internal half field (any precision)
+// max over all links of |row 2 - conj(row 0 x row 1)| of canonical links (V sites x 4),
+// per-block maxima written to part[0..nblk) (nblk = 1024); returns nblk
+int launch_su3_check(long V, const double2* U, double* part, hipStream_t st);
+// streaming reference kernels: kind 0 copy a -> b, 1 read a, 2 write b (bytes multiple of 16)
+void launch_stream(int kind, const void* a, void* b, size_t bytes, unsigned* sink, hipStream_t st);
 void launch_pack_half(const Geom& g, const double2* canon, const HalfField& f, hipStream_t st);
 void launch_unpack_half(const Geom& g, const HalfField& f, double2* canon, hipStream_t st);
 // canonical full lattice [V][24] <-> even + odd half fields

@@ -99,3 +99,25 @@ def test_errors_and_state(nd):
     with pytest.raises(nd.NdtmError):
         nd.Context((3, 4, 4, 4))
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_non_su3_links_use_all_rows(nd, prec):
+    """Links multiplied by a random U(1) phase per link are unitary but not SU(3):
+    their third row is not conj(row 0 x row 1), so the stencil must load all
+    three rows.  Parity with the oracle at each precision's bar, and the same
+    field without the phases still passes (the two-row path)."""
+    print(f"non-SU(3) links prec={prec}", flush=True)
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 23, 0.3)
+    ph = np.exp(1j * np.random.default_rng(3).uniform(-np.pi, np.pi, U.shape[:2]))
+    x = synth.gaussian_spinor(dims, 6)
+    for links in (U * ph[:, :, None, None], U):
+        op = NDOperator(Lattice(dims, links), K, MB, EB)
+        ctx = nd.Context(dims)
+        ctx.ndtm_set_gauge(dev(links))
+        ctx.ndtm_set_params(K, MB, EB)
+        got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT, dev(x), prec=prec))
+        want = op.Q_hat(x)
+        assert rel_err(got, want) < TOL[prec], (prec, rel_err(got, want))
+        ctx.close()
