@@ -264,7 +264,9 @@ enum {
   NDTM_PROF_HOP_F64 = 0,  /* stencil pass, per output site 1920 B (+384 per extra site vector) */
   NDTM_PROF_HOP_F32 = 1,  /* 960 B (+192) */
   NDTM_PROF_HOP_F16 = 2,  /* 488 B (+100) */
-  NDTM_PROF_MMS_UPDATE = 3, /* fused shift update, (3 + 4 N_active) x 384 B per odd site */
+  NDTM_PROF_MMS_UPDATE = 3, /* fused shift update, (1 + 4 N_active) x 384 B per odd site
+                               (r, p in, p out; x_s, p_s in and out; the base shift's
+                               direction is p itself) */
   NDTM_PROF_MMS_RESID = 4,  /* r -= alpha w with ||r||^2, 3 x 384 B per odd site */
   NDTM_PROF_RESTRICT = 5,   /* restriction, V x (12 Nv + 24) complex of the cycle precision */
   NDTM_PROF_PROLONG = 6,    /* prolongation, same bytes as the restriction */

@@ -270,13 +270,25 @@ struct ShiftPtrs {
   double2* p[kMaxShifts];
 };
 
-__global__ void mms_update_p_k(const double2* r, double2* p, ShiftPtrs P, int nsh, const double* S, size_t n) {
+// sb: the base shift (delta = 0).  Its zeta stays 1, so its direction equals the
+// base direction p and is not stored separately: x_sb += alpha p before p moves.
+__global__ void mms_update_p_k(const double2* r, double2* p, ShiftPtrs P, int nsh, int sb, const double* S,
+                               size_t n) {
   const double beta = S[MS_BETA];
   const bool any_before = S[MS_ALPHA] != 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const double2 ri = r[i];
+    const double2 pold = p[i];
     for (int s = 0; s < nsh; ++s) {
       if (S[MS_ACT + s] == 0.0) continue;
+      if (s == sb) {
+        const double as = S[MS_ALPHA_S + s];
+        double2 xs = P.x[s][i];
+        xs.x += as * pold.x;
+        xs.y += as * pold.y;
+        P.x[s][i] = xs;
+        continue;
+      }
       const double as = S[MS_ALPHA_S + s], bs = S[MS_BETA_S + s], z = S[MS_ZETA + s];
       double2 ps = P.p[s][i];
       double2 xs = P.x[s][i];
@@ -287,12 +299,7 @@ __global__ void mms_update_p_k(const double2* r, double2* p, ShiftPtrs P, int ns
       P.x[s][i] = xs;
       P.p[s][i] = ps;
     }
-    if (any_before) {
-      double2 pi = p[i];
-      pi.x = ri.x + beta * pi.x;
-      pi.y = ri.y + beta * pi.y;
-      p[i] = pi;
-    }
+    if (any_before) p[i] = make_double2(ri.x + beta * pold.x, ri.y + beta * pold.y);
   }
 }
 
@@ -446,14 +453,14 @@ void mms_update_r(double2* r, const double2* w, const double* S, size_t n, doubl
 void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts);
 }
-void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, const double* S,
-                  size_t n, hipStream_t st) {
+void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
+                  const double* S, size_t n, hipStream_t st) {
   ShiftPtrs P;
   for (int s = 0; s < nsh; ++s) {
     P.x[s] = xs[s];
     P.p[s] = ps[s];
   }
-  hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, S, n);
+  hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, sb, S, n);
 }
 int red_grid(size_t n) { return (int)grid_for(n); }
 void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,

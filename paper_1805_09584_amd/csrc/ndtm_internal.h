@@ -137,7 +137,9 @@ void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st);
 void mms_update_r(double2* r, const double2* w, const double* S, size_t n, double* partials,
                   hipStream_t st);
 void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st);
-void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh,
+// p_s, x_s of every active shift in one pass; sb = the base shift (delta 0), whose
+// direction is p itself and whose ps[sb] is not used
+void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
                   const double* S, size_t n, hipStream_t st);
 // mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
 void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,

@@ -28,6 +28,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   const int nsh = (int)sigmas.size();
   const size_t n = half_elems(c);
   const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
+  const int sb = (int)(std::min_element(sigmas.begin(), sigmas.end()) - sigmas.begin());
   HalfField r = half_field(c, "cg_r", P64), p = half_field(c, "cg_p", P64), w = half_field(c, "cg_w", P64);
   HalfField u = half_field(c, "cg_u", P64), te = half_field(c, "cg_te", P64);
   std::vector<double2*> ps(nsh), xv(nsh);
@@ -76,7 +77,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     {
       // bytes of this class are added after the loop, once the active counts are known
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, c->mms_S, n, st);
+      mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st);
     }
     ++it;
     if (it % poll_every == 0 || it == maxiter) {
@@ -98,7 +99,8 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     // a shift is active in exactly iters[s] launches, and all `it` launches ran
     double active_launches = 0;
     for (int s = 0; s < nsh; ++s) active_launches += res->iters[s];
-    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += (3.0 * it + 4.0 * active_launches) * 384.0 * c->g.vh;
+    // r, p read and p written, 4 vectors per active shift except the base shift (x_s only)
+    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += (1.0 * it + 4.0 * active_launches) * 384.0 * c->g.vh;
   }
   if (res->breakdown) return fail(c, NDTM_EBREAKDOWN, "mmscg: breakdown (non-finite or p.Ap <= 0)");
   return done ? NDTM_OK : NDTM_ENOCONV;
