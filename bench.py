@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--forms", default="hybrid,plain,lagrange,mixed,learned",
+    ap.add_argument("--forms", default="hybrid,plain,hybrid_direct,plain_direct,lagrange,mixed,learned",
                     help="comma list; the first is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
@@ -88,6 +88,12 @@ def form_params(ctx, nd, form):
     # per-class event timers
     if form == "plain":
         return ctx.solve_params(tol=1e-10)
+    if form == "plain_direct":
+        # shifted solutions and directions updated every iteration instead of once per 32
+        return ctx.solve_params(tol=1e-10, mms_defer=0)
+    if form == "hybrid_direct":
+        return ctx.solve_params(tol=1e-10, n_mmscg=N_MMS, guess=nd.NDTM_GUESS_PROJECTION, use_graphs=0,
+                                mms_defer=0)
     if form == "hybrid":
         return ctx.solve_params(tol=1e-10, n_mmscg=N_MMS, guess=nd.NDTM_GUESS_PROJECTION, use_graphs=0)
     if form == "lagrange":
@@ -129,9 +135,9 @@ def run_form(ctx, nd, bd, xs, form, steps, warmup, profile):
         "solves_per_s": steps / dt,
         "worst_true_res": max(max(r["true_res"]) for r in reps),
         "mms_iterations": last["mms_iterations"],
-        "mg_iterations": last["iterations"][N_MMS:] if form != "plain" else [],
-        "guess_res": last["guess_res"][N_MMS:] if form != "plain" else [],
-        "guess_kind": last["guess_kind"][N_MMS:] if form != "plain" else [],
+        "mg_iterations": [it for it, m in zip(last["iterations"], last["method"]) if m != 0],
+        "guess_res": [g for g, m in zip(last["guess_res"], last["method"]) if m != 0],
+        "guess_kind": [g for g, m in zip(last["guess_kind"], last["method"]) if m != 0],
         "t_mms_ms": last["t_mms_ms"], "t_mg_ms": last["t_mg_ms"], "t_guess_ms": last["t_guess_ms"],
     }, prof
 

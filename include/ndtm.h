@@ -183,6 +183,11 @@ typedef struct {
   int max_rounds;      /* FP64 defect-correction rounds per multigrid shift */
   int use_graphs;      /* 1: replay the multigrid cycle from a captured HIP graph (one per
                           shift sign, cached until the next setup); 0: launch eagerly */
+  int mms_defer;       /* FP64 MMS-CG: 2..32 forms the shifted solutions and directions once
+                          per block of this many iterations, from the block's residuals kept
+                          in as many extra half fields (same iterates up to rounding, far
+                          fewer vector passes); 0 or 1 updates them every iteration;
+                          larger values are clamped to 32 */
 } ndtm_solve_params;
 
 void ndtm_solve_default_params(ndtm_solve_params* p);

@@ -41,7 +41,7 @@ class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("n_mmscg", C.c_int), ("guess", C.c_int),
                 ("precision", C.c_int), ("poll_every", C.c_int), ("mg_tol", C.c_double),
                 ("fgmres_restart", C.c_int), ("fgmres_maxiter", C.c_int), ("max_rounds", C.c_int),
-                ("use_graphs", C.c_int)]
+                ("use_graphs", C.c_int), ("mms_defer", C.c_int)]
 
 
 _D16 = C.c_double * MAX_SHIFTS

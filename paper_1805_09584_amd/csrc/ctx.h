@@ -111,8 +111,10 @@ struct MmsResult {
   bool breakdown = false;
 };
 // MMS-CG for (Q^2 + sigma_s) x_s = b on internal FP64 fields; sigmas any order.
+// defer >= 2: shifted vectors formed once per block of `defer` iterations (at most
+// kMaxDefer); 0 or 1: updated every iteration.
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
-              const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
+              const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
               hipStream_t st);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
 // Gram matrix <B_i, B_j> of B = [b, x_1, x_2, ...] (row-major 17 x 17), filled

@@ -209,38 +209,38 @@ __global__ void mms_scal1_k(double* S, const double* partials, int nparts) {
   }
 }
 
-__global__ void mms_update_r_k(double2* r, const double2* w, const double* S, size_t n, double* partials) {
+// r_out = r_in - alpha w (in place when r_out == r_in), with ||r_out||^2 partials
+__global__ void mms_update_r_k(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
+                               double* partials) {
   const double alpha = S[MS_ALPHA];
   double acc = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double2 v = r[i];
+    double2 v = rin[i];
     const double2 wi = w[i];
     v.x -= alpha * wi.x;
     v.y -= alpha * wi.y;
-    r[i] = v;
+    rout[i] = v;
     acc += v.x * v.x + v.y * v.y;
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-__global__ void mms_scal2_k(double* S, const double* partials, int nparts) {
-  double rr = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) rr += partials[i];
-  rr = block_sum(rr);
-  if (threadIdx.x != 0) return;
+// Scalar part of mms_scal2_k (one thread).  Returns 1 when the shifts active in
+// this iteration took a step (their alpha_s, beta_s, zeta_s are then final).
+__device__ int mms_scal2_body(double* S, double rr) {
   const int nsh = (int)S[MS_NSH];
   int any = 0;
   for (int s = 0; s < nsh; ++s) any |= S[MS_ACT + s] != 0.0;
   if (!any) {
     S[MS_DONE] = 1.0;
-    return;
+    return 0;
   }
   if (!isfinite(rr)) {
     S[MS_BREAK] = 1.0;
     S[MS_DONE] = 1.0;
     for (int s = 0; s < nsh; ++s) S[MS_ACT_NEXT + s] = S[MS_ACT + s] = 0.0;
-    return;
+    return 0;
   }
   const double beta = rr / S[MS_RR];
   const double it = S[MS_IT] + 1.0;
@@ -263,6 +263,57 @@ __global__ void mms_scal2_k(double* S, const double* partials, int nparts) {
   S[MS_RR] = rr;
   S[MS_IT] = it;
   S[MS_DONE] = still ? 0.0 : 1.0;
+  return 1;
+}
+
+// slot >= 0: deferred form.  The residual r_{k+1} of this iteration sits in
+// slot `slot` of the current block of iterations; the coefficients of every
+// shift active in this iteration advance as
+//   x_s += alpha_s p_s:           e += alpha_s a,  d_j += alpha_s c_j
+//   p_s = zeta_s r + beta_s p_s:  a = beta_s a,    c_j = beta_s c_j,  c_slot = zeta_s
+// (c_slot is zero before this iteration, so d_slot is unchanged).
+__global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot) {
+  double rr = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) rr += partials[i];
+  rr = block_sum(rr);
+  __shared__ int go;
+  __shared__ double al[kMaxShifts], be[kMaxShifts], ze[kMaxShifts];
+  __shared__ int act[kMaxShifts];
+  if (threadIdx.x == 0) {
+    go = mms_scal2_body(S, rr);
+    const int nsh = (int)S[MS_NSH];
+    for (int s = 0; s < nsh; ++s) {
+      act[s] = S[MS_ACT + s] != 0.0;
+      al[s] = S[MS_ALPHA_S + s];
+      be[s] = S[MS_BETA_S + s];
+      ze[s] = S[MS_ZETA + s];
+    }
+  }
+  __syncthreads();
+  if (!go || slot < 0) return;
+  const int nsh = (int)S[MS_NSH];
+  for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
+    const int s = idx / kMaxDefer, j = idx % kMaxDefer;
+    if (!act[s] || j > slot) continue;
+    double* C = S + MS_COEF + s * kCoefStride;
+    const double cj = C[MC_C + j];
+    C[MC_D + j] += al[s] * cj;
+    C[MC_C + j] = j == slot ? ze[s] : be[s] * cj;
+    if (j == 0) {
+      C[MC_E] += al[s] * C[MC_A];
+      C[MC_A] *= be[s];
+      C[MC_TOUCHED] = 1.0;
+    }
+  }
+}
+
+// Start of a block of deferred iterations: a = 1, e = c = d = 0, untouched.
+__global__ void mms_coef_reset_k(double* S) {
+  const int nsh = (int)S[MS_NSH];
+  for (int idx = threadIdx.x; idx < nsh * kCoefStride; idx += blockDim.x) {
+    const int k = idx % kCoefStride;
+    S[MS_COEF + idx] = k == MC_A ? 1.0 : 0.0;
+  }
 }
 
 struct ShiftPtrs {
@@ -300,6 +351,84 @@ __global__ void mms_update_p_k(const double2* r, double2* p, ShiftPtrs P, int ns
       P.p[s][i] = ps;
     }
     if (any_before) p[i] = make_double2(ri.x + beta * pold.x, ri.y + beta * pold.y);
+  }
+}
+
+typedef double v2d_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const v2d_nt v = __builtin_nontemporal_load(reinterpret_cast<const v2d_nt*>(p));
+  return make_double2(v.x, v.y);
+}
+
+// Base direction of the deferred form: p = r + beta p (r is r_{k+1}); skipped
+// once no shift is left (alpha = 0).
+__global__ void __launch_bounds__(256) mms_update_pbase_k(const double2* r, double2* p, const double* S,
+                                                           size_t n) {
+  if (S[MS_ALPHA] == 0.0) return;
+  const double beta = S[MS_BETA];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const double2 ri = r[i], pi = p[i];
+    p[i] = make_double2(ri.x + beta * pi.x, ri.y + beta * pi.y);
+  }
+}
+
+struct DeferPtrs {
+  double2* x[kMaxShifts];
+  double2* p[kMaxShifts];
+};
+
+// End of a block of nr deferred iterations: for every shift touched in it,
+//   x_s += e P_s + sum_j d_j R_j,   P_s = a P_s + sum_j c_j R_j,
+// each residual R_j (slot j of the ring R, slots n apart) read once for all
+// shifts.  The direction of a shift that has frozen is not written back (it is
+// never used again).
+__global__ void __launch_bounds__(256) mms_flush_k(DeferPtrs P, const double2* R, int nr, const double* S,
+                                                   size_t n) {
+  __shared__ double cd[kMaxShifts][2][kMaxDefer];
+  __shared__ double ae[kMaxShifts][2];
+  __shared__ int todo[kMaxShifts], keep[kMaxShifts];
+  const int nsh = (int)S[MS_NSH];
+  for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
+    const int s = idx / kMaxDefer, j = idx % kMaxDefer;
+    const double* C = S + MS_COEF + s * kCoefStride;
+    cd[s][0][j] = C[MC_C + j];
+    cd[s][1][j] = C[MC_D + j];
+  }
+  if (threadIdx.x < nsh) {
+    const int s = threadIdx.x;
+    const double* C = S + MS_COEF + s * kCoefStride;
+    ae[s][0] = C[MC_A];
+    ae[s][1] = C[MC_E];
+    todo[s] = C[MC_TOUCHED] != 0.0;
+    keep[s] = S[MS_ACT_NEXT + s] != 0.0;
+  }
+  __syncthreads();
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double2 rv[kMaxDefer];
+#pragma unroll
+    for (int j = 0; j < kMaxDefer; ++j)
+      if (j < nr) rv[j] = ld_stream(R + (size_t)j * n + i);
+    for (int s = 0; s < nsh; ++s) {
+      if (!todo[s]) continue;
+      const double2 p0 = P.p[s][i];
+      double2 x = P.x[s][i];
+      const double a = ae[s][0], e = ae[s][1];
+      double2 pn = make_double2(a * p0.x, a * p0.y);
+      x.x += e * p0.x;
+      x.y += e * p0.y;
+#pragma unroll
+      for (int j = 0; j < kMaxDefer; ++j) {
+        if (j < nr) {
+          const double c = cd[s][0][j], d = cd[s][1][j];
+          pn.x += c * rv[j].x;
+          pn.y += c * rv[j].y;
+          x.x += d * rv[j].x;
+          x.y += d * rv[j].y;
+        }
+      }
+      P.x[s][i] = x;
+      if (keep[s]) P.p[s][i] = pn;
+    }
   }
 }
 
@@ -447,11 +576,27 @@ void blas_gram(const double2* const* V, int k, size_t n, double* partials, doubl
 void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(mms_scal1_k, dim3(1), dim3(256), 0, st, S, partials, nparts);
 }
-void mms_update_r(double2* r, const double2* w, const double* S, size_t n, double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(mms_update_r_k, dim3(grid_for(n)), dim3(256), 0, st, r, w, S, n, partials);
+void mms_update_r(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
+                  double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_r_k, dim3(grid_for(n)), dim3(256), 0, st, rin, rout, w, S, n, partials);
 }
-void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts);
+void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts, slot);
+}
+void mms_coef_reset(double* S, hipStream_t st) {
+  hipLaunchKernelGGL(mms_coef_reset_k, dim3(1), dim3(256), 0, st, S);
+}
+void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_pbase_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n);
+}
+void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
+               size_t n, hipStream_t st) {
+  DeferPtrs P;
+  for (int s = 0; s < nsh; ++s) {
+    P.x[s] = xs[s];
+    P.p[s] = ps[s];
+  }
+  hipLaunchKernelGGL(mms_flush_k, dim3(grid_for(n)), dim3(256), 0, st, P, R, nr, S, n);
 }
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
                   const double* S, size_t n, hipStream_t st) {

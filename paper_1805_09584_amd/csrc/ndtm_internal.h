@@ -132,20 +132,35 @@ void blas_lincomb(double2* y, const double2* const* V, const double2* c, int k, 
 void blas_gram(const double2* const* V, int k, size_t n, double* partials, double* dst, hipStream_t st);
 
 // ---- MMS-CG -----------------------------------------------------------------
-struct MmsState;  // device-side scalars, see kern_cg.hip
+// Device-side scalars in S (layout below).
 void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st);
-void mms_update_r(double2* r, const double2* w, const double* S, size_t n, double* partials,
-                  hipStream_t st);
-void mms_scal2(double* S, const double* partials, int nparts, hipStream_t st);
+// r_out = r_in - alpha w (r_out may equal r_in), ||r_out||^2 partials
+void mms_update_r(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
+                  double* partials, hipStream_t st);
+// beta, zeta_s, beta_s, freezing; slot >= 0 also advances the deferred coefficients
+// with the residual of this iteration in that slot
+void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st);
 // p_s, x_s of every active shift in one pass; sb = the base shift (delta 0), whose
 // direction is p itself and whose ps[sb] is not used
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
                   const double* S, size_t n, hipStream_t st);
+// deferred form: base direction p = r + beta p; coefficient reset at the start of a
+// block; flush of the residuals in slots 0..nr-1 of the ring R (slot j at R + j n) into
+// x_s, p_s of every shift touched in the block
+void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, hipStream_t st);
+void mms_coef_reset(double* S, hipStream_t st);
+void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
+               size_t n, hipStream_t st);
 // mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
 void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
                      double* partials, int nblk, hipStream_t st);
 void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
                      int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st);
+// Deferred multi-shift update: the shifted x_s, p_s are formed once per block of
+// at most kMaxDefer iterations from the residuals of that block.
+constexpr int kMaxDefer = 32;
+enum MmsCoefIdx { MC_A = 0, MC_E = 1, MC_TOUCHED = 2, MC_C = 4, MC_D = MC_C + kMaxDefer };
+constexpr int kCoefStride = MC_D + kMaxDefer;
 // Layout of the scalar block S (doubles).
 enum MmsIdx {
   MS_RR = 0, MS_PW, MS_ALPHA, MS_ALPHA_PREV, MS_BETA, MS_BB, MS_TOL2, MS_IT, MS_NSH, MS_DONE,
@@ -155,7 +170,9 @@ enum MmsIdx {
   MS_ALPHA_S = MS_ZETA_NEXT + kMaxShifts, MS_BETA_S = MS_ALPHA_S + kMaxShifts,
   MS_DELTA = MS_BETA_S + kMaxShifts, MS_ACT = MS_DELTA + kMaxShifts,
   MS_ACT_NEXT = MS_ACT + kMaxShifts, MS_ITERS = MS_ACT_NEXT + kMaxShifts,
-  MS_SIZE = MS_ITERS + kMaxShifts
+  // deferred form: per shift, kCoefStride doubles [a, e, touched, -, c[kMaxDefer], d[kMaxDefer]]
+  MS_COEF = MS_ITERS + kMaxShifts,
+  MS_SIZE = MS_COEF + kMaxShifts * kCoefStride
 };
 
 }  // namespace ndtm

@@ -11,6 +11,17 @@
 //   scalars (beta, beta_s, freeze)   one-block kernel
 //   x_s += alpha_s p_s, p_s = zeta_s r + beta_s p_s, p = r + beta p   fused over active shifts
 // with a host poll of the done flag every poll_every iterations.
+//
+// Deferred form (defer = m >= 2): the last step reads and writes x_s and p_s of
+// every active shift each iteration, 4 vectors per shift, more than the stencil
+// itself moves.  Over a block of m iterations all shifted vectors stay linear
+// combinations of their values at the block start and of the block's residuals
+// r_{k+1}, with real coefficients that the scalar kernel advances.  The residuals
+// go to m ring slots (r_{k+1} -> slot k mod m), the base direction p is updated
+// on its own, and once per block one pass forms x_s and p_s of all shifts from
+// the slots.  The iterates are those of the direct form up to rounding; the
+// vector traffic per iteration drops from (1 + 4 N_active) to about
+// 6 + (m + 4 N_active) / m vectors.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -23,7 +34,7 @@
 namespace ndtm {
 
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
-              const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res,
+              const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
               hipStream_t st) {
   const int nsh = (int)sigmas.size();
   const size_t n = half_elems(c);
@@ -39,6 +50,13 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     xv[s] = static_cast<double2*>(xs[s].v);
   }
   if (!r.v || !p.v || !w.v || !u.v || !te.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
+  if (defer > kMaxDefer) defer = kMaxDefer;
+  const bool deferred = defer >= 2;
+  double2* ring = nullptr;  // defer residual slots, n elements apart
+  if (deferred) {
+    ring = static_cast<double2*>(ws_get(c, "cg_ring", (size_t)defer * n * sizeof(double2)));
+    if (!ring) return fail(c, NDTM_ENOMEM, "mmscg: residual slots");
+  }
   const double2* bv = static_cast<const double2*>(b.v);
   blas_copy((double2*)r.v, bv, n, st);
   blas_copy((double2*)p.v, bv, n, st);
@@ -62,30 +80,47 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     blas_finalize(c->partials, g, 1, c->dscal, st);
     mms_seed(c->mms_S, c->dscal, st);
   }
+  if (deferred) mms_coef_reset(c->mms_S, st);
   const int hg = hop_grid(c->g);
   const int rg = red_grid(n);
   int it = 0;
   if (poll_every < 1) poll_every = 1;
+  std::vector<std::pair<int, int>> flushes;  // (first iteration, residuals) of each flush
+  auto flush = [&](int nr) {
+    ProfScope pf(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
+    mms_flush(xv.data(), ps.data(), nsh, ring, nr, c->mms_S, n, st);
+    mms_coef_reset(c->mms_S, st);
+    flushes.emplace_back(it - nr, nr);
+  };
   while (it < maxiter) {
     apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
     mms_scal1(c->mms_S, c->partials, hg, st);
+    // deferred: r_k is in slot (k-1) mod m (b for k = 0), r_{k+1} goes to slot k mod m
+    const int slot = deferred ? it % defer : -1;
+    const double2* rin = !deferred ? (const double2*)r.v : it == 0 ? bv : ring + (size_t)((it - 1) % defer) * n;
+    double2* rout = deferred ? ring + (size_t)slot * n : (double2*)r.v;
     {
       ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
-      mms_update_r((double2*)r.v, (const double2*)w.v, c->mms_S, n, c->partials, st);
+      mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st);
     }
-    mms_scal2(c->mms_S, c->partials, rg, st);
-    {
+    mms_scal2(c->mms_S, c->partials, rg, slot, st);
+    if (deferred) {
+      ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
+      mms_update_pbase(rout, (double2*)p.v, c->mms_S, n, st);
+    } else {
       // bytes of this class are added after the loop, once the active counts are known
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
       mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st);
     }
     ++it;
+    if (deferred && it % defer == 0) flush(defer);
     if (it % poll_every == 0 || it == maxiter) {
       NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S + MS_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
       NDTM_HIP(c, hipStreamSynchronize(st));
       if (c->hscal[0] != 0.0) break;
     }
   }
+  if (deferred && it % defer != 0) flush(it % defer);
   NDTM_HIP(c, hipGetLastError());
   NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
   NDTM_HIP(c, hipStreamSynchronize(st));
@@ -94,7 +129,20 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   res->iters.resize(nsh);
   for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
   bool done = c->hscal[MS_DONE] != 0.0;
-  if ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1) {
+  if (deferred && ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1)) {
+    // base direction: r read, p read and written per iteration; each flush reads its
+    // residuals and x_s, p_s of every shift active in its block (shift s is active in
+    // iterations 0..iters[s]-1), writes x_s and, while the shift stays active, p_s
+    double vecs = 3.0 * it;
+    for (const auto& f : flushes) {
+      vecs += f.second;
+      for (int s = 0; s < nsh; ++s) {
+        if (res->iters[s] > f.first) vecs += 3.0;
+        if (res->iters[s] > f.first + f.second) vecs += 1.0;
+      }
+    }
+    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += vecs * 384.0 * c->g.vh;
+  } else if ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1) {
     // every launch moves r, p (read, p written) and x_s, p_s (read and written) of each active shift;
     // a shift is active in exactly iters[s] launches, and all `it` launches ran
     double active_launches = 0;
@@ -156,7 +204,7 @@ int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::v
       mms_update_r_mx((float2*)r.v, (const __half2*)w16.v, w16.sc, c->mms_S, c->g.vh, c->g.stride, c->partials, nb,
                       st);
     }
-    mms_scal2(c->mms_S, c->partials, nb, st);
+    mms_scal2(c->mms_S, c->partials, nb, -1, st);
     {
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
       mms_update_p_mx((const float2*)r.v, (float2*)p.v, (__half2*)p16.v, p16.sc, xv.data(), ps.data(), nsh, c->mms_S,
@@ -211,7 +259,7 @@ static int polish_cg(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
     MmsResult mr;
     std::vector<HalfField> es{e};
     const double inner = std::min(0.5, 0.5 * tol / res);
-    int rc = run_mmscg(c, {sigma}, es, r, inner, maxiter, 8, &mr, st);
+    int rc = run_mmscg(c, {sigma}, es, r, inner, maxiter, 8, 0, &mr, st);
     total += mr.iterations;
     if (rc == NDTM_EBREAKDOWN) return rc;
     blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e.v, n, st);
@@ -292,6 +340,7 @@ void ndtm_solve_default_params(ndtm_solve_params* p) {
   p->fgmres_maxiter = 400;
   p->max_rounds = 6;
   p->use_graphs = 1;
+  p->mms_defer = 32;
 }
 
 int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_solve_params* p,
@@ -375,7 +424,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
     std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms);
     MmsResult mr;
-    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, &mr, st);
+    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, p->mms_defer, &mr, st);
     rep->mms_iterations = mr.iterations;
     if (rc == NDTM_EBREAKDOWN) {
       rep->status = rc;

@@ -7,6 +7,10 @@
 * 16^3x32 config, all 12 shifts by MMS-CG: sampled shifts checked by the
   oracle's true residual.
 * zero and non-finite right-hand sides.
+* deferred shifted updates (blocks of 2, 5, 32 iterations) against the direct
+  per-iteration updates: the base Krylov process is the same computation, so
+  the iteration counts agree exactly and the solutions to rounding; also when
+  the iteration cap ends the solve inside a block.
 """
 import numpy as np
 import pytest
@@ -106,4 +110,31 @@ def test_profile_classes(nd):
     assert 1920.0 <= per <= 1920.0 + 2 * 384.0
     # the multi-shift CG applies Q^2 (two Q, four stencil passes) once per iteration
     assert n >= 4 * rep["mms_iterations"]
+    ctx.close()
+
+
+def test_deferred_updates_match_direct(nd):
+    print("deferred vs direct shifted updates c1", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c1")
+    bd = dev(b)
+    x0, r0 = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=0))
+    ref = [host(x) for x in x0]
+    for m in (2, 5, 32):
+        xm, rm = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=m))
+        print("defer", m, rm["mms_iterations"], r0["mms_iterations"], flush=True)
+        assert rm["mms_iterations"] == r0["mms_iterations"]
+        assert rm["iterations"] == r0["iterations"]
+        for i, s in enumerate(sig):
+            x = host(xm[i])
+            assert np.linalg.norm(x - ref[i]) <= 1e-12 * np.linalg.norm(ref[i]), (m, i)
+            assert rel_residual(op, x, b, s) <= 1e-10, (m, i)
+    # the cap ends the solve after 37 iterations: inside the second block of 32
+    cap = ctx.solve_params(tol=1e-10, maxiter=37, mms_defer=0)
+    xa, ra = ctx.ndtm_solve(bd, cap, check=False)
+    cap.mms_defer = 32
+    xb, rb = ctx.ndtm_solve(bd, cap, check=False)
+    assert ra["status"] == rb["status"] and ra["mms_iterations"] == rb["mms_iterations"] == 37
+    for i in range(len(sig)):
+        a, c = host(xa[i]), host(xb[i])
+        assert np.linalg.norm(c - a) <= 1e-12 * np.linalg.norm(a), i
     ctx.close()
