@@ -80,7 +80,8 @@ enum {
  * as fallback; PROJECTION: the combination of all converged solutions with the
  * smallest residual, from the Gram matrix of [b, x_1..x_K] and the identity of
  * appendix B, refined on the true residual (a generalisation of section 4.2). */
-enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2, NDTM_GUESS_PROJECTION = 3 };
+enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2, NDTM_GUESS_PROJECTION = 3,
+       NDTM_GUESS_MMS = 4 /* report only: the shift's own multi-shift CG iterate (mms_predict) */ };
 
 /* Creates a context on HIP device `device` for a lattice of dims {T,Lz,Ly,Lx}.
  * EINVAL if a dim is odd or < 2, or if V/2 exceeds about 20.6 million sites
@@ -188,6 +189,12 @@ typedef struct {
                           in as many extra half fields (same iterates up to rounding, far
                           fewer vector passes); 0 or 1 updates them every iteration;
                           larger values are clamped to 32 */
+  int mms_predict;     /* FP64 hybrid: the first this many multigrid shifts ride along in the
+                          multi-shift CG without being waited for (section 4.2, initial guesses
+                          via MMS-CG); each starts from its multi-shift iterate when that has
+                          the smaller true residual than the `guess` proposal (report
+                          guess_kind NDTM_GUESS_MMS), and needs no multigrid work when the
+                          iterate already meets tol.  0 disables */
 } ndtm_solve_params;
 
 void ndtm_solve_default_params(ndtm_solve_params* p);

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 from .binding import (  # noqa: F401
     NDTM_GUESS_LAGRANGE,
+    NDTM_GUESS_MMS,
     NDTM_GUESS_MLP,
     NDTM_GUESS_PROJECTION,
     NDTM_GUESS_ZERO,

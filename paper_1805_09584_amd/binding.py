@@ -14,7 +14,7 @@ NDTM_OK = 0
 NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16 = 0, 1, 2
 (NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
  NDTM_OP_HOP_OE) = range(6)
-NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP, NDTM_GUESS_PROJECTION = 0, 1, 2, 3
+NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP, NDTM_GUESS_PROJECTION, NDTM_GUESS_MMS = 0, 1, 2, 3, 4
 PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
                 "coarse")
 MAX_SHIFTS = 16
@@ -41,7 +41,8 @@ class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("n_mmscg", C.c_int), ("guess", C.c_int),
                 ("precision", C.c_int), ("poll_every", C.c_int), ("mg_tol", C.c_double),
                 ("fgmres_restart", C.c_int), ("fgmres_maxiter", C.c_int), ("max_rounds", C.c_int),
-                ("use_graphs", C.c_int), ("mms_defer", C.c_int)]
+                ("use_graphs", C.c_int), ("mms_defer", C.c_int),
+                ("mms_predict", C.c_int)]
 
 
 _D16 = C.c_double * MAX_SHIFTS

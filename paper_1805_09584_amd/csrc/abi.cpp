@@ -94,7 +94,9 @@ void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& i
          const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
          double* partials, hipStream_t st) {
   ProfScope ps(c, NDTM_PROF_HOP_F64 + prec, hop_site_bytes(prec, epi) * c->g.vh, st);
-  launch_hop(prec, epi, red, c->g, parity, c->op, c->U[prec][parity], c->U[prec][1 - parity], in, out,
+  OpParams op = c->op;
+  op.skip = c->hop_skip;
+  launch_hop(prec, epi, red, c->g, parity, op, c->U[prec][parity], c->U[prec][1 - parity], in, out,
              xs, zs, ms, hop_coef, sigma, partials, st);
 }
 

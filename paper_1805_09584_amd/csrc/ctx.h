@@ -41,6 +41,7 @@ struct ndtm_ctx {
   double* mms_S = nullptr;
   std::map<std::string, ndtm::DevBuf> bufs;
   int prof_mask = 0;  // bit k: time kernel class k
+  const double* hop_skip = nullptr;  // device flag handed to stencil launches (see OpParams::skip)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[NDTM_PROF_NCLASS];
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   double prof_ms[NDTM_PROF_NCLASS] = {};
@@ -113,9 +114,11 @@ struct MmsResult {
 // MMS-CG for (Q^2 + sigma_s) x_s = b on internal FP64 fields; sigmas any order.
 // defer >= 2: shifted vectors formed once per block of `defer` iterations (at most
 // kMaxDefer); 0 or 1: updated every iteration.
+// The last npass shifts of sigmas are passengers: iterated along but not waited
+// for, so that their iterates can serve as initial guesses (section 4.2).
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st);
+              hipStream_t st, int npass = 0);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
 // Gram matrix <B_i, B_j> of B = [b, x_1, x_2, ...] (row-major 17 x 17), filled
 // for the first `count` vectors; kept across the multigrid targets of one solve

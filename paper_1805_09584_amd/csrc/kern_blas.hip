@@ -167,11 +167,10 @@ __global__ void lincomb_k(double2* y, VecList V, CoefList C, int k, size_t n) {
 }
 
 // ---------------- MMS-CG ----------------
-__global__ void mms_scal1_k(double* S, const double* partials, int nparts) {
-  double pw = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) pw += partials[i];
-  pw = block_sum(pw);
-  if (threadIdx.x != 0) return;
+// The recurrences of one iteration are a short serial chain on one thread; it
+// runs on a copy of the scalar header in LDS (loaded and stored back by the
+// whole block) so that the chain does not wait on global memory at every step.
+__device__ void mms_scal1_body(double* S, double pw) {
   const int nsh = (int)S[MS_NSH];
   S[MS_PW] = pw;
   int any = 0;
@@ -207,6 +206,21 @@ __global__ void mms_scal1_k(double* S, const double* partials, int nparts) {
     S[MS_ZETA_NEXT + s] = zn;
     S[MS_ALPHA_S + s] = alpha * zn / z;
   }
+}
+
+__device__ void stage_scalars(double* dst, const double* src) {
+  for (int i = threadIdx.x; i < MS_COEF; i += blockDim.x) dst[i] = src[i];
+}
+
+__global__ void mms_scal1_k(double* S, const double* partials, int nparts) {
+  __shared__ double sh[MS_COEF];
+  double pw = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) pw += partials[i];
+  stage_scalars(sh, S);
+  pw = block_sum(pw);  // synchronises the block
+  if (threadIdx.x == 0) mms_scal1_body(sh, pw);
+  __syncthreads();
+  stage_scalars(S, sh);
 }
 
 // r_out = r_in - alpha w (in place when r_out == r_in), with ||r_out||^2 partials
@@ -256,8 +270,11 @@ __device__ int mms_scal2_body(double* S, double rr) {
     // freeze once the shifted residual |zeta_s| ||r|| reaches tol ||b||
     const bool frozen = zn * zn * rr <= S[MS_TOL2] * S[MS_BB];
     S[MS_ACT_NEXT + s] = frozen ? 0.0 : 1.0;
-    still |= !frozen;
+    if (S[MS_PASS + s] == 0.0) still |= !frozen;
   }
+  // done: passengers stop with the last shift that is waited for
+  if (!still)
+    for (int s = 0; s < nsh; ++s) S[MS_ACT_NEXT + s] = 0.0;
   S[MS_BETA] = beta;
   S[MS_ALPHA_PREV] = S[MS_ALPHA];
   S[MS_RR] = rr;
@@ -273,28 +290,24 @@ __device__ int mms_scal2_body(double* S, double rr) {
 //   p_s = zeta_s r + beta_s p_s:  a = beta_s a,    c_j = beta_s c_j,  c_slot = zeta_s
 // (c_slot is zero before this iteration, so d_slot is unchanged).
 __global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot) {
+  __shared__ double sh[MS_COEF];
+  __shared__ int go;
   double rr = 0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) rr += partials[i];
-  rr = block_sum(rr);
-  __shared__ int go;
-  __shared__ double al[kMaxShifts], be[kMaxShifts], ze[kMaxShifts];
-  __shared__ int act[kMaxShifts];
-  if (threadIdx.x == 0) {
-    go = mms_scal2_body(S, rr);
-    const int nsh = (int)S[MS_NSH];
-    for (int s = 0; s < nsh; ++s) {
-      act[s] = S[MS_ACT + s] != 0.0;
-      al[s] = S[MS_ALPHA_S + s];
-      be[s] = S[MS_BETA_S + s];
-      ze[s] = S[MS_ZETA + s];
-    }
-  }
+  stage_scalars(sh, S);
+  rr = block_sum(rr);  // synchronises the block
+  if (threadIdx.x == 0) go = mms_scal2_body(sh, rr);
   __syncthreads();
+  stage_scalars(S, sh);
   if (!go || slot < 0) return;
-  const int nsh = (int)S[MS_NSH];
+  const int nsh = (int)sh[MS_NSH];
+  const double* act = sh + MS_ACT;
+  const double* al = sh + MS_ALPHA_S;
+  const double* be = sh + MS_BETA_S;
+  const double* ze = sh + MS_ZETA;
   for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
     const int s = idx / kMaxDefer, j = idx % kMaxDefer;
-    if (!act[s] || j > slot) continue;
+    if (act[s] == 0.0 || j > slot) continue;
     double* C = S + MS_COEF + s * kCoefStride;
     const double cj = C[MC_C + j];
     C[MC_D + j] += al[s] * cj;
@@ -386,7 +399,7 @@ __global__ void __launch_bounds__(256) mms_flush_k(DeferPtrs P, const double2* R
                                                    size_t n) {
   __shared__ double cd[kMaxShifts][2][kMaxDefer];
   __shared__ double ae[kMaxShifts][2];
-  __shared__ int todo[kMaxShifts], keep[kMaxShifts];
+  __shared__ int keep[kMaxShifts], list[kMaxShifts], nlist;
   const int nsh = (int)S[MS_NSH];
   for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
     const int s = idx / kMaxDefer, j = idx % kMaxDefer;
@@ -399,19 +412,33 @@ __global__ void __launch_bounds__(256) mms_flush_k(DeferPtrs P, const double2* R
     const double* C = S + MS_COEF + s * kCoefStride;
     ae[s][0] = C[MC_A];
     ae[s][1] = C[MC_E];
-    todo[s] = C[MC_TOUCHED] != 0.0;
     keep[s] = S[MS_ACT_NEXT + s] != 0.0;
   }
+  if (threadIdx.x == 0) {
+    int k = 0;
+    for (int s = 0; s < nsh; ++s)
+      if (S[MS_COEF + s * kCoefStride + MC_TOUCHED] != 0.0) list[k++] = s;
+    nlist = k;
+  }
   __syncthreads();
+  const int nl = nlist;
+  if (nl == 0) return;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double2 rv[kMaxDefer];
 #pragma unroll
     for (int j = 0; j < kMaxDefer; ++j)
       if (j < nr) rv[j] = ld_stream(R + (size_t)j * n + i);
-    for (int s = 0; s < nsh; ++s) {
-      if (!todo[s]) continue;
-      const double2 p0 = P.p[s][i];
-      double2 x = P.x[s][i];
+    // the next shift's P_s and x_s are loaded before the current one is stored
+    // (as far as the compiler knows the stores may alias them)
+    double2 p0n = P.p[list[0]][i], xn = P.x[list[0]][i];
+    for (int k = 0; k < nl; ++k) {
+      const int s = list[k];
+      const double2 p0 = p0n;
+      double2 x = xn;
+      if (k + 1 < nl) {
+        p0n = P.p[list[k + 1]][i];
+        xn = P.x[list[k + 1]][i];
+      }
       const double a = ae[s][0], e = ae[s][1];
       double2 pn = make_double2(a * p0.x, a * p0.y);
       x.x += e * p0.x;

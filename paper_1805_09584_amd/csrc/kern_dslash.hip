@@ -106,6 +106,7 @@ struct HopArgs {
   const S* zs;
   const float* zs_sc;
   double* partials;
+  const double* skip;
   int T, Lz, Ly, Lx, vh, stride, parity, antiperiodic;
   int bz;  // z-chunk of the traversal order (divides Lz)
   double a, mubar, epsbar, inv_den, ms, hop_coef, sigma;
@@ -365,6 +366,7 @@ __device__ __forceinline__ void block_reduce_store(double v, double* partials) {
 template <class S, class L, int EPI, int RED, bool R12>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   using R = typename RealOf<S>::T;
+  if (A.skip && *A.skip != 0.0) return;
   // XCD-aware block order: XCD k = b % 8 gets one contiguous range of logical blocks.
   const int nb = gridDim.x, b = blockIdx.x;
   const int q = nb >> 3, rem = nb & 7, xcd = b & 7, loc = b >> 3;
@@ -605,6 +607,7 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.zs = zs ? static_cast<const S*>(zs->v) : nullptr;
   A.zs_sc = zs ? zs->sc : nullptr;
   A.partials = partials;
+  A.skip = op.skip;
   A.T = g.T;
   A.Lz = g.Lz;
   A.Ly = g.Ly;

@@ -390,8 +390,9 @@ int guess_projection(ndtm_ctx* c, const std::vector<double>& nodes, const std::v
                      const HalfField& b, const HalfField& x, GramCache* gram, double* lag_res, double* proj_res,
                      hipStream_t st);
 
-int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std::vector<HalfField>& xs,
-                    const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st) {
+int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, int n_pred,
+                    std::vector<HalfField>& xs, const HalfField& b, const ndtm_solve_params* p,
+                    ndtm_solve_report* rep, hipStream_t st) {
   MGData* M = c->mg;
   if (!M || !M->ready) return fail(c, NDTM_ESTATE, "solve: multigrid shifts need ndtm_mg_setup first");
   M->use_graphs = p->use_graphs != 0;
@@ -399,8 +400,27 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
   const size_t n = half_elems(c);
   int status = NDTM_OK;
   GramCache gram;
+  HalfField R = half_field(c, "mg_pred_r", P64), Xp = half_field(c, "mg_pred_x", P64);
+  if (n_pred > 0 && (!R.v || !Xp.v)) return fail(c, NDTM_ENOMEM, "solve: predicted-guess workspace");
   for (int t = n_mms; t < nsh; ++t) {
     auto tg0 = std::chrono::steady_clock::now();
+    // ---- the shift's own multi-shift iterate (section 4.2, guesses via MMS-CG) ----
+    double pred_res = -1;
+    if (t < n_mms + n_pred) {
+      pred_res = true_residual(c, xs[t], b, sig[t], R, st);
+      if (pred_res <= p->tol) {
+        // already converged along with the multi-shift solve: no guess, no multigrid work
+        rep->guess_kind[t] = NDTM_GUESS_MMS;
+        rep->lagrange_res[t] = -1;
+        rep->method[t] = 1;
+        rep->iterations[t] = 0;
+        rep->rounds[t] = 0;
+        rep->true_res[t] = rep->guess_res[t] = pred_res;
+        rep->t_guess_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
+        continue;
+      }
+      blas_copy((double2*)Xp.v, (const double2*)xs[t].v, n, st);
+    }
     // ---- initial guess from the converged solutions (descending shifts) ----
     const int first = guess_first_node(std::vector<double>(sig.begin(), sig.begin() + t), sig[t]);
     std::vector<double> nodes(sig.begin() + first, sig.begin() + t);
@@ -437,6 +457,15 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, std:
         cc[i] = make_double2(coef[i], 0.0);
       }
       blas_lincomb((double2*)xs[t].v, V.data(), cc.data(), K, n, st);
+    }
+    if (pred_res >= 0) {
+      // keep whichever start has the smaller true residual
+      const double gres = true_residual(c, xs[t], b, sig[t], R, st);
+      if (p->guess == NDTM_GUESS_LAGRANGE) rep->lagrange_res[t] = gres;
+      if (!(gres <= pred_res)) {
+        blas_copy((double2*)xs[t].v, (const double2*)Xp.v, n, st);
+        rep->guess_kind[t] = NDTM_GUESS_MMS;
+      }
     }
     auto tg1 = std::chrono::steady_clock::now();
     rep->t_guess_ms += std::chrono::duration<double, std::milli>(tg1 - tg0).count();

@@ -69,6 +69,9 @@ enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2 };
 struct OpParams {
   double a, mubar, epsbar, inv_den;
   int recon12;  // links are SU(3): the stencil loads two rows and rebuilds the third
+  // optional device flag: a stencil launch returns at once while *skip != 0 (the
+  // iterations a solver runs past its done flag before the host sees it)
+  const double* skip = nullptr;
 };
 
 // A precision-tagged half field (device pointers).
@@ -170,8 +173,11 @@ enum MmsIdx {
   MS_ALPHA_S = MS_ZETA_NEXT + kMaxShifts, MS_BETA_S = MS_ALPHA_S + kMaxShifts,
   MS_DELTA = MS_BETA_S + kMaxShifts, MS_ACT = MS_DELTA + kMaxShifts,
   MS_ACT_NEXT = MS_ACT + kMaxShifts, MS_ITERS = MS_ACT_NEXT + kMaxShifts,
+  // passenger shifts: iterated along but not waited for (their iterates become
+  // initial guesses); the solve is done once every other shift is frozen
+  MS_PASS = MS_ITERS + kMaxShifts,
   // deferred form: per shift, kCoefStride doubles [a, e, touched, -, c[kMaxDefer], d[kMaxDefer]]
-  MS_COEF = MS_ITERS + kMaxShifts,
+  MS_COEF = MS_PASS + kMaxShifts,
   MS_SIZE = MS_COEF + kMaxShifts * kCoefStride
 };
 

@@ -33,9 +33,57 @@
 
 namespace ndtm {
 
+static_assert(MS_SIZE + 8 <= kScalN, "scalar block and poll slots fit the pinned mirror");
+
+namespace {
+
+// Host poll of a solver's done flag without draining the stream: poll j copies
+// the flag to pinned memory behind an event and reads the flag of poll j-1,
+// whose event has normally completed while the iterations after it were being
+// queued.  While it is installed, stencil launches return at once once the flag
+// is set, so the iterations queued past convergence cost only their launches.
+// With kernel timing on, every poll waits for its own flag instead, so that no
+// skipped launch enters the per-class statistics.
+struct LaggedPoll {
+  ndtm_ctx* c;
+  hipStream_t st;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double* slot;
+  int n = 0;
+  const double* flag;
+  bool lag;
+  LaggedPoll(ndtm_ctx* cc, const double* done_flag, hipStream_t s) : c(cc), st(s), flag(done_flag) {
+    slot = c->hscal + kScalN - 4;
+    for (auto& e : ev) (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    lag = c->prof_mask == 0;
+    if (lag) c->hop_skip = done_flag;
+  }
+  ~LaggedPoll() {
+    c->hop_skip = nullptr;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  // true once a completed poll has seen the flag set
+  bool done() {
+    const int k = n & 1;
+    (void)hipMemcpyAsync(slot + k, flag, sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipEventRecord(ev[k], st);
+    ++n;
+    if (!lag) {
+      (void)hipEventSynchronize(ev[k]);
+      return slot[k] != 0.0;
+    }
+    if (n < 2) return false;
+    (void)hipEventSynchronize(ev[1 - k]);
+    return slot[1 - k] != 0.0;
+  }
+};
+
+}  // namespace
+
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st) {
+              hipStream_t st, int npass) {
   const int nsh = (int)sigmas.size();
   const size_t n = half_elems(c);
   const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
@@ -73,6 +121,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     S[MS_ZETA + s] = S[MS_ZETA_PREV + s] = 1.0;
     S[MS_DELTA + s] = sigmas[s] - sig_base;
     S[MS_ACT_NEXT + s] = 1.0;
+    S[MS_PASS + s] = s >= nsh - npass ? 1.0 : 0.0;
   }
   NDTM_HIP(c, hipMemcpyAsync(c->mms_S, S.data(), MS_SIZE * sizeof(double), hipMemcpyHostToDevice, st));
   {
@@ -85,6 +134,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   const int rg = red_grid(n);
   int it = 0;
   if (poll_every < 1) poll_every = 1;
+  LaggedPoll poll(c, c->mms_S + MS_DONE, st);
   std::vector<std::pair<int, int>> flushes;  // (first iteration, residuals) of each flush
   auto flush = [&](int nr) {
     ProfScope pf(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
@@ -114,11 +164,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     }
     ++it;
     if (deferred && it % defer == 0) flush(defer);
-    if (it % poll_every == 0 || it == maxiter) {
-      NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S + MS_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
-      NDTM_HIP(c, hipStreamSynchronize(st));
-      if (c->hscal[0] != 0.0) break;
-    }
+    if (it % poll_every == 0 && poll.done()) break;
   }
   if (deferred && it % defer != 0) flush(it % defer);
   NDTM_HIP(c, hipGetLastError());
@@ -130,10 +176,11 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
   bool done = c->hscal[MS_DONE] != 0.0;
   if (deferred && ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1)) {
-    // base direction: r read, p read and written per iteration; each flush reads its
+    // base direction: r read, p read and written per iteration that moves (the launches
+    // queued after the done flag return at once); each flush reads its
     // residuals and x_s, p_s of every shift active in its block (shift s is active in
     // iterations 0..iters[s]-1), writes x_s and, while the shift stays active, p_s
-    double vecs = 3.0 * it;
+    double vecs = 3.0 * res->iterations;
     for (const auto& f : flushes) {
       vecs += f.second;
       for (int s = 0; s < nsh; ++s) {
@@ -196,6 +243,7 @@ int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::v
   const int nb = std::min(1024, (c->g.vh + 255) / 256);
   int it = 0;
   if (poll_every < 1) poll_every = 1;
+  LaggedPoll poll(c, c->mms_S + MS_DONE, st);
   while (it < maxiter) {
     apply_qhat2(c, P16, w16, p16, u16, te16, sig_base, c->partials, st);
     mms_scal1(c->mms_S, c->partials, hg, st);
@@ -211,11 +259,7 @@ int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::v
                       c->g.vh, c->g.stride, nb, st);
     }
     ++it;
-    if (it % poll_every == 0 || it == maxiter) {
-      NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S + MS_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
-      NDTM_HIP(c, hipStreamSynchronize(st));
-      if (c->hscal[0] != 0.0) break;
-    }
+    if (it % poll_every == 0 && poll.done()) break;
   }
   NDTM_HIP(c, hipGetLastError());
   NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -317,9 +361,11 @@ static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, dou
   return res <= tol ? NDTM_OK : rc;
 }
 
-// The hybrid part (multigrid shifts) lives in mg.cpp.
-int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig_desc, int n_mms, std::vector<HalfField>& xs,
-                    const HalfField& b, const ndtm_solve_params* p, ndtm_solve_report* rep, hipStream_t st);
+// The hybrid part (multigrid shifts) lives in mg.cpp; xs[n_mms .. n_mms+n_pred)
+// hold the multi-shift iterates of the passenger shifts.
+int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig_desc, int n_mms, int n_pred,
+                    std::vector<HalfField>& xs, const HalfField& b, const ndtm_solve_params* p,
+                    ndtm_solve_report* rep, hipStream_t st);
 
 }  // namespace ndtm
 
@@ -341,6 +387,7 @@ void ndtm_solve_default_params(ndtm_solve_params* p) {
   p->max_rounds = 6;
   p->use_graphs = 1;
   p->mms_defer = 32;
+  p->mms_predict = 2;
 }
 
 int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_solve_params* p,
@@ -421,10 +468,13 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       if (prc != NDTM_OK) status = prc;
     }
   } else {
-    std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
-    std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms);
+    // the first n_pred multigrid shifts ride along as passengers (predicted guesses)
+    const int n_pred = std::max(0, std::min(p->mms_predict, nsh - n_mms));
+    std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms + n_pred);
+    std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms + n_pred);
     MmsResult mr;
-    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, p->mms_defer, &mr, st);
+    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, p->mms_defer, &mr, st,
+                       n_pred);
     rep->mms_iterations = mr.iterations;
     if (rc == NDTM_EBREAKDOWN) {
       rep->status = rc;
@@ -448,7 +498,8 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   rep->t_mms_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   // ---- multigrid (case C) for the remaining shifts ----
   if (n_mms < nsh) {
-    int rc = solve_mg_shifts(c, sig, n_mms, xs, B, p, rep, st);
+    const int n_pred = p->precision == NDTM_PREC_F16 ? 0 : std::max(0, std::min(p->mms_predict, nsh - n_mms));
+    int rc = solve_mg_shifts(c, sig, n_mms, n_pred, xs, B, p, rep, st);
     if (rc != NDTM_OK && status == NDTM_OK) status = rc;
   }
   for (int i = 0; i < nsh; ++i) launch_unpack_half(c->g, xs[i], static_cast<double2*>(x_dev[order[i]]), st);

@@ -66,7 +66,7 @@ def test_hybrid_solve_with_learned_guess_held_out():
     ctx.ndtm_set_shifts(shifts)
     ctx.ndtm_mg_setup()
     ctx.ndtm_mlp_set_weights(np.load(nd.trained_weights_path())["w"])
-    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=nd.NDTM_GUESS_MLP))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=nd.NDTM_GUESS_MLP, mms_predict=0))
     print("report", {k: rep[k][9:] for k in ("guess_kind", "mlp_res", "lagrange_res", "guess_res", "iterations")},
           flush=True)
     for t in range(9, 12):

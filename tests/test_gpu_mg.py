@@ -91,7 +91,7 @@ def test_galerkin_identity_config2_shape(nd):
     ctx.close()
 
 
-def _hybrid(nd, cfg, n_mms, mgp, guess=1, tol=1e-10, amp=None):
+def _hybrid(nd, cfg, n_mms, mgp, guess=1, tol=1e-10, amp=None, predict=0):
     c = synth.CONFIGS[cfg]
     dims = c["dims"]
     U = synth.gauge_field(dims, c["gauge_seed"], amp if amp else c["amp"])
@@ -101,7 +101,7 @@ def _hybrid(nd, cfg, n_mms, mgp, guess=1, tol=1e-10, amp=None):
     ctx.ndtm_set_params(K, MB, EB)
     ctx.ndtm_set_shifts(list(c["shifts"]))
     ctx.ndtm_mg_setup(ctx.mg_params(**mgp))
-    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=tol, n_mmscg=n_mms, guess=guess))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=tol, n_mmscg=n_mms, guess=guess, mms_predict=predict))
     op = NDOperator(Lattice(dims, U), K, MB, EB)
     return ctx, op, b, c["shifts"], xs, rep
 
@@ -143,7 +143,7 @@ def test_graph_replay_matches_eager(nd):
     ctx.ndtm_mg_setup(ctx.mg_params())
     out = []
     for g in (0, 1, 1):
-        xs, rep = ctx.ndtm_solve(b, ctx.solve_params(n_mmscg=9, guess=0, use_graphs=g))
+        xs, rep = ctx.ndtm_solve(b, ctx.solve_params(n_mmscg=9, guess=0, use_graphs=g, mms_predict=0))
         out.append(([host(x) for x in xs[9:]], rep["iterations"][9:]))
     for k in (1, 2):
         assert out[k][1] == out[0][1]
@@ -194,10 +194,37 @@ def test_multigrid_failure_falls_back_to_cg(nd):
     ctx.ndtm_set_params(K, MB, EB)
     ctx.ndtm_set_shifts(list(c["shifts"]))
     ctx.ndtm_mg_setup(ctx.mg_params(block=(2, 2, 2, 2), n_vec=8))
-    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=7, guess=1, fgmres_maxiter=2, max_rounds=1))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=7, guess=1, fgmres_maxiter=2, max_rounds=1,
+                                                      mms_predict=0))
     print("report", {k: rep[k] for k in ("method", "iterations", "true_res")}, flush=True)
     op = NDOperator(Lattice(dims, U), K, MB, EB)
     assert rep["method"][7:] == [2, 2, 2]
     for i, s in enumerate(c["shifts"]):
         assert rel_residual(op, host(xs[i]), b, s) <= 1e-10, (i, s)
+    ctx.close()
+
+
+def test_predicted_guesses_config1(nd):
+    """Shifts n+1, n+2 ride along in the multi-shift CG (section 4.2, guesses via
+    MMS-CG): the multi-shift iteration count is that of the n shifts alone (the
+    passengers are not waited for), every shift converges (oracle residual), and a
+    passenger whose iterate already met the tolerance is returned as it is: within
+    the appendix A distance of the oracle's multi-shift solution."""
+    print("case c1 hybrid, predicted guesses", flush=True)
+    ctx, op, b, sig, xs0, rep0 = _hybrid(nd, "c1", 7, dict(block=(2, 2, 2, 2), n_vec=8), guess=1, predict=0)
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=7, guess=1, mms_predict=2))
+    print("report", {k: rep[k] for k in ("mms_iterations", "iterations", "guess_kind", "guess_res", "true_res")},
+          flush=True)
+    assert abs(rep["mms_iterations"] - rep0["mms_iterations"]) <= 2
+    for i, s in enumerate(sig):
+        assert rel_residual(op, host(xs[i]), b, s) <= 1e-10, (i, s)
+    assert rep["guess_kind"][9] != nd.NDTM_GUESS_MMS  # only shifts 7 and 8 are carried
+    xo, _, _ = solvers.mms_cg(lambda v: op.Q_hat2(v, sig[-1]), b, sig - sig[-1], tol=1e-10)
+    bn = np.sqrt(norm2(b))
+    for t in (7, 8):
+        if rep["guess_kind"][t] == nd.NDTM_GUESS_MMS and rep["iterations"][t] == 0:
+            assert np.linalg.norm(host(xs[t]) - xo[t]) <= 2e-10 * bn / sig[t]
+        elif rep["guess_kind"][t] == nd.NDTM_GUESS_MMS:
+            # the multigrid started from the iterate, which beat this run's Lagrange guess
+            assert rep["guess_res"][t] <= rep["lagrange_res"][t] * (1 + 1e-9)
     ctx.close()

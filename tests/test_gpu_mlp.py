@@ -182,11 +182,11 @@ def test_solve_with_learned_guess(nd):
     ctx.ndtm_set_shifts(list(c["shifts"]))
     ctx.ndtm_mg_setup(ctx.mg_params(block=(2, 2, 2, 2), n_vec=8))
     bd = dev(b)
-    xl, rl = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=1))
+    xl, rl = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=1, mms_predict=0))
     # zero output layer: y = 0, the proposal is the Lagrange guess itself
     p = mlp.init_params(4, out_scale=0.0)
     ctx.ndtm_mlp_set_weights(mlp.flatten(p))
-    xm, rm = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2))
+    xm, rm = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2, mms_predict=0))
     print("lagrange", rl["guess_res"][7:], "mlp0", rm["guess_res"][7:], rm["guess_kind"][7:], flush=True)
     assert rm["guess_kind"][7:] == [2, 2, 2]
     assert rm["guess_res"][7:] == rl["guess_res"][7:]
@@ -196,7 +196,7 @@ def test_solve_with_learned_guess(nd):
     # a random net: whatever is chosen, the predicted residual of the chosen guess
     # is no worse than Lagrange's, and every shift converges
     ctx.ndtm_mlp_set_weights(mlp.flatten(mlp.init_params(5, out_scale=0.5)))
-    xr, rr = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2))
+    xr, rr = ctx.ndtm_solve(bd, ctx.solve_params(n_mmscg=7, guess=2, mms_predict=0))
     print("random net", rr["guess_kind"][7:], rr["mlp_res"][7:], rr["lagrange_res"][7:], rr["guess_res"][7:],
           flush=True)
     for t in range(7, 10):
