@@ -10,6 +10,7 @@
 // one Krylov space for the smallest shift; the shifted systems follow from
 // r_s = zeta_s r.  All recurrences (alpha, beta, zeta_s, alpha_s, beta_s,
 // freezing) run on the device in FP64; the host only polls the done flag.
+#include "mms_scalars.h"
 #include "ndtm_internal.h"
 
 namespace ndtm {
@@ -167,65 +168,19 @@ __global__ void lincomb_k(double2* y, VecList V, CoefList C, int k, size_t n) {
 }
 
 // ---------------- MMS-CG ----------------
-// The recurrences of one iteration are a short serial chain on one thread; it
-// runs on a copy of the scalar header in LDS (loaded and stored back by the
-// whole block) so that the chain does not wait on global memory at every step.
-__device__ void mms_scal1_body(double* S, double pw) {
-  const int nsh = (int)S[MS_NSH];
-  S[MS_PW] = pw;
-  int any = 0;
-  for (int s = 0; s < nsh; ++s) {
-    S[MS_ACT + s] = S[MS_ACT_NEXT + s];
-    any |= S[MS_ACT + s] != 0.0;
-  }
-  if (!any || S[MS_BREAK] != 0.0) {
-    S[MS_ALPHA] = 0.0;
-    for (int s = 0; s < nsh; ++s) S[MS_ALPHA_S + s] = 0.0;
-    return;
-  }
-  if (!(pw > 0.0) || !isfinite(pw)) {
-    S[MS_BREAK] = 1.0;
-    S[MS_ALPHA] = 0.0;
-    for (int s = 0; s < nsh; ++s) {
-      S[MS_ALPHA_S + s] = 0.0;
-      S[MS_ACT + s] = 0.0;
-    }
-    return;
-  }
-  const double alpha = S[MS_RR] / pw;
-  const double ap = S[MS_ALPHA_PREV], bp = S[MS_BETA];
-  S[MS_ALPHA] = alpha;
-  for (int s = 0; s < nsh; ++s) {
-    if (S[MS_ACT + s] == 0.0) {
-      S[MS_ALPHA_S + s] = 0.0;
-      continue;
-    }
-    const double z = S[MS_ZETA + s], zp = S[MS_ZETA_PREV + s], d = S[MS_DELTA + s];
-    const double den = alpha * bp * (zp - z) + zp * ap * (1.0 + d * alpha);
-    const double zn = z * zp * ap / den;
-    S[MS_ZETA_NEXT + s] = zn;
-    S[MS_ALPHA_S + s] = alpha * zn / z;
-  }
+// Scalar steps of an iteration (one block each).
+__global__ void mms_scal1_k(double* S, const double* partials, int nparts) { mms::step1(S, partials, nparts); }
+
+__global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot) {
+  mms::step2(S, partials, nparts, slot);
 }
 
-__device__ void stage_scalars(double* dst, const double* src) {
-  for (int i = threadIdx.x; i < MS_COEF; i += blockDim.x) dst[i] = src[i];
-}
-
-__global__ void mms_scal1_k(double* S, const double* partials, int nparts) {
-  __shared__ double sh[MS_COEF];
-  double pw = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) pw += partials[i];
-  stage_scalars(sh, S);
-  pw = block_sum(pw);  // synchronises the block
-  if (threadIdx.x == 0) mms_scal1_body(sh, pw);
-  __syncthreads();
-  stage_scalars(S, sh);
-}
-
-// r_out = r_in - alpha w (in place when r_out == r_in), with ||r_out||^2 partials
-__global__ void mms_update_r_k(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
-                               double* partials) {
+// r_out = r_in - alpha w (in place when r_out == r_in), with ||r_out||^2 partials.
+// A set *skip (the solve's done flag) makes the launch return at once.
+__global__ void __launch_bounds__(256) mms_update_r_k(const double2* rin, double2* rout, const double2* w,
+                                                      const double* S, size_t n, double* partials,
+                                                      const double* skip) {
+  if (skip && *skip != 0.0) return;
   const double alpha = S[MS_ALPHA];
   double acc = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -238,86 +193,6 @@ __global__ void mms_update_r_k(const double2* rin, double2* rout, const double2*
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
-}
-
-// Scalar part of mms_scal2_k (one thread).  Returns 1 when the shifts active in
-// this iteration took a step (their alpha_s, beta_s, zeta_s are then final).
-__device__ int mms_scal2_body(double* S, double rr) {
-  const int nsh = (int)S[MS_NSH];
-  int any = 0;
-  for (int s = 0; s < nsh; ++s) any |= S[MS_ACT + s] != 0.0;
-  if (!any) {
-    S[MS_DONE] = 1.0;
-    return 0;
-  }
-  if (!isfinite(rr)) {
-    S[MS_BREAK] = 1.0;
-    S[MS_DONE] = 1.0;
-    for (int s = 0; s < nsh; ++s) S[MS_ACT_NEXT + s] = S[MS_ACT + s] = 0.0;
-    return 0;
-  }
-  const double beta = rr / S[MS_RR];
-  const double it = S[MS_IT] + 1.0;
-  int still = 0;
-  for (int s = 0; s < nsh; ++s) {
-    if (S[MS_ACT + s] == 0.0) continue;
-    const double z = S[MS_ZETA + s], zn = S[MS_ZETA_NEXT + s];
-    const double q = zn / z;
-    S[MS_BETA_S + s] = beta * q * q;
-    S[MS_ZETA_PREV + s] = z;
-    S[MS_ZETA + s] = zn;
-    S[MS_ITERS + s] = it;
-    // freeze once the shifted residual |zeta_s| ||r|| reaches tol ||b||
-    const bool frozen = zn * zn * rr <= S[MS_TOL2] * S[MS_BB];
-    S[MS_ACT_NEXT + s] = frozen ? 0.0 : 1.0;
-    if (S[MS_PASS + s] == 0.0) still |= !frozen;
-  }
-  // done: passengers stop with the last shift that is waited for
-  if (!still)
-    for (int s = 0; s < nsh; ++s) S[MS_ACT_NEXT + s] = 0.0;
-  S[MS_BETA] = beta;
-  S[MS_ALPHA_PREV] = S[MS_ALPHA];
-  S[MS_RR] = rr;
-  S[MS_IT] = it;
-  S[MS_DONE] = still ? 0.0 : 1.0;
-  return 1;
-}
-
-// slot >= 0: deferred form.  The residual r_{k+1} of this iteration sits in
-// slot `slot` of the current block of iterations; the coefficients of every
-// shift active in this iteration advance as
-//   x_s += alpha_s p_s:           e += alpha_s a,  d_j += alpha_s c_j
-//   p_s = zeta_s r + beta_s p_s:  a = beta_s a,    c_j = beta_s c_j,  c_slot = zeta_s
-// (c_slot is zero before this iteration, so d_slot is unchanged).
-__global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot) {
-  __shared__ double sh[MS_COEF];
-  __shared__ int go;
-  double rr = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) rr += partials[i];
-  stage_scalars(sh, S);
-  rr = block_sum(rr);  // synchronises the block
-  if (threadIdx.x == 0) go = mms_scal2_body(sh, rr);
-  __syncthreads();
-  stage_scalars(S, sh);
-  if (!go || slot < 0) return;
-  const int nsh = (int)sh[MS_NSH];
-  const double* act = sh + MS_ACT;
-  const double* al = sh + MS_ALPHA_S;
-  const double* be = sh + MS_BETA_S;
-  const double* ze = sh + MS_ZETA;
-  for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
-    const int s = idx / kMaxDefer, j = idx % kMaxDefer;
-    if (act[s] == 0.0 || j > slot) continue;
-    double* C = S + MS_COEF + s * kCoefStride;
-    const double cj = C[MC_C + j];
-    C[MC_D + j] += al[s] * cj;
-    C[MC_C + j] = j == slot ? ze[s] : be[s] * cj;
-    if (j == 0) {
-      C[MC_E] += al[s] * C[MC_A];
-      C[MC_A] *= be[s];
-      C[MC_TOUCHED] = 1.0;
-    }
-  }
 }
 
 // Start of a block of deferred iterations: a = 1, e = c = d = 0, untouched.
@@ -336,8 +211,11 @@ struct ShiftPtrs {
 
 // sb: the base shift (delta = 0).  Its zeta stays 1, so its direction equals the
 // base direction p and is not stored separately: x_sb += alpha p before p moves.
+// it >= 0: the launch belongs to iteration it and returns at once unless that
+// iteration took its scalar step (the iterations queued past convergence).
 __global__ void mms_update_p_k(const double2* r, double2* p, ShiftPtrs P, int nsh, int sb, const double* S,
-                               size_t n) {
+                               size_t n, int it) {
+  if (it >= 0 && S[MS_IT] != (double)(it + 1)) return;
   const double beta = S[MS_BETA];
   const bool any_before = S[MS_ALPHA] != 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -373,11 +251,11 @@ __device__ __forceinline__ double2 ld_stream(const double2* p) {
   return make_double2(v.x, v.y);
 }
 
-// Base direction of the deferred form: p = r + beta p (r is r_{k+1}); skipped
-// once no shift is left (alpha = 0).
+// Base direction of the deferred form: p = r + beta p (r is r_{k+1}) for
+// iteration it; skipped unless that iteration took its scalar step.
 __global__ void __launch_bounds__(256) mms_update_pbase_k(const double2* r, double2* p, const double* S,
-                                                           size_t n) {
-  if (S[MS_ALPHA] == 0.0) return;
+                                                           size_t n, int it) {
+  if (S[MS_IT] != (double)(it + 1) || S[MS_ALPHA] == 0.0) return;
   const double beta = S[MS_BETA];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const double2 ri = r[i], pi = p[i];
@@ -604,8 +482,8 @@ void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(mms_scal1_k, dim3(1), dim3(256), 0, st, S, partials, nparts);
 }
 void mms_update_r(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
-                  double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(mms_update_r_k, dim3(grid_for(n)), dim3(256), 0, st, rin, rout, w, S, n, partials);
+                  double* partials, hipStream_t st, const double* skip) {
+  hipLaunchKernelGGL(mms_update_r_k, dim3(grid_for(n)), dim3(256), 0, st, rin, rout, w, S, n, partials, skip);
 }
 void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st) {
   hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts, slot);
@@ -613,8 +491,8 @@ void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStrea
 void mms_coef_reset(double* S, hipStream_t st) {
   hipLaunchKernelGGL(mms_coef_reset_k, dim3(1), dim3(256), 0, st, S);
 }
-void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL(mms_update_pbase_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n);
+void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_pbase_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n, it);
 }
 void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
                size_t n, hipStream_t st) {
@@ -626,13 +504,13 @@ void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R
   hipLaunchKernelGGL(mms_flush_k, dim3(grid_for(n)), dim3(256), 0, st, P, R, nr, S, n);
 }
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
-                  const double* S, size_t n, hipStream_t st) {
+                  const double* S, size_t n, hipStream_t st, int it) {
   ShiftPtrs P;
   for (int s = 0; s < nsh; ++s) {
     P.x[s] = xs[s];
     P.p[s] = ps[s];
   }
-  hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, sb, S, n);
+  hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, sb, S, n, it);
 }
 int red_grid(size_t n) { return (int)grid_for(n); }
 void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,

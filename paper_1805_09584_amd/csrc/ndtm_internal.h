@@ -137,20 +137,23 @@ void blas_gram(const double2* const* V, int k, size_t n, double* partials, doubl
 // ---- MMS-CG -----------------------------------------------------------------
 // Device-side scalars in S (layout below).
 void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st);
-// r_out = r_in - alpha w (r_out may equal r_in), ||r_out||^2 partials
+// r_out = r_in - alpha w (r_out may equal r_in), ||r_out||^2 partials; a set *skip
+// returns at once
 void mms_update_r(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
-                  double* partials, hipStream_t st);
+                  double* partials, hipStream_t st, const double* skip = nullptr);
 // beta, zeta_s, beta_s, freezing; slot >= 0 also advances the deferred coefficients
 // with the residual of this iteration in that slot
 void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st);
 // p_s, x_s of every active shift in one pass; sb = the base shift (delta 0), whose
 // direction is p itself and whose ps[sb] is not used
+// it >= 0: returns at once unless iteration it took its scalar step
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
-                  const double* S, size_t n, hipStream_t st);
-// deferred form: base direction p = r + beta p; coefficient reset at the start of a
+                  const double* S, size_t n, hipStream_t st, int it = -1);
+// deferred form: base direction p = r + beta p of iteration it (returns at once unless
+// that iteration took its scalar step); coefficient reset at the start of a
 // block; flush of the residuals in slots 0..nr-1 of the ring R (slot j at R + j n) into
 // x_s, p_s of every shift touched in the block
-void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, hipStream_t st);
+void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st);
 void mms_coef_reset(double* S, hipStream_t st);
 void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
                size_t n, hipStream_t st);

@@ -10,7 +10,10 @@
 //   r -= alpha w, ||r||^2            fused
 //   scalars (beta, beta_s, freeze)   one-block kernel
 //   x_s += alpha_s p_s, p_s = zeta_s r + beta_s p_s, p = r + beta p   fused over active shifts
-// with a host poll of the done flag every poll_every iterations.
+// with a host poll of the done flag every poll_every iterations.  (Taking the
+// scalar steps in the last block of the vector kernels instead was slower: the
+// device-scope release of every block before the election writes back the
+// XCD's L2, which the stencil and the residual update have just filled.)
 //
 // Deferred form (defer = m >= 2): the last step reads and writes x_s and p_s of
 // every active shift each iteration, 4 vectors per shift, more than the stencil
@@ -130,8 +133,6 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     mms_seed(c->mms_S, c->dscal, st);
   }
   if (deferred) mms_coef_reset(c->mms_S, st);
-  const int hg = hop_grid(c->g);
-  const int rg = red_grid(n);
   int it = 0;
   if (poll_every < 1) poll_every = 1;
   LaggedPoll poll(c, c->mms_S + MS_DONE, st);
@@ -142,7 +143,11 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     mms_coef_reset(c->mms_S, st);
     flushes.emplace_back(it - nr, nr);
   };
+  const int hg = hop_grid(c->g);
+  const int rg = red_grid(n);
   while (it < maxiter) {
+    // past the done flag the stencil passes and the residual update return at once, and
+    // the update kernels of an iteration run only if its scalar step was taken
     apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
     mms_scal1(c->mms_S, c->partials, hg, st);
     // deferred: r_k is in slot (k-1) mod m (b for k = 0), r_{k+1} goes to slot k mod m
@@ -151,16 +156,16 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     double2* rout = deferred ? ring + (size_t)slot * n : (double2*)r.v;
     {
       ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
-      mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st);
+      mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st, c->hop_skip);
     }
     mms_scal2(c->mms_S, c->partials, rg, slot, st);
     if (deferred) {
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_pbase(rout, (double2*)p.v, c->mms_S, n, st);
+      mms_update_pbase(rout, (double2*)p.v, c->mms_S, n, it, st);
     } else {
       // bytes of this class are added after the loop, once the active counts are known
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st);
+      mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st, it);
     }
     ++it;
     if (deferred && it % defer == 0) flush(defer);

@@ -11,6 +11,9 @@
   per-iteration updates: the base Krylov process is the same computation, so
   the iteration counts agree exactly and the solutions to rounding; also when
   the iteration cap ends the solve inside a block.
+* the host polls that lag one poll behind (launches past convergence return at
+  once) give bit for bit the solutions of polls that wait for the flag (as with
+  kernel timing on), in both forms.
 """
 import numpy as np
 import pytest
@@ -137,4 +140,19 @@ def test_deferred_updates_match_direct(nd):
     for i in range(len(sig)):
         a, c = host(xa[i]), host(xb[i])
         assert np.linalg.norm(c - a) <= 1e-12 * np.linalg.norm(a), i
+    ctx.close()
+
+
+def test_lagged_polls_match_waiting_polls(nd):
+    print("lagged vs waiting polls c1", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c1")
+    bd = dev(b)
+    for m in (0, 32):
+        xa, ra = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=m))
+        ctx.ndtm_profile_enable(0xFF)  # kernel timing on: every poll waits for its own flag
+        xb, rb = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=m))
+        ctx.ndtm_profile_enable(0)
+        assert ra["iterations"] == rb["iterations"]
+        for i in range(len(sig)):
+            assert np.array_equal(host(xa[i]), host(xb[i])), (m, i)
     ctx.close()
