@@ -134,6 +134,12 @@ typedef struct {
   double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
   unsigned long long seed; /* seed of the random initial test vectors */
   int precision;       /* NDTM_PREC_F64 or NDTM_PREC_F32 for P, coarse ops and the cycle */
+  double coarse_tol;   /* 0: the coarse solve is coarse_iters GMRES iterations from zero (a fixed
+                          sequence, which the cycle graphs capture).  > 0: GMRES(coarse_iters)
+                          restarted on the true coarse residual until it is below coarse_tol
+                          relative (section 3: the coarse system solved to a loose tolerance);
+                          the host reads the residual after each cycle, so no graphs */
+  int coarse_cycles;   /* restart cap of the coarse solve when coarse_tol > 0 (>= 1) */
 } ndtm_mg_params;
 
 /* Fills *p with the defaults (4^4 aggregates, 24 vectors, ...). */
@@ -158,8 +164,9 @@ int ndtm_mg_prolong(ndtm_ctx* ctx, void* v_dev, const void* vc_dev, void* stream
  *                     + i m C_o x tau1) xc   (eq:non-degenerate_coarse). */
 int ndtm_mg_coarse_apply(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, double m, void* stream);
 
-/* xc ~ D'_c(m)^-1 bc by the coarse solver the cycle uses (coarse_iters GMRES
- * iterations from zero in the cycle precision; no convergence test). */
+/* xc ~ D'_c(m)^-1 bc by the coarse solver the cycle uses, in the cycle precision:
+ * coarse_iters GMRES iterations from zero, restarted while the relative residual
+ * is above coarse_tol (when that is > 0, at most coarse_cycles cycles). */
 int ndtm_mg_coarse_solve(ndtm_ctx* ctx, void* xc_dev, const void* bc_dev, double m, void* stream);
 
 /* ---- solve ------------------------------------------------------------- */

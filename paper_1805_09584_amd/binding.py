@@ -34,7 +34,8 @@ class MGParams(C.Structure):
     _fields_ = [("block", C.c_int * 4), ("n_vec", C.c_int), ("setup_iters", C.c_int),
                 ("setup_smooth", C.c_int), ("setup_refine", C.c_int), ("setup_nd", C.c_int),
                 ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
-                ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int)]
+                ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int),
+                ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int)]
 
 
 class SolveParams(C.Structure):

@@ -55,6 +55,8 @@ struct MGData {
   std::vector<void*> cV;  // coarse basis (cycle precision), coarse_iters + 1
   void* cW = nullptr;
   void* cR = nullptr;
+  void* cT = nullptr;     // coarse residual of the restarted solve
+  void* cX = nullptr;     // coarse solution (cW is the Arnoldi work vector)
   double* dH = nullptr;   // Hessenberg columns, coarse_iters x (coarse_iters+1) complex
   double* dsub = nullptr; // subdiagonal norms^2
   double* dy = nullptr;   // least-squares coefficients
@@ -111,15 +113,17 @@ static double coarse_bytes(const MGData* M) {
   return (double)M->g.Vc * (9.0 * n2 * n2 + 0.5 * n2 * n2) * es + 2.0 * (double)M->ncoarse * es;
 }
 
-// ---- coarse solve: fixed-length GMRES from zero, all on the device ----------
-static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
-                         hipStream_t st) {
+// ---- coarse solve: GMRES on the device ------------------------------------
+// One GMRES(kc) cycle from zero on D'_c y = src; *src2 = ||src||^2 on the device.
+// The solution is written (accumulate = 0) or added (1) to sol, which must not be
+// cW, the Arnoldi work vector.
+static void coarse_gmres_cycle(ndtm_ctx* c, MGData* M, const void* src, const double* src2, void* sol,
+                               int accumulate, double m, double eps, hipStream_t st) {
   const int cp = M->cprec;
   const size_t n = M->ncoarse;
   const int kc = M->prm.coarse_iters;
   const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
-  vnorm2(cp, rhs, n, c->vred, M->dbeta, st);
-  vscale_inv_sqrt(cp, M->cV[0], rhs, M->dbeta, n, st);
+  vscale_inv_sqrt(cp, M->cV[0], src, src2, n, st);
   for (int j = 0; j < kc; ++j) {
     {
       ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
@@ -135,8 +139,39 @@ static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, dou
     vadd_dev(hcol, M->dh2, 2 * (j + 1), st);
     vscale_inv_sqrt(cp, M->cV[j + 1], M->cW, M->dsub + j, n, st);
   }
-  hess_lsq(M->dH, kc + 1, kc, M->dbeta, M->dsub, M->dy, st);
-  vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, 0, n, st);
+  hess_lsq(M->dH, kc + 1, kc, src2, M->dsub, M->dy, st);
+  vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, accumulate, n, st);
+}
+
+// sol ~ D'_c(m)^-1 rhs.  coarse_tol = 0: one cycle from zero, a fixed launch
+// sequence with no host synchronisation.  coarse_tol > 0: restarted on the true
+// coarse residual (read by the host after each cycle) until it is below
+// coarse_tol ||rhs|| or coarse_cycles cycles have run.
+static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
+                         hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t n = M->ncoarse;
+  const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+  vnorm2(cp, rhs, n, c->vred, M->dbeta, st);
+  coarse_gmres_cycle(c, M, rhs, M->dbeta, sol, 0, m, eps, st);
+  if (!(M->prm.coarse_tol > 0.0)) return;
+  (void)hipMemcpyAsync(c->hscal, M->dbeta, sizeof(double), hipMemcpyDeviceToHost, st);
+  (void)hipStreamSynchronize(st);
+  const double rhs2 = c->hscal[0];
+  const double tol2 = M->prm.coarse_tol * M->prm.coarse_tol * rhs2;
+  for (int cyc = 1; cyc < M->prm.coarse_cycles && rhs2 > 0.0; ++cyc) {
+    {
+      ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
+      mg_coarse_apply(cp, M->g, M->Dc, M->Boc, sol, M->cT, mubar_c, eps, m, st);
+    }
+    vaxpby(cp, M->cT, make_double2(1, 0), rhs, make_double2(-1, 0), n, st);  // cT = rhs - D sol
+    vnorm2(cp, M->cT, n, c->vred, M->dbeta + 1, st);
+    (void)hipMemcpyAsync(c->hscal, M->dbeta + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    const double res2 = c->hscal[0];
+    if (!(res2 > tol2) || !std::isfinite(res2)) break;
+    coarse_gmres_cycle(c, M, M->cT, M->dbeta + 1, sol, 1, m, eps, st);
+  }
 }
 
 // full-lattice D' in the cycle precision
@@ -155,10 +190,10 @@ static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
     ProfScope ps(c, NDTM_PROF_RESTRICT, transfer_bytes(M), st);
     mg_restrict(cp, M->g, M->Pc, R.e.v, R.o.v, M->cR, st);
   }
-  coarse_solve(c, M, M->cR, M->cW, m, eps, st);
+  coarse_solve(c, M, M->cR, M->cX, m, eps, st);
   {
     ProfScope ps(c, NDTM_PROF_PROLONG, transfer_bytes(M), st);
-    mg_prolong(cp, M->g, M->Pc, M->cW, Z.e.v, Z.o.v, st);
+    mg_prolong(cp, M->g, M->Pc, M->cX, Z.e.v, Z.o.v, st);
   }
   // post-smoothing: minimal residual steps on D' z = r
   const int nu = M->prm.smooth_iters;
@@ -395,7 +430,8 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, int 
                     ndtm_solve_report* rep, hipStream_t st) {
   MGData* M = c->mg;
   if (!M || !M->ready) return fail(c, NDTM_ESTATE, "solve: multigrid shifts need ndtm_mg_setup first");
-  M->use_graphs = p->use_graphs != 0;
+  // a coarse solve to a tolerance reads its residual on the host: no capture
+  M->use_graphs = p->use_graphs != 0 && !(M->prm.coarse_tol > 0.0);
   const int nsh = (int)sig.size();
   const size_t n = half_elems(c);
   int status = NDTM_OK;
@@ -550,13 +586,15 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   }
   M->cW = mg_alloc(M, M->ncoarse * csz(M->cprec));
   M->cR = mg_alloc(M, M->ncoarse * csz(M->cprec));
+  M->cT = mg_alloc(M, M->ncoarse * csz(M->cprec));
+  M->cX = mg_alloc(M, M->ncoarse * csz(M->cprec));
   M->dH = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
   M->dsub = (double*)mg_alloc(M, (kc + 1) * sizeof(double));
   M->dy = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
   M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
   M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
   M->dh2 = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
-  if (!M->dh2 || !M->cW || !M->cR || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
+  if (!M->dh2 || !M->cW || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
   if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");
@@ -702,6 +740,8 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->coarse_mu_factor = 1.0;
   p->seed = 32;
   p->precision = NDTM_PREC_F32;
+  p->coarse_tol = 0.0;
+  p->coarse_cycles = 20;
 }
 
 int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* stream) {
@@ -719,6 +759,8 @@ int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* st
     return fail(c, NDTM_EINVAL, "mg_setup: n_vec even in [2, 32]");
   if (6 * nloc < p->n_vec) return fail(c, NDTM_EINVAL, "mg_setup: aggregate too small for n_vec vectors");
   if (p->coarse_iters < 1 || p->coarse_iters > 32) return fail(c, NDTM_EINVAL, "mg_setup: coarse_iters in [1, 32]");
+  if (!(p->coarse_tol >= 0.0) || (p->coarse_tol > 0.0 && p->coarse_cycles < 1))
+    return fail(c, NDTM_EINVAL, "mg_setup: coarse_tol >= 0 and coarse_cycles >= 1");
   if (p->smooth_iters < 0 || p->setup_iters < 0 || p->setup_smooth < 1 || p->setup_refine < 0 || !(p->coarse_mu_factor >= 1.0))
     return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
   if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32)
@@ -762,8 +804,8 @@ int ndtm_mg_coarse_solve(ndtm_ctx* c, void* xc, const void* bc, double m, void* 
   hipStream_t st = static_cast<hipStream_t>(stream);
   MGData* M = c->mg;
   vconvert(M->cprec, M->cR, P64, bc, M->ncoarse, st);
-  coarse_solve(c, M, M->cR, M->cW, m, c->epsbar, st);
-  vconvert(P64, xc, M->cprec, M->cW, M->ncoarse, st);
+  coarse_solve(c, M, M->cR, M->cX, m, c->epsbar, st);
+  vconvert(P64, xc, M->cprec, M->cX, M->ncoarse, st);
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }

@@ -228,3 +228,68 @@ def test_predicted_guesses_config1(nd):
             # the multigrid started from the iterate, which beat this run's Lagrange guess
             assert rep["guess_res"][t] <= rep["lagrange_res"][t] * (1 + 1e-9)
     ctx.close()
+
+
+def test_coarse_solve_to_tolerance(nd):
+    """With coarse_tol > 0 the coarse GMRES(2) restarts on the true coarse residual
+    until it is below the tolerance: the oracle's dense coarse operator (built from
+    the same P) confirms ||b_c - D'_c x_c|| <= coarse_tol ||b_c|| for both signs of
+    m, where a single two-iteration cycle stays well above it."""
+    dims, block, Nv = (8, 8, 8, 8), (4, 4, 4, 4), 8
+    print("case 8^4 coarse solve to tolerance", flush=True)
+    U = synth.gauge_field(dims, 31, 0.3)
+    lat = Lattice(dims, U)
+    op = NDOperator(lat, K, MB, EB)
+    tv = synth.gaussian_vectors((Nv, lat.V, 4, 3), 32)
+    P = omg.build_prolongator(tv, dims, block)
+    agg = omg.aggregate_of_site(dims, block)
+    Vc = int(np.prod(omg.coarse_dims(dims, block)))
+    Dc = omg.coarse_wilson_dense(lat, op.a, P, agg, Vc)
+    Bo = omg.odd_projector_coarse(lat, P, agg, Vc)
+    bc = synth.gaussian_vectors((Vc, 2, 2 * Nv), 6)
+    res = {}
+    for tol in (0.0, 1e-9):
+        ctx = nd.Context(dims)
+        ctx.ndtm_set_gauge(dev(U))
+        ctx.ndtm_set_params(K, MB, EB)
+        ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, coarse_iters=2, coarse_tol=tol,
+                                        coarse_cycles=400), test_vectors=dev(tv))
+        for m in (0.01, -0.01):
+            xc = host(ctx.ndtm_mg_coarse_solve(dev(bc), m))
+            r = bc - omg.coarse_nd_apply(Dc, Bo, xc, Nv, MB, EB, m=m)
+            res[(tol, m)] = np.linalg.norm(r) / np.linalg.norm(bc)
+        ctx.close()
+    print("relative coarse residuals", res, flush=True)
+    for m in (0.01, -0.01):
+        assert res[(1e-9, m)] <= 1e-9
+        assert res[(0.0, m)] > 1e-6
+
+
+def test_near_critical_coarse_tolerance_config(nd):
+    """kappa = 0.133 (near the critical value of these links) on 8^4: the
+    multigrid shifts converge (oracle residual) with the coarse system solved
+    to a tolerance, in no more outer iterations than with the fixed coarse solve."""
+    dims = (8, 8, 8, 8)
+    kap = 0.133
+    print("case 8^4 kappa 0.133 hybrid, coarse fixed vs to tolerance", flush=True)
+    U = synth.gauge_field(dims, 41, 0.3)
+    b = synth.gaussian_spinor(dims, 42)
+    shifts = synth.geometric_shifts(10, 1e-4)
+    op = NDOperator(Lattice(dims, U), kap, MB, EB)
+    its, meth = {}, {}
+    for tol in (0.0, 1e-2):
+        ctx = nd.Context(dims)
+        ctx.ndtm_set_gauge(dev(U))
+        ctx.ndtm_set_params(kap, MB, EB)
+        ctx.ndtm_set_shifts(list(shifts))
+        ctx.ndtm_mg_setup(ctx.mg_params(block=(4, 4, 4, 4), coarse_tol=tol, coarse_cycles=50))
+        xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=7, guess=1, mms_predict=0))
+        its[tol], meth[tol] = rep["iterations"][7:], rep["method"][7:]
+        print("coarse_tol", tol, "method", meth[tol], "iterations", its[tol], "t_mg_ms", rep["t_mg_ms"], flush=True)
+        for i, s in enumerate(shifts):
+            assert rel_residual(op, host(xs[i]), b, s) <= 1e-10, (tol, i)
+        ctx.close()
+    # solved to a tolerance, the multigrid finishes every shift itself
+    assert meth[1e-2] == [1, 1, 1]
+    if meth[0.0] == [1, 1, 1]:
+        assert sum(its[1e-2]) <= sum(its[0.0])
