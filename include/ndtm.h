@@ -234,6 +234,26 @@ typedef struct {
 int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
                const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
 
+/* ---- rational approximation (section "Rational approximation") ---------- */
+/* Zolotarev's optimal rational approximation R(y) = a prod_j (y + c_{2j-1})/(y + c_{2j})
+ * of 1/sqrt(y) on eps < y < 1, order n (eq:rational, eq:zolotarev_shifts): writes
+ * c[0..2n-1] = c_1..c_2n (descending), *a and *delta = max |1 - sqrt(y) R(y)|
+ * (eq:deviation; delta = d^2 / (1 + sqrt(1 - d^2))^2).  Host computation, no
+ * context or device; 0 <= n <= 16, 0 < eps < 1, else EINVAL. */
+int ndtm_zolotarev(int n, double eps, double* c, double* a, double* delta);
+
+/* y ~ (Q^2)^{-1/2} b by eq:ratapp, for a spectrum of Q^2 inside [eps lambda, lambda]:
+ * the order-n coefficients on [eps, 1] give the shifts sigma_i = lambda c_{2i}, which
+ * become the context's shifts (as ndtm_set_shifts would set them), all shifts are
+ * solved by ndtm_solve with *p (report in *report), and
+ * y = lambda^{-1/2} a (b + sum_i q_i lambda x_i).  b, y: odd-site canonical complex128
+ * on the device, not aliased.  The relative error of y is at most delta plus the solve
+ * tolerance amplified by the weights.  Returns ndtm_solve's status (y is written for
+ * ENOCONV too); EINVAL for 1 <= n <= 16, 0 < eps < 1, lambda > 0 violated.
+ * Synchronises the stream. */
+int ndtm_solve_rational(ndtm_ctx* ctx, void* y_dev, const void* b_dev, int n, double eps, double lambda,
+                        const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
+
 /* ---- learned initial-guess proposer ------------------------------------ */
 /* A 3-layer tanh network (59 -> 64 -> 64 -> 11) proposes the correction y to the
  * Lagrange coefficients over the converged solutions, c = l + tau y with
@@ -283,7 +303,10 @@ enum {
   NDTM_PROF_HOP_F64 = 0,  /* stencil pass, per output site 1920 B (+384 per extra site vector) */
   NDTM_PROF_HOP_F32 = 1,  /* 960 B (+192) */
   NDTM_PROF_HOP_F16 = 2,  /* 488 B (+100) */
-  NDTM_PROF_MMS_UPDATE = 3, /* fused shift update, (1 + 4 N_active) x 384 B per odd site
+  NDTM_PROF_MMS_UPDATE = 3, /* shifted updates.  Deferred form: p = r + beta p, 3 x 384 B
+                               per odd site and iteration, and each flush of m residuals,
+                               (m + 3 N_touched + N_still_active) x 384 B per odd site.
+                               Per-iteration form: (1 + 4 N_active) x 384 B per odd site
                                (r, p in, p out; x_s, p_s in and out; the base shift's
                                direction is p itself) */
   NDTM_PROF_MMS_RESID = 4,  /* r -= alpha w with ||r||^2, 3 x 384 B per odd site */

@@ -27,6 +27,7 @@ from .binding import (  # noqa: F401
     PROF_CLASSES,
     lib_path,
     load_library,
+    zolotarev,
 )
 
 

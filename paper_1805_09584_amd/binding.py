@@ -102,6 +102,8 @@ def load_library():
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
+        "ndtm_zolotarev": (i, [i, d, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "ndtm_solve_rational": (i, [vp, vp, vp, i, d, d, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_mlp_set_weights": (i, [vp, fp, C.c_size_t]),
         "ndtm_mlp_get_weights": (i, [vp, fp, C.c_size_t]),
         "ndtm_mlp_forward": (i, [vp, i, fp, fp, fp, fp, i, fp, fp]),
@@ -121,6 +123,16 @@ def load_library():
         f.argtypes = args
     _LIB = lib
     return lib
+
+
+def zolotarev(n, eps):
+    """(c_1..c_2n, a, delta) of Zolotarev's approximation of 1/sqrt(y) on [eps, 1] (host)."""
+    c = (C.c_double * max(2 * n, 1))()
+    a, d = C.c_double(), C.c_double()
+    rc = load_library().ndtm_zolotarev(int(n), float(eps), c, C.byref(a), C.byref(d))
+    if rc != 0:
+        raise NdtmError(rc, "ndtm_zolotarev: bad order or interval")
+    return np.array(c[:2 * n]), a.value, d.value
 
 
 def _fp(a):
@@ -253,6 +265,22 @@ class Context:
         d = rep.to_dict()
         d["rc"] = rc
         return xs, d
+
+    # -- rational approximation -----------------------------------------------
+    def ndtm_solve_rational(self, b, n, eps, lam, params=None, check=True):
+        """y ~ (Q^2)^{-1/2} b by the order-n Zolotarev approximation on [eps lam, lam];
+        the context's shifts become the approximation's.  Returns (y, report dict)."""
+        p = params if params is not None else self.solve_params()
+        y = torch.empty_like(b)
+        rep = SolveReport()
+        rc = self.lib.ndtm_solve_rational(self.h, _ptr(y), _ptr(b), int(n), float(eps), float(lam), C.byref(p),
+                                          C.byref(rep), _stream())
+        if check:
+            self._check(rc)
+        self.n_shifts = int(n)
+        d = rep.to_dict()
+        d["rc"] = rc
+        return y, d
 
     # -- learned guess proposer -----------------------------------------------
     def ndtm_mlp_set_weights(self, w):
