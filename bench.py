@@ -90,7 +90,7 @@ def form_params(ctx, nd, form):
     if form == "plain":
         return ctx.solve_params(tol=1e-10)
     if form == "plain_direct":
-        # shifted solutions and directions updated every iteration instead of once per 32
+        # shifted solutions and directions updated every iteration instead of once per block
         return ctx.solve_params(tol=1e-10, mms_defer=0)
     if form == "hybrid":
         # the paper's recipe (section 4.2): shifts n+1, n+2 start from their multi-shift
@@ -287,7 +287,7 @@ def main():
                                f"{forms[0]} ({N_MMS} multi-shift CG + {len(cfg['shifts']) - N_MMS} multigrid case C"
                                + (", the first two multigrid shifts carried in the multi-shift CG for predicted "
                                   "initial guesses, Lagrange-interpolated guesses for the rest; shifted vectors "
-                                  "formed once per 32 iterations)"
+                                  "formed once per block of up to 256 iterations)"
                                   if forms[0] == "hybrid" else ")")
                                if forms[0] != "plain" else "plain multi-shift CG",
                    "lattice": list(dims), "n_shifts": len(cfg["shifts"]), "form": forms[0],

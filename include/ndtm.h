@@ -191,11 +191,12 @@ typedef struct {
   int max_rounds;      /* FP64 defect-correction rounds per multigrid shift */
   int use_graphs;      /* 1: replay the multigrid cycle from a captured HIP graph (one per
                           shift sign, cached until the next setup); 0: launch eagerly */
-  int mms_defer;       /* FP64 MMS-CG: 2..32 forms the shifted solutions and directions once
-                          per block of this many iterations, from the block's residuals kept
-                          in as many extra half fields (same iterates up to rounding, far
-                          fewer vector passes); 0 or 1 updates them every iteration;
-                          larger values are clamped to 32 */
+  int mms_defer;       /* FP64 MMS-CG: 2..256 forms the shifted solutions (and, between
+                          blocks, directions) once per block of this many iterations from
+                          the block's residuals, kept in as many extra half fields (same
+                          iterates up to rounding, far fewer vector passes); 0 or 1 updates
+                          them every iteration.  Clamped to 256 and so that the residual
+                          slots take at most half of the free device memory */
   int mms_predict;     /* FP64 hybrid: the first this many multigrid shifts ride along in the
                           multi-shift CG without being waited for (section 4.2, initial guesses
                           via MMS-CG); each starts from its multi-shift iterate when that has

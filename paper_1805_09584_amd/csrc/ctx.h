@@ -39,6 +39,8 @@ struct ndtm_ctx {
   double* dscal = nullptr;  // device scalar scratch (kScalN doubles)
   double* hscal = nullptr;  // pinned host mirror
   double* mms_S = nullptr;
+  double* mms_H = nullptr;  // MMS-CG history of the deferred form [kMaxDefer][kMaxShifts][kHistStride]
+  double* mms_C = nullptr;  // its flush coefficients [kMaxShifts][kCoefStride]
   std::map<std::string, ndtm::DevBuf> bufs;
   int prof_mask = 0;  // bit k: time kernel class k
   const double* hop_skip = nullptr;  // device flag handed to stencil launches (see OpParams::skip)

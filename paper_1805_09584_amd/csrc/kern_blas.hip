@@ -171,8 +171,8 @@ __global__ void lincomb_k(double2* y, VecList V, CoefList C, int k, size_t n) {
 // Scalar steps of an iteration (one block each).
 __global__ void mms_scal1_k(double* S, const double* partials, int nparts) { mms::step1(S, partials, nparts); }
 
-__global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot) {
-  mms::step2(S, partials, nparts, slot);
+__global__ void mms_scal2_k(double* S, const double* partials, int nparts, int slot, double* H) {
+  mms::step2(S, partials, nparts, slot, H);
 }
 
 // r_out = r_in - alpha w (in place when r_out == r_in), with ||r_out||^2 partials.
@@ -195,14 +195,6 @@ __global__ void __launch_bounds__(256) mms_update_r_k(const double2* rin, double
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// Start of a block of deferred iterations: a = 1, e = c = d = 0, untouched.
-__global__ void mms_coef_reset_k(double* S) {
-  const int nsh = (int)S[MS_NSH];
-  for (int idx = threadIdx.x; idx < nsh * kCoefStride; idx += blockDim.x) {
-    const int k = idx % kCoefStride;
-    S[MS_COEF + idx] = k == MC_A ? 1.0 : 0.0;
-  }
-}
 
 struct ShiftPtrs {
   double2* x[kMaxShifts];
@@ -268,71 +260,134 @@ struct DeferPtrs {
   double2* p[kMaxShifts];
 };
 
-// End of a block of nr deferred iterations: for every shift touched in it,
-//   x_s += e P_s + sum_j d_j R_j,   P_s = a P_s + sum_j c_j R_j,
-// each residual R_j (slot j of the ring R, slots n apart) read once for all
-// shifts.  The direction of a shift that has frozen is not written back (it is
-// never used again).
+// Coefficients of a block of nr iterations that began at iteration k0 (one thread
+// per shift).  Only the iterations that took their step count (S[MS_IT] of them in
+// total): K = min(nr, S[MS_IT] - k0).  With x_{k+1} = x_k + alpha_k p_k and
+// p_{k+1} = zeta_{k+1} r_{k+1} + beta_k p_k, unrolled from the block start P, X:
+//   x_end = X + S_{k0} P + sum_j zeta_{k0+j+1} S_{k0+j+1} r_{k0+j+1},
+//   p_end = T_{k0} P + sum_j zeta_{k0+j+1} T_{k0+j+1} r_{k0+j+1},
+// with S_k = alpha_k + beta_k S_{k+1}, T_k = beta_k T_{k+1}, S_end = 0, T_end = 1.
+// A frozen shift records alpha = 0, so its S stays exact; its T is not used.
+__global__ void mms_flush_prep_k(const double* S, const double* H, double* C, int nr, int k0) {
+  // the history is staged through LDS in chunks of kPrepChunk slots (loaded by the
+  // whole block), so that the per-shift recurrence does not wait on global memory
+  constexpr int kPrepChunk = 64;
+  __shared__ double hs[kPrepChunk][kMaxShifts][kHistStride];
+  const int nsh = (int)S[MS_NSH];
+  const int K = max(0, min(nr, (int)S[MS_IT] - k0));
+  const int s = threadIdx.x;
+  double* c = C + (size_t)(s < kMaxShifts ? s : 0) * kCoefStride;
+  double sa = 0.0, t = 1.0;
+  bool touched = false;
+  if (s < nsh)
+    for (int j = K; j < nr; ++j) c[MC_C + j] = c[MC_D + j] = 0.0;
+  for (int top = K; top > 0; top -= kPrepChunk) {
+    const int lo = max(0, top - kPrepChunk);
+    __syncthreads();
+    for (int e = threadIdx.x; e < (top - lo) * kMaxShifts * kHistStride; e += blockDim.x)
+      (&hs[0][0][0])[e] = H[(size_t)lo * kMaxShifts * kHistStride + e];
+    __syncthreads();
+    if (s < nsh) {
+      for (int j = top - 1; j >= lo; --j) {
+        const double* h = hs[j - lo][s];
+        const double al = h[0], be = h[1], ze = h[2];
+        c[MC_D + j] = ze * sa;
+        c[MC_C + j] = ze * t;
+        sa = al + be * sa;
+        t = be * t;
+        touched |= h[3] != 0.0;
+      }
+    }
+  }
+  if (s < nsh) {
+    c[MC_A] = t;
+    c[MC_E] = sa;
+    c[MC_TOUCHED] = touched ? 1.0 : 0.0;
+  }
+}
+
+// The flush: for every shift touched in the block,
+//   x_s = x_s + e P_s + sum_j d_j R_j,   P_s = a P_s + sum_j c_j R_j (WITH_P),
+// with the shifts' sums kept in registers while the residuals stream by in chunks
+// of kFlushChunk, so each residual and each x_s, P_s moves once.  A chunk's
+// coefficients are staged in LDS (the loop over elements is block-uniform so that
+// every thread reaches the barriers).  The direction of a shift that has frozen is
+// not written back (it is never used again).
+constexpr int kFlushChunk = 8;
+template <bool WITH_P>
 __global__ void __launch_bounds__(256) mms_flush_k(DeferPtrs P, const double2* R, int nr, const double* S,
-                                                   size_t n) {
-  __shared__ double cd[kMaxShifts][2][kMaxDefer];
+                                                   const double* C, size_t n) {
+  __shared__ double cd[kMaxShifts][2][kFlushChunk];  // [k][0: c, 1: d][j] of the current chunk
   __shared__ double ae[kMaxShifts][2];
   __shared__ int keep[kMaxShifts], list[kMaxShifts], nlist;
   const int nsh = (int)S[MS_NSH];
-  for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
-    const int s = idx / kMaxDefer, j = idx % kMaxDefer;
-    const double* C = S + MS_COEF + s * kCoefStride;
-    cd[s][0][j] = C[MC_C + j];
-    cd[s][1][j] = C[MC_D + j];
-  }
-  if (threadIdx.x < nsh) {
-    const int s = threadIdx.x;
-    const double* C = S + MS_COEF + s * kCoefStride;
-    ae[s][0] = C[MC_A];
-    ae[s][1] = C[MC_E];
-    keep[s] = S[MS_ACT_NEXT + s] != 0.0;
-  }
   if (threadIdx.x == 0) {
     int k = 0;
     for (int s = 0; s < nsh; ++s)
-      if (S[MS_COEF + s * kCoefStride + MC_TOUCHED] != 0.0) list[k++] = s;
+      if (C[(size_t)s * kCoefStride + MC_TOUCHED] != 0.0) list[k++] = s;
     nlist = k;
   }
   __syncthreads();
   const int nl = nlist;
   if (nl == 0) return;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double2 rv[kMaxDefer];
+  if (threadIdx.x < nl) {
+    const int s = list[threadIdx.x];
+    const double* c = C + (size_t)s * kCoefStride;
+    ae[threadIdx.x][0] = c[MC_A];
+    ae[threadIdx.x][1] = c[MC_E];
+    keep[threadIdx.x] = S[MS_ACT_NEXT + s] != 0.0;
+  }
+  __syncthreads();
+  for (size_t base = blockIdx.x * (size_t)blockDim.x; base < n; base += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = base + threadIdx.x;
+    const bool valid = i < n;
+    double2 ax[kMaxShifts], ap[kMaxShifts];
 #pragma unroll
-    for (int j = 0; j < kMaxDefer; ++j)
-      if (j < nr) rv[j] = ld_stream(R + (size_t)j * n + i);
-    // the next shift's P_s and x_s are loaded before the current one is stored
-    // (as far as the compiler knows the stores may alias them)
-    double2 p0n = P.p[list[0]][i], xn = P.x[list[0]][i];
-    for (int k = 0; k < nl; ++k) {
-      const int s = list[k];
-      const double2 p0 = p0n;
-      double2 x = xn;
-      if (k + 1 < nl) {
-        p0n = P.p[list[k + 1]][i];
-        xn = P.x[list[k + 1]][i];
+    for (int k = 0; k < kMaxShifts; ++k) {
+      if (k < nl && valid) {
+        const double2 p0 = P.p[list[k]][i], x0 = P.x[list[k]][i];
+        const double a = ae[k][0], e = ae[k][1];
+        ax[k] = make_double2(x0.x + e * p0.x, x0.y + e * p0.y);
+        if (WITH_P) ap[k] = make_double2(a * p0.x, a * p0.y);
       }
-      const double a = ae[s][0], e = ae[s][1];
-      double2 pn = make_double2(a * p0.x, a * p0.y);
-      x.x += e * p0.x;
-      x.y += e * p0.y;
+    }
+    for (int c0 = 0; c0 < nr; c0 += kFlushChunk) {
+      __syncthreads();  // the previous chunk's coefficients are no longer read
+      if (threadIdx.x < nl * 2 * kFlushChunk) {
+        const int k = threadIdx.x / (2 * kFlushChunk), w = (threadIdx.x / kFlushChunk) & 1;
+        const int j = threadIdx.x % kFlushChunk;
+        cd[k][w][j] = c0 + j < nr ? C[(size_t)list[k] * kCoefStride + (w ? MC_D : MC_C) + c0 + j] : 0.0;
+      }
+      __syncthreads();
+      if (!valid) continue;
+      double2 rv[kFlushChunk];
 #pragma unroll
-      for (int j = 0; j < kMaxDefer; ++j) {
-        if (j < nr) {
-          const double c = cd[s][0][j], d = cd[s][1][j];
-          pn.x += c * rv[j].x;
-          pn.y += c * rv[j].y;
-          x.x += d * rv[j].x;
-          x.y += d * rv[j].y;
+      for (int j = 0; j < kFlushChunk; ++j)
+        rv[j] = c0 + j < nr ? ld_stream(R + (size_t)(c0 + j) * n + i) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < kMaxShifts; ++k) {
+        if (k < nl) {
+#pragma unroll
+          for (int j = 0; j < kFlushChunk; ++j) {
+            const double d = cd[k][1][j];
+            ax[k].x += d * rv[j].x;
+            ax[k].y += d * rv[j].y;
+            if (WITH_P) {
+              const double c = cd[k][0][j];
+              ap[k].x += c * rv[j].x;
+              ap[k].y += c * rv[j].y;
+            }
+          }
         }
       }
-      P.x[s][i] = x;
-      if (keep[s]) P.p[s][i] = pn;
+    }
+    if (!valid) continue;
+#pragma unroll
+    for (int k = 0; k < kMaxShifts; ++k) {
+      if (k < nl) {
+        P.x[list[k]][i] = ax[k];
+        if (WITH_P && keep[k]) P.p[list[k]][i] = ap[k];
+      }
     }
   }
 }
@@ -485,23 +540,24 @@ void mms_update_r(const double2* rin, double2* rout, const double2* w, const dou
                   double* partials, hipStream_t st, const double* skip) {
   hipLaunchKernelGGL(mms_update_r_k, dim3(grid_for(n)), dim3(256), 0, st, rin, rout, w, S, n, partials, skip);
 }
-void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st) {
-  hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts, slot);
-}
-void mms_coef_reset(double* S, hipStream_t st) {
-  hipLaunchKernelGGL(mms_coef_reset_k, dim3(1), dim3(256), 0, st, S);
+void mms_scal2(double* S, const double* partials, int nparts, int slot, double* H, hipStream_t st) {
+  hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts, slot, H);
 }
 void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st) {
   hipLaunchKernelGGL(mms_update_pbase_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n, it);
 }
-void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
-               size_t n, hipStream_t st) {
+void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, int k0, bool with_p,
+               const double* S, const double* H, double* C, size_t n, hipStream_t st) {
   DeferPtrs P;
   for (int s = 0; s < nsh; ++s) {
     P.x[s] = xs[s];
     P.p[s] = ps[s];
   }
-  hipLaunchKernelGGL(mms_flush_k, dim3(grid_for(n)), dim3(256), 0, st, P, R, nr, S, n);
+  hipLaunchKernelGGL(mms_flush_prep_k, dim3(1), dim3(256), 0, st, S, H, C, nr, k0);
+  if (with_p)
+    hipLaunchKernelGGL(mms_flush_k<true>, dim3(grid_for(n)), dim3(256), 0, st, P, R, nr, S, C, n);
+  else
+    hipLaunchKernelGGL(mms_flush_k<false>, dim3(grid_for(n)), dim3(256), 0, st, P, R, nr, S, C, n);
 }
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
                   const double* S, size_t n, hipStream_t st, int it) {

@@ -8,6 +8,7 @@
 // chirality spin/2, so column (chi, k) of P is nonzero only on its chirality's
 // rows), coarse blocks D[X][b][j][i] (column-major so that the threads of one
 // output row i read consecutive addresses), coarse vectors [X][flavour][chi*N_v + k].
+#include <algorithm>
 #include <cstdint>
 
 #include "vec.h"
@@ -356,7 +357,8 @@ __device__ __forceinline__ typename C2<R>::T mk(R x, R y) {
   return v;
 }
 
-constexpr int kGroups = 4;  // thread groups per coarse site in restrict / coarse apply
+constexpr int kGroups = 4;       // thread groups per coarse site in the restriction
+constexpr int kApplyGroups = 8;  // thread groups per coarse site in the coarse stencil
 
 // element of component c at half-site h of a fine field in the cycle precision R
 template <class R>
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C
   const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2, nout = 2 * n2;
   __shared__ T2 xs[9][2 * 64];
   __shared__ int nb[9];
-  __shared__ R red[kGroups][2][128];
+  __shared__ R red2[kApplyGroups][2][128];
   if (threadIdx.x < 9) {
     const int b = threadIdx.x;
     nb[b] = b == 0 ? X : coarse_nbr(m, X, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
@@ -469,28 +471,37 @@ __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C
     xs[b][q] = x[(long)nb[b] * nout + q];
   }
   __syncthreads();
-  const int t = threadIdx.x % nout, q = threadIdx.x / nout;
-  const int f = t / n2, i = t % n2;
-  if (q < kGroups) {
-    // the 9 * n2 products of row i are split over the groups: pair p = b * n2 + j
-    R ax = 0, ay = 0;
-    const T2* DX = D + (long)X * 9 * ntot;
-    for (int pidx = q; pidx < 9 * n2; pidx += kGroups) {
-      const int b = pidx / n2, j = pidx % n2;
-      const T2 dv = DX[(long)b * ntot + (long)j * n2 + i];
-      const T2 v = xs[b][f * n2 + j];
-      ax += dv.x * v.x - dv.y * v.y;
-      ay += dv.x * v.y + dv.y * v.x;
+  // thread (q, i): row i of both flavours (each block element is read once and
+  // used for the two flavour columns) over the pairs p = b * n2 + j with
+  // p = q mod kApplyGroups
+  {
+    const int i = threadIdx.x % n2, q = threadIdx.x / n2;
+    if (q < kApplyGroups) {
+      R a0x = 0, a0y = 0, a1x = 0, a1y = 0;
+      const T2* DX = D + (long)X * 9 * ntot;
+#pragma unroll 4
+      for (int pidx = q; pidx < 9 * n2; pidx += kApplyGroups) {
+        const int b = pidx / n2, j = pidx % n2;
+        const T2 dv = DX[(long)b * ntot + (long)j * n2 + i];
+        const T2 v0 = xs[b][j], v1 = xs[b][n2 + j];
+        a0x += dv.x * v0.x - dv.y * v0.y;
+        a0y += dv.x * v0.y + dv.y * v0.x;
+        a1x += dv.x * v1.x - dv.y * v1.y;
+        a1y += dv.x * v1.y + dv.y * v1.x;
+      }
+      red2[q][0][i] = a0x;
+      red2[q][1][i] = a0y;
+      red2[q][0][n2 + i] = a1x;
+      red2[q][1][n2 + i] = a1y;
     }
-    red[q][0][t] = ax;
-    red[q][1][t] = ay;
   }
   __syncthreads();
   if (threadIdx.x >= nout) return;
+  const int t = threadIdx.x, f = t / n2, i = t % n2;
   R ax = 0, ay = 0;
-  for (int g = 0; g < kGroups; ++g) {
-    ax += red[g][0][t];
-    ay += red[g][1][t];
+  for (int g = 0; g < kApplyGroups; ++g) {
+    ax += red2[g][0][t];
+    ay += red2[g][1][t];
   }
   const int chi = i / Nv, k = i % Nv;
   const R g5 = chi == 0 ? R(1) : R(-1);
@@ -597,10 +608,12 @@ void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* 
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
                      double mubar_c, double epsbar, double m, hipStream_t st) {
   if (prec == P64)
-    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(4 * g.Nv * kGroups), 0, st, g, (const double2*)D,
+    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv)), 0, st, g,
+                       (const double2*)D,
                        (const double2*)Bo, (const double2*)x, (double2*)y, mubar_c, epsbar, m);
   else
-    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(4 * g.Nv * kGroups), 0, st, g, (const float2*)D,
+    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv)), 0, st, g,
+                       (const float2*)D,
                        (const float2*)Bo, (const float2*)x, (float2*)y, mubar_c, epsbar, m);
 }
 

@@ -33,7 +33,7 @@ __device__ __forceinline__ double sum_partials(const double* part, int n) {
 }
 
 __device__ __forceinline__ void stage(double* dst, const double* src) {
-  for (int i = threadIdx.x; i < MS_COEF; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < MS_SIZE; i += blockDim.x) dst[i] = src[i];
 }
 
 // alpha, zeta_{k+1}, alpha_s from pw = <p, (Q^2 + sigma_base) p>
@@ -120,7 +120,7 @@ __device__ inline int step2_body(double* S, double rr) {
 
 // Whole block: pw from the partials, then step1 on an LDS copy of S.
 __device__ inline void step1(double* S, const double* partials, int nparts) {
-  __shared__ double sh[MS_COEF];
+  __shared__ double sh[MS_SIZE];
   stage(sh, S);
   const double pw = sum_partials(partials, nparts);  // synchronises the block
   if (threadIdx.x == 0) step1_body(sh, pw);
@@ -129,39 +129,25 @@ __device__ inline void step1(double* S, const double* partials, int nparts) {
 }
 
 // Whole block: rr from the partials, step2 on an LDS copy of S, and for slot >= 0
-// the deferred coefficients.  The residual r_{k+1} of this iteration sits in
-// slot `slot` of the current block of iterations; the coefficients of every
-// shift active in this iteration advance as
-//   x_s += alpha_s p_s:           e += alpha_s a,  d_j += alpha_s c_j
-//   p_s = zeta_s r + beta_s p_s:  a = beta_s a,    c_j = beta_s c_j,  c_slot = zeta_s
-// (c_slot is zero before this iteration, so d_slot is unchanged).
-__device__ inline void step2(double* S, const double* partials, int nparts, int slot) {
-  __shared__ double sh[MS_COEF];
+// the iteration's record in slot `slot` of the history H: per shift
+// (alpha_s, beta_s, zeta_{k+1}, 1) if it took a step, zeros otherwise.
+__device__ inline void step2(double* S, const double* partials, int nparts, int slot, double* H) {
+  __shared__ double sh[MS_SIZE];
   __shared__ int go;
   stage(sh, S);
   const double rr = sum_partials(partials, nparts);  // synchronises the block
   if (threadIdx.x == 0) go = step2_body(sh, rr);
   __syncthreads();
   stage(S, sh);
-  if (!go || slot < 0) return;
-  const int nsh = (int)sh[MS_NSH];
-  const double* act = sh + MS_ACT;
-  const double* al = sh + MS_ALPHA_S;
-  const double* be = sh + MS_BETA_S;
-  const double* ze = sh + MS_ZETA;
-  for (int idx = threadIdx.x; idx < nsh * kMaxDefer; idx += blockDim.x) {
-    const int s = idx / kMaxDefer, j = idx % kMaxDefer;
-    if (act[s] == 0.0 || j > slot) continue;
-    double* C = S + MS_COEF + s * kCoefStride;
-    const double cj = C[MC_C + j];
-    C[MC_D + j] += al[s] * cj;
-    C[MC_C + j] = j == slot ? ze[s] : be[s] * cj;
-    if (j == 0) {
-      C[MC_E] += al[s] * C[MC_A];
-      C[MC_A] *= be[s];
-      C[MC_TOUCHED] = 1.0;
-    }
-  }
+  if (slot < 0) return;
+  const int s = threadIdx.x;
+  if (s >= (int)sh[MS_NSH]) return;
+  double* h = H + ((size_t)slot * kMaxShifts + s) * kHistStride;
+  const bool act = go && sh[MS_ACT + s] != 0.0;
+  h[0] = act ? sh[MS_ALPHA_S + s] : 0.0;
+  h[1] = act ? sh[MS_BETA_S + s] : 0.0;
+  h[2] = act ? sh[MS_ZETA + s] : 0.0;
+  h[3] = act ? 1.0 : 0.0;
 }
 
 }  // namespace mms

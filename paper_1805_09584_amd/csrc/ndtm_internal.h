@@ -141,30 +141,34 @@ void mms_scal1(double* S, const double* partials, int nparts, hipStream_t st);
 // returns at once
 void mms_update_r(const double2* rin, double2* rout, const double2* w, const double* S, size_t n,
                   double* partials, hipStream_t st, const double* skip = nullptr);
-// beta, zeta_s, beta_s, freezing; slot >= 0 also advances the deferred coefficients
-// with the residual of this iteration in that slot
-void mms_scal2(double* S, const double* partials, int nparts, int slot, hipStream_t st);
+// beta, zeta_s, beta_s, freezing; slot >= 0 also records the iteration in slot
+// `slot` of the history H (deferred form)
+void mms_scal2(double* S, const double* partials, int nparts, int slot, double* H, hipStream_t st);
 // p_s, x_s of every active shift in one pass; sb = the base shift (delta 0), whose
 // direction is p itself and whose ps[sb] is not used
 // it >= 0: returns at once unless iteration it took its scalar step
 void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps, int nsh, int sb,
                   const double* S, size_t n, hipStream_t st, int it = -1);
 // deferred form: base direction p = r + beta p of iteration it (returns at once unless
-// that iteration took its scalar step); coefficient reset at the start of a
-// block; flush of the residuals in slots 0..nr-1 of the ring R (slot j at R + j n) into
-// x_s, p_s of every shift touched in the block
+// that iteration took its scalar step); the flush of a block of nr iterations that
+// began at iteration k0: coefficients from the history (H -> C), then x_s (and, with
+// with_p, the block-end p_s) of every shift touched in the block from the residuals
+// in slots 0..nr-1 of the ring R (slot j at R + j n)
 void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st);
-void mms_coef_reset(double* S, hipStream_t st);
-void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, const double* S,
-               size_t n, hipStream_t st);
+void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, int k0, bool with_p,
+               const double* S, const double* H, double* C, size_t n, hipStream_t st);
 // mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
 void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
                      double* partials, int nblk, hipStream_t st);
 void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
                      int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st);
 // Deferred multi-shift update: the shifted x_s, p_s are formed once per block of
-// at most kMaxDefer iterations from the residuals of that block.
-constexpr int kMaxDefer = 32;
+// at most kMaxDefer iterations from the residuals of that block.  Each iteration
+// records per shift (alpha_s or 0, beta_s, zeta_{k+1}, active) in slot k mod m of
+// the history H [slot][shift][kHistStride]; the flush turns the block's history
+// into the coefficients C [shift][kCoefStride] = [a, e, touched, -, c[m], d[m]].
+constexpr int kMaxDefer = 256;
+constexpr int kHistStride = 4;
 enum MmsCoefIdx { MC_A = 0, MC_E = 1, MC_TOUCHED = 2, MC_C = 4, MC_D = MC_C + kMaxDefer };
 constexpr int kCoefStride = MC_D + kMaxDefer;
 // Layout of the scalar block S (doubles).
@@ -179,9 +183,7 @@ enum MmsIdx {
   // passenger shifts: iterated along but not waited for (their iterates become
   // initial guesses); the solve is done once every other shift is frozen
   MS_PASS = MS_ITERS + kMaxShifts,
-  // deferred form: per shift, kCoefStride doubles [a, e, touched, -, c[kMaxDefer], d[kMaxDefer]]
-  MS_COEF = MS_PASS + kMaxShifts,
-  MS_SIZE = MS_COEF + kMaxShifts * kCoefStride
+  MS_SIZE = MS_PASS + kMaxShifts
 };
 
 }  // namespace ndtm

@@ -19,12 +19,13 @@
 // every active shift each iteration, 4 vectors per shift, more than the stencil
 // itself moves.  Over a block of m iterations all shifted vectors stay linear
 // combinations of their values at the block start and of the block's residuals
-// r_{k+1}, with real coefficients that the scalar kernel advances.  The residuals
-// go to m ring slots (r_{k+1} -> slot k mod m), the base direction p is updated
-// on its own, and once per block one pass forms x_s and p_s of all shifts from
-// the slots.  The iterates are those of the direct form up to rounding; the
-// vector traffic per iteration drops from (1 + 4 N_active) to about
-// 6 + (m + 4 N_active) / m vectors.
+// r_{k+1}, with real coefficients.  The residuals go to m ring slots
+// (r_{k+1} -> slot k mod m), the scalar kernel records alpha_s, beta_s, zeta_s of
+// each iteration, the base direction p is updated on its own, and once per block
+// the coefficients are formed from that record (a backward recurrence) and one
+// pass forms x_s (and p_s if more blocks follow) of all shifts from the slots.
+// The iterates are those of the direct form up to rounding; the vector traffic
+// per iteration drops from (1 + 4 N_active) to about 6 + (m + 3 N_active) / m.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -102,6 +103,15 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   }
   if (!r.v || !p.v || !w.v || !u.v || !te.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
   if (defer > kMaxDefer) defer = kMaxDefer;
+  if (defer >= 2) {
+    // the ring takes at most half of the device memory that is free (or already its own)
+    size_t fr = 0, tot = 0;
+    (void)hipMemGetInfo(&fr, &tot);
+    auto have = c->bufs.find("cg_ring");
+    const size_t own = have == c->bufs.end() ? 0 : have->second.bytes;
+    const size_t cap = (fr + own) / 2 / (n * sizeof(double2));
+    if ((size_t)defer > cap) defer = (int)cap;
+  }
   const bool deferred = defer >= 2;
   double2* ring = nullptr;  // defer residual slots, n elements apart
   if (deferred) {
@@ -132,16 +142,20 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     blas_finalize(c->partials, g, 1, c->dscal, st);
     mms_seed(c->mms_S, c->dscal, st);
   }
-  if (deferred) mms_coef_reset(c->mms_S, st);
   int it = 0;
   if (poll_every < 1) poll_every = 1;
   LaggedPoll poll(c, c->mms_S + MS_DONE, st);
-  std::vector<std::pair<int, int>> flushes;  // (first iteration, residuals) of each flush
-  auto flush = [&](int nr) {
+  struct Flush {
+    int first, nr;
+    bool with_p;
+  };
+  std::vector<Flush> flushes;
+  // a flush inside the loop also forms the block-end directions, which the next
+  // block starts from; the last one forms the solutions only
+  auto flush = [&](int nr, bool with_p) {
     ProfScope pf(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-    mms_flush(xv.data(), ps.data(), nsh, ring, nr, c->mms_S, n, st);
-    mms_coef_reset(c->mms_S, st);
-    flushes.emplace_back(it - nr, nr);
+    mms_flush(xv.data(), ps.data(), nsh, ring, nr, it - nr, with_p, c->mms_S, c->mms_H, c->mms_C, n, st);
+    flushes.push_back({it - nr, nr, with_p});
   };
   const int hg = hop_grid(c->g);
   const int rg = red_grid(n);
@@ -158,7 +172,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
       ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
       mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st, c->hop_skip);
     }
-    mms_scal2(c->mms_S, c->partials, rg, slot, st);
+    mms_scal2(c->mms_S, c->partials, rg, slot, c->mms_H, st);
     if (deferred) {
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
       mms_update_pbase(rout, (double2*)p.v, c->mms_S, n, it, st);
@@ -168,10 +182,10 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
       mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st, it);
     }
     ++it;
-    if (deferred && it % defer == 0) flush(defer);
+    if (deferred && it % defer == 0) flush(defer, true);
     if (it % poll_every == 0 && poll.done()) break;
   }
-  if (deferred && it % defer != 0) flush(it % defer);
+  if (deferred && it % defer != 0) flush(it % defer, false);
   NDTM_HIP(c, hipGetLastError());
   NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
   NDTM_HIP(c, hipStreamSynchronize(st));
@@ -182,15 +196,16 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   bool done = c->hscal[MS_DONE] != 0.0;
   if (deferred && ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1)) {
     // base direction: r read, p read and written per iteration that moves (the launches
-    // queued after the done flag return at once); each flush reads its
-    // residuals and x_s, p_s of every shift active in its block (shift s is active in
-    // iterations 0..iters[s]-1), writes x_s and, while the shift stays active, p_s
+    // queued after the done flag return at once); each flush reads its residuals and
+    // x_s, p_s of every shift active in its block (shift s is active in iterations
+    // 0..iters[s]-1), writes x_s and, inside the loop and while the shift stays
+    // active, p_s
     double vecs = 3.0 * res->iterations;
     for (const auto& f : flushes) {
-      vecs += f.second;
+      vecs += f.nr;
       for (int s = 0; s < nsh; ++s) {
         if (res->iters[s] > f.first) vecs += 3.0;
-        if (res->iters[s] > f.first + f.second) vecs += 1.0;
+        if (f.with_p && res->iters[s] > f.first + f.nr) vecs += 1.0;
       }
     }
     c->prof_bytes[NDTM_PROF_MMS_UPDATE] += vecs * 384.0 * c->g.vh;
@@ -257,7 +272,7 @@ int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::v
       mms_update_r_mx((float2*)r.v, (const __half2*)w16.v, w16.sc, c->mms_S, c->g.vh, c->g.stride, c->partials, nb,
                       st);
     }
-    mms_scal2(c->mms_S, c->partials, nb, -1, st);
+    mms_scal2(c->mms_S, c->partials, nb, -1, nullptr, st);
     {
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
       mms_update_p_mx((const float2*)r.v, (float2*)p.v, (__half2*)p16.v, p16.sc, xv.data(), ps.data(), nsh, c->mms_S,
@@ -391,7 +406,7 @@ void ndtm_solve_default_params(ndtm_solve_params* p) {
   p->fgmres_maxiter = 400;
   p->max_rounds = 6;
   p->use_graphs = 1;
-  p->mms_defer = 32;
+  p->mms_defer = 256;
   p->mms_predict = 2;
 }
 

@@ -7,7 +7,7 @@
 * 16^3x32 config, all 12 shifts by MMS-CG: sampled shifts checked by the
   oracle's true residual.
 * zero and non-finite right-hand sides.
-* deferred shifted updates (blocks of 2, 5, 32 iterations) against the direct
+* deferred shifted updates (blocks of 2, 5, 32, 256 iterations) against the direct
   per-iteration updates: the base Krylov process is the same computation, so
   the iteration counts agree exactly and the solutions to rounding; also when
   the iteration cap ends the solve inside a block.
@@ -122,7 +122,7 @@ def test_deferred_updates_match_direct(nd):
     bd = dev(b)
     x0, r0 = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=0))
     ref = [host(x) for x in x0]
-    for m in (2, 5, 32):
+    for m in (2, 5, 32, 256):
         xm, rm = ctx.ndtm_solve(bd, ctx.solve_params(tol=1e-10, mms_defer=m))
         print("defer", m, rm["mms_iterations"], r0["mms_iterations"], flush=True)
         assert rm["mms_iterations"] == r0["mms_iterations"]
