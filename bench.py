@@ -181,6 +181,47 @@ def dslash_block(nd, U_small, d0, reps):
     return out
 
 
+def coarse_batched_block(ctx, nd, reps=50):
+    """The coarse stencil of the 16^3x32 hierarchy for 8 systems (the 3 multigrid shifts'
+    signs and more): one batched launch on the matrix cores against 8 one-system launches."""
+    import torch
+
+    import synth
+
+    k, Vc, Nv = 8, ctx.Vc, ctx.n_vec
+    xc = torch.from_numpy(synth.gaussian_vectors((k, Vc, 2, 2 * Nv), 9)).to("cuda:0")
+    yc = torch.empty_like(xc)
+    ms = [0.009 * (1 if r % 2 == 0 else -1) * (r // 2 + 1) for r in range(k)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1000.0 / reps
+
+    def singles():
+        for r in range(k):
+            ctx.ndtm_mg_coarse_apply(xc[r], ms[r])
+
+    t_multi = timed(lambda: ctx.ndtm_mg_coarse_apply_multi(xc, ms, out=yc))
+    t_single = timed(singles)
+    n2 = 2 * Nv
+    block_bytes = Vc * (9 * n2 * n2 + 2 * Nv * Nv) * 16.0
+    vec_bytes = 2 * k * Vc * 2 * n2 * 16.0
+    flops = k * Vc * 9 * n2 * n2 * 2 * 8.0
+    return {"systems": k, "coarse_sites": Vc, "dof_per_site": 2 * n2, "precision": "f64",
+            "us_batched": t_multi, "us_one_system_each": t_single,
+            "speedup": t_single / t_multi,
+            "batched_gbs": (block_bytes + vec_bytes) / (t_multi * 1e-6) / 1e9,
+            "batched_tflops": flops / (t_multi * 1e-6) / 1e12}
+
+
 def copy_ceiling():
     """Measured streaming ceiling: a device-to-device copy of 2 GiB (read + write)."""
     import torch
@@ -254,6 +295,7 @@ def main():
         else:
             forms.remove("learned")
 
+    coarse_batched = coarse_batched_block(ctx, nd) if setup_ms is not None else None
     results = {}
     for f in forms:
         results[f], _ = run_form(ctx, nd, bd, xs, f, args.steps, args.warmup, profile=False)
@@ -306,6 +348,7 @@ def main():
                      "alg_bytes_per_launch": by / max(nl, 1)},
         "kernel_classes": classes,
         "mg_kernel_classes": mg_classes,
+        "coarse_batched": coarse_batched,
         "ms_per_step_profiled": prof_run["ms_per_solve"],
         "forms": results,
         "speedup_vs_plain": speedup,

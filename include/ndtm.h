@@ -164,6 +164,16 @@ int ndtm_mg_prolong(ndtm_ctx* ctx, void* v_dev, const void* vc_dev, void* stream
  *                     + i m C_o x tau1) xc   (eq:non-degenerate_coarse). */
 int ndtm_mg_coarse_apply(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, double m, void* stream);
 
+/* y_r = D'_c(m_r) x_r for k systems at once (1 <= k <= 8), FP64: xc, yc hold the k
+ * coarse vectors back to back, complex128 [k][Vc][2][2 N_v], not aliased; m: k host
+ * doubles.  The coarse blocks are shared by the systems and both flavours, so the
+ * products form one dense complex matrix product per coarse site, taken on the
+ * matrix cores (v_mfma_f64_16x16x4f64): the blocks are read once for all k systems
+ * (section 3.2, eq:non-degenerate_coarse; batching the coarse systems of the shifts
+ * and signs).  Same result as k calls of ndtm_mg_coarse_apply up to rounding. */
+int ndtm_mg_coarse_apply_multi(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, int k, const double* m,
+                               void* stream);
+
 /* xc ~ D'_c(m)^-1 bc by the coarse solver the cycle uses, in the cycle precision:
  * coarse_iters GMRES iterations from zero, restarted while the relative residual
  * is above coarse_tol (when that is > 0, at most coarse_cycles cycles). */

@@ -100,6 +100,7 @@ def load_library():
         "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
+        "ndtm_mg_coarse_apply_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_zolotarev": (i, [i, d, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -237,6 +238,14 @@ class Context:
         out = torch.empty_like(xc)
         self._check(self.lib.ndtm_mg_coarse_apply(self.h, _ptr(out), _ptr(xc), float(m), _stream()))
         return out
+
+    def ndtm_mg_coarse_apply_multi(self, xc, ms, out=None):
+        """D'_c(m_r) x_r for the k systems stacked in xc (complex128 CUDA (k, Vc, 2, 2Nv))."""
+        k = xc.shape[0]
+        mm = (C.c_double * k)(*[float(v) for v in ms])
+        y = torch.empty_like(xc) if out is None else out
+        self._check(self.lib.ndtm_mg_coarse_apply_multi(self.h, _ptr(y), _ptr(xc), int(k), mm, _stream()))
+        return y
 
     def ndtm_mg_coarse_solve(self, bc, m=0.0):
         out = torch.empty_like(bc)

@@ -527,6 +527,121 @@ __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C
   y[((long)X * 2 + f) * n2 + i] = mk<R>(ax, ay);
 }
 
+// ---------------- batched coarse stencil on MFMA ----------------
+// Up to kMultiMax coarse systems D'_c(m_r) x_r at once (FP64).  The hopping and
+// self blocks D_b are shared by all systems and both flavours, so per coarse site
+// the products form one complex (2Nv) x (9 * 2Nv) by (9 * 2Nv) x (2k) matrix
+// product, columns n = f k + r.  Each wave takes a tile of 16 rows and all 2k <= 16
+// columns with v_mfma_f64_16x16x4f64 (four real products per complex one):
+//   A (16x4): lane l holds row l % 16, column l / 16 of the D block;
+//   B (4x16): lane l holds row l / 16, column l % 16 of the neighbour vectors;
+//   C (16x16): lane l, register q holds row 4 q + l / 16, column l % 16.
+// The site terms (i d mubar Gamma5 tau3, -epsbar tau1, i m_r C_o tau1) follow per
+// output element, as in coarse_apply_k.  Rows beyond 2Nv are masked.
+struct MultiM {
+  double m[kMultiMax];
+};
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+// The nine blocks are split over kMultiBGroups groups of waves (more waves in
+// flight per coarse site); the groups' partial tiles are summed through LDS.
+constexpr int kMultiBGroups = 3;
+constexpr int kMultiMaxTiles = 4;  // 2 N_v <= 64
+__global__ __launch_bounds__(64 * kMultiBGroups * kMultiMaxTiles) void coarse_apply_multi_k(
+    MGGeom g, const double2* D, const double2* Bo, const double2* X, double2* Y, int k, MultiM ms, double mubar_c,
+    double epsbar) {
+  const int site = blockIdx.x;
+  const int Nv = g.Nv, n2 = 2 * Nv, ntot = n2 * n2;
+  const size_t vstride = (size_t)g.Vc * 2 * n2;  // one system's coarse vector
+  __shared__ int nb[9];
+  if (threadIdx.x < 9) {
+    const int b = threadIdx.x;
+    nb[b] = b == 0 ? site : coarse_nbr(g, site, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
+  }
+  __shared__ double part[kMultiBGroups - 1][kMultiMaxTiles][2][4][64];
+  __syncthreads();
+  const int tiles = (n2 + 15) / 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, mt = w % tiles, bg = w / tiles;
+  const int ia = mt * 16 + (lane & 15), kq = lane >> 4;  // A element of this lane
+  const int col = lane & 15;                             // B column / C column
+  const bool cvalid = col < 2 * k;
+  const int cf = cvalid ? col / k : 0, cr = cvalid ? col % k : 0;
+  mf_d4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+  // operands of four k-steps are loaded (from clamped, always valid addresses) before
+  // their products, so that the loads are in flight together; masked entries are zeroed
+  const int iac = ia < n2 ? ia : n2 - 1;
+  const bool rowok = ia < n2;
+  for (int b = bg * (9 / kMultiBGroups); b < (bg + 1) * (9 / kMultiBGroups); ++b) {
+    const double2* Db = D + ((size_t)site * 9 + b) * ntot;
+    const double2* xb = X + (size_t)cr * vstride + ((size_t)nb[b] * 2 + cf) * n2;
+    for (int kk = 0; kk < n2; kk += 16) {
+      double2 a[4], v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = kk + 4 * u + kq;
+        const int jc = jj < n2 ? jj : n2 - 1;
+        a[u] = Db[(size_t)jc * n2 + iac];
+        v[u] = xb[jc];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = kk + 4 * u + kq;
+        const double fa = (rowok && jj < n2) ? 1.0 : 0.0, fv = (cvalid && jj < n2) ? 1.0 : 0.0;
+        const double ar = fa * a[u].x, ai = fa * a[u].y, vr = fv * v[u].x, vi = fv * v[u].y;
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vr, accr, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, vi, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vi, acci, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, vr, acci, 0, 0, 0);
+      }
+    }
+  }
+  if (bg > 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      part[bg - 1][mt][0][q][lane] = accr[q];
+      part[bg - 1][mt][1][q][lane] = acci[q];
+    }
+  }
+  __syncthreads();
+  if (bg > 0) return;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    for (int h = 0; h < kMultiBGroups - 1; ++h) {
+      accr[q] += part[h][mt][0][q][lane];
+      acci[q] += part[h][mt][1][q][lane];
+    }
+  if (!cvalid) return;
+  const double2* xs = X + (size_t)cr * vstride + (size_t)site * 2 * n2;
+  const double mm = ms.m[cr];
+  const double t3 = cf == 0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = mt * 16 + 4 * q + (lane >> 4);
+    if (i >= n2) continue;
+    const int chi = i / Nv, kk = i % Nv;
+    const double g5 = chi == 0 ? 1.0 : -1.0;
+    const double2 xself = xs[cf * n2 + i], xoth = xs[(1 - cf) * n2 + i];
+    double ax = accr[q], ay = acci[q];
+    // + i d mubar g5 tau3 x_f - epsbar x_{1-f}
+    ax += -mubar_c * g5 * t3 * xself.y - epsbar * xoth.x;
+    ay += mubar_c * g5 * t3 * xself.x - epsbar * xoth.y;
+    if (mm != 0.0) {
+      // + i m g5 sum_k' Bo[chi][k][k'] x_{1-f}[chi, k']
+      const double2* B = Bo + ((size_t)site * 2 + chi) * Nv * Nv + (size_t)kk * Nv;
+      const double2* xo = xs + (1 - cf) * n2 + chi * Nv;
+      double bx = 0, by = 0;
+      for (int kp = 0; kp < Nv; ++kp) {
+        const double2 bv = B[kp], v = xo[kp];
+        bx += bv.x * v.x - bv.y * v.y;
+        by += bv.x * v.y + bv.y * v.x;
+      }
+      ax += -mm * g5 * by;
+      ay += mm * g5 * bx;
+    }
+    Y[(size_t)cr * vstride + ((size_t)site * 2 + cf) * n2 + i] = make_double2(ax, ay);
+  }
+}
+
 // ---------------- random test vectors ----------------
 __device__ __forceinline__ uint64_t splitmix(uint64_t z) {
   z += 0x9E3779B97F4A7C15ull;
@@ -615,6 +730,15 @@ void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, c
     hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv)), 0, st, g,
                        (const float2*)D,
                        (const float2*)Bo, (const float2*)x, (float2*)y, mubar_c, epsbar, m);
+}
+
+void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo, const double2* x, double2* y, int k,
+                           const double* m, double mubar_c, double epsbar, hipStream_t st) {
+  MultiM ms;
+  for (int r = 0; r < kMultiMax; ++r) ms.m[r] = r < k ? m[r] : 0.0;
+  const int tiles = (2 * g.Nv + 15) / 16;
+  hipLaunchKernelGGL(coarse_apply_multi_k, dim3(g.Vc), dim3(64 * tiles * kMultiBGroups), 0, st, g, D, Bo, x, y, k, ms,
+                     mubar_c, epsbar);
 }
 
 void mg_random_fill(const MGGeom& m, int vh, double2* fe, double2* fo, unsigned long long seed, hipStream_t st) {

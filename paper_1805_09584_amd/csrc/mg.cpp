@@ -821,4 +821,16 @@ int ndtm_mg_coarse_apply(ndtm_ctx* c, void* yc, const void* xc, double m, void* 
   return NDTM_OK;
 }
 
+int ndtm_mg_coarse_apply_multi(ndtm_ctx* c, void* yc, const void* xc, int k, const double* m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_apply_multi: no multigrid setup");
+  if (!yc || !xc || !m || yc == xc) return fail(c, NDTM_EINVAL, "mg_coarse_apply_multi: null or aliased pointer");
+  if (k < 1 || k > kMultiMax) return fail(c, NDTM_EINVAL, "mg_coarse_apply_multi: 1 <= k <= 8");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  mg_coarse_apply_multi(c->mg->g, c->mg->D64, c->mg->Bo64, static_cast<const double2*>(xc), static_cast<double2*>(yc),
+                        k, m, c->mg->prm.coarse_mu_factor * c->mubar, c->epsbar, st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
 }  // extern "C"

@@ -69,6 +69,10 @@ void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const
                  hipStream_t st);
 void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* fe, void* fo, hipStream_t st);
 // coarse doublet operator y = D'_c(m) x
+// k <= kMultiMax FP64 coarse systems y_r = D'_c(m_r) x_r at once on MFMA; x, y: [k][Vc][2][2Nv]
+constexpr int kMultiMax = 8;
+void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo, const double2* x, double2* y, int k,
+                           const double* m, double mubar_c, double epsbar, hipStream_t st);
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
                      double mubar_c, double epsbar, double m, hipStream_t st);
 // fill a full doublet field (both halves) with complex Gaussian numbers from a counter-based hash

@@ -293,3 +293,47 @@ def test_near_critical_coarse_tolerance_config(nd):
     assert meth[1e-2] == [1, 1, 1]
     if meth[0.0] == [1, 1, 1]:
         assert sum(its[1e-2]) <= sum(its[0.0])
+
+
+@pytest.mark.parametrize("dims,block,Nv,k", [((4, 2, 2, 4), (2, 2, 2, 2), 4, 3), ((8, 8, 8, 8), (4, 4, 4, 4), 8, 8),
+                                             ((8, 8, 8, 8), (4, 4, 4, 4), 6, 5)])
+def test_coarse_apply_multi_parity(nd, dims, block, Nv, k):
+    """The batched coarse stencil on the matrix cores (k systems, each with its own m)
+    against the oracle's dense coarse operator built from the same P, and against k
+    calls of the one-system kernel; 2 N_v of 8 and 12 exercise the masked rows of a
+    16-row tile, k < 8 the masked columns."""
+    print(f"case dims={dims} Nv={Nv} k={k} batched coarse stencil", flush=True)
+    lat, op, ctx, P, agg, Vc = _setup(nd, dims, block, Nv)
+    Dc = omg.coarse_wilson_dense(lat, op.a, P, agg, Vc)
+    Bo = omg.odd_projector_coarse(lat, P, agg, Vc)
+    ms = [0.0, 0.0316, -0.05, 0.01, -0.0316, 0.2, 1e-3, -1e-3][:k]
+    xc = synth.gaussian_vectors((k, Vc, 2, 2 * Nv), 8)
+    got = host(ctx.ndtm_mg_coarse_apply_multi(dev(xc), ms))
+    for r in range(k):
+        want = omg.coarse_nd_apply(Dc, Bo, xc[r], Nv, MB, EB, m=ms[r])
+        assert rel_err(got[r], want) < 1e-12, r
+        single = host(ctx.ndtm_mg_coarse_apply(dev(xc[r].copy()), ms[r]))
+        assert rel_err(got[r], single) < 1e-13, r
+    ctx.close()
+
+
+def test_coarse_apply_multi_config2_shape(nd):
+    """At the 16^3x32 shape (2 N_v = 48, three row tiles, 512 coarse sites) the
+    batched stencil matches the one-system kernel for 8 systems; bad k is refused."""
+    dims, block, Nv = (32, 16, 16, 16), (4, 4, 4, 4), 24
+    print("case c2 shape batched coarse stencil", flush=True)
+    lat, op, ctx, P, agg, Vc = _setup(nd, dims, block, Nv, seed=12)
+    ms = [np.sqrt(s) * sg for s in (8.111e-5, 2.848e-5, 1e-5, 2.31e-4) for sg in (1, -1)]
+    xc = synth.gaussian_vectors((8, Vc, 2, 2 * Nv), 9)
+    got = host(ctx.ndtm_mg_coarse_apply_multi(dev(xc), ms))
+    for r in range(8):
+        single = host(ctx.ndtm_mg_coarse_apply(dev(xc[r].copy()), ms[r]))
+        assert rel_err(got[r], single) < 1e-13, r
+    import ctypes
+    x9 = dev(synth.gaussian_vectors((9, Vc, 2, 2 * Nv), 1))
+    y9 = x9.clone()
+    m9 = (ctypes.c_double * 9)()
+    for kbad in (0, 9):
+        rc = ctx.lib.ndtm_mg_coarse_apply_multi(ctx.h, y9.data_ptr(), x9.data_ptr(), kbad, m9, None)
+        assert rc == -1, kbad
+    ctx.close()
