@@ -185,7 +185,8 @@ typedef struct {
   int maxiter;         /* MMS-CG iteration cap */
   int n_mmscg;         /* shifts solved by MMS-CG (the largest ones); the
                           rest go to the multigrid; >= number of shifts means
-                          plain MMS-CG for all */
+                          plain MMS-CG for all (ndtm_hybrid_split evaluates the
+                          section 4.4 cost model for a choice) */
   int guess;           /* NDTM_GUESS_* for the multigrid shifts */
   int precision;       /* NDTM_PREC_F64: FP64 throughout.  NDTM_PREC_F16: mixed form, the
                           multi-shift CG runs on FP16 stencil storage (one FP32 scale per
@@ -244,6 +245,23 @@ typedef struct {
  * EBREAKDOWN on non-finite input or a Krylov breakdown. */
 int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
                const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
+
+/* ---- hybrid split (section 4.4) ------------------------------------------ */
+/* The n minimising c_HY(n) = t_CG(m_n^2) + sum_{i>n} t_MG(m_i^2) (eq:costwo) for the
+ * shifts sigma_desc[0..n_shifts) (strictly descending, > 0): t_CG(sigma) is the CG
+ * iteration bound 0.5 sqrt(kappa) ln(2/tol), kappa = (lambda_max + sigma) /
+ * (lambda_min + sigma), times ms_per_iteration; t_MG = ms_per_mg_shift, a cost the
+ * caller measures for its multigrid and initial guesses (the paper fits both costs
+ * to measurements).  The spectrum may come from ndtm_spectrum_estimate.  Host
+ * computation, no context or device.  EINVAL on inconsistent arguments. */
+int ndtm_hybrid_split(int n_shifts, const double* sigma_desc, double lambda_min, double lambda_max, double tol,
+                      double ms_per_iteration, double ms_per_mg_shift, int* n_out);
+
+/* Extreme eigenvalues of Q^2 estimated from the Lanczos matrix of the base system
+ * of the last FP64 multi-shift solve on this context that fitted one block of the
+ * deferred form (Ritz values: inside the spectrum).  They bound the spectrum for
+ * ndtm_hybrid_split and for the interval of ndtm_solve_rational.  ESTATE before one. */
+int ndtm_spectrum_estimate(const ndtm_ctx* ctx, double* lambda_min, double* lambda_max);
 
 /* ---- rational approximation (section "Rational approximation") ---------- */
 /* Zolotarev's optimal rational approximation R(y) = a prod_j (y + c_{2j-1})/(y + c_{2j})

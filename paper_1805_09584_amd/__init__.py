@@ -26,6 +26,7 @@ from .binding import (  # noqa: F401
     NdtmError,
     PROF_CLASSES,
     lib_path,
+    hybrid_split,
     load_library,
     zolotarev,
 )

@@ -104,6 +104,8 @@ def load_library():
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_zolotarev": (i, [i, d, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "ndtm_hybrid_split": (i, [i, C.POINTER(C.c_double), d, d, d, d, d, C.POINTER(C.c_int)]),
+        "ndtm_spectrum_estimate": (i, [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
         "ndtm_solve_rational": (i, [vp, vp, vp, i, d, d, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_mlp_set_weights": (i, [vp, fp, C.c_size_t]),
         "ndtm_mlp_get_weights": (i, [vp, fp, C.c_size_t]),
@@ -134,6 +136,17 @@ def zolotarev(n, eps):
     if rc != 0:
         raise NdtmError(rc, "ndtm_zolotarev: bad order or interval")
     return np.array(c[:2 * n]), a.value, d.value
+
+
+def hybrid_split(sigma_desc, lambda_min, lambda_max, tol, ms_per_iteration, ms_per_mg_shift):
+    """n of the section 4.4 cost model (host computation)."""
+    sig = (C.c_double * len(sigma_desc))(*[float(v) for v in sigma_desc])
+    n = C.c_int()
+    rc = load_library().ndtm_hybrid_split(len(sigma_desc), sig, float(lambda_min), float(lambda_max), float(tol),
+                                          float(ms_per_iteration), float(ms_per_mg_shift), C.byref(n))
+    if rc != 0:
+        raise NdtmError(rc, "ndtm_hybrid_split: inconsistent arguments")
+    return n.value
 
 
 def _fp(a):
@@ -274,6 +287,12 @@ class Context:
         d = rep.to_dict()
         d["rc"] = rc
         return xs, d
+
+    def ndtm_spectrum_estimate(self):
+        """(lambda_min, lambda_max) of Q^2 from the last FP64 multi-shift solve's Lanczos matrix."""
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self.lib.ndtm_spectrum_estimate(self.h, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
 
     # -- rational approximation -----------------------------------------------
     def ndtm_solve_rational(self, b, n, eps, lam, params=None, check=True):

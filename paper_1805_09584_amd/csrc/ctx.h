@@ -50,6 +50,9 @@ struct ndtm_ctx {
   long long prof_n[NDTM_PROF_NCLASS] = {};
   double prof_bytes[NDTM_PROF_NCLASS] = {};
   ndtm::MGData* mg = nullptr;
+  // extreme eigenvalues of Q^2 from the base system's Lanczos coefficients of the last
+  // FP64 multi-shift solve (<= 0 while unknown)
+  double est_lmin = -1, est_lmax = -1;
   ndtm::MLPData* mlp = nullptr;
 };
 
@@ -112,7 +115,11 @@ struct MmsResult {
   int iterations = 0;
   std::vector<int> iters;
   bool breakdown = false;
+  double lam_lo = -1, lam_hi = -1;  // extreme eigenvalues of Q^2 from the Lanczos coefficients (deferred form)
 };
+bool lanczos_extremes(const std::vector<double>& alpha, const std::vector<double>& beta, double* lo, double* hi);
+int hybrid_choose(int N, const double* sig, double lmin, double lmax, double tol, double ms_iter, double ms_mg,
+                  int* n_out, double* cost_out);
 // MMS-CG for (Q^2 + sigma_s) x_s = b on internal FP64 fields; sigmas any order.
 // defer >= 2: shifted vectors formed once per block of `defer` iterations (at most
 // kMaxDefer); 0 or 1: updated every iteration.

@@ -194,6 +194,23 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   res->iters.resize(nsh);
   for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
   bool done = c->hscal[MS_DONE] != 0.0;
+  if (deferred && res->iterations >= 2 && res->iterations <= defer && !res->breakdown) {
+    // the base system's alpha_k, beta_k are in the record of the single block
+    std::vector<double> h((size_t)res->iterations * kMaxShifts * kHistStride);
+    NDTM_HIP(c, hipMemcpy(h.data(), c->mms_H, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> al, be;
+    for (int k = 0; k < res->iterations; ++k) {
+      const double* hk = &h[((size_t)k * kMaxShifts + sb) * kHistStride];
+      if (hk[3] == 0.0) break;
+      al.push_back(hk[0]);
+      be.push_back(hk[1]);
+    }
+    double lo = 0, hi = 0;
+    if (lanczos_extremes(al, be, &lo, &hi) && lo - sig_base > 0) {
+      res->lam_lo = lo - sig_base;
+      res->lam_hi = hi - sig_base;
+    }
+  }
   if (deferred && ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1)) {
     // base direction: r read, p read and written per iteration that moves (the launches
     // queued after the done flag return at once); each flush reads its residuals and
@@ -500,6 +517,10 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       rep->status = rc;
       return rc;
     }
+    if (mr.lam_lo > 0) {
+      c->est_lmin = mr.lam_lo;
+      c->est_lmax = mr.lam_hi;
+    }
     HalfField R = half_field(c, "sv_r", P64);
     for (int i = 0; i < n_mms; ++i) {
       rep->method[i] = 0;
@@ -516,11 +537,13 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   }
   auto t1 = std::chrono::steady_clock::now();
   rep->t_mms_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
   // ---- multigrid (case C) for the remaining shifts ----
   if (n_mms < nsh) {
     const int n_pred = p->precision == NDTM_PREC_F16 ? 0 : std::max(0, std::min(p->mms_predict, nsh - n_mms));
     int rc = solve_mg_shifts(c, sig, n_mms, n_pred, xs, B, p, rep, st);
     if (rc != NDTM_OK && status == NDTM_OK) status = rc;
+
   }
   for (int i = 0; i < nsh; ++i) launch_unpack_half(c->g, xs[i], static_cast<double2*>(x_dev[order[i]]), st);
   NDTM_HIP(c, hipStreamSynchronize(st));

@@ -156,3 +156,26 @@ def test_lagged_polls_match_waiting_polls(nd):
         for i in range(len(sig)):
             assert np.array_equal(host(xa[i]), host(xb[i])), (m, i)
     ctx.close()
+
+
+def test_spectrum_estimate_config1(nd):
+    """The Lanczos matrix of the base system's CG coefficients (recorded by the deferred
+    multi-shift solve) gives Ritz values inside the spectrum of Q^2 that match its
+    extreme eigenvalues from the dense Hermitian Q-hat of the 4^4 config."""
+    print("spectrum estimate c1", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c1")
+    with pytest.raises(nd.NdtmError):
+        ctx.ndtm_spectrum_estimate()
+    ctx.ndtm_solve(dev(b), ctx.solve_params(tol=1e-10))
+    lo, hi = ctx.ndtm_spectrum_estimate()
+    n = op.lat.V // 2 * 24
+    Q = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        e = np.zeros(n, dtype=complex)
+        e[j] = 1
+        Q[:, j] = op.Q_hat(e.reshape(-1, 2, 4, 3)).reshape(-1)
+    ev = np.linalg.eigvalsh(Q) ** 2
+    print("Ritz", lo, hi, "exact", ev.min(), ev.max(), flush=True)
+    assert ev.min() * (1 - 1e-9) <= lo <= ev.min() * (1 + 1e-2)
+    assert ev.max() * (1 - 1e-4) <= hi <= ev.max() * (1 + 1e-9)
+    ctx.close()
