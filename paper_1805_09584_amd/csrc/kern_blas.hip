@@ -105,8 +105,7 @@ __global__ void dot_k(const double2* x, const double2* y, size_t n, double* part
 // partials laid out [width][nparts]; block j sums column j in a fixed order.
 __global__ void finalize_k(const double* partials, int nparts, double* dst) {
   const double* p = partials + (size_t)blockIdx.x * nparts;
-  double s = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[i];
+  double s = strided_sum(p, nparts);
   s = block_sum(s);
   if (threadIdx.x == 0) dst[blockIdx.x] = s;
 }
@@ -168,6 +167,97 @@ __global__ void lincomb_k(double2* y, VecList V, CoefList C, int k, size_t n) {
 }
 
 // ---------------- MMS-CG ----------------
+constexpr int kFusedPrefetch = 4;  // elements per thread loaded before the scalar is known
+
+// Deferred form, fused: the two vector passes of iteration `it` also carry its two
+// scalar steps.  Every block takes alpha (beta) from the partials itself, in the
+// same order as the stand-alone steps, and block 0 also takes the step on S, before
+// its share of the vector (so that the serial step does not end the launch).  No
+// block reads a value that the step of the same launch changes (beta takes
+// ||r_k||^2 from MS_RR_OLD, written by step 1 in the previous launch; the step
+// writes the rest of the header back unchanged).  A set *skip (the done flag)
+// makes the residual pass return at once, before step 1; the direction pass then
+// sees no MS_GO mark for this iteration and returns too (it cannot read the done
+// flag itself: its own step 2 may set it).
+__global__ void __launch_bounds__(256) mms_update_r_fused_k(const double2* rin, double2* rout, const double2* w,
+                                                            double* S, size_t n, const double* pst, int nst,
+                                                            double* partials, const double* skip, int it) {
+  if (skip && *skip != 0.0) return;
+  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+  // the first elements are on their way while alpha is formed
+  double2 rp[kFusedPrefetch], wp[kFusedPrefetch];
+#pragma unroll
+  for (int j = 0; j < kFusedPrefetch; ++j) {
+    const size_t i = i0 + j * stride;
+    if (i < n) {
+      rp[j] = rin[i];
+      wp[j] = w[i];
+    }
+  }
+  const double pw = mms::sum_partials(pst, nst);
+  const double alpha = mms::alpha_of(S, pw);
+  // block 0 takes the step first, while the other blocks stream
+  if (blockIdx.x == 0) mms::step1_pw(S, pw, (double)(it + 1));
+  double acc = 0;
+#pragma unroll
+  for (int j = 0; j < kFusedPrefetch; ++j) {
+    const size_t i = i0 + j * stride;
+    if (i < n) {
+      double2 v = rp[j];
+      v.x -= alpha * wp[j].x;
+      v.y -= alpha * wp[j].y;
+      rout[i] = v;
+      acc += v.x * v.x + v.y * v.y;
+    }
+  }
+  for (size_t i = i0 + kFusedPrefetch * stride; i < n; i += stride) {
+    double2 v = rin[i];
+    const double2 wi = w[i];
+    v.x -= alpha * wi.x;
+    v.y -= alpha * wi.y;
+    rout[i] = v;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(256) mms_update_pbase_fused_k(const double2* r, double2* p, double* S, size_t n,
+                                                                const double* pr, int npr, int slot, double* H,
+                                                                int it) {
+  if (S[MS_GO] != (double)(it + 1)) return;
+  const bool stepped = S[MS_ALPHA] != 0.0;
+  const size_t i0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+  double2 rp[kFusedPrefetch], pp[kFusedPrefetch];
+  if (stepped) {
+#pragma unroll
+    for (int j = 0; j < kFusedPrefetch; ++j) {
+      const size_t i = i0 + j * stride;
+      if (i < n) {
+        rp[j] = r[i];
+        pp[j] = p[i];
+      }
+    }
+  }
+  const double rr = mms::sum_partials(pr, npr);
+  // block 0 takes the step first, while the other blocks stream
+  if (blockIdx.x == 0) mms::step2_rr(S, rr, slot, H);
+  if (stepped) {
+    if (isfinite(rr)) {
+      const double beta = rr / S[MS_RR_OLD];
+#pragma unroll
+      for (int j = 0; j < kFusedPrefetch; ++j) {
+        const size_t i = i0 + j * stride;
+        if (i < n) p[i] = make_double2(rp[j].x + beta * pp[j].x, rp[j].y + beta * pp[j].y);
+      }
+      for (size_t i = i0 + kFusedPrefetch * stride; i < n; i += stride) {
+        const double2 ri = r[i], pi = p[i];
+        p[i] = make_double2(ri.x + beta * pi.x, ri.y + beta * pi.y);
+      }
+    }
+  }
+}
+
 // Scalar steps of an iteration (one block each).
 __global__ void mms_scal1_k(double* S, const double* partials, int nparts) { mms::step1(S, partials, nparts); }
 
@@ -542,6 +632,15 @@ void mms_update_r(const double2* rin, double2* rout, const double2* w, const dou
 }
 void mms_scal2(double* S, const double* partials, int nparts, int slot, double* H, hipStream_t st) {
   hipLaunchKernelGGL(mms_scal2_k, dim3(1), dim3(256), 0, st, S, partials, nparts, slot, H);
+}
+void mms_update_r_fused(const double2* rin, double2* rout, const double2* w, double* S, size_t n, const double* pst,
+                        int nst, double* partials, const double* skip, int it, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_r_fused_k, dim3(grid_for(n)), dim3(256), 0, st, rin, rout, w, S, n, pst, nst, partials,
+                     skip, it);
+}
+void mms_update_pbase_fused(const double2* r, double2* p, double* S, size_t n, const double* pr, int npr, int slot,
+                            double* H, int it, hipStream_t st) {
+  hipLaunchKernelGGL(mms_update_pbase_fused_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n, pr, npr, slot, H, it);
 }
 void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st) {
   hipLaunchKernelGGL(mms_update_pbase_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, S, n, it);

@@ -4,6 +4,7 @@
 // Coefficients of the Krylov updates are read from device memory so that a
 // whole fixed-length Arnoldi loop runs without a host round trip.
 #include "vec.h"
+#include "reduce.h"
 
 namespace ndtm {
 namespace {
@@ -189,8 +190,7 @@ __global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* 
 // sums column j of partials [width][nparts] into dst[j*dst_stride]
 __global__ void finalize_k(const double* part, int nparts, double* dst, int dst_stride) {
   const double* p = part + (size_t)blockIdx.x * nparts;
-  double s = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += p[i];
+  double s = strided_sum(p, nparts);
   s = bsum(s);
   if (threadIdx.x == 0) dst[(size_t)blockIdx.x * dst_stride] = s;
 }

@@ -7,6 +7,7 @@
 #pragma once
 
 #include "ndtm_internal.h"
+#include "reduce.h"
 
 namespace ndtm {
 namespace mms {
@@ -16,8 +17,7 @@ namespace mms {
 __device__ __forceinline__ double sum_partials(const double* part, int n) {
   __shared__ double ws[kBlock / 64];
   __shared__ double tot;
-  double v = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  double v = strided_sum(part, n);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
   __syncthreads();
@@ -36,10 +36,21 @@ __device__ __forceinline__ void stage(double* dst, const double* src) {
   for (int i = threadIdx.x; i < MS_SIZE; i += blockDim.x) dst[i] = src[i];
 }
 
+// alpha of step 1 from pw, from the values step 1 reads (so that every block of a
+// kernel can take it before, and while, block 0 runs the step itself)
+__device__ inline double alpha_of(const double* S, double pw) {
+  const int nsh = (int)S[MS_NSH];
+  int any = 0;
+  for (int s = 0; s < nsh; ++s) any |= S[MS_ACT_NEXT + s] != 0.0;
+  if (!any || S[MS_BREAK] != 0.0 || !(pw > 0.0) || !isfinite(pw)) return 0.0;
+  return S[MS_RR] / pw;
+}
+
 // alpha, zeta_{k+1}, alpha_s from pw = <p, (Q^2 + sigma_base) p>
 __device__ inline void step1_body(double* S, double pw) {
   const int nsh = (int)S[MS_NSH];
   S[MS_PW] = pw;
+  S[MS_RR_OLD] = S[MS_RR];
   int any = 0;
   for (int s = 0; s < nsh; ++s) {
     S[MS_ACT + s] = S[MS_ACT_NEXT + s];
@@ -118,24 +129,34 @@ __device__ inline int step2_body(double* S, double rr) {
   return 1;
 }
 
-// Whole block: pw from the partials, then step1 on an LDS copy of S.
-__device__ inline void step1(double* S, const double* partials, int nparts) {
+// Whole block: step1 on an LDS copy of S, from pw already summed (the same value in
+// every thread); go > 0 is stored in MS_GO with it.
+__device__ inline void step1_pw(double* S, double pw, double go = 0.0) {
   __shared__ double sh[MS_SIZE];
   stage(sh, S);
-  const double pw = sum_partials(partials, nparts);  // synchronises the block
-  if (threadIdx.x == 0) step1_body(sh, pw);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    step1_body(sh, pw);
+    if (go > 0.0) sh[MS_GO] = go;
+  }
   __syncthreads();
   stage(S, sh);
+}
+
+// Whole block: pw from the partials, then step1.
+__device__ inline void step1(double* S, const double* partials, int nparts) {
+  step1_pw(S, sum_partials(partials, nparts));
 }
 
 // Whole block: rr from the partials, step2 on an LDS copy of S, and for slot >= 0
 // the iteration's record in slot `slot` of the history H: per shift
 // (alpha_s, beta_s, zeta_{k+1}, 1) if it took a step, zeros otherwise.
-__device__ inline void step2(double* S, const double* partials, int nparts, int slot, double* H) {
+// step2_rr takes rr already summed (the same value in every thread).
+__device__ inline void step2_rr(double* S, double rr, int slot, double* H) {
   __shared__ double sh[MS_SIZE];
   __shared__ int go;
   stage(sh, S);
-  const double rr = sum_partials(partials, nparts);  // synchronises the block
+  __syncthreads();
   if (threadIdx.x == 0) go = step2_body(sh, rr);
   __syncthreads();
   stage(S, sh);
@@ -148,6 +169,10 @@ __device__ inline void step2(double* S, const double* partials, int nparts, int 
   h[1] = act ? sh[MS_BETA_S + s] : 0.0;
   h[2] = act ? sh[MS_ZETA + s] : 0.0;
   h[3] = act ? 1.0 : 0.0;
+}
+
+__device__ inline void step2(double* S, const double* partials, int nparts, int slot, double* H) {
+  step2_rr(S, sum_partials(partials, nparts), slot, H);
 }
 
 }  // namespace mms

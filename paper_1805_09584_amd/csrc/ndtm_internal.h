@@ -155,6 +155,15 @@ void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps
 // with_p, the block-end p_s) of every shift touched in the block from the residuals
 // in slots 0..nr-1 of the ring R (slot j at R + j n)
 void mms_update_pbase(const double2* r, double2* p, const double* S, size_t n, int it, hipStream_t st);
+// deferred form with the scalar steps of iteration `it` fused: the residual update
+// takes step 1 from the stencil partials pst[0..nst) (block 0), writing its own
+// partials (not over pst); the base direction update takes step 2 from those (npr of
+// them) and records slot `slot` of H (block 0).  The first returns at once while
+// *skip is set, and the second whenever the first did.
+void mms_update_r_fused(const double2* rin, double2* rout, const double2* w, double* S, size_t n, const double* pst,
+                        int nst, double* partials, const double* skip, int it, hipStream_t st);
+void mms_update_pbase_fused(const double2* r, double2* p, double* S, size_t n, const double* pr, int npr, int slot,
+                            double* H, int it, hipStream_t st);
 void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, int k0, bool with_p,
                const double* S, const double* H, double* C, size_t n, hipStream_t st);
 // mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
@@ -174,7 +183,8 @@ constexpr int kCoefStride = MC_D + kMaxDefer;
 // Layout of the scalar block S (doubles).
 enum MmsIdx {
   MS_RR = 0, MS_PW, MS_ALPHA, MS_ALPHA_PREV, MS_BETA, MS_BB, MS_TOL2, MS_IT, MS_NSH, MS_DONE,
-  MS_BREAK, MS_HDR = 16,
+  MS_BREAK, MS_RR_OLD /* ||r_k||^2 of the iteration in progress (step 1 copies it) */,
+  MS_GO /* fused deferred form: k + 1 once step 1 of iteration k has run */, MS_HDR = 16,
   // per-shift arrays of length kMaxShifts follow
   MS_ZETA = MS_HDR, MS_ZETA_PREV = MS_ZETA + kMaxShifts, MS_ZETA_NEXT = MS_ZETA_PREV + kMaxShifts,
   MS_ALPHA_S = MS_ZETA_NEXT + kMaxShifts, MS_BETA_S = MS_ALPHA_S + kMaxShifts,

@@ -163,20 +163,28 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     // past the done flag the stencil passes and the residual update return at once, and
     // the update kernels of an iteration run only if its scalar step was taken
     apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
-    mms_scal1(c->mms_S, c->partials, hg, st);
     // deferred: r_k is in slot (k-1) mod m (b for k = 0), r_{k+1} goes to slot k mod m
     const int slot = deferred ? it % defer : -1;
     const double2* rin = !deferred ? (const double2*)r.v : it == 0 ? bv : ring + (size_t)((it - 1) % defer) * n;
     double2* rout = deferred ? ring + (size_t)slot * n : (double2*)r.v;
-    {
-      ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
-      mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st, c->hop_skip);
-    }
-    mms_scal2(c->mms_S, c->partials, rg, slot, c->mms_H, st);
     if (deferred) {
+      // the scalar steps ride in the two vector passes; the residual norms go behind
+      // the stencil's partials, which the first pass still reads
+      double* pr_r = c->partials + hg;
+      {
+        ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
+        mms_update_r_fused(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, hg, pr_r, c->hop_skip, it,
+                           st);
+      }
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_pbase(rout, (double2*)p.v, c->mms_S, n, it, st);
+      mms_update_pbase_fused(rout, (double2*)p.v, c->mms_S, n, pr_r, rg, slot, c->mms_H, it, st);
     } else {
+      mms_scal1(c->mms_S, c->partials, hg, st);
+      {
+        ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
+        mms_update_r(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, st, c->hop_skip);
+      }
+      mms_scal2(c->mms_S, c->partials, rg, slot, c->mms_H, st);
       // bytes of this class are added after the loop, once the active counts are known
       ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
       mms_update_p((double2*)r.v, (double2*)p.v, xv.data(), ps.data(), nsh, sb, c->mms_S, n, st, it);
