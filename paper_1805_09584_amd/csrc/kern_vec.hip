@@ -59,6 +59,22 @@ __device__ __forceinline__ double bsum(double v) {
 }
 
 // grid-stride loop, unrolled so that several independent loads per thread are in flight
+// Reduction loops: a thread visits its grid-stride indices in increasing order, in
+// batches of kRB whose loads are all issued before the first is used (a plain loop,
+// even unrolled, waits on each load in turn).  The additions keep their order.
+constexpr int kRB = 8;
+#define BATCH_LOOP(b, n) \
+  for (size_t b = blockIdx.x * (size_t)blockDim.x + threadIdx.x; b < (n); b += (size_t)kRB * gridDim.x * blockDim.x)
+#define BATCH_IDX(b, j) ((b) + (size_t)(j) * gridDim.x * blockDim.x)
+// the loads of a batch read index min(i, n - 1), so they need no branch (n >= 1 inside
+// the loop); only the visits with i < n are added
+#define BATCH_LD(p, b, j, n) (p)[BATCH_IDX(b, j) < (n) ? BATCH_IDX(b, j) : (n) - 1]
+__device__ __forceinline__ double2 wide(double2 v) { return v; }
+__device__ __forceinline__ double2 wide(float2 v) { return make_double2(v.x, v.y); }
+
+__device__ __forceinline__ double2 rounded(const double2*, double2 v) { return v; }
+__device__ __forceinline__ double2 rounded(const float2*, double2 v) { return make_double2((float)v.x, (float)v.y); }
+
 #define GRID_LOOP(i, n)  \
   _Pragma("unroll 4") for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
@@ -130,9 +146,16 @@ __device__ bool last_block_sum(double* ws, int width, double* dst) {
 template <class T2>
 __global__ __launch_bounds__(256) void norm2_k(const T2* x, size_t n, double* ws, double* dst) {
   double s = 0;
-  GRID_LOOP(i, n) {
-    const double2 v = ld2(x, i);
-    s += v.x * v.x + v.y * v.y;
+  BATCH_LOOP(b, n) {
+    T2 v[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) v[j] = BATCH_LD(x, b, j, n);
+#pragma unroll
+    for (int j = 0; j < kRB; ++j)
+      if (BATCH_IDX(b, j) < n) {
+        const double2 a = wide(v[j]);
+        s += a.x * a.x + a.y * a.y;
+      }
   }
   s = bsum(s);
   if (threadIdx.x == 0) ws[8 + blockIdx.x] = s;
@@ -144,10 +167,20 @@ template <class T2>
 __global__ __launch_bounds__(256) void dot_k(const T2* x, const T2* y, size_t n, double* ws, double* dst) {
   double* part = ws + 8;
   double re = 0, im = 0;
-  GRID_LOOP(i, n) {
-    const double2 a = ld2(x, i), b = ld2(y, i);
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
+  BATCH_LOOP(b0, n) {
+    T2 xa[kRB], ya[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      xa[j] = BATCH_LD(x, b0, j, n);
+      ya[j] = BATCH_LD(y, b0, j, n);
+    }
+#pragma unroll
+    for (int j = 0; j < kRB; ++j)
+      if (BATCH_IDX(b0, j) < n) {
+        const double2 a = wide(xa[j]), b = wide(ya[j]);
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+      }
   }
   re = bsum(re);
   im = bsum(im);
@@ -222,7 +255,7 @@ __global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int
       acc.y -= t.y;
     }
     st2(w, i, acc);
-    const double2 r = ld2(w, i);  // the stored (rounded) value
+    const double2 r = rounded(w, acc);  // the stored value
     s += r.x * r.x + r.y * r.y;
   }
   s = bsum(s);
@@ -235,11 +268,21 @@ __global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int
 template <class T2>
 __global__ __launch_bounds__(256) void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws, double* dst) {
   double re = 0, im = 0, tt = 0;
-  GRID_LOOP(i, n) {
-    const double2 a = ld2(t, i), b = ld2(sv, i);
-    re += a.x * b.x + a.y * b.y;
-    im += a.x * b.y - a.y * b.x;
-    tt += a.x * a.x + a.y * a.y;
+  BATCH_LOOP(b0, n) {
+    T2 ta[kRB], sa[kRB];
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      ta[j] = BATCH_LD(t, b0, j, n);
+      sa[j] = BATCH_LD(sv, b0, j, n);
+    }
+#pragma unroll
+    for (int j = 0; j < kRB; ++j)
+      if (BATCH_IDX(b0, j) < n) {
+        const double2 a = wide(ta[j]), b = wide(sa[j]);
+        re += a.x * b.x + a.y * b.y;
+        im += a.x * b.y - a.y * b.x;
+        tt += a.x * a.x + a.y * a.y;
+      }
   }
   re = bsum(re);
   im = bsum(im);
