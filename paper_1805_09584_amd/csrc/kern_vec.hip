@@ -21,7 +21,7 @@ struct Basis {
 // reductions: at most 256 blocks (the completion of each block costs a release
 // fence and an atomic on one counter, which grows with the block count)
 inline unsigned rgrid(size_t n) {
-  size_t g = (n + 4 * kVB - 1) / (4 * kVB);
+  size_t g = (n + kVB - 1) / kVB;
   if (g > 256) g = 256;
   return (unsigned)(g ? g : 1);
 }
@@ -220,26 +220,53 @@ __global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* 
   last_block_sum(ws, 2 * k, dst);
 }
 
+// w -= sum_j coef[j] V_j, then <V_j, w> for j < k (one pass: the first Gram-Schmidt
+// pass's update and the second pass's overlaps; the overlaps use the stored w)
+template <class T2, int KM>
+__global__ __launch_bounds__(256) void multi_axpy_dot_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n,
+                                                        double* ws, double* dst) {
+  double* part = ws + 8;
+  double re[KM], im[KM];
+#pragma unroll
+  for (int j = 0; j < KM; ++j) re[j] = im[j] = 0;
+#pragma unroll 1
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double2 acc = ld2(w, i);
+    double2 v[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k) {
+        v[j] = ld2(V.v[j], i);
+        const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), v[j]);
+        acc.x -= t.x;
+        acc.y -= t.y;
+      }
+    st2(w, i, acc);
+    const double2 r = rounded(w, acc);
+#pragma unroll
+    for (int j = 0; j < KM; ++j)
+      if (j < k) {
+        re[j] += v[j].x * r.x + v[j].y * r.y;
+        im[j] += v[j].x * r.y - v[j].y * r.x;
+      }
+  }
+  for (int j = 0; j < k; ++j) {
+    const double a = bsum(re[j]);
+    const double b = bsum(im[j]);
+    if (threadIdx.x == 0) {
+      part[(size_t)(2 * j) * gridDim.x + blockIdx.x] = a;
+      part[(size_t)(2 * j + 1) * gridDim.x + blockIdx.x] = b;
+    }
+  }
+  last_block_sum(ws, 2 * k, dst);
+}
+
 // sums column j of partials [width][nparts] into dst[j*dst_stride]
 __global__ void finalize_k(const double* part, int nparts, double* dst, int dst_stride) {
   const double* p = part + (size_t)blockIdx.x * nparts;
   double s = strided_sum(p, nparts);
   s = bsum(s);
   if (threadIdx.x == 0) dst[(size_t)blockIdx.x * dst_stride] = s;
-}
-
-// w -= sum_j coef[j] V_j   (coef complex, 2 doubles each, device)
-template <class T2>
-__global__ __launch_bounds__(256) void multi_axpy_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n) {
-  GRID_LOOP(i, n) {
-    double2 acc = ld2(w, i);
-    for (int j = 0; j < k; ++j) {
-      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.v[j], i));
-      acc.x -= t.x;
-      acc.y -= t.y;
-    }
-    st2(w, i, acc);
-  }
 }
 
 // w -= sum_j coef[j] V_j and ||w||^2 into dst (single launch)
@@ -330,10 +357,6 @@ __global__ __launch_bounds__(256) void lincomb_dev_k(T2* y, Basis<T2> V, int k, 
   }
 }
 
-__global__ void vadd_k(double* a, const double* b, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] += b[i];
-}
-
 // omega = <t, r> / <t, t> from d = [re<t,r>, im<t,r>, <t,t>]
 __global__ void mr_coef_k(const double* d, double* omega) {
   if (threadIdx.x == 0) {
@@ -345,7 +368,8 @@ __global__ void mr_coef_k(const double* d, double* omega) {
 
 // Least squares of a (m+1) x m Hessenberg system by Givens rotations, one thread.
 // H column-major with leading dimension ldh (complex, 2 doubles); beta = sqrt(*beta2).
-__global__ void hess_lsq_k(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y) {
+__global__ void hess_lsq_k(const double* H, const double* H2, int ldh, int m, const double* beta2, const double* sub2,
+                           double* y) {
   // small dense work in LDS (a private array would live in scratch memory)
   __shared__ double2 R[kMaxBasis + 1][kMaxBasis];
   __shared__ double2 g[kMaxBasis + 1];
@@ -353,7 +377,10 @@ __global__ void hess_lsq_k(const double* H, int ldh, int m, const double* beta2,
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int j = 0; j < m; ++j)
   {
-    for (int i = 0; i <= j; ++i) R[i][j] = make_double2(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
+    for (int i = 0; i <= j; ++i) {
+      const size_t e = 2 * ((size_t)j * ldh + i);
+      R[i][j] = H2 ? make_double2(H[e] + H2[e], H[e + 1] + H2[e + 1]) : make_double2(H[e], H[e + 1]);
+    }
     R[j + 1][j] = make_double2(sqrt(fmax(sub2[j], 0.0)), 0.0);
   }
   for (int i = 0; i <= m; ++i) g[i] = make_double2(0, 0);
@@ -527,13 +554,25 @@ void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, d
 }
 
 template <class T2>
-static void vmulti_axpy_t(void* w, const void* const* V, int k, const double* coef, size_t n, hipStream_t st) {
-  hipLaunchKernelGGL(multi_axpy_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(w), basis<T2>(V, k), k,
-                     coef, n);
+static void vmulti_axpy_dot_t(void* w, const void* const* V, int k, const double* coef, size_t n, double* part,
+                              double* dst, hipStream_t st) {
+  const unsigned g = rgrid(n);
+  auto B = basis<T2>(V, k);
+  T2* wp = static_cast<T2*>(w);
+  if (k <= 4)
+    hipLaunchKernelGGL((multi_axpy_dot_k<T2, 4>), dim3(g), dim3(kVB), 0, st, wp, B, k, coef, n, part, dst);
+  else if (k <= 8)
+    hipLaunchKernelGGL((multi_axpy_dot_k<T2, 8>), dim3(g), dim3(kVB), 0, st, wp, B, k, coef, n, part, dst);
+  else if (k <= 16)
+    hipLaunchKernelGGL((multi_axpy_dot_k<T2, 16>), dim3(g), dim3(kVB), 0, st, wp, B, k, coef, n, part, dst);
+  else if (k <= 24)
+    hipLaunchKernelGGL((multi_axpy_dot_k<T2, 24>), dim3(g), dim3(kVB), 0, st, wp, B, k, coef, n, part, dst);
+  else
+    hipLaunchKernelGGL((multi_axpy_dot_k<T2, kMaxBasis>), dim3(g), dim3(kVB), 0, st, wp, B, k, coef, n, part, dst);
 }
-void vmulti_axpy_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n,
-                     hipStream_t st) {
-  DISPATCH(prec, vmulti_axpy_t, w, V, k, coef, n, st);
+void vmulti_axpy_multidot(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* part,
+                          double* dst, hipStream_t st) {
+  DISPATCH(prec, vmulti_axpy_dot_t, w, V, k, coef, n, part, dst, st);
 }
 
 template <class T2>
@@ -578,17 +617,13 @@ void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int
   DISPATCH(prec, vmr_update_t, z, s, t, om, update_s, n, st);
 }
 
-void vadd_dev(double* a, const double* b, int n, hipStream_t st) {
-  hipLaunchKernelGGL(vadd_k, dim3(1), dim3(128), 0, st, a, b, n);
-}
-
 void mr_coef(const double* d, double* omega, hipStream_t st) {
   hipLaunchKernelGGL(mr_coef_k, dim3(1), dim3(64), 0, st, d, omega);
 }
 
-void hess_lsq(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y,
+void hess_lsq(const double* H, const double* H2, int ldh, int m, const double* beta2, const double* sub2, double* y,
               hipStream_t st) {
-  hipLaunchKernelGGL(hess_lsq_k, dim3(1), dim3(64), 0, st, H, ldh, m, beta2, sub2, y);
+  hipLaunchKernelGGL(hess_lsq_k, dim3(1), dim3(64), 0, st, H, H2, ldh, m, beta2, sub2, y);
 }
 
 }  // namespace ndtm

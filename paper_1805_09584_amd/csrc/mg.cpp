@@ -62,7 +62,7 @@ struct MGData {
   double* dy = nullptr;   // least-squares coefficients
   double* dbeta = nullptr;
   double* dtmp = nullptr;
-  double* dh2 = nullptr;  // second Gram-Schmidt pass coefficients
+  double* dh2 = nullptr;  // second Gram-Schmidt pass coefficients, laid out as dH
   std::vector<void*> owned;
   bool ready = false;
   // cycle graphs: one per value of the odd-site shift m, replayed on the caller's stream
@@ -130,16 +130,16 @@ static void coarse_gmres_cycle(ndtm_ctx* c, MGData* M, const void* src, const do
       mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, eps, m, st);
     }
     // classical Gram-Schmidt with one reorthogonalisation; the second pass's
-    // coefficients are added into the Hessenberg column on the device
+    // coefficients go to their own Hessenberg array, added to the first by the
+    // least-squares step
     double* hcol = M->dH + 2 * (size_t)j * (kc + 1);
+    double* hcol2 = M->dh2 + 2 * (size_t)j * (kc + 1);
     vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->vred, hcol, st);
-    vmulti_axpy_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol, n, st);
-    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->vred, M->dh2, st);
-    vmulti_axpy_norm_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, M->dh2, n, c->vred, M->dsub + j, st);
-    vadd_dev(hcol, M->dh2, 2 * (j + 1), st);
+    vmulti_axpy_multidot(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol, n, c->vred, hcol2, st);
+    vmulti_axpy_norm_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol2, n, c->vred, M->dsub + j, st);
     vscale_inv_sqrt(cp, M->cV[j + 1], M->cW, M->dsub + j, n, st);
   }
-  hess_lsq(M->dH, kc + 1, kc, src2, M->dsub, M->dy, st);
+  hess_lsq(M->dH, M->dh2, kc + 1, kc, src2, M->dsub, M->dy, st);
   vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, accumulate, n, st);
 }
 
@@ -288,8 +288,7 @@ static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField&
       apply_sshift(c, P64, W, Z[k], te, m, st);
       // classical Gram-Schmidt, two passes
       vmultidot(P64, Vp.data(), k + 1, W.v, n, c->vred, dh, st);
-      vmulti_axpy_dev(P64, W.v, Vp.data(), k + 1, dh, n, st);
-      vmultidot(P64, Vp.data(), k + 1, W.v, n, c->vred, dh + 2 * restart, st);
+      vmulti_axpy_multidot(P64, W.v, Vp.data(), k + 1, dh, n, c->vred, dh + 2 * restart, st);
       vmulti_axpy_norm_dev(P64, W.v, Vp.data(), k + 1, dh + 2 * restart, n, c->vred, dh + 4 * restart, st);
       vscale_inv_sqrt(P64, V[k + 1].v, W.v, dh + 4 * restart, n, st);
       (void)hipMemcpyAsync(c->hscal, dh, (4 * restart + 1) * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -593,7 +592,7 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->dy = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
   M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
   M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
-  M->dh2 = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
+  M->dh2 = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
   if (!M->dh2 || !M->cW || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);

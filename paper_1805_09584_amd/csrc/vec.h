@@ -24,10 +24,12 @@ void vnorm2(int prec, const void* x, size_t n, double* part, double* dst, hipStr
 void vdot(int prec, const void* x, const void* y, size_t n, double* part, double* dst, hipStream_t st);  // dst[0..1]
 void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
                hipStream_t st);                                                                  // dst[2j..]
-void vmulti_axpy_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n,
-                     hipStream_t st);                                                            // w -= sum c_j V_j
 void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* coef, int accumulate, size_t n,
                   hipStream_t st);
+// w -= sum_j coef[j] V_j, then <V_j, w> into dst[2j..2j+1] for j < k (one launch; dst
+// must not overlap coef)
+void vmulti_axpy_multidot(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* part,
+                          double* dst, hipStream_t st);
 // w -= sum_j coef[j] V_j, then ||w||^2 into dst[0] (one launch)
 void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
                           double* dst, hipStream_t st);
@@ -38,11 +40,10 @@ void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int
                 hipStream_t st);
 void vfinalize(const double* part, int nparts, int width, double* dst, int dst_stride, hipStream_t st);
 void mr_coef(const double* d, double* omega, hipStream_t st);
-// a[i] += b[i], i < n (device scalars)
-void vadd_dev(double* a, const double* b, int n, hipStream_t st);
-// least squares min || beta e_1 - H y || for the (m+1) x m Hessenberg matrix with upper part H
-// (column-major, ldh, complex) and subdiagonal sqrt(sub2[j])
-void hess_lsq(const double* H, int ldh, int m, const double* beta2, const double* sub2, double* y,
+// least squares min || beta e_1 - H y || for the (m+1) x m Hessenberg matrix with upper part
+// H (+ H2 when not null: the two Gram-Schmidt passes; column-major, ldh, complex) and
+// subdiagonal sqrt(sub2[j])
+void hess_lsq(const double* H, const double* H2, int ldh, int m, const double* beta2, const double* sub2, double* y,
               hipStream_t st);
 
 // ---- multigrid ----
