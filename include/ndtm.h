@@ -129,8 +129,8 @@ typedef struct {
   int setup_nd;        /* 0: iterate the one-flavour operators D_W +- i mubar Gamma5
                           (section 3.2's reuse of the twisted-mass setup); 1: iterate the
                           doublet operator D_ND itself and use both flavour components */
-  int smooth_iters;    /* post-smoothing iterations per cycle (0 pre) */
-  int coarse_iters;    /* GMRES iterations of the coarse solve per cycle */
+  int smooth_iters;    /* post-smoothing iterations per cycle (0 pre; default 8) */
+  int coarse_iters;    /* GMRES iterations of the coarse solve per cycle (default 12) */
   double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
   unsigned long long seed; /* seed of the random initial test vectors */
   int precision;       /* NDTM_PREC_F64 or NDTM_PREC_F32 for P, coarse ops and the cycle */

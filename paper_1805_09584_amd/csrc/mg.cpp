@@ -735,7 +735,7 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->setup_refine = 0;
   p->setup_nd = 1;
   p->smooth_iters = 8;
-  p->coarse_iters = 8;
+  p->coarse_iters = 12;
   p->coarse_mu_factor = 1.0;
   p->seed = 32;
   p->precision = NDTM_PREC_F32;
