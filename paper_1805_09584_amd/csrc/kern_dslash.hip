@@ -363,6 +363,26 @@ __device__ __forceinline__ void block_reduce_store(double v, double* partials) {
   }
 }
 
+// the three RED_MR partials of a block, at partials[q * 2 gridDim + blockIdx]
+__device__ __forceinline__ void block_reduce_store3(double v0, double v1, double v2, double* partials) {
+  double v[3] = {v0, v1, v2};
+  __shared__ double ws3[3][kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off);
+    if (lane == 0) ws3[q][w] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s += ws3[threadIdx.x][i];
+    partials[(size_t)threadIdx.x * 2 * gridDim.x + blockIdx.x] = s;
+  }
+}
+
 template <class S, class L, int EPI, int RED, bool R12>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   using R = typename RealOf<S>::T;
@@ -388,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     xh = r - y * Lxh;
     h = ((t * A.Lz + z) * A.Ly + y) * Lxh + xh;
   }
-  double red = 0.0;
+  double red = 0.0, red_im = 0.0, red_tt = 0.0;
 
   cx<R> acc[4][3];
 #pragma unroll
@@ -502,6 +522,19 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
         out[s][c] = y;
       }
     }
+    if constexpr (RED == RED_MR) {
+      // <out, x> and ||out||^2, x the site vector just read (zero off the lattice)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double ox = double(out[s][c].x), oy = double(out[s][c].y);
+          const double xx = double(xv[s][c].x), xy = double(xv[s][c].y);
+          red += ox * xx + oy * xy;
+          red_im += ox * xy - oy * xx;
+          red_tt += valid ? ox * ox + oy * oy : 0.0;
+        }
+    }
     if constexpr (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) {
       // Gamma5 tau1: out_f = g5 y_{1-f}
 #pragma unroll
@@ -577,7 +610,8 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
         for (int c = 0; c < 3; ++c) stc_nt(at(A.out, (long)(s * 3 + c) * A.stride, vout), out[s][c]);
     }
   }
-  if constexpr (RED != RED_NONE) block_reduce_store(red, A.partials);
+  if constexpr (RED == RED_MR) block_reduce_store3(red, red_im, red_tt, A.partials);
+  else if constexpr (RED != RED_NONE) block_reduce_store(red, A.partials);
 }
 
 // Largest divisor bz of Lz whose bz-plane window of input spinors (the reuse
@@ -641,7 +675,10 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
       if (red == RED_REDOT) NDTM_HOP(EPI_QHAT_SIG, RED_REDOT);
       else NDTM_HOP(EPI_QHAT_SIG, RED_NONE);
       break;
-    case EPI_SITE: NDTM_HOP(EPI_SITE, RED_NONE); break;
+    case EPI_SITE:
+      if (red == RED_MR) NDTM_HOP(EPI_SITE, RED_MR);
+      else NDTM_HOP(EPI_SITE, RED_NONE);
+      break;
   }
 #undef NDTM_HOP
 }

@@ -290,47 +290,35 @@ __global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int
   last_block_sum(ws, 1, dst);
 }
 
-// minimal-residual coefficient omega = <t, s> / <t, t> (single launch; dst[0..1] = omega,
-// dst[2..4] = re<t,s>, im<t,s>, <t,t>)
-template <class T2>
-__global__ __launch_bounds__(256) void mr_coef_fused_k(const T2* t, const T2* sv, size_t n, double* ws, double* dst) {
-  double re = 0, im = 0, tt = 0;
-  BATCH_LOOP(b0, n) {
-    T2 ta[kRB], sa[kRB];
+// sum of part[0..np) in a fixed order, valid in every thread of the block
+__device__ double block_total(const double* part, int np) {
+  __shared__ double wsum[kVB / 64];
+  __shared__ double tot;
+  double v = strided_sum(part, np);
 #pragma unroll
-    for (int j = 0; j < kRB; ++j) {
-      ta[j] = BATCH_LD(t, b0, j, n);
-      sa[j] = BATCH_LD(sv, b0, j, n);
-    }
-#pragma unroll
-    for (int j = 0; j < kRB; ++j)
-      if (BATCH_IDX(b0, j) < n) {
-        const double2 a = wide(ta[j]), b = wide(sa[j]);
-        re += a.x * b.x + a.y * b.y;
-        im += a.x * b.y - a.y * b.x;
-        tt += a.x * a.x + a.y * a.y;
-      }
-  }
-  re = bsum(re);
-  im = bsum(im);
-  tt = bsum(tt);
-  double* part = ws + 8;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = re;
-    part[gridDim.x + blockIdx.x] = im;
-    part[2 * gridDim.x + blockIdx.x] = tt;
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wsum[w];
+    tot = s;
   }
-  if (last_block_sum(ws, 3, dst + 2) && threadIdx.x == 0) {
-    const double tts = dst[4];
-    dst[0] = tts > 0 ? dst[2] / tts : 0.0;
-    dst[1] = tts > 0 ? dst[3] / tts : 0.0;
-  }
+  __syncthreads();
+  return tot;
 }
 
-// z += omega s ; s -= omega t  (omega complex at dev[0..1])
+// minimal-residual update with omega = <t, s> / <t, t> taken from the partials of
+// the stencil passes that formed t = D' s (part[q * np + i], q = re, im, norm): every
+// block sums them in the same order, so all use the same omega
 template <class T2>
-__global__ __launch_bounds__(256) void mr_update_k(T2* z, T2* sv, const T2* t, const double* om, int update_s, size_t n) {
-  const double2 w = make_double2(om[0], om[1]);
+__global__ __launch_bounds__(256) void mr_update_part_k(T2* z, T2* sv, const T2* t, const double* part, int np,
+                                                        int update_s, size_t n) {
+  const double re = block_total(part, np);
+  const double im = block_total(part + np, np);
+  const double tt = block_total(part + 2 * (size_t)np, np);
+  const double2 w = tt > 0 ? make_double2(re / tt, im / tt) : make_double2(0.0, 0.0);
   GRID_LOOP(i, n) {
     const double2 sval = ld2(sv, i);
     const double2 zs = cm(w, sval);
@@ -357,14 +345,6 @@ __global__ __launch_bounds__(256) void lincomb_dev_k(T2* y, Basis<T2> V, int k, 
   }
 }
 
-// omega = <t, r> / <t, t> from d = [re<t,r>, im<t,r>, <t,t>]
-__global__ void mr_coef_k(const double* d, double* omega) {
-  if (threadIdx.x == 0) {
-    const double tt = d[2];
-    omega[0] = tt > 0 ? d[0] / tt : 0.0;
-    omega[1] = tt > 0 ? d[1] / tt : 0.0;
-  }
-}
 
 // Least squares of a (m+1) x m Hessenberg system by Givens rotations, one thread.
 // H column-major with leading dimension ldh (complex, 2 doubles); beta = sqrt(*beta2).
@@ -598,28 +578,17 @@ void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const 
 }
 
 template <class T2>
-static void vmr_coef_t(const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st) {
-  hipLaunchKernelGGL(mr_coef_fused_k<T2>, dim3(rgrid(n)), dim3(kVB), 0, st, static_cast<const T2*>(t),
-                     static_cast<const T2*>(s), n, ws, dst);
+static void vmr_update_part_t(void* z, void* s, const void* t, const double* part, int np, int update_s, size_t n,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(mr_update_part_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(z),
+                     static_cast<T2*>(s), static_cast<const T2*>(t), part, np, update_s, n);
 }
-void vmr_coef(int prec, const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st) {
-  DISPATCH(prec, vmr_coef_t, t, s, n, ws, dst, st);
-}
-
-template <class T2>
-static void vmr_update_t(void* z, void* s, const void* t, const double* om, int update_s, size_t n,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(mr_update_k<T2>, dim3(vgrid(n)), dim3(kVB), 0, st, static_cast<T2*>(z), static_cast<T2*>(s),
-                     static_cast<const T2*>(t), om, update_s, n);
-}
-void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int update_s, size_t n,
-                hipStream_t st) {
-  DISPATCH(prec, vmr_update_t, z, s, t, om, update_s, n, st);
+void vmr_update_part(int prec, void* z, void* s, const void* t, const double* part, int np, int update_s, size_t n,
+                     hipStream_t st) {
+  DISPATCH(prec, vmr_update_part_t, z, s, t, part, np, update_s, n, st);
 }
 
-void mr_coef(const double* d, double* omega, hipStream_t st) {
-  hipLaunchKernelGGL(mr_coef_k, dim3(1), dim3(64), 0, st, d, omega);
-}
+
 
 void hess_lsq(const double* H, const double* H2, int ldh, int m, const double* beta2, const double* sub2, double* y,
               hipStream_t st) {

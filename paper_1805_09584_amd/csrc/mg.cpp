@@ -63,6 +63,7 @@ struct MGData {
   double* dbeta = nullptr;
   double* dtmp = nullptr;
   double* dh2 = nullptr;  // second Gram-Schmidt pass coefficients, laid out as dH
+  double* dpart = nullptr;  // smoother: stencil partials of <D'S, S>, ||D'S||^2 ([3][2 nblk])
   std::vector<void*> owned;
   bool ready = false;
   // cycle graphs: one per value of the odd-site shift m, replayed on the caller's stream
@@ -179,6 +180,14 @@ static void dprime(ndtm_ctx* c, int prec, const Full& y, const Full& x, double m
   apply_dfull(c, prec, y.e, y.o, x.e, x.o, m, st);
 }
 
+// y = D' x, with the partials of <y, x> and ||y||^2 of both parity passes in
+// part[q * 2 nblk + i] (the two hops of apply_dfull, each reducing over its sites)
+static void dprime_mr(ndtm_ctx* c, int prec, const Full& y, const Full& x, double m, double* part, hipStream_t st) {
+  const int hg = hop_grid(c->g);
+  hop(c, prec, EPI_SITE, RED_MR, 0, x.o, y.e, &x.e, nullptr, 0.0, -0.5, 0, part, st);
+  hop(c, prec, EPI_SITE, RED_MR, 1, x.e, y.o, &x.o, nullptr, m, -0.5, 0, part + hg, st);
+}
+
 // Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
 // smooth_iters minimal-residual steps.  The fine operator is the one in c->op
 // (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
@@ -201,9 +210,10 @@ static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
     dprime(c, cp, S, Z, m, st);
     vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
     for (int it = 0; it < nu; ++it) {
-      dprime(c, cp, Tt, S, m, st);
-      vmr_coef(cp, Tt.base, S.base, 2 * nh, c->vred, M->dtmp, st);
-      vmr_update(cp, Z.base, S.base, Tt.base, M->dtmp, it + 1 < nu, 2 * nh, st);
+      // T = D' S with <T, S>, ||T||^2 reduced in the stencil epilogue; the update
+      // kernel forms omega from those partials
+      dprime_mr(c, cp, Tt, S, m, M->dpart, st);
+      vmr_update_part(cp, Z.base, S.base, Tt.base, M->dpart, 2 * hop_grid(c->g), it + 1 < nu, 2 * nh, st);
     }
   }
 }
@@ -593,7 +603,8 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
   M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
   M->dh2 = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
-  if (!M->dh2 || !M->cW || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
+  M->dpart = (double*)mg_alloc(M, 6 * (size_t)hop_grid(c->g) * sizeof(double));
+  if (!M->dpart || !M->dh2 || !M->cW || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
   if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");

@@ -64,7 +64,11 @@ enum Epi {
   EPI_QHAT_SIG = 3,// out = Gamma5 tau1 (A xs - 1/4 H in) + sigma zs
   EPI_SITE = 4     // out = (A + i ms Gamma5 tau1) xs + hop_coef H in
 };
-enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2 };
+// RED_MR (site epilogue): per block, <out, x> (complex) and ||out||^2 over the block's
+// sites, with x the site vector the epilogue reads; stored at partials[q * 2 nblk + b]
+// for q = re, im, norm, so that the two parity passes of one full-lattice operator
+// (partials offset by nblk for the second) fill one [3][2 nblk] table
+enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2, RED_MR = 3 };
 
 struct OpParams {
   double a, mubar, epsbar, inv_den;

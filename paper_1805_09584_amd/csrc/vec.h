@@ -33,13 +33,11 @@ void vmulti_axpy_multidot(int prec, void* w, const void* const* V, int k, const 
 // w -= sum_j coef[j] V_j, then ||w||^2 into dst[0] (one launch)
 void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
                           double* dst, hipStream_t st);
-// minimal-residual step: dst[0..1] = <t,s>/<t,t>, dst[2..4] scratch
-void vmr_coef(int prec, const void* t, const void* s, size_t n, double* ws, double* dst, hipStream_t st);
-// z += omega s, and s -= omega t if update_s (omega at om[0..1], device)
-void vmr_update(int prec, void* z, void* s, const void* t, const double* om, int update_s, size_t n,
-                hipStream_t st);
+// minimal-residual step: z += omega s, and s -= omega t if update_s, with omega = <t,s>/<t,t>
+// summed from stencil partials part[q * np + i] (q = re, im, norm) by every block
+void vmr_update_part(int prec, void* z, void* s, const void* t, const double* part, int np, int update_s, size_t n,
+                     hipStream_t st);
 void vfinalize(const double* part, int nparts, int width, double* dst, int dst_stride, hipStream_t st);
-void mr_coef(const double* d, double* omega, hipStream_t st);
 // least squares min || beta e_1 - H y || for the (m+1) x m Hessenberg matrix with upper part
 // H (+ H2 when not null: the two Gram-Schmidt passes; column-major, ldh, complex) and
 // subdiagonal sqrt(sub2[j])
