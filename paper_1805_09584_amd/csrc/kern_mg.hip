@@ -450,11 +450,15 @@ __global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>:
 }
 
 // ---------------- coarse stencil ----------------
+// y = D'_c x.  With xnorm2 the input is x / sqrt(*xnorm2) (scaled as it is read,
+// with the rounding of a separate scaling pass), and xout, when given, receives the
+// scaled input of the block's own site: the coarse Arnoldi step normalises its new
+// basis vector this way instead of in a pass of its own.
 template <class R>
 __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C2<R>::T* D,
                                                       const typename C2<R>::T* Bo, const typename C2<R>::T* x,
                                                       typename C2<R>::T* y, double mubar_c, double epsbar,
-                                                      double mm) {
+                                                      double mm, const double* xnorm2, typename C2<R>::T* xout) {
   using T2 = typename C2<R>::T;
   const int X = blockIdx.x;
   const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2, nout = 2 * n2;
@@ -466,11 +470,15 @@ __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C
     nb[b] = b == 0 ? X : coarse_nbr(m, X, (b - 1) >> 1, ((b - 1) & 1) ? -1 : 1);
   }
   __syncthreads();
+  const double sc = xnorm2 ? (*xnorm2 > 1e-300 ? 1.0 / sqrt(*xnorm2) : 0.0) : 1.0;
   for (int e = threadIdx.x; e < 9 * nout; e += blockDim.x) {
     const int b = e / nout, q = e % nout;
-    xs[b][q] = x[(long)nb[b] * nout + q];
+    const T2 v = x[(long)nb[b] * nout + q];
+    xs[b][q] = xnorm2 ? mk<R>(R(sc * double(v.x)), R(sc * double(v.y))) : v;
   }
   __syncthreads();
+  if (xout)
+    for (int e = threadIdx.x; e < nout; e += blockDim.x) xout[(long)X * nout + e] = xs[0][e];
   // thread (q, i): row i of both flavours (each block element is read once and
   // used for the two flavour columns) over the pairs p = b * n2 + j with
   // p = q mod kApplyGroups
@@ -721,15 +729,14 @@ void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* 
 }
 
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
-                     double mubar_c, double epsbar, double m, hipStream_t st) {
+                     double mubar_c, double epsbar, double m, hipStream_t st, const double* xnorm2, void* xout) {
+  const dim3 blk(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv));
   if (prec == P64)
-    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), dim3(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv)), 0, st, g,
-                       (const double2*)D,
-                       (const double2*)Bo, (const double2*)x, (double2*)y, mubar_c, epsbar, m);
+    hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), blk, 0, st, g, (const double2*)D, (const double2*)Bo,
+                       (const double2*)x, (double2*)y, mubar_c, epsbar, m, xnorm2, (double2*)xout);
   else
-    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), dim3(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv)), 0, st, g,
-                       (const float2*)D,
-                       (const float2*)Bo, (const float2*)x, (float2*)y, mubar_c, epsbar, m);
+    hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), blk, 0, st, g, (const float2*)D, (const float2*)Bo,
+                       (const float2*)x, (float2*)y, mubar_c, epsbar, m, xnorm2, (float2*)xout);
 }
 
 void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo, const double2* x, double2* y, int k,

@@ -53,10 +53,11 @@ struct MGData {
   void* Boc = nullptr;
   size_t ncoarse = 0;   // complex elements of a coarse doublet vector
   std::vector<void*> cV;  // coarse basis (cycle precision), coarse_iters + 1
-  void* cW = nullptr;
+  void* cW = nullptr;     // Arnoldi work vectors: step j's new direction in cW (j even) or cW2 (odd)
+  void* cW2 = nullptr;
   void* cR = nullptr;
   void* cT = nullptr;     // coarse residual of the restarted solve
-  void* cX = nullptr;     // coarse solution (cW is the Arnoldi work vector)
+  void* cX = nullptr;     // coarse solution
   double* dH = nullptr;   // Hessenberg columns, coarse_iters x (coarse_iters+1) complex
   double* dsub = nullptr; // subdiagonal norms^2
   double* dy = nullptr;   // least-squares coefficients
@@ -117,7 +118,9 @@ static double coarse_bytes(const MGData* M) {
 // ---- coarse solve: GMRES on the device ------------------------------------
 // One GMRES(kc) cycle from zero on D'_c y = src; *src2 = ||src||^2 on the device.
 // The solution is written (accumulate = 0) or added (1) to sol, which must not be
-// cW, the Arnoldi work vector.
+// cW or cW2, the Arnoldi work vectors.  Step j's direction w_j is orthogonalised in
+// place; the coarse stencil of step j + 1 reads it, normalises it as it reads, and
+// stores the basis vector V_{j+1} (the last w is never normalised: no step reads it).
 static void coarse_gmres_cycle(ndtm_ctx* c, MGData* M, const void* src, const double* src2, void* sol,
                                int accumulate, double m, double eps, hipStream_t st) {
   const int cp = M->cprec;
@@ -126,19 +129,23 @@ static void coarse_gmres_cycle(ndtm_ctx* c, MGData* M, const void* src, const do
   const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
   vscale_inv_sqrt(cp, M->cV[0], src, src2, n, st);
   for (int j = 0; j < kc; ++j) {
+    void* w = (j & 1) ? M->cW2 : M->cW;
     {
       ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
-      mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[j], M->cW, mubar_c, eps, m, st);
+      if (j == 0)
+        mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cV[0], w, mubar_c, eps, m, st);
+      else
+        mg_coarse_apply(cp, M->g, M->Dc, M->Boc, (j & 1) ? M->cW : M->cW2, w, mubar_c, eps, m, st, M->dsub + j - 1,
+                        M->cV[j]);
     }
     // classical Gram-Schmidt with one reorthogonalisation; the second pass's
     // coefficients go to their own Hessenberg array, added to the first by the
     // least-squares step
     double* hcol = M->dH + 2 * (size_t)j * (kc + 1);
     double* hcol2 = M->dh2 + 2 * (size_t)j * (kc + 1);
-    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, M->cW, n, c->vred, hcol, st);
-    vmulti_axpy_multidot(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol, n, c->vred, hcol2, st);
-    vmulti_axpy_norm_dev(cp, M->cW, (const void* const*)M->cV.data(), j + 1, hcol2, n, c->vred, M->dsub + j, st);
-    vscale_inv_sqrt(cp, M->cV[j + 1], M->cW, M->dsub + j, n, st);
+    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, w, n, c->vred, hcol, st);
+    vmulti_axpy_multidot(cp, w, (const void* const*)M->cV.data(), j + 1, hcol, n, c->vred, hcol2, st);
+    vmulti_axpy_norm_dev(cp, w, (const void* const*)M->cV.data(), j + 1, hcol2, n, c->vred, M->dsub + j, st);
   }
   hess_lsq(M->dH, M->dh2, kc + 1, kc, src2, M->dsub, M->dy, st);
   vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, accumulate, n, st);
@@ -594,6 +601,7 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     if (!M->cV[j]) return fail(c, NDTM_ENOMEM, "mg_setup: coarse basis");
   }
   M->cW = mg_alloc(M, M->ncoarse * csz(M->cprec));
+  M->cW2 = mg_alloc(M, M->ncoarse * csz(M->cprec));
   M->cR = mg_alloc(M, M->ncoarse * csz(M->cprec));
   M->cT = mg_alloc(M, M->ncoarse * csz(M->cprec));
   M->cX = mg_alloc(M, M->ncoarse * csz(M->cprec));
@@ -604,7 +612,7 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
   M->dh2 = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
   M->dpart = (double*)mg_alloc(M, 6 * (size_t)hop_grid(c->g) * sizeof(double));
-  if (!M->dpart || !M->dh2 || !M->cW || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
+  if (!M->dpart || !M->dh2 || !M->cW || !M->cW2 || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
   if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");

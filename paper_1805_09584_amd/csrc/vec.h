@@ -72,8 +72,11 @@ void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* 
 constexpr int kMultiMax = 8;
 void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo, const double2* x, double2* y, int k,
                            const double* m, double mubar_c, double epsbar, hipStream_t st);
+// y = D'_c(m) x; with xnorm2 the input is x / sqrt(*xnorm2), and xout (if given) receives that
+// scaled input (every coarse site written once)
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
-                     double mubar_c, double epsbar, double m, hipStream_t st);
+                     double mubar_c, double epsbar, double m, hipStream_t st, const double* xnorm2 = nullptr,
+                     void* xout = nullptr);
 // fill a full doublet field (both halves) with complex Gaussian numbers from a counter-based hash
 void mg_random_fill(const MGGeom& m, int vh, double2* fe, double2* fo, unsigned long long seed, hipStream_t st);
 
