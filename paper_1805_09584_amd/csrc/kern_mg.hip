@@ -357,7 +357,7 @@ __device__ __forceinline__ typename C2<R>::T mk(R x, R y) {
   return v;
 }
 
-constexpr int kGroups = 4;       // thread groups per coarse site in the restriction
+constexpr int kGroups = 8;       // thread groups per coarse site in the restriction
 constexpr int kApplyGroups = 8;  // thread groups per coarse site in the coarse stencil
 
 // element of component c at half-site h of a fine field in the cycle precision R
@@ -368,7 +368,7 @@ __device__ __forceinline__ long fine_idx(int c, int stride, long h) {
 }
 
 template <class R>
-__global__ __launch_bounds__(512) void restrict_k(MGGeom m, const typename C2<R>::T* P,
+__global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R>::T* P,
                                                   const typename C2<R>::T* fe, const typename C2<R>::T* fo,
                                                   typename C2<R>::T* vc) {
   using T2 = typename C2<R>::T;
