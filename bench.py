@@ -239,12 +239,15 @@ def copy_ceiling():
     return 10 * 2 * a.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def recorded_traffic(kernel_class):
+def recorded_traffic(kernel_class, dims):
     """HBM bytes per launch of the dominant kernel class from the committed counter
-    summary, if the stencil source is unchanged since the counters were taken."""
+    summary, if it was taken on this lattice (the 32x16x16x16 hybrid solve) and the
+    stencil source is unchanged since."""
     import hashlib
     import re
 
+    if tuple(dims) != (32, 16, 16, 16):
+        return None
     path = os.path.join(ROOT, "profiles", f"{kernel_class}_16x16x16x32_hybrid_counters.md")
     src = os.path.join(ROOT, "paper_1805_09584_amd", "csrc", "kern_dslash.hip")
     if not os.path.exists(path):
@@ -343,7 +346,7 @@ def main():
                    "lattice": list(dims), "n_shifts": len(cfg["shifts"]), "form": forms[0],
                    "kappa": synth.KAPPA, "mubar": synth.MUBAR, "epsbar": synth.EPSBAR, "link_amp": cfg["amp"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom, dims),
                      "launches": nl, "avg_launch_us": 1000.0 * ms / max(nl, 1),
                      "alg_bytes_per_launch": by / max(nl, 1)},
         "kernel_classes": classes,
