@@ -141,6 +141,7 @@ def run_form(ctx, nd, bd, xs, form, steps, warmup, profile):
         "worst_true_res": max(max(r["true_res"]) for r in reps),
         "mms_iterations": last["mms_iterations"],
         "mg_iterations": [it for it, m in zip(last["iterations"], last["method"]) if m != 0],
+        "iterations_per_shift": list(last["iterations"]),
         "guess_res": [g for g, m in zip(last["guess_res"], last["method"]) if m != 0],
         "guess_kind": [g for g, m in zip(last["guess_kind"], last["method"]) if m != 0],
         "t_mms_ms": last["t_mms_ms"], "t_mg_ms": last["t_mg_ms"], "t_guess_ms": last["t_guess_ms"],
@@ -300,8 +301,19 @@ def main():
 
     coarse_batched = coarse_batched_block(ctx, nd) if setup_ms is not None else None
     results = {}
+    spectrum = None
     for f in forms:
         results[f], _ = run_form(ctx, nd, bd, xs, f, args.steps, args.warmup, profile=False)
+        if f == "plain":
+            # extreme eigenvalues of Q^2 for this field from the Lanczos matrix of the plain
+            # solve's recorded CG coefficients (available when the solve fits one block of
+            # deferred updates)
+            try:
+                lo, hi = ctx.ndtm_spectrum_estimate()
+                spectrum = {"lambda_min": lo, "lambda_max": hi, "source": "Lanczos matrix of the plain "
+                            "multi-shift CG coefficients (base shift removed)"}
+            except nd.NdtmError:
+                spectrum = None
     # roofline: the same K steps of the headline form again, with every kernel
     # class timed by HIP events on the launch stream (the event pairs add a few
     # percent, so the headline value comes from the unprofiled pass above)
@@ -351,6 +363,7 @@ def main():
                      "alg_bytes_per_launch": by / max(nl, 1)},
         "kernel_classes": classes,
         "mg_kernel_classes": mg_classes,
+        "spectrum_q2": spectrum,
         "coarse_batched": coarse_batched,
         "ms_per_step_profiled": prof_run["ms_per_solve"],
         "forms": results,
