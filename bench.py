@@ -195,16 +195,16 @@ def coarse_batched_block(ctx, nd, reps=50):
     ms = [0.009 * (1 if r % 2 == 0 else -1) * (r // 2 + 1) for r in range(k)]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed(fn):
+    def timed(fn, n=reps):
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
         e0.record()
-        for _ in range(reps):
+        for _ in range(n):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1000.0 / reps
+        return e0.elapsed_time(e1) * 1000.0 / n
 
     def singles():
         for r in range(k):
@@ -212,6 +212,16 @@ def coarse_batched_block(ctx, nd, reps=50):
 
     t_multi = timed(lambda: ctx.ndtm_mg_coarse_apply_multi(xc, ms, out=yc))
     t_single = timed(singles)
+
+    # the coarse solve (one GMRES(coarse_iters) cycle from zero per system): the 8 systems
+    # together in FP64, the batched stencil in every Arnoldi step, against 8 one-system
+    # solves in the cycle precision
+    def solve_singles():
+        for r in range(k):
+            ctx.ndtm_mg_coarse_solve(xc[r], ms[r])
+
+    t_solve_multi = timed(lambda: ctx.ndtm_mg_coarse_solve_multi(xc, ms, out=yc), 10)
+    t_solve_single = timed(solve_singles, 10)
     n2 = 2 * Nv
     block_bytes = Vc * (9 * n2 * n2 + 2 * Nv * Nv) * 16.0
     vec_bytes = 2 * k * Vc * 2 * n2 * 16.0
@@ -220,7 +230,10 @@ def coarse_batched_block(ctx, nd, reps=50):
             "us_batched": t_multi, "us_one_system_each": t_single,
             "speedup": t_single / t_multi,
             "batched_gbs": (block_bytes + vec_bytes) / (t_multi * 1e-6) / 1e9,
-            "batched_tflops": flops / (t_multi * 1e-6) / 1e12}
+            "batched_tflops": flops / (t_multi * 1e-6) / 1e12,
+            "solve": {"us_batched_f64": t_solve_multi, "us_one_system_each_cycle_precision": t_solve_single,
+                      "note": "one GMRES cycle from zero per system; the one-system solves run in the "
+                              "cycle precision (FP32 by default), the batched one in FP64"}}
 
 
 def copy_ceiling():

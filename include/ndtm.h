@@ -179,6 +179,22 @@ int ndtm_mg_coarse_apply_multi(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, 
  * is above coarse_tol (when that is > 0, at most coarse_cycles cycles). */
 int ndtm_mg_coarse_solve(ndtm_ctx* ctx, void* xc_dev, const void* bc_dev, double m, void* stream);
 
+/* x_r ~ D'_c(m_r)^-1 b_r for k systems at once (1 <= k <= 8), FP64, by the same
+ * algorithm as ndtm_mg_coarse_solve per system: coarse_iters GMRES iterations from
+ * zero, restarted on the true coarse residual while it is above coarse_tol (when
+ * that is > 0, at most coarse_cycles cycles; a converged system stops).  Each
+ * Arnoldi step applies the coarse operator to the k basis vectors in one
+ * matrix-core launch (as ndtm_mg_coarse_apply_multi): the coarse blocks are read
+ * once for all systems (section 3.2; the coarse systems of the shifts and signs).
+ * xc, bc: the k coarse vectors back to back, complex128 [k][Vc][2][2 N_v], device,
+ * not aliased; m: k host doubles.  The library keeps its workspace (about
+ * (coarse_iters + 3) k coarse vectors).  Same result as k calls of
+ * ndtm_mg_coarse_solve with an FP64 cycle (precision NDTM_PREC_F64) up to rounding.
+ * Errors: NDTM_ESTATE without a multigrid setup, NDTM_EINVAL for k out of range or
+ * null or aliased pointers, NDTM_ENOMEM if the workspace cannot be allocated. */
+int ndtm_mg_coarse_solve_multi(ndtm_ctx* ctx, void* xc_dev, const void* bc_dev, int k, const double* m,
+                               void* stream);
+
 /* ---- solve ------------------------------------------------------------- */
 typedef struct {
   double tol;          /* target true relative residual per shift (1e-10) */

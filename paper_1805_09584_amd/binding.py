@@ -101,6 +101,7 @@ def load_library():
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
+        "ndtm_mg_coarse_solve_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
         "ndtm_solve_default_params": (None, [C.POINTER(SolveParams)]),
         "ndtm_solve": (i, [vp, C.POINTER(vp), vp, C.POINTER(SolveParams), C.POINTER(SolveReport), vp]),
         "ndtm_zolotarev": (i, [i, d, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
@@ -264,6 +265,14 @@ class Context:
         out = torch.empty_like(bc)
         self._check(self.lib.ndtm_mg_coarse_solve(self.h, _ptr(out), _ptr(bc), float(m), _stream()))
         return out
+
+    def ndtm_mg_coarse_solve_multi(self, bc, ms, out=None):
+        """D'_c(m_r)^-1 b_r for the k systems stacked in bc (complex128 CUDA (k, Vc, 2, 2Nv)), FP64."""
+        k = bc.shape[0]
+        mm = (C.c_double * k)(*[float(v) for v in ms])
+        x = torch.empty_like(bc) if out is None else out
+        self._check(self.lib.ndtm_mg_coarse_solve_multi(self.h, _ptr(x), _ptr(bc), int(k), mm, _stream()))
+        return x
 
     # -- solve ----------------------------------------------------------------
     @staticmethod

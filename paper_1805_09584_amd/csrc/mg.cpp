@@ -851,4 +851,94 @@ int ndtm_mg_coarse_apply_multi(ndtm_ctx* c, void* yc, const void* xc, int k, con
   return NDTM_OK;
 }
 
+
+// k coarse systems D'_c(m_r) x_r = b_r at once, FP64 (section 3.2: the coarse
+// systems of several shifts and signs share the coarse blocks).  Per system the
+// algorithm is the single-system coarse solve's: GMRES(coarse_iters) from zero,
+// restarted on the true coarse residual while it is above coarse_tol (at most
+// coarse_cycles cycles; one cycle when coarse_tol = 0).  Each Arnoldi step applies
+// the coarse operator to the k current basis vectors in one matrix-core launch; the
+// Gram-Schmidt passes and the least squares stay per system.  A system whose
+// residual has converged (or turned non-finite) takes no further cycles.
+int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, const double* m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_solve_multi: no multigrid setup");
+  if (!xc || !bc || !m || xc == bc) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: null or aliased pointer");
+  if (k < 1 || k > kMultiMax) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: 1 <= k <= 8");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MGData* M = c->mg;
+  const size_t n = M->ncoarse;
+  const int kc = M->prm.coarse_iters;
+  const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+  // basis blocks V_j = [k][n] (j = 0..kc), work block W, residual block R; per system
+  // scalars: H, H2 (Hessenberg passes), sub, y, beta = {||b||^2, ||r||^2}
+  const size_t hsz = 2 * (size_t)(kc + 1) * (kc + 1), per = 2 * hsz + (kc + 1) + 2 * (kc + 1) + 2;
+  double2* V = static_cast<double2*>(ws_get(c, "cm_V", (size_t)(kc + 1) * k * n * sizeof(double2)));
+  double2* W = static_cast<double2*>(ws_get(c, "cm_W", (size_t)k * n * sizeof(double2)));
+  double2* R = static_cast<double2*>(ws_get(c, "cm_R", (size_t)k * n * sizeof(double2)));
+  double* sc = static_cast<double*>(ws_get(c, "cm_s", (size_t)k * per * sizeof(double)));
+  if (!V || !W || !R || !sc) return fail(c, NDTM_ENOMEM, "mg_coarse_solve_multi: workspace");
+  const double2* B = static_cast<const double2*>(bc);
+  double2* X = static_cast<double2*>(xc);
+  auto Hs = [&](int s) { return sc + (size_t)s * per; };
+  auto H2s = [&](int s) { return Hs(s) + hsz; };
+  auto subs = [&](int s) { return Hs(s) + 2 * hsz; };
+  auto ys = [&](int s) { return subs(s) + (kc + 1); };
+  auto betas = [&](int s) { return ys(s) + 2 * (kc + 1); };
+  auto Vj = [&](int j, int s) { return V + ((size_t)j * k + s) * n; };
+  for (int s = 0; s < k; ++s) vnorm2(P64, B + s * n, n, c->vred, betas(s), st);
+  std::vector<char> active(k, 1);
+  std::vector<double> tol2(k, 0.0);
+  const bool restart = M->prm.coarse_tol > 0.0;
+  const int cycles = restart ? std::max(1, M->prm.coarse_cycles) : 1;
+  for (int cyc = 0; cyc < cycles; ++cyc) {
+    for (int s = 0; s < k; ++s)
+      if (active[s])
+        vscale_inv_sqrt(P64, Vj(0, s), cyc == 0 ? (const void*)(B + s * n) : (const void*)(R + s * n),
+                        betas(s) + (cyc == 0 ? 0 : 1), n, st);
+    for (int j = 0; j < kc; ++j) {
+      mg_coarse_apply_multi(M->g, M->D64, M->Bo64, Vj(j, 0), W, k, m, mubar_c, c->epsbar, st);
+      for (int s = 0; s < k; ++s) {
+        if (!active[s]) continue;
+        std::vector<const void*> Vp(j + 1);
+        for (int i = 0; i <= j; ++i) Vp[i] = Vj(i, s);
+        double2* w = W + s * n;
+        double* hcol = Hs(s) + 2 * (size_t)j * (kc + 1);
+        double* hcol2 = H2s(s) + 2 * (size_t)j * (kc + 1);
+        vmultidot(P64, Vp.data(), j + 1, w, n, c->vred, hcol, st);
+        vmulti_axpy_multidot(P64, w, Vp.data(), j + 1, hcol, n, c->vred, hcol2, st);
+        vmulti_axpy_norm_dev(P64, w, Vp.data(), j + 1, hcol2, n, c->vred, subs(s) + j, st);
+        vscale_inv_sqrt(P64, Vj(j + 1, s), w, subs(s) + j, n, st);
+      }
+    }
+    for (int s = 0; s < k; ++s) {
+      if (!active[s]) continue;
+      std::vector<const void*> Vp(kc);
+      for (int i = 0; i < kc; ++i) Vp[i] = Vj(i, s);
+      hess_lsq(Hs(s), H2s(s), kc + 1, kc, betas(s) + (cyc == 0 ? 0 : 1), subs(s), ys(s), st);
+      vlincomb_dev(P64, X + s * n, Vp.data(), kc, ys(s), cyc > 0, n, st);
+    }
+    if (!restart || cyc + 1 == cycles) break;
+    // true residuals r = b - D' x of all systems (one launch), their norms on the host
+    mg_coarse_apply_multi(M->g, M->D64, M->Bo64, X, R, k, m, mubar_c, c->epsbar, st);
+    for (int s = 0; s < k; ++s) {
+      vaxpby(P64, R + s * n, make_double2(1, 0), B + s * n, make_double2(-1, 0), n, st);  // R = B - D'X
+      vnorm2(P64, R + s * n, n, c->vred, betas(s) + 1, st);
+    }
+    for (int s = 0; s < k; ++s)
+      NDTM_HIP(c, hipMemcpyAsync(c->hscal + 2 * s, betas(s), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    int any = 0;
+    for (int s = 0; s < k; ++s) {
+      const double b2 = c->hscal[2 * s], r2 = c->hscal[2 * s + 1];
+      tol2[s] = M->prm.coarse_tol * M->prm.coarse_tol * b2;
+      if (active[s] && (!(b2 > 0.0) || !(r2 > tol2[s]) || !std::isfinite(r2))) active[s] = 0;
+      any |= active[s];
+    }
+    if (!any) break;
+  }
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
 }  // extern "C"

@@ -337,3 +337,51 @@ def test_coarse_apply_multi_config2_shape(nd):
         rc = ctx.lib.ndtm_mg_coarse_apply_multi(ctx.h, y9.data_ptr(), x9.data_ptr(), kbad, m9, None)
         assert rc == -1, kbad
     ctx.close()
+
+
+def test_coarse_solve_multi(nd):
+    """k coarse systems solved together (one matrix-core stencil launch per Arnoldi
+    step) against k one-system coarse solves with an FP64 cycle: one GMRES cycle from
+    zero agrees to rounding, with the same residual under the oracle's dense coarse
+    operator; restarted to coarse_tol every system reaches it; bad k and aliased
+    pointers are refused."""
+    dims, block, Nv, k = (8, 8, 8, 8), (4, 4, 4, 4), 8, 5
+    print(f"case dims={dims} Nv={Nv} k={k} batched coarse solve", flush=True)
+    lat, op, ctx, P, agg, Vc = _setup(nd, dims, block, Nv)
+    Dc = omg.coarse_wilson_dense(lat, op.a, P, agg, Vc)
+    Bo = omg.odd_projector_coarse(lat, P, agg, Vc)
+    ms = [0.0, 0.0316, -0.0316, 0.01, 0.2][:k]
+    bc = synth.gaussian_vectors((k, Vc, 2, 2 * Nv), 10)
+
+    def res(x, r):
+        return rel_err(omg.coarse_nd_apply(Dc, Bo, x, Nv, MB, EB, m=ms[r]), bc[r])
+
+    got = host(ctx.ndtm_mg_coarse_solve_multi(dev(bc), ms))
+    for r in range(k):
+        single = host(ctx.ndtm_mg_coarse_solve(dev(bc[r].copy()), ms[r]))
+        rg, rs = res(got[r], r), res(single, r)
+        print("system", r, "m", ms[r], "residual batched", rg, "single", rs, flush=True)
+        assert rel_err(got[r], single) < 1e-9, r
+        assert abs(rg - rs) <= 1e-8 * rs + 1e-14, r
+        assert rg < 1.0, r
+    # restarted on the true coarse residual down to coarse_tol
+    tv = synth.gaussian_vectors((Nv, lat.V, 4, 3), 32)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, coarse_tol=1e-8, coarse_cycles=60),
+                      test_vectors=dev(tv))
+    P2 = omg.build_prolongator(tv, dims, block)
+    Dc = omg.coarse_wilson_dense(lat, op.a, P2, agg, Vc)
+    Bo = omg.odd_projector_coarse(lat, P2, agg, Vc)
+    got = host(ctx.ndtm_mg_coarse_solve_multi(dev(bc), ms))
+    for r in range(k):
+        single = host(ctx.ndtm_mg_coarse_solve(dev(bc[r].copy()), ms[r]))
+        rg, rs = res(got[r], r), res(single, r)
+        print("restarted system", r, "residual batched", rg, "single", rs, flush=True)
+        assert rg <= 2e-8 and rs <= 2e-8, r
+    import ctypes
+    x = dev(bc)
+    y = x.clone()
+    m9 = (ctypes.c_double * 9)()
+    for kbad in (0, 9):
+        assert ctx.lib.ndtm_mg_coarse_solve_multi(ctx.h, y.data_ptr(), x.data_ptr(), kbad, m9, None) == -1, kbad
+    assert ctx.lib.ndtm_mg_coarse_solve_multi(ctx.h, x.data_ptr(), x.data_ptr(), k, m9, None) == -1
+    ctx.close()
