@@ -3,6 +3,8 @@
 // one partial per block, and are finalised in a fixed order (deterministic).
 // Coefficients of the Krylov updates are read from device memory so that a
 // whole fixed-length Arnoldi loop runs without a host round trip.
+#include <type_traits>
+
 #include "vec.h"
 #include "reduce.h"
 
@@ -16,6 +18,13 @@ constexpr int kMaxBasis = 40;
 template <class T2>
 struct Basis {
   const T2* v[kMaxBasis];
+  __device__ __forceinline__ const T2* at(int j) const { return v[j]; }
+};
+// k systems' bases back to back: vector j of this system at base + j ldv
+struct StridedBasis {
+  const double2* base;
+  size_t ldv;
+  __device__ __forceinline__ const double2* at(int j) const { return base + j * ldv; }
 };
 
 // reductions: at most 256 blocks (the completion of each block costs a release
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(256) void axpby_k(T2* y, double2 a, const double* a
 
 // y *= 1 / sqrt(*nrm2)
 template <class T2>
-__global__ __launch_bounds__(256) void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t n) {
+__device__ __forceinline__ void scale_inv_sqrt_body(T2* y, const T2* x, const double* nrm2, size_t n) {
   const double s = *nrm2 > 1e-300 ? 1.0 / sqrt(*nrm2) : 0.0;
   GRID_LOOP(i, n) {
     const double2 v = ld2(x, i);
@@ -191,8 +200,8 @@ __global__ __launch_bounds__(256) void dot_k(const T2* x, const T2* y, size_t n,
   last_block_sum(ws, 2, dst);
 }
 
-template <class T2, int KM>
-__global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* ws, double* dst) {
+template <class T2, int KM, class B>
+__device__ __forceinline__ void multidot_body(const B& V, int k, const T2* w, size_t n, double* ws, double* dst) {
   double* part = ws + 8;
   double re[KM], im[KM];
 #pragma unroll
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* 
 #pragma unroll
     for (int j = 0; j < KM; ++j)
       if (j < k) {
-        const double2 v = ld2(V.v[j], i);
+        const double2 v = ld2(V.at(j), i);
         re[j] += v.x * wi.x + v.y * wi.y;
         im[j] += v.x * wi.y - v.y * wi.x;
       }
@@ -222,9 +231,9 @@ __global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* 
 
 // w -= sum_j coef[j] V_j, then <V_j, w> for j < k (one pass: the first Gram-Schmidt
 // pass's update and the second pass's overlaps; the overlaps use the stored w)
-template <class T2, int KM>
-__global__ __launch_bounds__(256) void multi_axpy_dot_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n,
-                                                        double* ws, double* dst) {
+template <class T2, int KM, class B>
+__device__ __forceinline__ void multi_axpy_dot_body(T2* w, const B& V, int k, const double* coef, size_t n,
+                                                    double* ws, double* dst) {
   double* part = ws + 8;
   double re[KM], im[KM];
 #pragma unroll
@@ -236,7 +245,7 @@ __global__ __launch_bounds__(256) void multi_axpy_dot_k(T2* w, Basis<T2> V, int 
 #pragma unroll
     for (int j = 0; j < KM; ++j)
       if (j < k) {
-        v[j] = ld2(V.v[j], i);
+        v[j] = ld2(V.at(j), i);
         const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), v[j]);
         acc.x -= t.x;
         acc.y -= t.y;
@@ -270,14 +279,14 @@ __global__ void finalize_k(const double* part, int nparts, double* dst, int dst_
 }
 
 // w -= sum_j coef[j] V_j and ||w||^2 into dst (single launch)
-template <class T2>
-__global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n, double* ws,
-                                  double* dst) {
+template <class T2, class B>
+__device__ __forceinline__ void multi_axpy_norm_body(T2* w, const B& V, int k, const double* coef, size_t n,
+                                                     double* ws, double* dst) {
   double s = 0;
   GRID_LOOP(i, n) {
     double2 acc = ld2(w, i);
     for (int j = 0; j < k; ++j) {
-      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.v[j], i));
+      const double2 t = cm(make_double2(coef[2 * j], coef[2 * j + 1]), ld2(V.at(j), i));
       acc.x -= t.x;
       acc.y -= t.y;
     }
@@ -406,6 +415,58 @@ __global__ void hess_lsq_k(const double* H, const double* H2, int ldh, int m, co
   }
 }
 
+// ---- kernels: the bodies above, one system per launch or k systems per launch ----
+template <class T2>
+__global__ __launch_bounds__(256) void scale_inv_sqrt_k(T2* y, const T2* x, const double* nrm2, size_t n) {
+  scale_inv_sqrt_body(y, x, nrm2, n);
+}
+template <class T2, int KM>
+__global__ __launch_bounds__(256) void multidot_k(Basis<T2> V, int k, const T2* w, size_t n, double* ws, double* dst) {
+  multidot_body<T2, KM>(V, k, w, n, ws, dst);
+}
+template <class T2, int KM>
+__global__ __launch_bounds__(256) void multi_axpy_dot_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n,
+                                                        double* ws, double* dst) {
+  multi_axpy_dot_body<T2, KM>(w, V, k, coef, n, ws, dst);
+}
+template <class T2>
+__global__ __launch_bounds__(256) void multi_axpy_norm_k(T2* w, Basis<T2> V, int k, const double* coef, size_t n,
+                                                         double* ws, double* dst) {
+  multi_axpy_norm_body<T2>(w, V, k, coef, n, ws, dst);
+}
+
+// k systems per launch (system s = blockIdx.y): basis vector i of system s at
+// V + i ldv + s n, its vector w + s n, its coefficients coef + s cs, its reduction
+// workspace ws + s wss (own counter and partials), its outputs dst + s ds
+struct SysArgs {
+  size_t ldv, wss, cs, ds;
+};
+template <int KM>
+__global__ __launch_bounds__(256) void multidot_sys_k(const double2* V, int cnt, const double2* w, size_t n,
+                                                      double* ws, double* dst, SysArgs a) {
+  const size_t s = blockIdx.y;
+  multidot_body<double2, KM>(StridedBasis{V + s * n, a.ldv}, cnt, w + s * n, n, ws + s * a.wss, dst + s * a.ds);
+}
+template <int KM>
+__global__ __launch_bounds__(256) void multi_axpy_dot_sys_k(double2* w, const double2* V, int cnt, const double* coef,
+                                                            size_t n, double* ws, double* dst, SysArgs a) {
+  const size_t s = blockIdx.y;
+  multi_axpy_dot_body<double2, KM>(w + s * n, StridedBasis{V + s * n, a.ldv}, cnt, coef + s * a.cs, n,
+                                   ws + s * a.wss, dst + s * a.ds);
+}
+__global__ __launch_bounds__(256) void multi_axpy_norm_sys_k(double2* w, const double2* V, int cnt,
+                                                             const double* coef, size_t n, double* ws, double* dst,
+                                                             SysArgs a) {
+  const size_t s = blockIdx.y;
+  multi_axpy_norm_body<double2>(w + s * n, StridedBasis{V + s * n, a.ldv}, cnt, coef + s * a.cs, n, ws + s * a.wss,
+                                dst + s * a.ds);
+}
+__global__ __launch_bounds__(256) void scale_inv_sqrt_sys_k(double2* y, const double2* x, const double* nrm2,
+                                                            size_t n, size_t ds) {
+  const size_t s = blockIdx.y;
+  scale_inv_sqrt_body(y + s * n, x + s * n, nrm2 + s * ds, n);
+}
+
 template <class T2>
 Basis<T2> basis(const void* const* V, int k) {
   Basis<T2> B;
@@ -531,6 +592,42 @@ static void vmultidot_t(const void* const* V, int k, const void* w, size_t n, do
 void vmultidot(int prec, const void* const* V, int k, const void* w, size_t n, double* part, double* dst,
                hipStream_t st) {
   DISPATCH(prec, vmultidot_t, V, k, w, n, part, dst, st);
+}
+
+// ---- k systems per launch (FP64) ----
+template <class F>
+static void by_km(int cnt, F f) {
+  if (cnt <= 4) f(std::integral_constant<int, 4>{});
+  else if (cnt <= 8) f(std::integral_constant<int, 8>{});
+  else if (cnt <= 16) f(std::integral_constant<int, 16>{});
+  else if (cnt <= 24) f(std::integral_constant<int, 24>{});
+  else f(std::integral_constant<int, kMaxBasis>{});
+}
+void vmultidot_sys(const double2* V, size_t ldv, int cnt, const double2* w, size_t n, int k, double* ws, size_t wss,
+                   double* dst, size_t ds, hipStream_t st) {
+  const SysArgs a{ldv, wss, 0, ds};
+  const dim3 g(rgrid(n), k);
+  by_km(cnt, [&](auto km) {
+    hipLaunchKernelGGL((multidot_sys_k<decltype(km)::value>), g, dim3(kVB), 0, st, V, cnt, w, n, ws, dst, a);
+  });
+}
+void vmulti_axpy_multidot_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs,
+                              size_t n, int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st) {
+  const SysArgs a{ldv, wss, cs, ds};
+  const dim3 g(rgrid(n), k);
+  by_km(cnt, [&](auto km) {
+    hipLaunchKernelGGL((multi_axpy_dot_sys_k<decltype(km)::value>), g, dim3(kVB), 0, st, w, V, cnt, coef, n, ws, dst,
+                       a);
+  });
+}
+void vmulti_axpy_norm_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs, size_t n,
+                          int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st) {
+  const SysArgs a{ldv, wss, cs, ds};
+  hipLaunchKernelGGL(multi_axpy_norm_sys_k, dim3(rgrid(n), k), dim3(kVB), 0, st, w, V, cnt, coef, n, ws, dst, a);
+}
+void vscale_inv_sqrt_sys(double2* y, const double2* x, const double* nrm2, size_t ds, size_t n, int k,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(scale_inv_sqrt_sys_k, dim3(vgrid(n), k), dim3(kVB), 0, st, y, x, nrm2, n, ds);
 }
 
 template <class T2>

@@ -857,8 +857,9 @@ int ndtm_mg_coarse_apply_multi(ndtm_ctx* c, void* yc, const void* xc, int k, con
 // algorithm is the single-system coarse solve's: GMRES(coarse_iters) from zero,
 // restarted on the true coarse residual while it is above coarse_tol (at most
 // coarse_cycles cycles; one cycle when coarse_tol = 0).  Each Arnoldi step applies
-// the coarse operator to the k current basis vectors in one matrix-core launch; the
-// Gram-Schmidt passes and the least squares stay per system.  A system whose
+// the coarse operator to the k current basis vectors in one matrix-core launch and
+// takes the Gram-Schmidt passes of all k systems in one launch each; the least
+// squares and the solution update stay per system.  A system whose
 // residual has converged (or turned non-finite) takes no further cycles.
 int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, const double* m, void* stream) {
   if (!c) return NDTM_EINVAL;
@@ -877,7 +878,10 @@ int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, con
   double2* W = static_cast<double2*>(ws_get(c, "cm_W", (size_t)k * n * sizeof(double2)));
   double2* R = static_cast<double2*>(ws_get(c, "cm_R", (size_t)k * n * sizeof(double2)));
   double* sc = static_cast<double*>(ws_get(c, "cm_s", (size_t)k * per * sizeof(double)));
-  if (!V || !W || !R || !sc) return fail(c, NDTM_ENOMEM, "mg_coarse_solve_multi: workspace");
+  // per system reduction workspace: counter and the partials of up to kc + 1 complex sums
+  const size_t wss = 8 + 2 * (size_t)(kc + 1) * 256;
+  double* red = static_cast<double*>(ws_get(c, "cm_red", (size_t)k * wss * sizeof(double)));
+  if (!V || !W || !R || !sc || !red) return fail(c, NDTM_ENOMEM, "mg_coarse_solve_multi: workspace");
   const double2* B = static_cast<const double2*>(bc);
   double2* X = static_cast<double2*>(xc);
   auto Hs = [&](int s) { return sc + (size_t)s * per; };
@@ -898,18 +902,13 @@ int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, con
                         betas(s) + (cyc == 0 ? 0 : 1), n, st);
     for (int j = 0; j < kc; ++j) {
       mg_coarse_apply_multi(M->g, M->D64, M->Bo64, Vj(j, 0), W, k, m, mubar_c, c->epsbar, st);
-      for (int s = 0; s < k; ++s) {
-        if (!active[s]) continue;
-        std::vector<const void*> Vp(j + 1);
-        for (int i = 0; i <= j; ++i) Vp[i] = Vj(i, s);
-        double2* w = W + s * n;
-        double* hcol = Hs(s) + 2 * (size_t)j * (kc + 1);
-        double* hcol2 = H2s(s) + 2 * (size_t)j * (kc + 1);
-        vmultidot(P64, Vp.data(), j + 1, w, n, c->vred, hcol, st);
-        vmulti_axpy_multidot(P64, w, Vp.data(), j + 1, hcol, n, c->vred, hcol2, st);
-        vmulti_axpy_norm_dev(P64, w, Vp.data(), j + 1, hcol2, n, c->vred, subs(s) + j, st);
-        vscale_inv_sqrt(P64, Vj(j + 1, s), w, subs(s) + j, n, st);
-      }
+      // Gram-Schmidt of all k systems per launch (a finished system's results go unused)
+      double* hcol = Hs(0) + 2 * (size_t)j * (kc + 1);
+      double* hcol2 = H2s(0) + 2 * (size_t)j * (kc + 1);
+      vmultidot_sys(V, (size_t)k * n, j + 1, W, n, k, red, wss, hcol, per, st);
+      vmulti_axpy_multidot_sys(W, V, (size_t)k * n, j + 1, hcol, per, n, k, red, wss, hcol2, per, st);
+      vmulti_axpy_norm_sys(W, V, (size_t)k * n, j + 1, hcol2, per, n, k, red, wss, subs(0) + j, per, st);
+      vscale_inv_sqrt_sys(Vj(j + 1, 0), W, subs(0) + j, per, n, k, st);
     }
     for (int s = 0; s < k; ++s) {
       if (!active[s]) continue;

@@ -30,6 +30,19 @@ void vlincomb_dev(int prec, void* y, const void* const* V, int k, const double* 
 // must not overlap coef)
 void vmulti_axpy_multidot(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* part,
                           double* dst, hipStream_t st);
+// The Gram-Schmidt steps for k systems in one launch each (FP64; system s = 0..k-1): basis
+// vector i of system s at V + i ldv + s n, its vector w + s n, its coefficients coef + s cs,
+// its reduction workspace ws + s wss (its own counter and partials: wss >= 8 + 2 cnt * 256),
+// its outputs dst + s ds.  Per system the same arithmetic, in the same order, as the
+// one-system calls.
+void vmultidot_sys(const double2* V, size_t ldv, int cnt, const double2* w, size_t n, int k, double* ws, size_t wss,
+                   double* dst, size_t ds, hipStream_t st);
+void vmulti_axpy_multidot_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs,
+                              size_t n, int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st);
+void vmulti_axpy_norm_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs, size_t n,
+                          int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st);
+void vscale_inv_sqrt_sys(double2* y, const double2* x, const double* nrm2, size_t ds, size_t n, int k,
+                         hipStream_t st);
 // w -= sum_j coef[j] V_j, then ||w||^2 into dst[0] (one launch)
 void vmulti_axpy_norm_dev(int prec, void* w, const void* const* V, int k, const double* coef, size_t n, double* ws,
                           double* dst, hipStream_t st);
