@@ -385,3 +385,20 @@ def test_coarse_solve_multi(nd):
         assert ctx.lib.ndtm_mg_coarse_solve_multi(ctx.h, y.data_ptr(), x.data_ptr(), kbad, m9, None) == -1, kbad
     assert ctx.lib.ndtm_mg_coarse_solve_multi(ctx.h, x.data_ptr(), x.data_ptr(), k, m9, None) == -1
     ctx.close()
+
+
+def test_coarse_solve_multi_config2_shape(nd):
+    """At the 16^3x32 shape (512 coarse sites, 2 N_v = 48) the batched coarse solve of
+    8 systems matches 8 one-system solves with an FP64 cycle."""
+    dims, block, Nv = (32, 16, 16, 16), (4, 4, 4, 4), 24
+    print("case c2 shape batched coarse solve", flush=True)
+    lat, op, ctx, P, agg, Vc = _setup(nd, dims, block, Nv, seed=12)
+    ms = [np.sqrt(s) * sg for s in (8.111e-5, 2.848e-5, 1e-5, 2.31e-4) for sg in (1, -1)]
+    bc = synth.gaussian_vectors((8, Vc, 2, 2 * Nv), 11)
+    got = host(ctx.ndtm_mg_coarse_solve_multi(dev(bc), ms))
+    for r in range(8):
+        single = host(ctx.ndtm_mg_coarse_solve(dev(bc[r].copy()), ms[r]))
+        err = rel_err(got[r], single)
+        print("system", r, "rel diff", err, flush=True)
+        assert err < 1e-9, r
+    ctx.close()
