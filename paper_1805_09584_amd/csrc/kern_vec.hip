@@ -67,7 +67,6 @@ __device__ __forceinline__ double bsum(double v) {
   return s;
 }
 
-// grid-stride loop, unrolled so that several independent loads per thread are in flight
 // Reduction loops: a thread visits its grid-stride indices in increasing order, in
 // batches of kRB whose loads are all issued before the first is used (a plain loop,
 // even unrolled, waits on each load in turn).  The additions keep their order.
@@ -84,6 +83,8 @@ __device__ __forceinline__ double2 wide(float2 v) { return make_double2(v.x, v.y
 __device__ __forceinline__ double2 rounded(const double2*, double2 v) { return v; }
 __device__ __forceinline__ double2 rounded(const float2*, double2 v) { return make_double2((float)v.x, (float)v.y); }
 
+// grid-stride loop of the elementwise kernels (the unrolled copies each keep their own
+// bounds branch, so their loads do not overlap; the reductions use BATCH_LOOP)
 #define GRID_LOOP(i, n)  \
   _Pragma("unroll 4") for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (n); i += (size_t)gridDim.x * blockDim.x)
 
