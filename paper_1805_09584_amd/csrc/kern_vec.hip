@@ -325,19 +325,40 @@ __device__ double block_total(const double* part, int np) {
 template <class T2>
 __global__ __launch_bounds__(256) void mr_update_part_k(T2* z, T2* sv, const T2* t, const double* part, int np,
                                                         int update_s, size_t n) {
+  // the vectors stream in batches of kRB visits with all loads issued first; the first
+  // batch is in flight while omega is summed
+  T2 za[kRB], sa[kRB], ta[kRB];
+  size_t b0 = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  auto load = [&](size_t b) {
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      za[j] = BATCH_LD(z, b, j, n);
+      sa[j] = BATCH_LD(sv, b, j, n);
+      if (update_s) ta[j] = BATCH_LD(t, b, j, n);
+    }
+  };
+  if (b0 < n) load(b0);
   const double re = block_total(part, np);
   const double im = block_total(part + np, np);
   const double tt = block_total(part + 2 * (size_t)np, np);
   const double2 w = tt > 0 ? make_double2(re / tt, im / tt) : make_double2(0.0, 0.0);
-  GRID_LOOP(i, n) {
-    const double2 sval = ld2(sv, i);
-    const double2 zs = cm(w, sval);
-    const double2 zv = ld2(z, i);
-    st2(z, i, make_double2(zv.x + zs.x, zv.y + zs.y));
-    if (update_s) {
-      const double2 tw = cm(w, ld2(t, i));
-      st2(sv, i, make_double2(sval.x - tw.x, sval.y - tw.y));
+  while (b0 < n) {
+#pragma unroll
+    for (int j = 0; j < kRB; ++j) {
+      const size_t i = BATCH_IDX(b0, j);
+      if (i < n) {
+        const double2 sval = wide(sa[j]);
+        const double2 zs = cm(w, sval);
+        const double2 zv = wide(za[j]);
+        st2(z, i, make_double2(zv.x + zs.x, zv.y + zs.y));
+        if (update_s) {
+          const double2 tw = cm(w, wide(ta[j]));
+          st2(sv, i, make_double2(sval.x - tw.x, sval.y - tw.y));
+        }
+      }
     }
+    b0 += (size_t)kRB * gridDim.x * blockDim.x;
+    if (b0 < n) load(b0);
   }
 }
 
