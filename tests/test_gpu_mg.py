@@ -402,3 +402,34 @@ def test_coarse_solve_multi_config2_shape(nd):
         print("system", r, "rel diff", err, flush=True)
         assert err < 1e-9, r
     ctx.close()
+
+
+def test_coarse_solve_multi_fp32_cycle_and_one_system(nd):
+    """With the default FP32 cycle the batched solve still runs in FP64 on the FP64
+    coarse operator: one system (k = 1) agrees with the one-system FP32 solve to FP32
+    accuracy and with the oracle's residual of it."""
+    dims, block, Nv = (8, 8, 8, 8), (4, 4, 4, 4), 8
+    print("case batched coarse solve, k = 1, FP32 cycle setup", flush=True)
+    U = synth.gauge_field(dims, 31, 0.3)
+    lat = Lattice(dims, U)
+    op = NDOperator(lat, K, MB, EB)
+    tv = synth.gaussian_vectors((Nv, lat.V, 4, 3), 32)
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=1), test_vectors=dev(tv))
+    P = omg.build_prolongator(tv, dims, block)
+    agg = omg.aggregate_of_site(dims, block)
+    Vc = int(np.prod(omg.coarse_dims(dims, block)))
+    Dc = omg.coarse_wilson_dense(lat, op.a, P, agg, Vc)
+    Bo = omg.odd_projector_coarse(lat, P, agg, Vc)
+    m = 0.0316
+    bc = synth.gaussian_vectors((1, Vc, 2, 2 * Nv), 12)
+    got = host(ctx.ndtm_mg_coarse_solve_multi(dev(bc), [m]))[0]
+    single = host(ctx.ndtm_mg_coarse_solve(dev(bc[0].copy()), m))
+    rg = rel_err(omg.coarse_nd_apply(Dc, Bo, got, Nv, MB, EB, m=m), bc[0])
+    rs = rel_err(omg.coarse_nd_apply(Dc, Bo, single, Nv, MB, EB, m=m), bc[0])
+    print("k=1 rel diff", rel_err(got, single), "residual FP64 batched", rg, "FP32 single", rs, flush=True)
+    assert rel_err(got, single) < 1e-4
+    assert abs(rg - rs) <= 1e-3 * rs + 1e-6
+    ctx.close()
