@@ -367,12 +367,21 @@ __device__ __forceinline__ long fine_idx(int c, int stride, long h) {
   else return idx32(c, stride, h);
 }
 
+// Coarse site of a transfer block: XCD k = blockIdx % 8 takes one contiguous range of
+// coarse sites, so neighbouring aggregates, which share the cache lines of the fine
+// field, run on the same XCD and its L2 (dealt round-robin, each XCD fetched every
+// such line itself).  A bijection onto [0, gridDim) for any grid size.
+__device__ __forceinline__ int xcd_site(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, xcd = b & 7, loc = b >> 3;
+  return xcd * q + min(xcd, rem) + loc;
+}
+
 template <class R>
 __global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R>::T* P,
                                                   const typename C2<R>::T* fe, const typename C2<R>::T* fo,
                                                   typename C2<R>::T* vc) {
   using T2 = typename C2<R>::T;
-  const int X = blockIdx.x;
+  const int X = xcd_site(blockIdx.x, gridDim.x);
   const int Nv = m.Nv, n2 = 2 * Nv, nout = 2 * n2;
   __shared__ int ph[1024];
   __shared__ R red[kGroups][2][128];
@@ -381,10 +390,14 @@ __global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R
     ph[l] = (s.h << 1) | s.par;
   }
   __syncthreads();
+  // lane t of a group takes flavour t & 1 of output row t >> 1: the two flavour lanes
+  // of a row are neighbours, so their loads of the same element of P are one request
+  // (with the flavours n2 lanes apart they fell in different waves, and the second
+  // read could miss the L2)
   const int t = threadIdx.x % nout, q = threadIdx.x / nout;
   R ax = 0, ay = 0;
   if (q < kGroups) {
-    const int f = t / n2, i = t % n2, chi = i / Nv, k = i % Nv;
+    const int f = t & 1, i = t >> 1, chi = i / Nv, k = i % Nv;
     const T2* PX = P + (long)X * m.nloc * 12 * Nv;
     for (int l = q; l < m.nloc; l += kGroups) {
       const int hp = ph[l];
@@ -404,10 +417,12 @@ __global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R
   }
   __syncthreads();
   if (threadIdx.x < nout) {
+    // output element (f, i) = threadIdx.x = f n2 + i, held by lane 2 i + f
+    const int tt = 2 * (threadIdx.x % n2) + threadIdx.x / n2;
     R sx = 0, sy = 0;
     for (int g = 0; g < kGroups; ++g) {
-      sx += red[g][0][threadIdx.x];
-      sy += red[g][1][threadIdx.x];
+      sx += red[g][0][tt];
+      sy += red[g][1][tt];
     }
     vc[(long)X * nout + threadIdx.x] = mk<R>(sx, sy);
   }
@@ -418,7 +433,7 @@ __global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>:
                                                  const typename C2<R>::T* vc, typename C2<R>::T* fe,
                                                  typename C2<R>::T* fo) {
   using T2 = typename C2<R>::T;
-  const int X = blockIdx.x;
+  const int X = xcd_site(blockIdx.x, gridDim.x);
   const int Nv = m.Nv, n2 = 2 * Nv;
   __shared__ T2 cv[2 * 64];
   __shared__ int ph[1024];
