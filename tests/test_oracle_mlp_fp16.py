@@ -7,6 +7,10 @@
 * BF16 rounding: ties to even on exact midpoints, representable values kept,
   relative error <= 2^-8, and the BF16 forward equals the FP64 forward on
   weights and inputs that are already bfloat16 with activations that are too;
+* Adam (Kingma & Ba 2015): the bias-corrected first step is -lr g/(|g| + eps)
+  elementwise (m_hat = g, v_hat = g^2), a constant gradient gives that same step
+  at every t, and on a 1-D quadratic far from its minimum each step moves
+  towards it by between 0.9 lr and lr;
 * FP16 codec: round-trip error <= 2^-11 * scale; NumPy's float16 rounding is
   round-to-nearest-even on exactly representable midpoints.
 """
@@ -140,3 +144,52 @@ def test_forward_bf16_reduces_to_fp64_on_bf16_values():
     # the only differences come from rounding h1, h2: bounded by 2^-8 |h| propagated
     bound = 2.0 ** -8 * (np.abs(p["W3"]) @ (np.abs(h2).T + np.abs(p["W2"]) @ np.abs(h1).T)).T
     assert (np.abs(y16 - y64) <= bound + 1e-15).all()
+
+
+def _adam_params(seed=3):
+    rng = np.random.default_rng(seed)
+    return {"W": rng.standard_normal((4, 3)), "b": rng.standard_normal(3)}
+
+
+def test_adam_first_step_is_signed_lr():
+    p = _adam_params()
+    g = {k: np.random.default_rng(7).standard_normal(v.shape) * 10.0 ** np.arange(v.size).reshape(v.shape) % 5 - 2.5
+         for k, v in p.items()}
+    lr, eps = 1e-2, 1e-8
+    p0 = {k: v.copy() for k, v in p.items()}
+    mlp.adam_step(p, g, {}, lr, eps=eps)
+    for k in p:
+        want = p0[k] - lr * g[k] / (np.abs(g[k]) + eps)
+        assert np.abs(p[k] - want).max() < 1e-15
+        # magnitude lr in every component whose gradient is not tiny
+        big = np.abs(g[k]) > 1e-3
+        assert np.allclose(np.abs(p[k] - p0[k])[big], lr, rtol=1e-5)
+
+
+def test_adam_constant_gradient_same_step_every_t():
+    # with bias correction m_hat = g and v_hat = g^2 at every t for a constant g; a wrong
+    # correction exponent (t+1, or none) changes the early steps by tens of percent
+    p = _adam_params()
+    g = {k: np.full(v.shape, -0.3) for k, v in p.items()}
+    state, lr = {}, 5e-3
+    for t in range(1, 8):
+        before = {k: v.copy() for k, v in p.items()}
+        mlp.adam_step(p, g, state, lr)
+        for k in p:
+            step = p[k] - before[k]
+            assert np.abs(step - lr * 0.3 / (0.3 + 1e-8)).max() < 1e-15, (t, k)
+    assert state["t"] == 7
+
+
+def test_adam_walks_down_a_quadratic_at_rate_lr():
+    # f(w) = (w - 5)^2 / 2 from w = 0: the gradient keeps its sign and changes slowly,
+    # so every step moves towards the minimum by a little less than lr (|m_hat| / sqrt(v_hat)
+    # <= 1 while |g| shrinks, since v_hat remembers the larger past gradients)
+    p = {"w": np.zeros(1)}
+    state, lr = {}, 1e-2
+    prev = 0.0
+    for _ in range(100):
+        mlp.adam_step(p, {"w": p["w"] - 5.0}, state, lr)
+        step = p["w"][0] - prev
+        assert 0.9 * lr < step <= lr * (1 + 1e-12)
+        prev = p["w"][0]

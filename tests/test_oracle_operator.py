@@ -5,7 +5,10 @@ site inverse; free-field plane waves (eq:Wilson at U = 1); an independent
 site-by-site dense assembly on 2^4 (neighbours alias, so both hops must add);
 (Gamma5 x tau1)-hermiticity (eq:g5tau1-hermiticity); gauge covariance; the
 epsbar = 0 and mubar = 0 special cases (eq:non-degenerate, section 3.2.1);
-the Schur identity [D^-1]_oo = S^-1 (even-odd reduction).
+the Schur identity [D^-1]_oo = S^-1 (even-odd reduction), also for the
+shifted operator D' = D_ND + i m (Gamma5 x tau1) P_odd, whose odd Schur
+complement is S + i m Gamma5 tau1 (the multigrid's reading of the shifted
+odd system, section 3.1 with eq:g5tau1-hermiticity).
 """
 import itertools
 
@@ -123,6 +126,34 @@ def test_schur_identity_dense():
         S[:, j] = op.S_hat(ej.reshape(-1, 2, 4, 3)).reshape(-1)
     assert np.abs(np.linalg.inv(S) - Dinv[np.ix_(o, o)]).max() < 1e-12
     assert np.abs(S - dense.dense_schur_odd(D, dims)).max() < 1e-12
+
+
+@pytest.mark.parametrize("m", [0.37, -0.37, 1e-3])
+def test_shifted_schur_is_odd_complement_of_dprime(m):
+    # D' = D_ND + i m (Gamma5 x tau1) on the odd sites only leaves the even-even block
+    # untouched, so its odd Schur complement is S + i m Gamma5 tau1 exactly; the dense
+    # side inverts D'_ee numerically and never uses the closed-form A^-1
+    dims = (2, 2, 2, 2)
+    lat, op, U = _op(dims)
+    Dp = dense.dense_D_ND(dims, U, K, MB, EB, odd_shift=m)
+    n = len(dense.parity_indices(dims)[1])
+    S = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        ej = np.zeros(n, dtype=complex)
+        ej[j] = 1
+        S[:, j] = op.S_shift(ej.reshape(-1, 2, 4, 3), m).reshape(-1)
+    assert np.abs(S - dense.dense_schur_odd(Dp, dims)).max() < 1e-12
+    # and Gamma5 tau1 (S + i m Gamma5 tau1) = Q + i m is Q shifted by i m
+    Q = np.zeros((n, n), dtype=complex)
+    for j in range(n):
+        ej = np.zeros(n, dtype=complex)
+        ej[j] = 1
+        Q[:, j] = op.Q_hat(ej.reshape(-1, 2, 4, 3)).reshape(-1)
+    G = dense.dense_g5t1(n // 24)
+    assert np.abs(G @ S - (Q + 1j * m * np.eye(n))).max() < 1e-12
+    # the [D'^-1]_oo block is the inverse of the shifted Schur complement
+    e, o = dense.parity_indices(dims)
+    assert np.abs(np.linalg.inv(S) - np.linalg.inv(Dp)[np.ix_(o, o)]).max() < 1e-10
 
 
 @pytest.mark.parametrize("antiperiodic", [False, True])
