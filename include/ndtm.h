@@ -30,9 +30,15 @@
  * Ownership: every pointer argument is owned by the caller; device pointers
  * must be device memory of the context's GPU, 16-byte aligned, and are only
  * used during the call (asynchronously on `stream`, a hipStream_t, NULL for
- * the default stream).  The library never keeps a caller pointer.  It owns
- * its internal storage (repacked links, Krylov vectors, multigrid data),
- * allocated with hipMalloc on demand and freed by ndtm_destroy.
+ * the default stream).  The library never keeps a caller pointer, with one
+ * exception: the workspace region of ndtm_set_workspace.  Lattice-sized
+ * storage (repacked links, Krylov vectors, multigrid data, network buffers)
+ * lives either in that caller-owned region, carved up by the library (no
+ * hipMalloc or hipFree after ndtm_set_workspace), or, without a region, in
+ * hipMalloc allocations made on demand and freed by ndtm_destroy.  ndtm_create
+ * itself allocates a fixed few MB of reduction and scalar buffers and a pinned
+ * host mirror.  Call order: create -> (workspace_bytes -> set_workspace) ->
+ * set_gauge -> set_params -> set_shifts -> (mg_setup) -> solve / apply.
  *
  * Errors: every call returns an ndtm_status; ndtm_last_error gives a
  * per-context message.  No exception crosses the boundary.  A call made
@@ -83,9 +89,13 @@ enum {
 enum { NDTM_GUESS_ZERO = 0, NDTM_GUESS_LAGRANGE = 1, NDTM_GUESS_MLP = 2, NDTM_GUESS_PROJECTION = 3,
        NDTM_GUESS_MMS = 4 /* report only: the shift's own multi-shift CG iterate (mms_predict) */ };
 
-/* Creates a context on HIP device `device` for a lattice of dims {T,Lz,Ly,Lx}.
- * EINVAL if a dim is odd or < 2, or if V/2 exceeds about 20.6 million sites
- * (the stencil's 32-bit per-field byte offsets; 128 x 64^3 fits). */
+/* Creates a context on HIP device `device` for the T x L^3 lattice of section 2
+ * (dims {T,Lz,Ly,Lx}; the fields of eq:Wilson live on its sites, the even-odd
+ * reduction of section 2 splits it by parity).  EINVAL if a dim is odd or < 2, or
+ * if V/2 exceeds about 20.6 million sites (the stencil's 32-bit per-field byte
+ * offsets; 128 x 64^3 fits); EHIP for a bad device; ENOMEM if its fixed buffers
+ * cannot be allocated.  *out receives the context, owned by the caller until
+ * ndtm_destroy. */
 int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out);
 void ndtm_destroy(ndtm_ctx* ctx);
 const char* ndtm_last_error(const ndtm_ctx* ctx);
@@ -110,10 +120,16 @@ int ndtm_set_params(ndtm_ctx* ctx, double kappa, double mubar, double epsbar);
  * (section 4.2: sigma_1 > sigma_2 > ...). */
 int ndtm_set_shifts(ndtm_ctx* ctx, int n, const double* sigma);
 
-/* Applies an operator (NDTM_OP_*) in precision prec (NDTM_PREC_*).  x_dev and
- * y_dev are canonical complex128 device arrays (odd-site, even-site or full
- * lattice as the op states); y_dev must not alias x_dev.  Lower precisions
- * convert x to the internal storage format, apply, and convert back. */
+/* Applies an operator (NDTM_OP_*) in precision prec (NDTM_PREC_*): Q = Gamma5 tau1 S
+ * and Q^2 + sigma on the odd sites (section 2, even-odd reduction, with
+ * eq:g5tau1-hermiticity), S + i m Gamma5 tau1 (its shifted Schur form, section 3.1),
+ * D_ND + i m (Gamma5 x tau1) P_odd on the full lattice (eq:non-degenerate), or one
+ * hopping term H_eo / H_oe of eq:Wilson.  x_dev and y_dev are canonical complex128
+ * device arrays (odd-site, even-site or full lattice as the op states), owned by the
+ * caller; y_dev must not alias x_dev.  Lower precisions convert x to the internal
+ * storage format, apply, and convert back.  EINVAL for null or aliased pointers, an
+ * unknown op or precision; ESTATE before set_gauge and set_params; ENOMEM if the
+ * workspace cannot hold its five temporary fields.  Asynchronous on stream. */
 int ndtm_apply(ndtm_ctx* ctx, int op, int prec, void* y_dev, const void* x_dev,
                double param, void* stream);
 
@@ -140,6 +156,10 @@ typedef struct {
                           relative (section 3: the coarse system solved to a loose tolerance);
                           the host reads the residual after each cycle, so no graphs */
   int coarse_cycles;   /* restart cap of the coarse solve when coarse_tol > 0 (>= 1) */
+  int keep_f64;        /* 1 (default): keep the FP64 P and coarse blocks, which the FP64 calls
+                          ndtm_mg_restrict/prolong/coarse_apply(_multi)/coarse_solve_multi
+                          use; 0 with an FP32 cycle: free them after the setup (those
+                          calls then return NDTM_ESTATE), about 2/3 of the multigrid storage */
 } ndtm_mg_params;
 
 /* Fills *p with the defaults (4^4 aggregates, 24 vectors, ...). */
@@ -262,6 +282,40 @@ typedef struct {
 int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
                const ndtm_solve_params* p, ndtm_solve_report* report, void* stream);
 
+/* ---- device storage ----------------------------------------------------------
+ * Not an operation of the paper: storage for the fields the solve of
+ * eq:shifted_linear works on (links, the Krylov vectors of section 4.2, the
+ * multigrid data of section 3).
+ *
+ * ndtm_workspace_bytes: an upper bound, in *bytes, on the lattice storage that
+ * set_gauge, apply (any op and precision), mg_setup with *mg and the multigrid
+ * calls, and solve / solve_rational with *sp for n_shifts shifts need together
+ * (mg or sp NULL: that part left out; the learned-guess training calls with batch B
+ * need about B x 35 KB more).  EINVAL for a null ctx or bytes, n_shifts outside
+ * [1, NDTM_MAX_SHIFTS] with sp, or mg parameters that do not fit the lattice.
+ *
+ * ndtm_set_workspace: hands the context a device region of `bytes` (256-byte
+ * aligned) that the caller owns and keeps alive until ndtm_destroy or a later
+ * ndtm_set_workspace(ctx, NULL, 0).  From then on every lattice-sized buffer is
+ * carved out of it (first fit, 256-byte blocks) and no call allocates device
+ * memory; a call whose storage does not fit returns NDTM_ENOMEM.  With a region
+ * smaller than the bound for the solve's mms_defer, the multi-shift CG keeps fewer
+ * residual slots (same iterates).  dev NULL returns to hipMalloc storage.  ESTATE
+ * once the context holds lattice storage (call it before set_gauge); EINVAL for a
+ * misaligned or tiny region.
+ *
+ * ndtm_workspace_stats: live and peak bytes of lattice storage and the number of
+ * hipMalloc calls the context has made for it (0 in a caller region). */
+int ndtm_workspace_bytes(const ndtm_ctx* ctx, int n_shifts, const ndtm_mg_params* mg, const ndtm_solve_params* sp,
+                         size_t* bytes);
+int ndtm_set_workspace(ndtm_ctx* ctx, void* dev, size_t bytes);
+int ndtm_workspace_stats(const ndtm_ctx* ctx, size_t* live, size_t* peak, long long* device_allocs);
+/* Gives back the temporary fields that earlier solve, apply, guess and multigrid calls
+ * keep for reuse (to hipFree, or to the caller region); the links, the multigrid setup
+ * and the network weights stay.  Later calls take them again.  Synchronises the
+ * device. */
+int ndtm_trim(ndtm_ctx* ctx);
+
 /* ---- hybrid split (section 4.4) ------------------------------------------ */
 /* The n minimising c_HY(n) = t_CG(m_n^2) + sum_{i>n} t_MG(m_i^2) (eq:costwo) for the
  * shifts sigma_desc[0..n_shifts) (strictly descending, > 0): t_CG(sigma) is the CG
@@ -345,9 +399,11 @@ int ndtm_mlp_sample(ndtm_ctx* ctx, int K, void* const* x_dev, const double* node
  * milliseconds, the launch count and the algorithmic bytes since the last
  * reset (it synchronises the recorded events). */
 enum {
-  NDTM_PROF_HOP_F64 = 0,  /* stencil pass, per output site 1920 B (+384 per extra site vector) */
-  NDTM_PROF_HOP_F32 = 1,  /* 960 B (+192) */
-  NDTM_PROF_HOP_F16 = 2,  /* 488 B (+100) */
+  NDTM_PROF_HOP_F64 = 0,  /* stencil pass, per output site 1920 B: 8 links of 18 reals, one
+                             input and one output doublet spinor; the fused site epilogues
+                             also move 384 B per site vector they read (ndtm_profile_moved) */
+  NDTM_PROF_HOP_F32 = 1,  /* 960 B (moved: +192 per epilogue vector) */
+  NDTM_PROF_HOP_F16 = 2,  /* 488 B (moved: +100 per epilogue vector) */
   NDTM_PROF_MMS_UPDATE = 3, /* shifted updates.  Deferred form: p = r + beta p, 3 x 384 B
                                per odd site and iteration, and each flush of m residuals,
                                (m + 3 N_touched + N_still_active) x 384 B per odd site.
@@ -373,6 +429,10 @@ int ndtm_stream_bandwidth(ndtm_ctx* ctx, size_t bytes, int reps, double* copy_gb
 int ndtm_profile_enable(ndtm_ctx* ctx, int mask);
 int ndtm_profile_read(ndtm_ctx* ctx, int kernel_class, double* total_ms, long long* launches,
                       double* alg_bytes, int reset);
+/* Bytes the class's timed launches moved since the last reset: the algorithmic bytes
+ * plus, for the stencil, the site vectors its fused epilogues read.  Call after
+ * ndtm_profile_read (which collects the events) and before its reset. */
+int ndtm_profile_moved(const ndtm_ctx* ctx, int kernel_class, double* moved_bytes);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ class MGParams(C.Structure):
                 ("setup_smooth", C.c_int), ("setup_refine", C.c_int), ("setup_nd", C.c_int),
                 ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
                 ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int),
-                ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int)]
+                ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int), ("keep_f64", C.c_int)]
 
 
 class SolveParams(C.Structure):
@@ -117,6 +117,13 @@ def load_library():
                                 C.POINTER(C.c_double), vp]),
         "ndtm_stream_bandwidth": (i, [vp, C.c_size_t, i, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
+        "ndtm_workspace_bytes": (i, [vp, i, C.POINTER(MGParams), C.POINTER(SolveParams),
+                                     C.POINTER(C.c_size_t)]),
+        "ndtm_set_workspace": (i, [vp, vp, C.c_size_t]),
+        "ndtm_trim": (i, [vp]),
+        "ndtm_workspace_stats": (i, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                     C.POINTER(C.c_longlong)]),
+        "ndtm_profile_moved": (i, [vp, i, C.POINTER(C.c_double)]),
         "ndtm_profile_enable": (i, [vp, i]),
         "ndtm_profile_read": (i, [vp, i, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_double), i]),
@@ -211,6 +218,33 @@ class Context:
         arr = (C.c_double * len(sigma))(*[float(s) for s in sigma])
         self._check(self.lib.ndtm_set_shifts(self.h, len(sigma), arr))
         self.n_shifts = len(sigma)
+
+    # -- device storage -------------------------------------------------------
+    def ndtm_workspace_bytes(self, n_shifts, mg_params=None, solve_params=None):
+        nb = C.c_size_t()
+        self._check(self.lib.ndtm_workspace_bytes(
+            self.h, int(n_shifts), C.byref(mg_params) if mg_params is not None else None,
+            C.byref(solve_params) if solve_params is not None else None, C.byref(nb)))
+        return nb.value
+
+    def ndtm_set_workspace(self, region):
+        """region: a CUDA tensor the caller keeps alive (None: back to hipMalloc storage)."""
+        if region is None:
+            self._check(self.lib.ndtm_set_workspace(self.h, None, 0))
+            self._region = None
+            return
+        assert region.is_cuda and region.is_contiguous()
+        self._check(self.lib.ndtm_set_workspace(self.h, C.c_void_p(region.data_ptr()),
+                                                region.numel() * region.element_size()))
+        self._region = region
+
+    def ndtm_trim(self):
+        self._check(self.lib.ndtm_trim(self.h))
+
+    def ndtm_workspace_stats(self):
+        live, peak, n = C.c_size_t(), C.c_size_t(), C.c_longlong()
+        self._check(self.lib.ndtm_workspace_stats(self.h, C.byref(live), C.byref(peak), C.byref(n)))
+        return {"live": live.value, "peak": peak.value, "device_allocs": n.value}
 
     # -- operators ------------------------------------------------------------
     def ndtm_apply(self, op, x, param=0.0, prec=NDTM_PREC_F64, out=None):
@@ -385,3 +419,9 @@ class Context:
         self._check(self.lib.ndtm_profile_read(self.h, kernel_class, C.byref(ms), C.byref(n), C.byref(by),
                                                1 if reset else 0))
         return ms.value, n.value, by.value
+
+    def ndtm_profile_moved(self, kernel_class=0):
+        """Bytes moved by the class's timed launches (algorithmic + fused epilogue vectors)."""
+        mv = C.c_double()
+        self._check(self.lib.ndtm_profile_moved(self.h, kernel_class, C.byref(mv)))
+        return mv.value

@@ -21,11 +21,11 @@ int hip_check(ndtm_ctx* c, hipError_t e, const char* what) {
 void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes) {
   DevBuf& b = c->bufs[name];
   if (b.bytes >= bytes && b.p) return b.p;
-  if (b.p) (void)hipFree(b.p);
-  b.p = nullptr;
+  if (b.p) dev_free(c, b.p);
+  b.p = dev_alloc(c, bytes);
   b.bytes = 0;
-  if (hipMalloc(&b.p, bytes) != hipSuccess) {
-    b.p = nullptr;
+  if (!b.p) {
+    c->bufs.erase(name);
     return nullptr;
   }
   (void)hipMemset(b.p, 0, bytes);
@@ -33,10 +33,15 @@ void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes) {
   return b.p;
 }
 
+size_t ws_bytes(const ndtm_ctx* c, const std::string& name) {
+  auto it = c->bufs.find(name);
+  return it == c->bufs.end() ? 0 : it->second.bytes;
+}
+
 void ws_free_prefix(ndtm_ctx* c, const std::string& prefix) {
   for (auto it = c->bufs.begin(); it != c->bufs.end();) {
     if (it->first.compare(0, prefix.size(), prefix) == 0) {
-      if (it->second.p) (void)hipFree(it->second.p);
+      dev_free(c, it->second.p);
       it = c->bufs.erase(it);
     } else {
       ++it;
@@ -68,11 +73,13 @@ static std::pair<hipEvent_t, hipEvent_t> take_events(ndtm_ctx* c) {
   return e;
 }
 
-ProfScope::ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_) : c(c_), cls(cls_), st(st_) {
+ProfScope::ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_, double moved)
+    : c(c_), cls(cls_), st(st_) {
   if (!((c->prof_mask >> cls) & 1)) return;
   ev = take_events(c);
   (void)hipEventRecord(ev.first, st);
   c->prof_bytes[cls] += bytes;
+  c->prof_moved[cls] += moved >= 0 ? moved : bytes;
 }
 
 ProfScope::~ProfScope() {
@@ -81,19 +88,22 @@ ProfScope::~ProfScope() {
   c->ev_used[cls].push_back(ev);
 }
 
-// algorithmic bytes per output site of one stencil pass
-static double hop_site_bytes(int prec, int epi) {
-  const double base[3] = {1920.0, 960.0, 488.0}, vec[3] = {384.0, 192.0, 100.0};
-  int extra = 0;
-  if (epi == EPI_QHAT || epi == EPI_SITE) extra = 1;
-  if (epi == EPI_QHAT_SIG) extra = 2;
-  return base[prec] + extra * vec[prec];
+// Algorithmic bytes per output site of one stencil pass: 8 links of 18 reals and one
+// input and one output doublet spinor, each read or written once.  The fused site
+// epilogues also read one or two site vectors; those bytes count as moved, not as
+// the pass's algorithmic bytes.
+static const double kHopBase[3] = {1920.0, 960.0, 488.0}, kHopVec[3] = {384.0, 192.0, 100.0};
+static double hop_epi_vectors(int epi) {
+  if (epi == EPI_QHAT || epi == EPI_SITE) return 1;
+  if (epi == EPI_QHAT_SIG) return 2;
+  return 0;
 }
 
 void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& in, const HalfField& out,
          const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
          double* partials, hipStream_t st) {
-  ProfScope ps(c, NDTM_PROF_HOP_F64 + prec, hop_site_bytes(prec, epi) * c->g.vh, st);
+  ProfScope ps(c, NDTM_PROF_HOP_F64 + prec, kHopBase[prec] * c->g.vh, st,
+               (kHopBase[prec] + hop_epi_vectors(epi) * kHopVec[prec]) * c->g.vh);
   OpParams op = c->op;
   op.skip = c->hop_skip;
   launch_hop(prec, epi, red, c->g, parity, op, c->U[prec][parity], c->U[prec][1 - parity], in, out,
@@ -200,11 +210,11 @@ void ndtm_destroy(ndtm_ctx* c) {
   (void)hipDeviceSynchronize();
   ndtm_mg_free(c);
   ndtm_mlp_free(c);
-  for (auto& kv : c->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& kv : c->bufs) dev_free(c, kv.second.p);
+  c->bufs.clear();
   for (int p = 0; p < 3; ++p)
-    for (int q = 0; q < 2; ++q)
-      if (c->U[p][q]) (void)hipFree(c->U[p][q]);
+    for (int q = 0; q < 2; ++q) dev_free(c, c->U[p][q]);
+  arena_release(c);
   if (c->partials) (void)hipFree(c->partials);
   if (c->dscal) (void)hipFree(c->dscal);
   if (c->mms_S) (void)hipFree(c->mms_S);
@@ -238,10 +248,8 @@ int ndtm_set_gauge(ndtm_ctx* c, const void* U_dev, void* stream) {
   for (int p = 0; p < 3; ++p)
     for (int q = 0; q < 2; ++q) {
       if (!c->U[p][q]) {
-        if (hipMalloc(&c->U[p][q], n * esz[p]) != hipSuccess) {
-          c->U[p][q] = nullptr;
-          return fail(c, NDTM_ENOMEM, "set_gauge: link storage");
-        }
+        c->U[p][q] = dev_alloc(c, n * esz[p]);
+        if (!c->U[p][q]) return fail(c, NDTM_ENOMEM, "set_gauge: link storage");
         NDTM_HIP(c, hipMemsetAsync(c->U[p][q], 0, n * esz[p], st));
       }
     }
@@ -417,7 +425,14 @@ int ndtm_profile_read(ndtm_ctx* c, int cls, double* total_ms, long long* launche
     c->prof_ms[cls] = 0;
     c->prof_n[cls] = 0;
     c->prof_bytes[cls] = 0;
+    c->prof_moved[cls] = 0;
   }
+  return NDTM_OK;
+}
+
+int ndtm_profile_moved(const ndtm_ctx* c, int cls, double* moved_bytes) {
+  if (!c || cls < 0 || cls >= NDTM_PROF_NCLASS || !moved_bytes) return NDTM_EINVAL;
+  *moved_bytes = c->prof_moved[cls];
   return NDTM_OK;
 }
 

@@ -19,6 +19,7 @@ struct DevBuf {
 
 struct MGData;  // multigrid state (mg.cpp)
 struct MLPData; // learned proposer state (mlp.cpp)
+struct Arena;   // caller-provided device region (memory.cpp)
 
 }  // namespace ndtm
 
@@ -48,12 +49,22 @@ struct ndtm_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
   double prof_ms[NDTM_PROF_NCLASS] = {};
   long long prof_n[NDTM_PROF_NCLASS] = {};
-  double prof_bytes[NDTM_PROF_NCLASS] = {};
+  double prof_bytes[NDTM_PROF_NCLASS] = {};  // algorithmic bytes
+  double prof_moved[NDTM_PROF_NCLASS] = {};  // bytes the launches move (fused epilogue vectors too)
   ndtm::MGData* mg = nullptr;
   // extreme eigenvalues of Q^2 from the base system's Lanczos coefficients of the last
   // FP64 multi-shift solve (<= 0 while unknown)
   double est_lmin = -1, est_lmax = -1;
   ndtm::MLPData* mlp = nullptr;
+  // device storage (memory.cpp): caller region or hipMalloc per buffer
+  ndtm::Arena* arena = nullptr;
+  std::map<void*, size_t> mem_sizes;  // every live buffer from dev_alloc
+  size_t mem_live = 0, mem_peak = 0;
+  long long mem_device_allocs = 0;    // hipMalloc calls made for lattice storage
+  // the running solve's phase region (ndtm_solve): the multi-shift phase's shifted
+  // directions and residual ring, then the multigrid phase's case-C and FGMRES vectors
+  void* region = nullptr;
+  size_t region_fields = 0;  // FP64 half fields it holds
 };
 
 namespace ndtm {
@@ -70,6 +81,16 @@ int hip_check(ndtm_ctx* c, hipError_t e, const char* what);
     if (_e != hipSuccess) return ndtm::hip_check(ctx, _e, #call); \
   } while (0)
 
+// device storage: every lattice-sized buffer comes from dev_alloc (caller region
+// after ndtm_set_workspace, else hipMalloc); nullptr when it cannot be had
+void* dev_alloc(ndtm_ctx* c, size_t bytes);
+void dev_free(ndtm_ctx* c, void* p);
+size_t dev_largest_free(const ndtm_ctx* c);  // largest block dev_alloc could still return
+int arena_set(ndtm_ctx* c, void* dev, size_t bytes);
+void arena_release(ndtm_ctx* c);
+// bytes of the named buffer (0 if absent)
+size_t ws_bytes(const ndtm_ctx* c, const std::string& name);
+
 // named workspace (grown on demand, zero-filled when (re)allocated)
 void* ws_get(ndtm_ctx* c, const std::string& name, size_t bytes);
 HalfField half_field(ndtm_ctx* c, const std::string& name, int prec);
@@ -81,7 +102,8 @@ struct ProfScope {
   int cls;
   hipStream_t st;
   std::pair<hipEvent_t, hipEvent_t> ev{};
-  ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_);
+  // bytes: algorithmic bytes of the launch; moved: bytes it moves (default: the same)
+  ProfScope(ndtm_ctx* c_, int cls_, double bytes, hipStream_t st_, double moved = -1.0);
   ~ProfScope();
 };
 
@@ -125,9 +147,14 @@ int hybrid_choose(int N, const double* sig, double lmin, double lmax, double tol
 // kMaxDefer); 0 or 1: updated every iteration.
 // The last npass shifts of sigmas are passengers: iterated along but not waited
 // for, so that their iterates can serve as initial guesses (section 4.2).
+// region (optional): holds the shifted directions of shifts 1.. and the `defer`
+// residual slots, (nsh - 1 + defer) FP64 half fields; without it they are named
+// workspace buffers and defer is clamped to half of the free device memory.
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st, int npass = 0);
+              hipStream_t st, int npass = 0, void* region = nullptr);
+// FP64 half fields the multigrid phase takes from the solve's region (case C and FGMRES)
+int mg_region_fields(int fgmres_restart);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
 // Gram matrix <B_i, B_j> of B = [b, x_1, x_2, ...] (row-major 17 x 17), filled
 // for the first `count` vectors; kept across the multigrid targets of one solve

@@ -73,9 +73,9 @@ struct MGData {
   bool use_graphs = true;
 };
 
-static void* mg_alloc(MGData* M, size_t bytes) {
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+static void* mg_alloc(ndtm_ctx* c, MGData* M, size_t bytes) {
+  void* p = dev_alloc(c, bytes);
+  if (!p) return nullptr;
   (void)hipMemset(p, 0, bytes);
   M->owned.push_back(p);
   return p;
@@ -268,14 +268,38 @@ static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfFie
 
 // FGMRES in FP64 for (S + i m Gamma5 tau1) x = rhs, x starting from zero.
 // Stops when the recursive residual <= tol * ||rhs||.  Returns iterations.
+// Case C takes 5 FP64 half fields of the solve's phase region, FGMRES(k) 2k + 4 more.
+static int fgmres_restart_clamp(int restart) { return std::max(2, std::min(restart, 32)); }
+int mg_region_fields(int fgmres_restart) { return 5 + 2 * fgmres_restart_clamp(fgmres_restart) + 4; }
+
+// FP64 half field j of the solve's phase region, else the named workspace buffer
+static HalfField region_field(ndtm_ctx* c, size_t j, const std::string& name) {
+  if (c->region && j < c->region_fields) {
+    HalfField f;
+    f.prec = P64;
+    f.v = static_cast<double2*>(c->region) + j * half_elems(c);
+    return f;
+  }
+  return half_field(c, name, P64);
+}
+
 static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField& x, double m, double tol, int restart,
                   int maxiter, double* res_out, hipStream_t st) {
   const size_t n = half_elems(c);
-  restart = std::max(2, std::min(restart, 32));
+  restart = fgmres_restart_clamp(restart);
   std::vector<HalfField> V(restart + 1), Z(restart);
-  for (int j = 0; j <= restart; ++j) V[j] = half_field(c, "fg_v" + std::to_string(j), P64);
-  for (int j = 0; j < restart; ++j) Z[j] = half_field(c, "fg_z" + std::to_string(j), P64);
-  HalfField W = half_field(c, "fg_w", P64), te = half_field(c, "fg_te", P64), r = half_field(c, "fg_r", P64);
+  size_t j0 = 5;  // after case C's five fields
+  for (int j = 0; j <= restart; ++j) V[j] = region_field(c, j0++, "fg_v" + std::to_string(j));
+  for (int j = 0; j < restart; ++j) Z[j] = region_field(c, j0++, "fg_z" + std::to_string(j));
+  HalfField W = region_field(c, j0, "fg_w"), te = region_field(c, j0 + 1, "fg_te"),
+            r = region_field(c, j0 + 2, "fg_r");
+  bool have = W.v && te.v && r.v;
+  for (auto& f : V) have = have && f.v;
+  for (auto& f : Z) have = have && f.v;
+  if (!have) {  // workspace exhausted: the caller reports NDTM_ENOMEM
+    *res_out = INFINITY;
+    return -1;
+  }
   std::vector<const void*> Vp(restart + 1), Zp(restart);
   for (int j = 0; j <= restart; ++j) Vp[j] = V[j].v;
   for (int j = 0; j < restart; ++j) Zp[j] = Z[j].v;
@@ -372,9 +396,9 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
                         hipStream_t st) {
   const size_t n = half_elems(c);
   const double m = std::sqrt(sigma);
-  HalfField r = half_field(c, "cc_r", P64), cr = half_field(c, "cc_c", P64), ep = half_field(c, "cc_ep", P64),
-            em = half_field(c, "cc_em", P64);
-  HalfField xb = half_field(c, "cc_xb", P64);
+  HalfField r = region_field(c, 0, "cc_r"), cr = region_field(c, 1, "cc_c"), ep = region_field(c, 2, "cc_ep"),
+            em = region_field(c, 3, "cc_em");
+  HalfField xb = region_field(c, 4, "cc_xb");
   if (!r.v || !cr.v || !ep.v || !em.v || !xb.v) return fail(c, NDTM_ENOMEM, "multigrid shift: workspace");
   double res = true_residual(c, x, b, sigma, r, st);
   *guess_res = res;
@@ -387,8 +411,11 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
     rho = std::max(1e-14, std::min(rho, p->mg_tol));
     launch_g5t1(c->g, (const double2*)r.v, (double2*)cr.v, st);
     double rp = 0, rm = 0;
-    it_total += fgmres(c, M, cr, ep, +m, rho, p->fgmres_restart, p->fgmres_maxiter, &rp, st);
-    it_total += fgmres(c, M, cr, em, -m, rho, p->fgmres_restart, p->fgmres_maxiter, &rm, st);
+    const int ip = fgmres(c, M, cr, ep, +m, rho, p->fgmres_restart, p->fgmres_maxiter, &rp, st);
+    if (ip < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
+    const int im = fgmres(c, M, cr, em, -m, rho, p->fgmres_restart, p->fgmres_maxiter, &rm, st);
+    if (im < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
+    it_total += ip + im;
     // x += (i/2m)(e_+ - e_-)
     blas_axpy((double2*)x.v, make_double2(0, 0.5 / m), (const double2*)ep.v, n, st);
     blas_axpy((double2*)x.v, make_double2(0, -0.5 / m), (const double2*)em.v, n, st);
@@ -533,6 +560,7 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, int 
     if (rep->lagrange_res[t] < 0 && p->guess == NDTM_GUESS_LAGRANGE) rep->lagrange_res[t] = gres;
     auto tg2 = std::chrono::steady_clock::now();
     rep->t_mg_ms += std::chrono::duration<double, std::milli>(tg2 - tg1).count();
+    if (rc == NDTM_ENOMEM) return rc;
     if (rc != NDTM_OK) {
       // the multigrid did not reach the tolerance: finish this shift with FP64 CG
       // from the best iterate, so that every shift still converges
@@ -553,6 +581,12 @@ int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig, int n_mms, int 
 // ---- setup ----------------------------------------------------------------
 static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, hipStream_t st) {
   ndtm_mg_free(c);
+  // with hipMalloc storage, the solve's phase region (sized to the free memory it found)
+  // is given back; the next solve sizes it again around the multigrid data
+  if (!c->arena) {
+    ws_free_prefix(c, "sv_region");
+    ws_free_prefix(c, "cg_ring");
+  }
   MGData* M = new MGData();
   c->mg = M;
   M->prm = *prm;
@@ -579,9 +613,9 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   const size_t nD = (size_t)g.Vc * 9 * n2 * n2;
   const size_t nB = (size_t)g.Vc * 2 * Nv * Nv;
   M->ncoarse = (size_t)g.Vc * 2 * n2;
-  M->P64 = (double2*)mg_alloc(M, nP * 16);
-  M->D64 = (double2*)mg_alloc(M, nD * 16);
-  M->Bo64 = (double2*)mg_alloc(M, nB * 16);
+  M->P64 = (double2*)mg_alloc(c, M, nP * 16);
+  M->D64 = (double2*)mg_alloc(c, M, nD * 16);
+  M->Bo64 = (double2*)mg_alloc(c, M, nB * 16);
   if (!M->P64 || !M->D64 || !M->Bo64) return fail(c, NDTM_ENOMEM, "mg_setup: P / coarse operator");
   const size_t nh = half_elems(c);
   if (M->cprec == P64) {
@@ -589,29 +623,29 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     M->Dc = M->D64;
     M->Boc = M->Bo64;
   } else {
-    M->Pc = mg_alloc(M, nP * 8);
-    M->Dc = mg_alloc(M, nD * 8);
-    M->Boc = mg_alloc(M, nB * 8);
+    M->Pc = mg_alloc(c, M, nP * 8);
+    M->Dc = mg_alloc(c, M, nD * 8);
+    M->Boc = mg_alloc(c, M, nB * 8);
     if (!M->Pc || !M->Dc || !M->Boc) return fail(c, NDTM_ENOMEM, "mg_setup: FP32 copies");
   }
   const int kc = prm->coarse_iters;
   M->cV.resize(kc + 1);
   for (int j = 0; j <= kc; ++j) {
-    M->cV[j] = mg_alloc(M, M->ncoarse * csz(M->cprec));
+    M->cV[j] = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
     if (!M->cV[j]) return fail(c, NDTM_ENOMEM, "mg_setup: coarse basis");
   }
-  M->cW = mg_alloc(M, M->ncoarse * csz(M->cprec));
-  M->cW2 = mg_alloc(M, M->ncoarse * csz(M->cprec));
-  M->cR = mg_alloc(M, M->ncoarse * csz(M->cprec));
-  M->cT = mg_alloc(M, M->ncoarse * csz(M->cprec));
-  M->cX = mg_alloc(M, M->ncoarse * csz(M->cprec));
-  M->dH = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
-  M->dsub = (double*)mg_alloc(M, (kc + 1) * sizeof(double));
-  M->dy = (double*)mg_alloc(M, 2 * (kc + 1) * sizeof(double));
-  M->dbeta = (double*)mg_alloc(M, 8 * sizeof(double));
-  M->dtmp = (double*)mg_alloc(M, 16 * sizeof(double));
-  M->dh2 = (double*)mg_alloc(M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
-  M->dpart = (double*)mg_alloc(M, 6 * (size_t)hop_grid(c->g) * sizeof(double));
+  M->cW = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+  M->cW2 = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+  M->cR = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+  M->cT = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+  M->cX = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+  M->dH = (double*)mg_alloc(c, M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
+  M->dsub = (double*)mg_alloc(c, M, (kc + 1) * sizeof(double));
+  M->dy = (double*)mg_alloc(c, M, 2 * (kc + 1) * sizeof(double));
+  M->dbeta = (double*)mg_alloc(c, M, 8 * sizeof(double));
+  M->dtmp = (double*)mg_alloc(c, M, 16 * sizeof(double));
+  M->dh2 = (double*)mg_alloc(c, M, 2 * (size_t)(kc + 1) * (kc + 1) * sizeof(double));
+  M->dpart = (double*)mg_alloc(c, M, 6 * (size_t)hop_grid(c->g) * sizeof(double));
   if (!M->dpart || !M->dh2 || !M->cW || !M->cW2 || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
@@ -725,6 +759,16 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     vzero(M->cprec, R.base, 2 * nh, st);
     NDTM_HIP(c, hipStreamSynchronize(st));
   }
+  if (M->cprec != P64 && !prm->keep_f64) {
+    // the FP32 cycle reads only the FP32 copies: give the FP64 ones back
+    for (void* q : {(void*)M->P64, (void*)M->D64, (void*)M->Bo64}) {
+      M->owned.erase(std::remove(M->owned.begin(), M->owned.end(), q), M->owned.end());
+      dev_free(c, q);
+    }
+    M->P64 = nullptr;
+    M->D64 = nullptr;
+    M->Bo64 = nullptr;
+  }
   M->ready = true;
   return NDTM_OK;
 }
@@ -740,7 +784,7 @@ void ndtm_mg_free(ndtm_ctx* c) {
   (void)hipDeviceSynchronize();
   for (auto& g : c->mg->graphs) (void)hipGraphExecDestroy(g.second);
   if (c->mg->cap) (void)hipStreamDestroy(c->mg->cap);
-  for (void* p : c->mg->owned) (void)hipFree(p);
+  for (void* p : c->mg->owned) dev_free(c, p);
   delete c->mg;
   c->mg = nullptr;
 }
@@ -760,6 +804,7 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->precision = NDTM_PREC_F32;
   p->coarse_tol = 0.0;
   p->coarse_cycles = 20;
+  p->keep_f64 = 1;
 }
 
 int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* stream) {
@@ -794,6 +839,7 @@ long long ndtm_mg_coarse_volume(const ndtm_ctx* c) { return (c && c->mg && c->mg
 int ndtm_mg_restrict(ndtm_ctx* c, void* vc, const void* v, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_restrict: no multigrid setup");
+  if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_restrict: FP64 operators not kept (keep_f64 = 0)");
   if (!vc || !v) return fail(c, NDTM_EINVAL, "mg_restrict: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Full F = full_field(c, "ab_f", P64);
@@ -806,6 +852,7 @@ int ndtm_mg_restrict(ndtm_ctx* c, void* vc, const void* v, void* stream) {
 int ndtm_mg_prolong(ndtm_ctx* c, void* v, const void* vc, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_prolong: no multigrid setup");
+  if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_prolong: FP64 operators not kept (keep_f64 = 0)");
   if (!vc || !v) return fail(c, NDTM_EINVAL, "mg_prolong: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Full F = full_field(c, "ab_f", P64);
@@ -831,6 +878,7 @@ int ndtm_mg_coarse_solve(ndtm_ctx* c, void* xc, const void* bc, double m, void* 
 int ndtm_mg_coarse_apply(ndtm_ctx* c, void* yc, const void* xc, double m, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_apply: no multigrid setup");
+  if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_coarse_apply: FP64 operators not kept (keep_f64 = 0)");
   if (!yc || !xc || yc == xc) return fail(c, NDTM_EINVAL, "mg_coarse_apply: null or aliased pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   mg_coarse_apply(P64, c->mg->g, c->mg->D64, c->mg->Bo64, xc, yc, c->mg->prm.coarse_mu_factor * c->mubar,
@@ -842,6 +890,7 @@ int ndtm_mg_coarse_apply(ndtm_ctx* c, void* yc, const void* xc, double m, void* 
 int ndtm_mg_coarse_apply_multi(ndtm_ctx* c, void* yc, const void* xc, int k, const double* m, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_apply_multi: no multigrid setup");
+  if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_coarse_apply_multi: FP64 operators not kept (keep_f64 = 0)");
   if (!yc || !xc || !m || yc == xc) return fail(c, NDTM_EINVAL, "mg_coarse_apply_multi: null or aliased pointer");
   if (k < 1 || k > kMultiMax) return fail(c, NDTM_EINVAL, "mg_coarse_apply_multi: 1 <= k <= 8");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -864,6 +913,7 @@ int ndtm_mg_coarse_apply_multi(ndtm_ctx* c, void* yc, const void* xc, int k, con
 int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, const double* m, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_coarse_solve_multi: no multigrid setup");
+  if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_coarse_solve_multi: FP64 operators not kept (keep_f64 = 0)");
   if (!xc || !bc || !m || xc == bc) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: null or aliased pointer");
   if (k < 1 || k > kMultiMax) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: 1 <= k <= 8");
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -36,13 +36,19 @@ struct MLPData {
   int cap = 0;
 };
 
-static void mlp_release_batch(MLPData* D) {
+static void mlp_release_batch(ndtm_ctx* c, MLPData* D) {
   for (float** p : {&D->feat, &D->mask, &D->G, &D->h, &D->y, &D->loss, &D->gbuf})
     if (*p) {
-      (void)hipFree(*p);
+      dev_free(c, *p);
       *p = nullptr;
     }
   D->cap = 0;
+}
+
+template <class T>
+static bool mlp_get(ndtm_ctx* c, T** p, size_t bytes) {
+  *p = static_cast<T*>(dev_alloc(c, bytes));
+  return *p != nullptr;
 }
 
 static int mlp_ensure(ndtm_ctx* c) {
@@ -50,8 +56,8 @@ static int mlp_ensure(ndtm_ctx* c) {
   MLPData* D = new MLPData();
   c->mlp = D;
   const size_t n = kMlpNParam * sizeof(float);
-  if (hipMalloc(&D->W, n) != hipSuccess || hipMalloc(&D->m, n) != hipSuccess || hipMalloc(&D->v, n) != hipSuccess ||
-      hipMalloc(&D->gout, n) != hipSuccess || hipMalloc(&D->Wb, kMlpNParam * 2) != hipSuccess)
+  if (!mlp_get(c, &D->W, n) || !mlp_get(c, &D->m, n) || !mlp_get(c, &D->v, n) || !mlp_get(c, &D->gout, n) ||
+      !mlp_get(c, &D->Wb, kMlpNParam * 2))
     return fail(c, NDTM_ENOMEM, "mlp: weights");
   (void)hipMemset(D->m, 0, n);
   (void)hipMemset(D->v, 0, n);
@@ -61,12 +67,11 @@ static int mlp_ensure(ndtm_ctx* c) {
 static int mlp_batch(ndtm_ctx* c, int B) {
   MLPData* D = c->mlp;
   if (D->cap >= B) return NDTM_OK;
-  mlp_release_batch(D);
+  mlp_release_batch(c, D);
   const size_t b = (size_t)B;
-  if (hipMalloc(&D->feat, b * kMlpNFeat * 4) != hipSuccess || hipMalloc(&D->mask, b * kMlpKMax * 4) != hipSuccess ||
-      hipMalloc(&D->G, b * kMlpKMax * kMlpKMax * 4) != hipSuccess || hipMalloc(&D->h, b * kMlpKMax * 4) != hipSuccess ||
-      hipMalloc(&D->y, b * kMlpKMax * 4) != hipSuccess || hipMalloc(&D->loss, b * 4) != hipSuccess ||
-      hipMalloc(&D->gbuf, b * kMlpNParam * 4) != hipSuccess)
+  if (!mlp_get(c, &D->feat, b * kMlpNFeat * 4) || !mlp_get(c, &D->mask, b * kMlpKMax * 4) ||
+      !mlp_get(c, &D->G, b * kMlpKMax * kMlpKMax * 4) || !mlp_get(c, &D->h, b * kMlpKMax * 4) ||
+      !mlp_get(c, &D->y, b * kMlpKMax * 4) || !mlp_get(c, &D->loss, b * 4) || !mlp_get(c, &D->gbuf, b * kMlpNParam * 4))
     return fail(c, NDTM_ENOMEM, "mlp: batch buffers");
   D->cap = B;
   return NDTM_OK;
@@ -228,9 +233,8 @@ extern "C" {
 void ndtm_mlp_free(ndtm_ctx* c) {
   if (!c || !c->mlp) return;
   MLPData* D = c->mlp;
-  mlp_release_batch(D);
-  for (void* p : {(void*)D->W, (void*)D->m, (void*)D->v, D->Wb, (void*)D->gout, (void*)D->hist})
-    if (p) (void)hipFree(p);
+  mlp_release_batch(c, D);
+  for (void* p : {(void*)D->W, (void*)D->m, (void*)D->v, D->Wb, (void*)D->gout, (void*)D->hist}) dev_free(c, p);
   delete D;
   c->mlp = nullptr;
 }
@@ -310,9 +314,8 @@ int ndtm_mlp_train(ndtm_ctx* c, int B, const float* feat, const float* mask, con
   if ((rc = mlp_upload(c, B, feat, mask, G, h, nullptr)) != NDTM_OK) return rc;
   MLPData* D = c->mlp;
   if (D->hist_cap < steps) {
-    if (D->hist) (void)hipFree(D->hist);
-    if (hipMalloc(&D->hist, (size_t)steps * 4) != hipSuccess) {
-      D->hist = nullptr;
+    dev_free(c, D->hist);
+    if (!mlp_get(c, &D->hist, (size_t)steps * 4)) {
       D->hist_cap = 0;
       return fail(c, NDTM_ENOMEM, "mlp_train: history");
     }

@@ -83,11 +83,24 @@ struct LaggedPoll {
   }
 };
 
+// installs the solve's phase region on the context for the scope of a phase
+struct RegionScope {
+  ndtm_ctx* c;
+  RegionScope(ndtm_ctx* cc, void* region, size_t fields) : c(cc) {
+    c->region = region;
+    c->region_fields = fields;
+  }
+  ~RegionScope() {
+    c->region = nullptr;
+    c->region_fields = 0;
+  }
+};
+
 }  // namespace
 
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st, int npass) {
+              hipStream_t st, int npass, void* region) {
   const int nsh = (int)sigmas.size();
   const size_t n = half_elems(c);
   const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
@@ -96,14 +109,18 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   HalfField u = half_field(c, "cg_u", P64), te = half_field(c, "cg_te", P64);
   std::vector<double2*> ps(nsh), xv(nsh);
   for (int s = 0; s < nsh; ++s) {
-    HalfField f = half_field(c, "cg_ps" + std::to_string(s), P64);
-    if (!f.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
-    ps[s] = static_cast<double2*>(f.v);
+    if (region && s > 0) {
+      ps[s] = static_cast<double2*>(region) + (size_t)(s - 1) * n;
+    } else {
+      HalfField f = half_field(c, "cg_ps" + std::to_string(s), P64);
+      if (!f.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
+      ps[s] = static_cast<double2*>(f.v);
+    }
     xv[s] = static_cast<double2*>(xs[s].v);
   }
   if (!r.v || !p.v || !w.v || !u.v || !te.v) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
   if (defer > kMaxDefer) defer = kMaxDefer;
-  if (defer >= 2) {
+  if (defer >= 2 && !region) {
     // the ring takes at most half of the device memory that is free (or already its own)
     size_t fr = 0, tot = 0;
     (void)hipMemGetInfo(&fr, &tot);
@@ -114,7 +131,9 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   }
   const bool deferred = defer >= 2;
   double2* ring = nullptr;  // defer residual slots, n elements apart
-  if (deferred) {
+  if (deferred && region) {
+    ring = static_cast<double2*>(region) + (size_t)(nsh - 1) * n;
+  } else if (deferred) {
     ring = static_cast<double2*>(ws_get(c, "cg_ring", (size_t)defer * n * sizeof(double2)));
     if (!ring) return fail(c, NDTM_ENOMEM, "mmscg: residual slots");
   }
@@ -517,9 +536,27 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     const int n_pred = std::max(0, std::min(p->mms_predict, nsh - n_mms));
     std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms + n_pred);
     std::vector<HalfField> x_mms(xs.begin(), xs.begin() + n_mms + n_pred);
+    // one region serves both phases: shifted directions 1.. and the residual ring, then
+    // the multigrid phase's vectors; the ring gets what the region can hold beyond them
+    const int n_ps = n_mms + n_pred;
+    const size_t fb = n * sizeof(double2);
+    const size_t mg_fields = n_mms < nsh ? (size_t)mg_region_fields(p->fgmres_restart) : 0;
+    int defer = std::min(p->mms_defer, kMaxDefer);
+    if (defer < 2) defer = 0;
+    {
+      const size_t own = ws_bytes(c, "sv_region") / fb;
+      // managed storage: the ring takes at most half of the free device memory
+      const size_t avail = own + (c->arena ? dev_largest_free(c) : dev_largest_free(c) / 2) / fb;
+      const size_t fixed = (size_t)(n_ps - 1);
+      if (defer && fixed + defer > avail) defer = avail > fixed + 2 ? (int)(avail - fixed) : 0;
+    }
+    const size_t fields = std::max(mg_fields, (size_t)(n_ps - 1 + defer));
+    void* region = fields ? ws_get(c, "sv_region", fields * fb) : nullptr;
+    if (fields && !region) return fail(c, NDTM_ENOMEM, "solve: phase region");
+    RegionScope rs(c, region, fields);
     MmsResult mr;
-    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, p->mms_defer, &mr, st,
-                       n_pred);
+    int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, defer, &mr, st, n_pred,
+                       region);
     rep->mms_iterations = mr.iterations;
     if (rc == NDTM_EBREAKDOWN) {
       rep->status = rc;
@@ -549,6 +586,10 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   // ---- multigrid (case C) for the remaining shifts ----
   if (n_mms < nsh) {
     const int n_pred = p->precision == NDTM_PREC_F16 ? 0 : std::max(0, std::min(p->mms_predict, nsh - n_mms));
+    const size_t fields = (size_t)mg_region_fields(p->fgmres_restart);
+    void* region = ws_get(c, "sv_region", std::max(ws_bytes(c, "sv_region"), fields * n * sizeof(double2)));
+    if (!region) return fail(c, NDTM_ENOMEM, "solve: phase region");
+    RegionScope rs(c, region, fields);
     int rc = solve_mg_shifts(c, sig, n_mms, n_pred, xs, B, p, rep, st);
     if (rc != NDTM_OK && status == NDTM_OK) status = rc;
 

@@ -18,6 +18,8 @@ Canonical layouts (the C-ABI uses the same ones):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 KAPPA = 0.1275
@@ -66,25 +68,49 @@ def volume(dims) -> int:
     return int(np.prod(dims))
 
 
-def gauge_field(dims, seed: int, amp: float = 0.3, chunk: int = 1 << 20) -> np.ndarray:
+def _exp_i_amp_h(h: np.ndarray, amp: float) -> np.ndarray:
+    """exp(i*amp*H) for H = sum_a h_a lambda_a / 2, one link per row of h (n x 8)."""
+    H = np.einsum("na,aij->nij", h, _GM) * 0.5
+    w, vec = np.linalg.eigh(H)
+    ph = np.exp(1j * amp * w)
+    return np.einsum("nij,nj,nkj->nik", vec, ph, vec.conj())
+
+
+def gauge_field(dims, seed: int, amp: float = 0.3, chunk: int = 1 << 20, workers: int | None = None) -> np.ndarray:
     """U = exp(i*amp*H) per link, H = sum_a h_a lambda_a / 2, h_a ~ N(0,1) iid.
 
     Returns complex128 array of shape (V, 4, 3, 3).  The exponential is taken
     through the eigendecomposition of the Hermitian H, so U is unitary with
     unit determinant to rounding.  Generated in chunks of links so that large
-    lattices fit in host memory.
+    lattices fit in host memory.  The normal deviates are always drawn in link
+    order from one generator.  With ``workers`` > 1 the exponentials of the
+    chunks are taken by that many forked processes, which gives the same array
+    as the serial loop; call it so only before the process has touched a GPU.
     """
     V = volume(dims)
     n = 4 * V
     rng = np.random.default_rng(seed)
     out = np.empty((n, 3, 3), dtype=np.complex128)
-    for lo in range(0, n, chunk):
-        hi = min(n, lo + chunk)
-        h = rng.standard_normal((hi - lo, 8))
-        H = np.einsum("na,aij->nij", h, _GM) * 0.5
-        w, vec = np.linalg.eigh(H)
-        ph = np.exp(1j * amp * w)
-        out[lo:hi] = np.einsum("nij,nj,nkj->nik", vec, ph, vec.conj())
+    n_chunks = (n + chunk - 1) // chunk
+    if n_chunks <= 2 or not workers or workers <= 1:
+        for lo in range(0, n, chunk):
+            hi = min(n, lo + chunk)
+            out[lo:hi] = _exp_i_amp_h(rng.standard_normal((hi - lo, 8)), amp)
+        return out.reshape(V, 4, 3, 3)
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    with cf.ProcessPoolExecutor(max_workers=min(workers, os.cpu_count() or 1),
+                                mp_context=mp.get_context("fork")) as ex:
+        pending = []
+        for lo in range(0, n, chunk):
+            hi = min(n, lo + chunk)
+            pending.append((lo, hi, ex.submit(_exp_i_amp_h, rng.standard_normal((hi - lo, 8)), amp)))
+            while len(pending) > 2 * workers:
+                a, b_, f = pending.pop(0)
+                out[a:b_] = f.result()
+        for a, b_, f in pending:
+            out[a:b_] = f.result()
     return out.reshape(V, 4, 3, 3)
 
 

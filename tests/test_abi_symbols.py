@@ -18,7 +18,7 @@ def _declared():
 def test_header_declares_entry_points():
     names = _declared()
     for n in ("ndtm_create", "ndtm_set_gauge", "ndtm_set_params", "ndtm_set_shifts", "ndtm_apply",
-              "ndtm_mg_setup", "ndtm_solve"):
+              "ndtm_mg_setup", "ndtm_solve", "ndtm_workspace_bytes", "ndtm_set_workspace"):
         assert n in names
 
 

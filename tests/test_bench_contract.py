@@ -23,7 +23,7 @@ def test_recorded_traffic_only_for_its_lattice():
     import hashlib
     import re
 
-    summary = open(os.path.join(ROOT, "profiles", "hop_f64_16x16x16x32_hybrid_counters.md")).read()
+    summary = open(os.path.join(ROOT, "profiles", "hop_f64_16x16x16x32_counters.md")).read()
     rec = json.loads(re.search(r"traffic_json: (\{.*\})", summary).group(1))
     src = open(os.path.join(ROOT, "paper_1805_09584_amd", "csrc", "kern_dslash.hip"), "rb").read()
     current = rec["source_sha256"] == hashlib.sha256(src).hexdigest()
