@@ -347,6 +347,12 @@ double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
                      hipStream_t st) {
   const size_t n = half_elems(c);
   HalfField u = half_field(c, "tr_u", P64), te = half_field(c, "tr_te", P64);
+  // ndtm_solve takes these fields before any work; a caller outside it that runs out of
+  // storage gets a non-finite residual (no kernel sees a missing buffer)
+  if (!u.v || !te.v || !r.v || !x.v || !b.v) {
+    c->err = "true residual: workspace";
+    return INFINITY;
+  }
   apply_qhat2(c, P64, r, x, u, te, sigma, nullptr, st);
   // r = b - (Q^2 + sigma) x
   blas_axpby((double2*)r.v, make_double2(1, 0), (const double2*)b.v, make_double2(-1, 0), n, st);
@@ -369,7 +375,7 @@ static int polish_cg(ndtm_ctx* c, const HalfField& x, const HalfField& b, double
     const double inner = std::min(0.5, 0.5 * tol / res);
     int rc = run_mmscg(c, {sigma}, es, r, inner, maxiter, 8, 0, &mr, st);
     total += mr.iterations;
-    if (rc == NDTM_EBREAKDOWN) return rc;
+    if (rc != NDTM_OK && rc != NDTM_ENOCONV) return rc;
     blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e.v, n, st);
     res = true_residual(c, x, b, sigma, r, st);
   }
@@ -406,6 +412,7 @@ static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, dou
     int rc = run_mmscg_mixed(c, {sigma}, es, r32, inner, maxiter, 8, &mr, st);
     total += mr.iterations;
     ++rounds;
+    if (rc == NDTM_ENOMEM) return rc;
     if (rc == NDTM_EBREAKDOWN) break;
     vconvert_field(P64, e64.v, P32, e32.v, 1, c->g.vh, c->g.stride, st);
     blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e64.v, n, st);
@@ -494,6 +501,10 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     xs[i] = half_field(c, "sv_x" + std::to_string(i), P64);
     if (!xs[i].v) return fail(c, NDTM_ENOMEM, "solve: workspace");
   }
+  // the fixed fields of the later steps (true residuals, CG polish and fallback, the base
+  // Krylov vectors) are taken now, so that no step runs out of storage half way
+  for (const char* name : {"sv_r", "tr_u", "tr_te", "pol_r", "pol_e", "cg_r", "cg_p", "cg_w", "cg_u", "cg_te", "cg_ps0"})
+    if (!half_field(c, name, P64).v) return fail(c, NDTM_ENOMEM, "solve: workspace");
   if (bb == 0.0) {
     for (int i = 0; i < nsh; ++i) blas_zero(xs[i].v, n * sizeof(double2), st);
     for (int i = 0; i < nsh; ++i) launch_unpack_half(c->g, xs[i], static_cast<double2*>(x_dev[order[i]]), st);
@@ -516,7 +527,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     MmsResult mr;
     int rc = run_mmscg_mixed(c, s_mms, x32, B32, std::max(p->tol, 1e-5), p->maxiter, p->poll_every, &mr, st);
     rep->mms_iterations = mr.iterations;
-    if (rc == NDTM_EBREAKDOWN) {
+    if (rc != NDTM_OK && rc != NDTM_ENOCONV) {
       rep->status = rc;
       return rc;
     }
@@ -558,7 +569,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, defer, &mr, st, n_pred,
                        region);
     rep->mms_iterations = mr.iterations;
-    if (rc == NDTM_EBREAKDOWN) {
+    if (rc != NDTM_OK && rc != NDTM_ENOCONV) {
       rep->status = rc;
       return rc;
     }
