@@ -425,6 +425,14 @@ enum {
 int ndtm_stream_bandwidth(ndtm_ctx* ctx, size_t bytes, int reps, double* copy_gbs, double* read_gbs,
                           double* write_gbs);
 
+/* Traversal of the hopping stencil (eq:Wilson's H on one parity).  A tuning knob: the
+ * result is bit for bit the same, as every output site sums its eight hops in the same
+ * order.  Output sites are visited in (z, y) tiles of bz x by sites with whole x rows,
+ * each tile marched through t, so that a site's t-neighbours are still in the L2 when
+ * they are read again.  bz = 0: chosen from the L2 size; by = 0: whole y planes.
+ * EINVAL unless bz and by are 0 or divide Lz and Ly. */
+int ndtm_set_stencil_tile(ndtm_ctx* ctx, int bz, int by);
+
 /* mask: bit k enables timing of kernel class k (NDTM_PROF_*); 0 disables. */
 int ndtm_profile_enable(ndtm_ctx* ctx, int mask);
 int ndtm_profile_read(ndtm_ctx* ctx, int kernel_class, double* total_ms, long long* launches,

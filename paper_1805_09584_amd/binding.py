@@ -121,6 +121,7 @@ def load_library():
                                      C.POINTER(C.c_size_t)]),
         "ndtm_set_workspace": (i, [vp, vp, C.c_size_t]),
         "ndtm_trim": (i, [vp]),
+        "ndtm_set_stencil_tile": (i, [vp, i, i]),
         "ndtm_workspace_stats": (i, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                      C.POINTER(C.c_longlong)]),
         "ndtm_profile_moved": (i, [vp, i, C.POINTER(C.c_double)]),
@@ -237,6 +238,9 @@ class Context:
         self._check(self.lib.ndtm_set_workspace(self.h, C.c_void_p(region.data_ptr()),
                                                 region.numel() * region.element_size()))
         self._region = region
+
+    def ndtm_set_stencil_tile(self, bz, by=0):
+        self._check(self.lib.ndtm_set_stencil_tile(self.h, int(bz), int(by)))
 
     def ndtm_trim(self):
         self._check(self.lib.ndtm_trim(self.h))

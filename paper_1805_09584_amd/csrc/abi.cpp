@@ -61,7 +61,27 @@ HalfField half_field(ndtm_ctx* c, const std::string& name, int prec) {
   return f;
 }
 
+// Moves the timed launches that have completed (in launch order per class) into the
+// class totals and their event pairs back to the free list.
+static void harvest_events(ndtm_ctx* c) {
+  for (int k = 0; k < NDTM_PROF_NCLASS; ++k) {
+    auto& used = c->ev_used[k];
+    size_t done = 0;
+    for (; done < used.size(); ++done) {
+      if (hipEventQuery(used[done].second) != hipSuccess) break;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, used[done].first, used[done].second) != hipSuccess) break;
+      c->prof_ms[k] += ms;
+      c->prof_n[k] += 1;
+      c->ev_free.push_back(used[done]);
+    }
+    used.erase(used.begin(), used.begin() + done);
+  }
+}
+
 static std::pair<hipEvent_t, hipEvent_t> take_events(ndtm_ctx* c) {
+  // creating events costs far more than recording them: recycle completed pairs first
+  if (c->ev_free.empty()) harvest_events(c);
   if (!c->ev_free.empty()) {
     auto e = c->ev_free.back();
     c->ev_free.pop_back();
@@ -360,6 +380,15 @@ int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, do
   return NDTM_OK;
 }
 
+int ndtm_set_stencil_tile(ndtm_ctx* c, int bz, int by) {
+  if (!c) return NDTM_EINVAL;
+  if (bz < 0 || (bz > 0 && c->g.Lz % bz != 0) || by < 0 || (by > 0 && c->g.Ly % by != 0))
+    return fail(c, NDTM_EINVAL, "set_stencil_tile: bz, by must be 0 or divide Lz, Ly");
+  c->op.chunk = bz;
+  c->op.chunk_y = by;
+  return NDTM_OK;
+}
+
 int ndtm_stream_bandwidth(ndtm_ctx* c, size_t bytes, int reps, double* copy_gbs, double* read_gbs,
                           double* write_gbs) {
   if (!c) return NDTM_EINVAL;
@@ -402,6 +431,16 @@ int ndtm_stream_bandwidth(ndtm_ctx* c, size_t bytes, int reps, double* copy_gbs,
 int ndtm_profile_enable(ndtm_ctx* c, int on) {
   if (!c) return NDTM_EINVAL;
   c->prof_mask = on;
+  if (on) {
+    // a pool of event pairs made now, outside the region the caller times
+    NDTM_HIP(c, hipSetDevice(c->device));
+    while (c->ev_free.size() < 2048) {
+      std::pair<hipEvent_t, hipEvent_t> e;
+      NDTM_HIP(c, hipEventCreate(&e.first));
+      NDTM_HIP(c, hipEventCreate(&e.second));
+      c->ev_free.push_back(e);
+    }
+  }
   return NDTM_OK;
 }
 

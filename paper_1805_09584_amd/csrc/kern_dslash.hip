@@ -108,7 +108,7 @@ struct HopArgs {
   double* partials;
   const double* skip;
   int T, Lz, Ly, Lx, vh, stride, parity, antiperiodic;
-  int bz;  // z-chunk of the traversal order (divides Lz)
+  int bz, by;  // (z, y) tile of the traversal order (divide Lz, Ly); x rows are whole
   double a, mubar, epsbar, inv_den, ms, hop_coef, sigma;
 };
 
@@ -392,20 +392,26 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   const int q = nb >> 3, rem = nb & 7, xcd = b & 7, loc = b >> 3;
   const int lb = xcd * q + min(xcd, rem) + loc;
   const int f = threadIdx.x & 1;
-  // traversal order: z-chunks of bz planes outermost, then t, z within the chunk,
-  // y, x; the reuse distance of the t-neighbours is bz planes instead of Lz
+  // traversal order: (z, y) tiles of bz x by whole x rows outermost (y tiles fastest),
+  // each marched through t, then z, y, x within the tile.  A site's t-neighbours are
+  // read two tile slices apart and its z, y neighbours within one, so the window the
+  // L2 must hold is a few tile slices instead of a few 3-d slices of the lattice.
   const int o = lb * kSitesPerBlock + (threadIdx.x >> 1);
   const bool valid = o < A.vh;
   const int Lxh = A.Lx >> 1;
-  const int plane = A.Ly * Lxh;
   int h = 0, t = 0, z = 0, y = 0, xh = 0;
   {
-    const int p = o / plane, r = o - p * plane;
-    const int zin = p % A.bz, q = p / A.bz;
-    t = q % A.T;
-    z = (q / A.T) * A.bz + zin;
-    y = r / Lxh;
-    xh = r - y * Lxh;
+    const int row = A.by * Lxh, tslice = A.bz * row, tile = A.T * tslice;
+    const int k = o / tile, r0 = o - k * tile;
+    t = r0 / tslice;
+    const int r1 = r0 - t * tslice;
+    const int zin = r1 / row, r2 = r1 - zin * row;
+    const int yin = r2 / Lxh;
+    xh = r2 - yin * Lxh;
+    const int nty = A.Ly / A.by;
+    const int kz = k / nty, ky = k - kz * nty;
+    z = kz * A.bz + zin;
+    y = ky * A.by + yin;
     h = ((t * A.Lz + z) * A.Ly + y) * Lxh + xh;
   }
   double red = 0.0, red_im = 0.0, red_tt = 0.0;
@@ -615,10 +621,12 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
 }
 
 // Largest divisor bz of Lz whose bz-plane window of input spinors (the reuse
-// distance of the t-neighbours) stays within half of an XCD's 4 MB L2.
+// distance of the t-neighbours) stays within 3 MB of an XCD's 4 MB L2 (a sweep of
+// (z, y) tiles at 96x48^3 found whole-plane chunks of 6 planes best, within 1% of
+// the best y-split tiles).
 int hop_chunk(const Geom& g, int site_bytes) {
   const double plane = (double)g.Ly * (g.Lx / 2);
-  const double budget = 2.0 * 1024.0 * 1024.0;
+  const double budget = 3.0 * 1024.0 * 1024.0;
   int bz = g.Lz;
   while (bz > 1 && (g.Lz % bz != 0 || bz * plane * site_bytes > budget)) --bz;
   return bz;
@@ -650,7 +658,8 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.stride = g.stride;
   A.parity = parity;
   A.antiperiodic = g.antiperiodic;
-  A.bz = hop_chunk(g, sizeof(S) * 24 + (kHalf<S> ? 4 : 0));
+  A.bz = op.chunk > 0 ? op.chunk : hop_chunk(g, sizeof(S) * 24 + (kHalf<S> ? 4 : 0));
+  A.by = op.chunk_y > 0 ? op.chunk_y : g.Ly;
   A.a = op.a;
   A.mubar = op.mubar;
   A.epsbar = op.epsbar;

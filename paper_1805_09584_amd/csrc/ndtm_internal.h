@@ -76,6 +76,8 @@ struct OpParams {
   // optional device flag: a stencil launch returns at once while *skip != 0 (the
   // iterations a solver runs past its done flag before the host sees it)
   const double* skip = nullptr;
+  int chunk = 0;    // z extent of the stencil's traversal tile (divides Lz); 0: from the L2 size
+  int chunk_y = 0;  // y extent (divides Ly); 0: whole planes
 };
 
 // A precision-tagged half field (device pointers).

@@ -4,6 +4,9 @@ Bar: FP64 applications match to 1e-12 relative (norm-wise and per-site max);
 FP32 to 2e-6; FP16 storage (per-site scale, FP32 arithmetic) to 5e-3.
 Lattices: 2^4 (neighbours alias), a ragged one (V/2 not a multiple of the
 128-site block), the 4^4 config and the 16^3x32 config (several hundred blocks).
+Traversal tiles: every operator (all site epilogues) with (z, y) tiles smaller than
+the lattice in both directions, so that tile edges, t-marching and the XCD block
+order are all exercised element by element.
 """
 import numpy as np
 import pytest
@@ -52,7 +55,7 @@ def test_hop_and_qhat_fp64(nd, dims, ap):
     got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT, xd))
     want = op.Q_hat(x)
     assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
-    if dims != (32, 16, 16, 16):
+    if True:
         got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.0123))
         want = op.Q_hat2(x, 0.0123)
         assert rel_err(got, want) < 1e-12
@@ -63,6 +66,38 @@ def test_hop_and_qhat_fp64(nd, dims, ap):
         got = host(ctx.ndtm_apply(nd.NDTM_OP_DFULL, dev(xf), 0.05))
         want = op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=0.05).reshape(xf.shape)
         assert rel_err(got, want) < 1e-12 and site_err(got, want) < 1e-12
+    ctx.close()
+
+
+TILES = [((8, 8, 4, 8), (2, 2), False), ((8, 8, 4, 8), (4, 1), True), ((8, 12, 6, 4), (3, 2), False),
+         ((16, 8, 8, 8), (2, 4), True)]
+
+
+@pytest.mark.parametrize("dims,tile,ap", TILES)
+def test_tiled_traversal_every_operator(nd, dims, tile, ap):
+    print(f"case tiled dims={dims} tile={tile} antiperiodic={ap}", flush=True)
+    lat, op, ctx = _setup(nd, dims, ap, seed=17)
+    ctx.ndtm_set_stencil_tile(*tile)
+    x = synth.gaussian_spinor(dims, 9)
+    xf = synth.gaussian_spinor(dims, 10, "full")
+    xd, xfd = dev(x), dev(xf)
+    refs = [(nd.NDTM_OP_HOP_EO, xd, 0.0, op.H_eo(x)), (nd.NDTM_OP_HOP_OE, xd, 0.0, op.H_oe(x)),
+            (nd.NDTM_OP_QHAT, xd, 0.0, op.Q_hat(x)), (nd.NDTM_OP_QHAT2, xd, 0.031, op.Q_hat2(x, 0.031)),
+            (nd.NDTM_OP_SHAT_SHIFT, xd, 0.17, op.S_shift(x, 0.17)),
+            (nd.NDTM_OP_DFULL, xfd, -0.09, op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=-0.09).reshape(xf.shape))]
+    for prec in (0, 1, 2):
+        for opc, xin, par, want in refs:
+            got = host(ctx.ndtm_apply(opc, xin, par, prec=prec))
+            e = rel_err(got, want)
+            assert e < TOL[prec], (prec, opc, e)
+            if prec == 0:
+                assert site_err(got, want) < 1e-12, (opc, site_err(got, want))
+    # the same results bit for bit as the whole-plane traversal
+    got = host(ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.031))
+    ctx.ndtm_set_stencil_tile(0, 0)
+    assert np.array_equal(got, host(ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.031)))
+    with pytest.raises(nd.NdtmError):
+        ctx.ndtm_set_stencil_tile(dims[1] + 1, 0)
     ctx.close()
 
 

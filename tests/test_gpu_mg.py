@@ -122,9 +122,11 @@ def test_hybrid_config2(nd):
     ctx, op, b, sig, xs, rep = _hybrid(nd, "c2", 9, dict())
     print("report", {k: rep[k] for k in ("iterations", "rounds", "true_res", "guess_res", "t_mms_ms", "t_mg_ms")},
           flush=True)
-    for i in (9, 10, 11):
+    for i in range(12):
         r = rel_residual(op, host(xs[i]), b, sig[i])
         assert r <= 1e-10, (i, r)
+        # the three smallest shifts are the multigrid's (case C), none fell back to CG
+        assert rep["method"][i] == (1 if i >= 9 else 0), rep["method"]
     ctx.close()
 
 

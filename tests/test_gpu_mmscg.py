@@ -64,13 +64,14 @@ def test_mmscg_config1(nd):
     ctx.close()
 
 
-def test_mmscg_config2_sampled(nd):
+def test_mmscg_config2_every_shift(nd):
     print("case c2 plain MMS-CG", flush=True)
     ctx, op, b, sig = _ctx(nd, "c2")
     xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=1e-10))
-    for i in (0, 6, 11):
+    for i in range(len(sig)):
         r = rel_residual(op, host(xs[i]), b, sig[i])
         assert r <= 1e-10, (i, r)
+        assert rep["method"][i] == 0
     print("c2 report", rep["mms_iterations"], rep["iterations"], rep["t_total_ms"], flush=True)
     ctx.close()
 
