@@ -133,6 +133,20 @@ int ndtm_set_shifts(ndtm_ctx* ctx, int n, const double* sigma);
 int ndtm_apply(ndtm_ctx* ctx, int op, int prec, void* y_dev, const void* x_dev,
                double param, void* stream);
 
+/* ndtm_apply without device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  FP64 only,
+ * same operators and layouts as ndtm_apply, same results bit for bit.  Its four
+ * internal half fields live in a fixed device array of ndtm_apply_noalloc_max_bytes()
+ * bytes (128 MiB) that each GPU the library runs on holds until the process ends; a
+ * lattice needing more (4 x 24 x (V/2 rounded up to 256, + 256) x 16 bytes, about
+ * V/2 <= 87,000 sites) is refused with NDTM_EINVAL.  The array is shared by all calls
+ * on one GPU and keeps the last call's contents: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  No hipMalloc, hipFree
+ * or other allocating call is made.  Errors as ndtm_apply; NDTM_EHIP if the array's
+ * device address could not be resolved when the context was created. */
+int ndtm_apply_noalloc(ndtm_ctx* ctx, int op, void* y_dev, const void* x_dev, double param, void* stream);
+size_t ndtm_apply_noalloc_max_bytes(void);
+
 /* ---- multigrid (section 3, section 3.2) -------------------------------- */
 typedef struct {
   int block[4];        /* aggregate extents {bt,bz,by,bx}; each divides the dim */

@@ -122,6 +122,8 @@ def load_library():
         "ndtm_set_workspace": (i, [vp, vp, C.c_size_t]),
         "ndtm_trim": (i, [vp]),
         "ndtm_set_stencil_tile": (i, [vp, i, i]),
+        "ndtm_apply_noalloc": (i, [vp, i, vp, vp, d, vp]),
+        "ndtm_apply_noalloc_max_bytes": (C.c_size_t, []),
         "ndtm_workspace_stats": (i, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                      C.POINTER(C.c_longlong)]),
         "ndtm_profile_moved": (i, [vp, i, C.POINTER(C.c_double)]),
@@ -255,6 +257,13 @@ class Context:
         if out is None:
             out = torch.empty_like(x)
         self._check(self.lib.ndtm_apply(self.h, op, prec, _ptr(out), _ptr(x), float(param), _stream()))
+        return out
+
+    def ndtm_apply_noalloc(self, op, x, param=0.0, out=None):
+        """ndtm_apply in FP64 with the library's fixed scratch array (no device allocation)."""
+        if out is None:
+            out = torch.empty_like(x)
+        self._check(self.lib.ndtm_apply_noalloc(self.h, op, _ptr(out), _ptr(x), float(param), _stream()))
         return out
 
     # -- multigrid ------------------------------------------------------------

@@ -192,6 +192,7 @@ int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NDTM_EHIP;
   if (hipSetDevice(device) != hipSuccess) return NDTM_EHIP;
+  noalloc_setup(device);
   ndtm_ctx* c = new (std::nothrow) ndtm_ctx();
   if (!c) return NDTM_ENOMEM;
   c->device = device;

@@ -88,6 +88,8 @@ void dev_free(ndtm_ctx* c, void* p);
 size_t dev_largest_free(const ndtm_ctx* c);  // largest block dev_alloc could still return
 int arena_set(ndtm_ctx* c, void* dev, size_t bytes);
 void arena_release(ndtm_ctx* c);
+// resolves this device's address of the fixed scratch array of ndtm_apply_noalloc
+void noalloc_setup(int device);
 // bytes of the named buffer (0 if absent)
 size_t ws_bytes(const ndtm_ctx* c, const std::string& name);
 
