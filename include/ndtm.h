@@ -67,6 +67,7 @@ typedef enum {
 } ndtm_status;
 
 #define NDTM_MAX_SHIFTS 16
+#define NDTM_NMMS_AUTO (-1)
 
 /* Precision of the stencil / multigrid inner work. */
 enum { NDTM_PREC_F64 = 0, NDTM_PREC_F32 = 1, NDTM_PREC_F16 = 2 };
@@ -235,8 +236,14 @@ typedef struct {
   int maxiter;         /* MMS-CG iteration cap */
   int n_mmscg;         /* shifts solved by MMS-CG (the largest ones); the
                           rest go to the multigrid; >= number of shifts means
-                          plain MMS-CG for all (ndtm_hybrid_split evaluates the
-                          section 4.4 cost model for a choice) */
+                          plain MMS-CG for all.  NDTM_NMMS_AUTO: chosen by the
+                          cost model of section 4.4 (eq:costwo, as ndtm_hybrid_split)
+                          from this context's spectrum estimate of Q^2 and its measured
+                          costs of one multi-shift iteration and of one multigrid shift
+                          (the mean over earlier solves); while no multigrid shift has
+                          been timed on a context with a multigrid setup, one shift goes
+                          to the multigrid so that its cost is measured; without a
+                          setup or a spectrum estimate, all shifts go to MMS-CG */
   int guess;           /* NDTM_GUESS_* for the multigrid shifts */
   int precision;       /* NDTM_PREC_F64: FP64 throughout.  NDTM_PREC_F16: mixed form, the
                           multi-shift CG runs on FP16 stencil storage (one FP32 scale per
@@ -286,6 +293,7 @@ typedef struct {
   double t_mms_ms, t_guess_ms, t_mg_ms, t_total_ms;
   double hop_ms;                    /* summed duration of FP64 stencil launches (if profiling) */
   long long hop_launches;
+  int n_mmscg;                      /* shifts the multi-shift CG solved (the choice of NDTM_NMMS_AUTO) */
 } ndtm_solve_report;
 
 /* Solves all shifts for one b.  x_dev[i] receives the solution of the i-th

@@ -33,8 +33,48 @@ def _ext(dims):
     return [T, X, Y, Z]  # extent along direction mu
 
 
-def dense_D_ND(dims, U, kappa, mubar, epsbar, antiperiodic_t=False, odd_shift=0.0):
-    """Dense D_ND (optionally + i*odd_shift*(Gamma5 x tau1) on odd sites) on the full lattice."""
+def _link(U, dims, c, mu):
+    return U[_site(c, dims), mu]
+
+
+def _step(c, mu, d, dims):
+    e = list(c)
+    ext = _ext(dims)
+    e[mu] = (c[mu] + d) % ext[mu]
+    return e
+
+
+def dense_clover_site(U, dims, s, csw):
+    """The clover term of eq:Wilson at site s, 12x12 over (spin, colour), walked out
+    leaf by leaf with explicit coordinate steps (a second spelling of oracle.clover)."""
+    c = _coords(s, dims)
+    C = np.zeros((12, 12), dtype=np.complex128)
+    dag = lambda m: m.conj().T
+    for mu in range(4):
+        for nu in range(4):
+            if mu == nu:
+                continue
+            Q = {}
+            for a, b in ((mu, nu), (nu, mu)):
+                xa = _step(c, a, 1, dims)
+                xb = _step(c, b, 1, dims)
+                xab = _step(xb, a, -1, dims)      # x + b - a
+                xma = _step(c, a, -1, dims)        # x - a
+                xmab = _step(xma, b, -1, dims)     # x - a - b
+                xmb = _step(c, b, -1, dims)        # x - b
+                xmba = _step(xmb, a, 1, dims)      # x - b + a
+                L = lambda cc, d: _link(U, dims, cc, d)
+                Q[(a, b)] = (L(c, a) @ L(xa, b) @ dag(L(xb, a)) @ dag(L(c, b))
+                             + L(c, b) @ dag(L(xab, a)) @ dag(L(xma, b)) @ L(xma, a)
+                             + dag(L(xma, a)) @ dag(L(xmab, b)) @ L(xmab, a) @ L(xmb, b)
+                             + dag(L(xmb, b)) @ L(xmb, a) @ L(xmba, b) @ dag(L(c, a)))
+            C += np.kron(GAMMA[mu] @ GAMMA[nu], Q[(mu, nu)] - Q[(nu, mu)])
+    return -csw / 32.0 * C
+
+
+def dense_D_ND(dims, U, kappa, mubar, epsbar, antiperiodic_t=False, odd_shift=0.0, csw=0.0):
+    """Dense D_ND (optionally + i*odd_shift*(Gamma5 x tau1) on odd sites, and with the
+    clover term of eq:Wilson for csw != 0) on the full lattice."""
     V = int(np.prod(dims))
     U = np.asarray(U).reshape(V, 4, 3, 3)
     n = V * 24
@@ -48,6 +88,10 @@ def dense_D_ND(dims, U, kappa, mubar, epsbar, antiperiodic_t=False, odd_shift=0.
         par = sum(c) % 2
         blk = site_blk + (1j * odd_shift * g5t1 if par == 1 else 0)
         D[s * 24:(s + 1) * 24, s * 24:(s + 1) * 24] += np.kron(blk, np.eye(3))
+        if csw != 0.0:
+            Cs = dense_clover_site(U, dims, s, csw)
+            for f in range(2):
+                D[s * 24 + f * 12:s * 24 + f * 12 + 12, s * 24 + f * 12:s * 24 + f * 12 + 12] += Cs
         for mu in range(4):
             # forward neighbour
             cf = list(c)

@@ -10,7 +10,8 @@ eq:non-degenerate, eq:D(mu), eq:Wilson, eq:g5tau1-hermiticity and the even-odd
 reduction paragraph.
 
 Readings where the paper is silent (listed in the design notes as well):
-* the site term of eq:Wilson is a = m + 4 = 1/(2 kappa); the clover term is off;
+* the site term of eq:Wilson is a = m + 4 = 1/(2 kappa); the clover term is off
+  unless c_sw is given (oracle/clover.py holds its reading of Q_mu_nu);
 * chiral gamma basis gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i s_k],[i s_k,0]],
   which gives gamma_5 = gamma_0 gamma_1 gamma_2 gamma_3 = diag(1,1,-1,-1) as the
   paper states;
@@ -140,11 +141,12 @@ class NDOperator:
     D_W  = a - H/2 with a = 1/(2 kappa)     (eq:Wilson with m + 4 = a, c_sw = 0).
     """
 
-    def __init__(self, lat: Lattice, kappa, mubar, epsbar):
+    def __init__(self, lat: Lattice, kappa, mubar, epsbar, csw=0.0):
         self.lat = lat
         self.a = 1.0 / (2.0 * kappa)
         self.mubar = float(mubar)
         self.epsbar = float(epsbar)
+        self.csw = float(csw)
         # 8x8 site block over (flavour, spin) in kron(flavour, spin) order.
         self.A_block = (self.a * np.eye(8) + 1j * self.mubar * np.kron(TAU3, GAMMA5)
                         - self.epsbar * np.kron(TAU1, np.eye(4)))
@@ -156,6 +158,18 @@ class NDOperator:
         self.Ainv_block = (self.a * np.eye(8) - 1j * self.mubar * np.kron(TAU3, GAMMA5)
                            + self.epsbar * np.kron(TAU1, np.eye(4))) / den
         self.G5T1_block = np.kron(TAU1, GAMMA5)
+        if self.csw != 0.0:
+            # with the clover term of eq:Wilson the site term varies by site: the 24x24 matrix
+            # (a + C(x)) x I_2 + i mubar Gamma5 x tau3 - epsbar tau1 over (flavour, spin,
+            # colour), inverted numerically on every site
+            from .clover import clover_term
+            C = clover_term(lat.U, self.csw).reshape(lat.V, 12, 12)
+            self.C_site = C
+            twist = np.kron(1j * self.mubar * np.kron(TAU3, GAMMA5) - self.epsbar * np.kron(TAU1, np.eye(4)),
+                            np.eye(3))
+            self.A_site = np.einsum("fg,vij->vfigj", np.eye(2), self.a * np.eye(12) + C).reshape(lat.V, 24, 24)
+            self.A_site = self.A_site + twist
+            self.Ainv_site = np.linalg.inv(self.A_site)
 
     # site-local (flavour, spin) blocks acting on [..., f, s, c]
     @staticmethod
@@ -164,11 +178,33 @@ class NDOperator:
         v = psi.reshape(sh[:-3] + (8, 3))
         return np.einsum("ij,...jc->...ic", block8, v).reshape(sh)
 
+    @staticmethod
+    def _per_site(mats, psi):
+        sh = psi.shape
+        v = psi.reshape(mats.shape[0], 24)
+        return np.einsum("vij,vj->vi", mats, v).reshape(sh)
+
     def A(self, psi):
-        return self._site(self.A_block, psi)
+        """Site term on a full-lattice doublet (dims + (2, 4, 3))."""
+        if self.csw == 0.0:
+            return self._site(self.A_block, psi)
+        return self._per_site(self.A_site, psi)
+
+    def A_odd(self, v_odd):
+        if self.csw == 0.0:
+            return self._site(self.A_block, v_odd)
+        return self._per_site(self.A_site[self.lat.odd_sites], v_odd)
 
     def Ainv(self, psi):
-        return self._site(self.Ainv_block, psi)
+        """Inverse site term on a full-lattice doublet."""
+        if self.csw == 0.0:
+            return self._site(self.Ainv_block, psi)
+        return self._per_site(self.Ainv_site, psi)
+
+    def Ainv_even(self, v_even):
+        if self.csw == 0.0:
+            return self._site(self.Ainv_block, v_even)
+        return self._per_site(self.Ainv_site[self.lat.even_sites], v_even)
 
     def g5t1(self, psi):
         return self._site(self.G5T1_block, psi)
@@ -191,8 +227,8 @@ class NDOperator:
 
     def S_hat(self, v_odd):
         """Odd-site Schur complement S = A - 1/4 H_oe A^-1 H_eo (even-odd reduction, section 2)."""
-        t = self.Ainv(self.H_eo(v_odd))
-        return self.A(v_odd) - 0.25 * self.H_oe(t)
+        t = self.Ainv_even(self.H_eo(v_odd))
+        return self.A_odd(v_odd) - 0.25 * self.H_oe(t)
 
     def Q_hat(self, v_odd):
         """Q = (Gamma5 x tau1) S, Hermitian by eq:g5tau1-hermiticity."""

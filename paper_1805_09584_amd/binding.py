@@ -14,6 +14,7 @@ NDTM_OK = 0
 NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16 = 0, 1, 2
 (NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
  NDTM_OP_HOP_OE) = range(6)
+NDTM_NMMS_AUTO = -1
 NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP, NDTM_GUESS_PROJECTION, NDTM_GUESS_MMS = 0, 1, 2, 3, 4
 PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
                 "coarse")
@@ -56,12 +57,12 @@ class SolveReport(C.Structure):
                 ("rounds", _I16), ("true_res", _D16), ("guess_res", _D16), ("lagrange_res", _D16),
                 ("mlp_res", _D16), ("guess_kind", _I16), ("t_mms_ms", C.c_double),
                 ("t_guess_ms", C.c_double), ("t_mg_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("hop_ms", C.c_double), ("hop_launches", C.c_longlong)]
+                ("hop_ms", C.c_double), ("hop_launches", C.c_longlong), ("n_mmscg", C.c_int)]
 
     def to_dict(self):
         n = self.n_shifts
         d = {k: getattr(self, k) for k in ("status", "n_shifts", "mms_iterations", "t_mms_ms", "t_guess_ms",
-                                          "t_mg_ms", "t_total_ms", "hop_ms", "hop_launches")}
+                                          "t_mg_ms", "t_total_ms", "hop_ms", "hop_launches", "n_mmscg")}
         for k in ("sigma", "input_index", "method", "iterations", "rounds", "true_res", "guess_res",
                   "lagrange_res", "mlp_res", "guess_kind"):
             d[k] = list(getattr(self, k)[:n])

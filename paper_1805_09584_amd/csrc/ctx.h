@@ -55,6 +55,10 @@ struct ndtm_ctx {
   // extreme eigenvalues of Q^2 from the base system's Lanczos coefficients of the last
   // FP64 multi-shift solve (<= 0 while unknown)
   double est_lmin = -1, est_lmax = -1;
+  // measured costs for the section 4.4 cost model: mean milliseconds per FP64 multi-shift
+  // iteration and per multigrid shift (guess and case C), with their sample counts
+  double cost_iter_ms = 0, cost_mg_ms = 0;
+  long long cost_iter_n = 0, cost_mg_n = 0;
   ndtm::MLPData* mlp = nullptr;
   // device storage (memory.cpp): caller region or hipMalloc per buffer
   ndtm::Arena* arena = nullptr;
@@ -168,6 +172,7 @@ struct GramCache {
 int cg_shift(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
              double* res_out, int* iters_out, hipStream_t st);
 int guess_first_node(const std::vector<double>& nodes, double sig_t);
+bool mg_ready(const ndtm_ctx* c);  // a multigrid setup is in place
 double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma,
                      const HalfField& r, hipStream_t st);
 

@@ -435,6 +435,8 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
   return res <= p->tol ? NDTM_OK : NDTM_ENOCONV;
 }
 
+bool mg_ready(const ndtm_ctx* c) { return c->mg && c->mg->ready; }
+
 // Lagrange coefficients l_i(target) over the nodes (section 4.2, appendix B).
 static std::vector<double> lagrange(const std::vector<double>& nodes, double t) {
   const size_t k = nodes.size();

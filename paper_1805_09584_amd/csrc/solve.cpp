@@ -511,7 +511,22 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     NDTM_HIP(c, hipStreamSynchronize(st));
     return NDTM_OK;
   }
-  const int n_mms = std::max(1, std::min(p->n_mmscg, nsh));
+  int n_req = p->n_mmscg;
+  if (n_req == NDTM_NMMS_AUTO) {
+    // section 4.4: n minimising c_HY(n) = t_CG(m_n^2) + sum_{i>n} t_MG(m_i^2) (eq:costwo)
+    n_req = nsh;
+    const bool mg = c->mg != nullptr && mg_ready(c);
+    if (mg && c->cost_mg_n == 0 && nsh > 1) {
+      n_req = nsh - 1;  // measure one multigrid shift first
+    } else if (mg && c->est_lmin > 0 && c->cost_iter_n > 0) {
+      int n = nsh;
+      if (hybrid_choose(nsh, sig.data(), c->est_lmin, c->est_lmax, p->tol, c->cost_iter_ms, c->cost_mg_ms, &n,
+                        nullptr) == NDTM_OK)
+        n_req = n;
+    }
+  }
+  const int n_mms = std::max(1, std::min(n_req, nsh));
+  rep->n_mmscg = n_mms;
   int status = NDTM_OK;
   // ---- MMS-CG for the n_mms largest shifts ----
   if (p->precision == NDTM_PREC_F16) {
@@ -577,6 +592,11 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       c->est_lmin = mr.lam_lo;
       c->est_lmax = mr.lam_hi;
     }
+    if (mr.iterations > 0) {
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      c->cost_iter_ms = (c->cost_iter_ms * c->cost_iter_n + ms / mr.iterations) / (c->cost_iter_n + 1);
+      ++c->cost_iter_n;
+    }
     HalfField R = half_field(c, "sv_r", P64);
     for (int i = 0; i < n_mms; ++i) {
       rep->method[i] = 0;
@@ -601,7 +621,15 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     void* region = ws_get(c, "sv_region", std::max(ws_bytes(c, "sv_region"), fields * n * sizeof(double2)));
     if (!region) return fail(c, NDTM_ENOMEM, "solve: phase region");
     RegionScope rs(c, region, fields);
+    const double g0 = rep->t_guess_ms, m0 = rep->t_mg_ms;
     int rc = solve_mg_shifts(c, sig, n_mms, n_pred, xs, B, p, rep, st);
+    // multigrid cost per shift, guesses included (a shift whose predicted guess already
+    // meets tol costs only its residual check)
+    if (rc == NDTM_OK && p->precision != NDTM_PREC_F16) {
+      const double ms = (rep->t_guess_ms - g0 + rep->t_mg_ms - m0) / (nsh - n_mms);
+      c->cost_mg_ms = (c->cost_mg_ms * c->cost_mg_n + ms) / (c->cost_mg_n + 1);
+      ++c->cost_mg_n;
+    }
     if (rc != NDTM_OK && status == NDTM_OK) status = rc;
 
   }

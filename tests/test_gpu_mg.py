@@ -435,3 +435,36 @@ def test_coarse_solve_multi_fp32_cycle_and_one_system(nd):
     assert rel_err(got, single) < 1e-4
     assert abs(rg - rs) <= 1e-3 * rs + 1e-6
     ctx.close()
+
+
+def test_automatic_hybrid_split(nd):
+    """n_mmscg = NDTM_NMMS_AUTO: without a multigrid setup every shift goes to the
+    multi-shift CG; with one, the first solve sends one shift to the multigrid (its
+    cost is measured), later ones take the cost model's n (section 4.4), and every
+    shift still meets 1e-10 by the oracle's residual."""
+    print("case automatic hybrid split c1", flush=True)
+    c = synth.CONFIGS["c1"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    sig = c["shifts"]
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_shifts(list(sig))
+    sp = ctx.solve_params(n_mmscg=nd.NDTM_NMMS_AUTO, use_graphs=0)
+    _, rep = ctx.ndtm_solve(dev(b), sp)
+    assert rep["n_mmscg"] == len(sig)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=(2, 2, 2, 2), n_vec=8))
+    xs, rep = ctx.ndtm_solve(dev(b), sp)
+    assert rep["n_mmscg"] == len(sig) - 1
+    chosen = []
+    for _ in range(2):
+        xs, rep = ctx.ndtm_solve(dev(b), sp)
+        chosen.append(rep["n_mmscg"])
+        for i, s in enumerate(sig):
+            assert rel_residual(op, host(xs[i]), b, s) <= 1e-10
+    assert all(1 <= n <= len(sig) for n in chosen)
+    print("auto n", chosen, flush=True)
+    ctx.close()
