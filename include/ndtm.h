@@ -116,6 +116,18 @@ int ndtm_set_gauge(ndtm_ctx* ctx, const void* U_dev, void* stream);
  * closed-form inverse of the site block A).  Invalidates the coarse operator. */
 int ndtm_set_params(ndtm_ctx* ctx, double kappa, double mubar, double epsbar);
 
+/* The clover term of eq:Wilson, -c_sw/32 sum_{mu,nu} (gamma_mu gamma_nu) x (Q_mu_nu - Q_nu_mu),
+ * with Q_mu_nu(x) the sum of the four plaquettes of the mu-nu plane at x (clover leaf), added
+ * to the site term a; c_sw = 0 (the default) switches it off.  The site blocks (a + C per
+ * site and chirality, and on the even sites the inverse of the doublet's site block through
+ * N = ((a + C)^2 + mubar^2 - epsbar^2)^-1) are built on the device when the gauge field and
+ * the parameters are set, and rebuilt by set_gauge / set_params; every operator, solve and
+ * multigrid setup then uses them (the Galerkin coarse operator gets P^+ C P).  Invalidates
+ * any multigrid setup.  EINVAL for non-finite c_sw or site blocks that cannot be inverted;
+ * ENOMEM if the storage (about 3 x 72 x V/2 doubles and as many floats) is not there.
+ * Synchronises the device. */
+int ndtm_set_clover(ndtm_ctx* ctx, double csw);
+
 /* n in [1, NDTM_MAX_SHIFTS] shifts sigma_i = m_i^2 > 0, any order, distinct
  * (eq:shifted_linear).  The solve orders them descending internally
  * (section 4.2: sigma_1 > sigma_2 > ...). */
@@ -310,7 +322,8 @@ int ndtm_solve(ndtm_ctx* ctx, void* const* x_dev, const void* b_dev,
  * multigrid data of section 3).
  *
  * ndtm_workspace_bytes: an upper bound, in *bytes, on the lattice storage that
- * set_gauge, apply (any op and precision), mg_setup with *mg and the multigrid
+ * set_gauge (with the clover term if c_sw is already set), apply (any op and
+ * precision), mg_setup with *mg and the multigrid
  * calls, and solve / solve_rational with *sp for n_shifts shifts need together
  * (mg or sp NULL: that part left out; the learned-guess training calls with batch B
  * need about B x 35 KB more).  EINVAL for a null ctx or bytes, n_shifts outside

@@ -93,6 +93,7 @@ def load_library():
         "ndtm_set_gauge": (i, [vp, vp, vp]),
         "ndtm_set_params": (i, [vp, d, d, d]),
         "ndtm_set_shifts": (i, [vp, i, C.POINTER(C.c_double)]),
+        "ndtm_set_clover": (i, [vp, d]),
         "ndtm_apply": (i, [vp, i, i, vp, vp, d, vp]),
         "ndtm_mg_default_params": (None, [C.POINTER(MGParams)]),
         "ndtm_mg_setup": (i, [vp, C.POINTER(MGParams), vp, vp]),
@@ -217,6 +218,9 @@ class Context:
 
     def ndtm_set_params(self, kappa, mubar, epsbar):
         self._check(self.lib.ndtm_set_params(self.h, kappa, mubar, epsbar))
+
+    def ndtm_set_clover(self, csw):
+        self._check(self.lib.ndtm_set_clover(self.h, float(csw)))
 
     def ndtm_set_shifts(self, sigma):
         arr = (C.c_double * len(sigma))(*[float(s) for s in sigma])

@@ -172,11 +172,61 @@ double2 dot_host(ndtm_ctx* c, const double2* x, const double2* y, size_t n, hipS
   return make_double2(c->hscal[0], c->hscal[1]);
 }
 
+int clover_build(ndtm_ctx* c, hipStream_t st) {
+  if (c->csw == 0.0) {
+    c->op.clover = 0;
+    return NDTM_OK;
+  }
+  if (!c->have_gauge || !c->have_params) return NDTM_OK;  // built once both are set
+  const size_t sm = (size_t)72 * c->g.stride, si = (size_t)144 * c->g.stride;
+  for (int q = 0; q < 2; ++q) {
+    const size_t es = q == 0 ? 8 : 4;
+    for (int par = 0; par < 2; ++par)
+      if (!c->clv_m[q][par] && !(c->clv_m[q][par] = dev_alloc(c, sm * es)))
+        return fail(c, NDTM_ENOMEM, "clover: site blocks");
+    if (!c->clv_inv[q] && !(c->clv_inv[q] = dev_alloc(c, si * es))) return fail(c, NDTM_ENOMEM, "clover: site blocks");
+  }
+  if (!c->clv_bad && !(c->clv_bad = static_cast<unsigned*>(dev_alloc(c, 256))))
+    return fail(c, NDTM_ENOMEM, "clover: counter");
+  unsigned bad[2] = {0, 0};
+  for (int par = 0; par < 2; ++par) {
+    launch_clover_build(c->g, (const double2*)c->U[P64][0], (const double2*)c->U[P64][1], par, c->op.a, c->csw,
+                        c->mubar, c->epsbar, (double*)c->clv_m[0][par], par == 0 ? (double*)c->clv_inv[0] : nullptr,
+                        c->clv_bad, st);
+    NDTM_HIP(c, hipMemcpyAsync(&bad[par], c->clv_bad, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    NDTM_HIP(c, hipStreamSynchronize(st));
+    launch_to_f32((const double*)c->clv_m[0][par], (float*)c->clv_m[1][par], (long)sm, st);
+  }
+  launch_to_f32((const double*)c->clv_inv[0], (float*)c->clv_inv[1], (long)si, st);
+  NDTM_HIP(c, hipGetLastError());
+  NDTM_HIP(c, hipStreamSynchronize(st));
+  if (bad[0] + bad[1]) {
+    c->op.clover = 0;
+    return fail(c, NDTM_EINVAL, "clover: M^2 + mubar^2 - epsbar^2 is singular on " + std::to_string(bad[0] + bad[1]) +
+                                    " site blocks");
+  }
+  for (int q = 0; q < 2; ++q) {
+    for (int par = 0; par < 2; ++par) c->op.clv_m[q][par] = c->clv_m[q][par];
+    c->op.clv_inv[q] = c->clv_inv[q];
+  }
+  c->op.clover = 1;
+  return NDTM_OK;
+}
+
 }  // namespace ndtm
 
 using namespace ndtm;
 
 extern "C" {
+
+int ndtm_set_clover(ndtm_ctx* c, double csw) {
+  if (!c) return NDTM_EINVAL;
+  if (!std::isfinite(csw)) return fail(c, NDTM_EINVAL, "set_clover: c_sw must be finite");
+  NDTM_HIP(c, hipSetDevice(c->device));
+  c->csw = csw;
+  ndtm_mg_free(c);
+  return clover_build(c, nullptr);
+}
 
 int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
   if (!dims || !out) return NDTM_EINVAL;
@@ -235,6 +285,12 @@ void ndtm_destroy(ndtm_ctx* c) {
   c->bufs.clear();
   for (int p = 0; p < 3; ++p)
     for (int q = 0; q < 2; ++q) dev_free(c, c->U[p][q]);
+  for (int q = 0; q < 2; ++q) {
+    dev_free(c, c->clv_m[q][0]);
+    dev_free(c, c->clv_m[q][1]);
+    dev_free(c, c->clv_inv[q]);
+  }
+  dev_free(c, c->clv_bad);
   arena_release(c);
   if (c->partials) (void)hipFree(c->partials);
   if (c->dscal) (void)hipFree(c->dscal);
@@ -292,7 +348,7 @@ int ndtm_set_gauge(ndtm_ctx* c, const void* U_dev, void* stream) {
   }
   c->have_gauge = true;
   ndtm_mg_free(c);
-  return NDTM_OK;
+  return clover_build(c, st);
 }
 
 int ndtm_set_params(ndtm_ctx* c, double kappa, double mubar, double epsbar) {
@@ -311,7 +367,7 @@ int ndtm_set_params(ndtm_ctx* c, double kappa, double mubar, double epsbar) {
   c->op.inv_den = 1.0 / den;
   c->have_params = true;
   ndtm_mg_free(c);
-  return NDTM_OK;
+  return clover_build(c, nullptr);
 }
 
 int ndtm_set_shifts(ndtm_ctx* c, int n, const double* sigma) {

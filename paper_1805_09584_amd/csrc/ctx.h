@@ -34,6 +34,11 @@ struct ndtm_ctx {
   double su3_dev = 0;  // max deviation of the stored links from SU(3) row structure
   std::vector<double> shifts;
   void* U[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
+  // clover term (eq:Wilson): c_sw and the site blocks [FP64, FP32][parity], even inverse
+  double csw = 0;
+  void* clv_m[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  void* clv_inv[2] = {nullptr, nullptr};
+  unsigned* clv_bad = nullptr;
   double* partials = nullptr;
   double* vred = nullptr;  // single-launch reduction workspace: [counter][partials]
   size_t partials_n = 0;
@@ -92,6 +97,8 @@ void dev_free(ndtm_ctx* c, void* p);
 size_t dev_largest_free(const ndtm_ctx* c);  // largest block dev_alloc could still return
 int arena_set(ndtm_ctx* c, void* dev, size_t bytes);
 void arena_release(ndtm_ctx* c);
+// (re)builds the clover site blocks from the links and parameters (no-op when c_sw = 0)
+int clover_build(ndtm_ctx* c, hipStream_t st);
 // resolves this device's address of the fixed scratch array of ndtm_apply_noalloc
 void noalloc_setup(int device);
 // bytes of the named buffer (0 if absent)

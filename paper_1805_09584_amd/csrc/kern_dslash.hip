@@ -107,6 +107,11 @@ struct HopArgs {
   const float* zs_sc;
   double* partials;
   const double* skip;
+  // clover site blocks of the output parity (packed Hermitian 6x6 per chirality, component
+  // arrays of `stride` entries in the arithmetic precision): M = a + C (72 arrays) and, for
+  // the even parity, N and M N (144 arrays); null without the clover term
+  const typename RealOf<S>::T* clm;
+  const typename RealOf<S>::T* clinv;
   int T, Lz, Ly, Lx, vh, stride, parity, antiperiodic;
   int bz, by;  // (z, y) tile of the traversal order (divide Lz, Ly); x rows are whole
   double a, mubar, epsbar, inv_den, ms, hop_coef, sigma;
@@ -209,6 +214,31 @@ __device__ __forceinline__ void load_flav(cx<R> (&v)[4][3], const S* p, const fl
         else v[sp][c] = cvt(*q);
       }
   }
+}
+
+// y = H u for one chirality chi of v (spins 2 chi, 2 chi + 1), H a packed Hermitian 6x6
+// (6 real diagonal entries, then the upper entries row by row as re, im) stored as
+// component arrays starting at comp0.
+template <class R, class CT>
+__device__ __forceinline__ void herm6(const CT* base, int stride, int h, int comp0, const cx<R> (&v)[4][3], int chi,
+                                      cx<R> (&y)[6]) {
+  cx<R> u[6];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[q * 3 + c] = v[2 * chi + q][c];
+  const unsigned off = (unsigned)h * (unsigned)sizeof(CT);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) y[i] = R(*at(base, (long)(comp0 + i) * stride, off)) * u[i];
+  int k = 6;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 6; ++j, k += 2) {
+      const cx<R> e = {R(*at(base, (long)(comp0 + k) * stride, off)), R(*at(base, (long)(comp0 + k + 1) * stride, off))};
+      y[i] = cmac(y[i], e, u[j]);
+      y[j] = cmacc(y[j], e, u[i]);
+    }
 }
 
 // Raw operands of one hop in storage precision: the neighbour spinor of the
@@ -383,7 +413,7 @@ __device__ __forceinline__ void block_reduce_store3(double v0, double v1, double
   }
 }
 
-template <class S, class L, int EPI, int RED, bool R12>
+template <class S, class L, int EPI, int RED, bool R12, bool CLV>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   using R = typename RealOf<S>::T;
   if (A.skip && *A.skip != 0.0) return;
@@ -495,6 +525,25 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) out[s][c] = acc[s][c];
+  } else if constexpr (EPI == EPI_AINV && CLV) {
+    // A^-1 acc with the clover term: M N acc_f - i mubar g5 tau3 N acc_f + epsbar N acc_{1-f}
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+      cx<R> nu[6], mnu[6];
+      if (valid) {
+        herm6(A.clinv, A.stride, h, 36 * chi, acc, chi, nu);
+        herm6(A.clinv, A.stride, h, 72 + 36 * chi, acc, chi, mnu);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) nu[i] = mnu[i] = {0, 0};
+      }
+      const R g5 = chi == 0 ? R(1) : R(-1);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const cx<R> o = shfl1(nu[i]);
+        out[2 * chi + i / 3][i % 3] = mnu[i] - (mub * g5 * t3) * ipl(nu[i]) + eps * o;
+      }
+    }
   } else if constexpr (EPI == EPI_AINV) {
     const R id = R(A.inv_den);
 #pragma unroll
@@ -516,14 +565,35 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
     if (valid) load_flav<S, R, true>(xv, A.xs, A.xs_sc, f, A.stride, h);
     const R hc = (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) ? R(-0.25) : R(A.hop_coef);
     const R ms = R(A.ms);
+    // the site's own term a x, or M x = (a + C) x with the clover term
+    cx<R> mx[4][3];
+    if constexpr (CLV) {
+#pragma unroll
+      for (int chi = 0; chi < 2; ++chi) {
+        cx<R> y6[6];
+        if (valid) {
+          herm6(A.clm, A.stride, h, 36 * chi, xv, chi, y6);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) y6[i] = {0, 0};
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) mx[2 * chi + i / 3][i % 3] = y6[i];
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mx[s][c] = a * xv[s][c];
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const R g5 = s < 2 ? R(1) : R(-1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const cx<R> xo = shfl1(xv[s][c]);
-        // y_f = a x_f + i mubar g5 tau3 x_f - epsbar x_{1-f} + hc acc_f (+ i ms g5 x_{1-f})
-        cx<R> y = a * xv[s][c] + (mub * g5 * t3) * ipl(xv[s][c]) - eps * xo + hc * acc[s][c];
+        // y_f = M x_f + i mubar g5 tau3 x_f - epsbar x_{1-f} + hc acc_f (+ i ms g5 x_{1-f})
+        cx<R> y = mx[s][c] + (mub * g5 * t3) * ipl(xv[s][c]) - eps * xo + hc * acc[s][c];
         if constexpr (EPI == EPI_SITE) y = y + (ms * g5) * ipl(xo);
         out[s][c] = y;
       }
@@ -650,6 +720,11 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.zs_sc = zs ? zs->sc : nullptr;
   A.partials = partials;
   A.skip = op.skip;
+  using CT = typename RealOf<S>::T;
+  const int cp = std::is_same<S, double2>::value ? 0 : 1;
+  A.clm = static_cast<const CT*>(op.clv_m[cp][parity]);
+  A.clinv = parity == 0 ? static_cast<const CT*>(op.clv_inv[cp]) : nullptr;
+  const bool clv = op.clover != 0;
   A.T = g.T;
   A.Lz = g.Lz;
   A.Ly = g.Ly;
@@ -668,10 +743,15 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.hop_coef = hop_coef;
   A.sigma = sigma;
   const dim3 grid(hop_grid(g)), block(kBlock);
-#define NDTM_HOP(E, RD)                                                            \
-  do {                                                                             \
-    if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true>), grid, block, 0, st, A); \
-    else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false>), grid, block, 0, st, A);           \
+#define NDTM_HOP(E, RD)                                                                         \
+  do {                                                                                          \
+    if (clv && E != EPI_PLAIN) {                                                                \
+      if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, true>), grid, block, 0, st, A);   \
+      else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false, true>), grid, block, 0, st, A);             \
+    } else {                                                                                    \
+      if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, false>), grid, block, 0, st, A);  \
+      else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false, false>), grid, block, 0, st, A);            \
+    }                                                                                           \
   } while (0)
   switch (epi) {
     case EPI_PLAIN: NDTM_HOP(EPI_PLAIN, RED_NONE); break;

@@ -317,6 +317,46 @@ __global__ void galerkin_self_k(MGGeom m, double a, const double2* scratch, doub
   }
 }
 
+// element (r, r') of the packed Hermitian 6x6 (6 real diagonal entries, then the upper
+// entries row by row as re, im) at half-site h of component arrays of `stride` entries
+__device__ double2 herm6_elem(const double* M, int stride, long h, int r, int rp) {
+  if (r == rp) return make_double2(M[(long)r * stride + h], 0.0);
+  const int i = r < rp ? r : rp, j = r < rp ? rp : r;
+  const int k = 6 + 2 * (i * 6 - i * (i + 1) / 2 + (j - i - 1));
+  const double re = M[(long)k * stride + h], im = M[(long)(k + 1) * stride + h];
+  return r < rp ? make_double2(re, im) : make_double2(re, -im);
+}
+
+// Clover part of the Galerkin self block: D[X][0] += sum_l P_l^+ C(x_l) P_l per chirality,
+// with C = M - a read from the fine site blocks M = a + C (eq:Wilson's clover term on the
+// coarse grid, section 3).  Entry (row i, column j) sits at j * 2Nv + i.
+__global__ void galerkin_clover_k(MGGeom m, const double2* P, const double* Me, const double* Mo, double a,
+                                  double2* D) {
+  const int X = blockIdx.x;
+  const int Nv = m.Nv, n2 = 2 * Nv, nb = Nv * Nv;
+  for (int o = threadIdx.x; o < 2 * nb; o += blockDim.x) {
+    const int chi = o / nb, k = (o % nb) / Nv, kp = o % Nv;
+    double2 s = make_double2(0, 0);
+    for (int l = 0; l < m.nloc; ++l) {
+      const SiteLoc sl = agg_site(m, X, l);
+      const double* Mp = (sl.par ? Mo : Me) + (long)chi * 36 * m.stride;
+      const double2* Pl = P + ((long)X * m.nloc + l) * 12 * Nv;
+      for (int r = 0; r < 6; ++r) {
+        double2 t = make_double2(0, 0);
+        for (int rp = 0; rp < 6; ++rp) {
+          double2 e = herm6_elem(Mp, m.stride, sl.h, r, rp);
+          if (r == rp) e.x -= a;
+          t = cadd(t, cmul(e, Pl[(6 * chi + rp) * Nv + kp]));
+        }
+        s = cadd(s, cmulc(Pl[(6 * chi + r) * Nv + k], t));
+      }
+    }
+    const int i = chi * Nv + k, j = chi * Nv + kp;
+    double2* d = D + (long)X * 9 * n2 * n2 + (long)j * n2 + i;
+    *d = cadd(*d, s);
+  }
+}
+
 // B_o[X][chi][k][k'] = sum_{odd l} sum_{rows of chi} conj(P[l][r][k]) P[l][r][k']
 __global__ void odd_block_k(MGGeom m, const double2* P, double2* Bo) {
   const int X = blockIdx.x;
@@ -722,6 +762,11 @@ void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int 
   hipLaunchKernelGGL(galerkin_k, dim3(16 * m.Vc), dim3(256), shmem, st, A);
   hipLaunchKernelGGL(galerkin_self_k, dim3(m.Vc), dim3(256), 0, st, m, a, scratch, D);
   hipLaunchKernelGGL(odd_block_k, dim3(m.Vc), dim3(256), 0, st, m, P, Bo);
+}
+
+void mg_galerkin_clover(const MGGeom& m, const double2* P, const double* Me, const double* Mo, double a, double2* D,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(galerkin_clover_k, dim3(m.Vc), dim3(256), 0, st, m, P, Me, Mo, a, D);
 }
 
 void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,

@@ -657,6 +657,8 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     mg_orthonormalize(g, M->P64, st);
     mg_galerkin(g, (const double2*)c->U[P64][0], (const double2*)c->U[P64][1], c->g.antiperiodic, c->op.a, M->P64,
                 M->D64, scratch, M->Bo64, st);
+    if (c->op.clover)
+      mg_galerkin_clover(g, M->P64, (const double*)c->clv_m[0][0], (const double*)c->clv_m[0][1], c->op.a, M->D64, st);
     if (M->cprec != P64) {
       vconvert(P32, M->Pc, P64, M->P64, nP, st);
       vconvert(P32, M->Dc, P64, M->D64, nD, st);

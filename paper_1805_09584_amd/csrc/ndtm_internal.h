@@ -78,6 +78,12 @@ struct OpParams {
   const double* skip = nullptr;
   int chunk = 0;    // z extent of the stencil's traversal tile (divides Lz); 0: from the L2 size
   int chunk_y = 0;  // y extent (divides Ly); 0: whole planes
+  // clover term of eq:Wilson (0: off).  Site blocks per parity in FP64 ([0]) and FP32 ([1],
+  // used by the FP32 and FP16 stencils): M = a + C, 72 component arrays of `stride`
+  // entries; the even parity's N and M N, 144 arrays
+  int clover = 0;
+  const void* clv_m[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  const void* clv_inv[2] = {nullptr, nullptr};
 };
 
 // A precision-tagged half field (device pointers).
@@ -95,6 +101,12 @@ void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpP
                 const HalfField* xs, const HalfField* zs, double ms, double hop_coef,
                 double sigma, double* partials, hipStream_t st);
 int hop_grid(const Geom& g);
+
+// Clover site blocks of one parity from the FP64 links (kern_clover.hip); Ninv only for the
+// even parity.  bad counts blocks M^2 + mubar^2 - epsbar^2 that could not be inverted.
+void launch_clover_build(const Geom& g, const double2* Ue, const double2* Uo, int parity, double a, double csw,
+                         double mubar, double epsbar, double* Mout, double* Ninv, unsigned* bad, hipStream_t st);
+void launch_to_f32(const double* src, float* dst, long n, hipStream_t st);
 
 // ---- layout conversion -------------------------------------------------
 void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* U64o, float2* U32e,

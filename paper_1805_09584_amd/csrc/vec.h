@@ -76,6 +76,9 @@ void mg_orthonormalize(const MGGeom& m, double2* P, hipStream_t st);
 // 8*Vc*(2Nv)^2 complex for the partial self blocks; B_o[X][chi][k][k'] = sum over odd sites P^+ P
 void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int antiperiodic, double a,
                  const double2* P, double2* D, double2* scratch, double2* Bo, hipStream_t st);
+// clover part of the Galerkin self blocks from the fine site blocks M = a + C of both parities
+void mg_galerkin_clover(const MGGeom& m, const double2* P, const double* Me, const double* Mo, double a, double2* D,
+                        hipStream_t st);
 // restrict / prolong between fine full fields (even half at fe, odd half at fo) and coarse [X][2][2Nv]
 void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
                  hipStream_t st);

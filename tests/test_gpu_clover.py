@@ -1,0 +1,118 @@
+"""The clover term of eq:Wilson on the GPU (ndtm_set_clover) against the FP64 oracle.
+
+* Every operator (the even-odd Q, Q^2 + sigma, S + i m Gamma5 tau1, D' on the full
+  lattice) with c_sw = 1.76 matches the oracle's: FP64 to 1e-12 (norm and per site),
+  FP32 and FP16 storage within their bars; also under traversal tiles smaller than the
+  lattice and with antiperiodic time.  Setting c_sw back to 0 restores the clover-free
+  operator bit for bit.
+* Plain multi-shift CG with the clover term: every shift's true residual (oracle) <= 1e-10.
+* Multigrid: the coarse operator, Galerkin with the clover term (P^+ C P in the self
+  blocks), equals P^+ D'(m) P with the oracle's clover D'; the hybrid solve meets 1e-10
+  on every shift by the oracle's residual, its multigrid shifts going through case C
+  (at this hot 4^4 field with c_sw = 1.76 one of them needs the CG completion).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mg as omg
+from oracle.lattice import Lattice, NDOperator, rel_residual
+from tests.gpu_util import dev, host, rel_err, site_err
+
+pytestmark = pytest.mark.gpu
+
+K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
+CSW = 1.76
+TOL = {0: 1e-12, 1: 2e-6, 2: 5e-3}
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1805_09584_amd as nd
+    return nd
+
+
+def _setup(nd, dims, ap=False, seed=11, csw=CSW):
+    U = synth.gauge_field(dims, seed, 0.3)
+    op = NDOperator(Lattice(dims, U, antiperiodic_t=ap), K, MB, EB, csw=csw)
+    ctx = nd.Context(dims, bc_flags=1 if ap else 0)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_clover(csw)
+    return U, op, ctx
+
+
+@pytest.mark.parametrize("dims,ap,tile", [((4, 4, 4, 4), False, (0, 0)), ((6, 4, 2, 10), True, (0, 0)),
+                                          ((8, 8, 4, 8), False, (2, 2))])
+def test_clover_operators(nd, dims, ap, tile):
+    print(f"case clover operators dims={dims} ap={ap} tile={tile}", flush=True)
+    U, op, ctx = _setup(nd, dims, ap)
+    ctx.ndtm_set_stencil_tile(*tile)
+    x = synth.gaussian_spinor(dims, 9)
+    xf = synth.gaussian_spinor(dims, 10, "full")
+    xd, xfd = dev(x), dev(xf)
+    refs = [(nd.NDTM_OP_QHAT, xd, 0.0, op.Q_hat(x)), (nd.NDTM_OP_QHAT2, xd, 0.031, op.Q_hat2(x, 0.031)),
+            (nd.NDTM_OP_SHAT_SHIFT, xd, 0.17, op.S_shift(x, 0.17)),
+            (nd.NDTM_OP_DFULL, xfd, -0.09, op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=-0.09).reshape(xf.shape))]
+    for prec in (0, 1, 2):
+        for opc, xin, par, want in refs:
+            got = host(ctx.ndtm_apply(opc, xin, par, prec=prec))
+            assert rel_err(got, want) < TOL[prec], (prec, opc, rel_err(got, want))
+            if prec == 0:
+                assert site_err(got, want) < 1e-12, (opc, site_err(got, want))
+    # c_sw = 0 switches the term off: the clover-free operator, bit for bit
+    plain = nd.Context(dims, bc_flags=1 if ap else 0)
+    plain.ndtm_set_gauge(dev(U))
+    plain.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_clover(0.0)
+    assert np.array_equal(host(ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.031)),
+                          host(plain.ndtm_apply(nd.NDTM_OP_QHAT2, xd, 0.031)))
+    plain.close()
+    ctx.close()
+
+
+def test_clover_mmscg_config1(nd):
+    print("case clover MMS-CG c1", flush=True)
+    c = synth.CONFIGS["c1"]
+    U, op, ctx = _setup(nd, c["dims"], seed=c["gauge_seed"])
+    b = synth.gaussian_spinor(c["dims"], c["rhs_seed"])
+    ctx.ndtm_set_shifts(list(c["shifts"]))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(tol=1e-10))
+    for i, s in enumerate(c["shifts"]):
+        assert rel_residual(op, host(xs[i]), b, s) <= 1e-10, i
+    ctx.close()
+
+
+def test_clover_coarse_operator_and_hybrid(nd):
+    print("case clover multigrid 8^4", flush=True)
+    dims, block, Nv = (8, 8, 8, 8), (4, 4, 4, 4), 8
+    U, op, ctx = _setup(nd, dims, seed=31)
+    lat = op.lat
+    tv = synth.gaussian_vectors((Nv, lat.V, 4, 3), 32)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0), test_vectors=dev(tv))
+    P = omg.build_prolongator(tv, dims, block)
+    agg = omg.aggregate_of_site(dims, block)
+    Vc = int(np.prod(omg.coarse_dims(dims, block)))
+    vc = synth.gaussian_vectors((Vc, 2, 2 * Nv), 4)
+    for m in (0.0, -0.05):
+        got = host(ctx.ndtm_mg_coarse_apply(dev(vc), m))
+        f = omg.prolong(P, vc, agg).reshape(dims + (2, 4, 3))
+        want = omg.restrict(P, op.D_full(f, odd_shift=m).reshape(lat.V, 2, 4, 3), agg, Vc)
+        assert rel_err(got, want) < 1e-12, m
+    ctx.close()
+    # hybrid on the 4^4 configuration with the clover term: multigrid shifts by the multigrid
+    c = synth.CONFIGS["c1"]
+    U, op, ctx = _setup(nd, c["dims"], seed=c["gauge_seed"])
+    b = synth.gaussian_spinor(c["dims"], c["rhs_seed"])
+    ctx.ndtm_set_shifts(list(c["shifts"]))
+    ctx.ndtm_mg_setup(ctx.mg_params(block=(2, 2, 2, 2), n_vec=8))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=7, mms_predict=0, use_graphs=0))
+    for i, s in enumerate(c["shifts"]):
+        assert rel_residual(op, host(xs[i]), b, s) <= 1e-10, i
+    # every multigrid shift is handled by the multigrid path (1: case C to tol; 2: case C then
+    # the FP64 CG completion when the capped multigrid rounds fall short) and at least one
+    # converges by the multigrid alone
+    print("clover hybrid methods", rep["method"], rep["iterations"], flush=True)
+    assert rep["method"][:7] == [0] * 7 and all(m in (1, 2) for m in rep["method"][7:])
+    assert 1 in rep["method"][7:]
+    ctx.close()
