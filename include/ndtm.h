@@ -448,7 +448,8 @@ enum {
   NDTM_PROF_MMS_RESID = 4,  /* r -= alpha w with ||r||^2, 3 x 384 B per odd site */
   NDTM_PROF_RESTRICT = 5,   /* restriction, V x (12 Nv + 24) complex of the cycle precision */
   NDTM_PROF_PROLONG = 6,    /* prolongation, same bytes as the restriction */
-  NDTM_PROF_COARSE = 7,     /* coarse stencil, Vc x 9.5 (2 Nv)^2 complex + 2 coarse vectors */
+  NDTM_PROF_COARSE = 7,     /* coarse stencil, Vc x 5.5 (2 Nv)^2 complex (self and forward blocks,
+                               the odd-projector block) + 2 coarse vectors */
   NDTM_PROF_NCLASS = 8
 };
 /* Streaming reference on the context's device: a copy (read + write), a read

@@ -13,6 +13,7 @@ from .binding import (  # noqa: F401
     NDTM_GUESS_MLP,
     NDTM_GUESS_PROJECTION,
     NDTM_GUESS_ZERO,
+    NDTM_NMMS_AUTO,
     NDTM_OP_DFULL,
     NDTM_OP_HOP_EO,
     NDTM_OP_HOP_OE,

@@ -180,6 +180,10 @@ __global__ __launch_bounds__(256) void orthonormalize_k(MGGeom m, double2* P) {
 }
 
 // ---------------- Galerkin coarse operator ----------------
+// Stored coarse blocks per coarse site: the self block and the forward hop of each
+// direction, (2 N_v)^2 each; a backward hop is the Gamma5_c-conjugated adjoint of the
+// neighbour's forward hop (D_c^+ = Gamma5_c D_c Gamma5_c).
+constexpr int kCoarseBlocks = 5;
 // gamma matrices of the chiral basis (same as the fine stencil): gamma[mu][row][col]
 __constant__ double2 kGamma[4][4][4] = {
     // gamma_0 = [[0,-1],[-1,0]]
@@ -219,6 +223,9 @@ __global__ __launch_bounds__(256) void galerkin_k(GalArgs A) {
   const int X = blockIdx.x >> 4, dd = blockIdx.x & 15;
   const bool face = dd < 8;
   const int d = dd & 7, mu = d >> 1, bwd = d & 1;
+  // the backward hopping blocks are not stored: D_c^+ = Gamma5_c D_c Gamma5_c gives them
+  // from the forward block of the neighbour (section 3, Gamma5-compatible P)
+  if (face && bwd) return;
   const int Nv = m.Nv, n2 = 2 * Nv;
   extern __shared__ double2 sm[];
   double2* Px = sm;               // 12 * Nv
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(256) void galerkin_k(GalArgs A) {
       acc[q] = s;
     }
   }
-  double2* out = face ? A.D + ((long)X * 9 + 1 + d) * ntot : A.scratch + ((long)X * 8 + d) * ntot;
+  double2* out = face ? A.D + ((long)X * kCoarseBlocks + 1 + mu) * ntot : A.scratch + ((long)X * 8 + d) * ntot;
   for (int q = 0; q < kPer; ++q) {
     const int o = threadIdx.x + q * blockDim.x;
     if (o < ntot) out[o] = acc[q];
@@ -313,7 +320,7 @@ __global__ void galerkin_self_k(MGGeom m, double a, const double2* scratch, doub
   for (int o = threadIdx.x; o < ntot; o += blockDim.x) {
     double2 s = make_double2((o / n2 == o % n2) ? a : 0.0, 0.0);
     for (int d = 0; d < 8; ++d) s = cadd(s, scratch[((long)X * 8 + d) * ntot + o]);
-    D[(long)X * 9 * ntot + o] = s;
+    D[(long)X * kCoarseBlocks * ntot + o] = s;
   }
 }
 
@@ -352,7 +359,7 @@ __global__ void galerkin_clover_k(MGGeom m, const double2* P, const double* Me, 
       }
     }
     const int i = chi * Nv + k, j = chi * Nv + kp;
-    double2* d = D + (long)X * 9 * n2 * n2 + (long)j * n2 + i;
+    double2* d = D + (long)X * kCoarseBlocks * n2 * n2 + (long)j * n2 + i;
     *d = cadd(*d, s);
   }
 }
@@ -541,11 +548,21 @@ __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C
     const int i = threadIdx.x % n2, q = threadIdx.x / n2;
     if (q < kApplyGroups) {
       R a0x = 0, a0y = 0, a1x = 0, a1y = 0;
-      const T2* DX = D + (long)X * 9 * ntot;
+      const R si = i < Nv ? R(1) : R(-1);
 #pragma unroll 4
       for (int pidx = q; pidx < 9 * n2; pidx += kApplyGroups) {
         const int b = pidx / n2, j = pidx % n2;
-        const T2 dv = DX[(long)b * ntot + (long)j * n2 + i];
+        T2 dv;
+        if (b == 0 || (b & 1)) {
+          // self block and forward hops: stored at the site, entry (i, j) at j * 2Nv + i
+          dv = D[((long)X * kCoarseBlocks + (b + 1) / 2) * ntot + (long)j * n2 + i];
+        } else {
+          // backward hop mu: Gamma5_c F^+ Gamma5_c with F the forward block of the
+          // neighbour X - mu, entry (i, j) = s_i s_j conj(F_ji)
+          const T2 f = D[((long)nb[b] * kCoarseBlocks + b / 2) * ntot + (long)i * n2 + j];
+          const R sg = (j < Nv ? R(1) : R(-1)) * si;
+          dv = mk<R>(sg * f.x, -sg * f.y);
+        }
         const T2 v0 = xs[b][j], v1 = xs[b][n2 + j];
         a0x += dv.x * v0.x - dv.y * v0.y;
         a0y += dv.x * v0.y + dv.y * v0.x;
@@ -634,8 +651,13 @@ __global__ __launch_bounds__(64 * kMultiBGroups * kMultiMaxTiles) void coarse_ap
   // their products, so that the loads are in flight together; masked entries are zeroed
   const int iac = ia < n2 ? ia : n2 - 1;
   const bool rowok = ia < n2;
+  const double si = iac < Nv ? 1.0 : -1.0;
   for (int b = bg * (9 / kMultiBGroups); b < (bg + 1) * (9 / kMultiBGroups); ++b) {
-    const double2* Db = D + ((size_t)site * 9 + b) * ntot;
+    // logical block b: self (0), forward hop mu (1 + 2 mu), backward hop mu (2 + 2 mu), the
+    // latter from the neighbour's stored forward block as Gamma5_c F^+ Gamma5_c
+    const bool adj = b > 0 && !(b & 1);
+    const double2* Db = adj ? D + ((size_t)nb[b] * kCoarseBlocks + b / 2) * ntot
+                            : D + ((size_t)site * kCoarseBlocks + (b + 1) / 2) * ntot;
     const double2* xb = X + (size_t)cr * vstride + ((size_t)nb[b] * 2 + cf) * n2;
     for (int kk = 0; kk < n2; kk += 16) {
       double2 a[4], v[4];
@@ -643,7 +665,13 @@ __global__ __launch_bounds__(64 * kMultiBGroups * kMultiMaxTiles) void coarse_ap
       for (int u = 0; u < 4; ++u) {
         const int jj = kk + 4 * u + kq;
         const int jc = jj < n2 ? jj : n2 - 1;
-        a[u] = Db[(size_t)jc * n2 + iac];
+        if (adj) {
+          const double2 f = Db[(size_t)iac * n2 + jc];
+          const double sg = (jc < Nv ? 1.0 : -1.0) * si;
+          a[u] = make_double2(sg * f.x, -sg * f.y);
+        } else {
+          a[u] = Db[(size_t)jc * n2 + iac];
+        }
         v[u] = xb[jc];
       }
 #pragma unroll

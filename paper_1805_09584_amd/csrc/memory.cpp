@@ -219,7 +219,7 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     const size_t Vc = (size_t)c->V / nloc, Nv = (size_t)mg->n_vec, n2 = 2 * Nv, kc = (size_t)mg->coarse_iters;
     const int cp = mg->precision == NDTM_PREC_F64 ? P64 : P32;
     const size_t cs = cp == P64 ? 16 : 8;
-    const size_t nP = Vc * nloc * 12 * Nv, nD = Vc * 9 * n2 * n2, nB = Vc * 2 * Nv * Nv, nc = Vc * 2 * n2;
+    const size_t nP = Vc * nloc * 12 * Nv, nD = Vc * 5 * n2 * n2, nB = Vc * 2 * Nv * Nv, nc = Vc * 2 * n2;
     t += R(nP * 16) + R(nD * 16) + R(nB * 16);
     if (cp == P32) t += R(nP * 8) + R(nD * 8) + R(nB * 8);
     t += (kc + 1 + 5) * R(nc * cs) + 2 * R(2 * (kc + 1) * (kc + 1) * 8) + R((kc + 1) * 8) + R(2 * (kc + 1) * 8) +

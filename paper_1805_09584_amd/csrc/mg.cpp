@@ -112,7 +112,9 @@ static double transfer_bytes(const MGData* M) {
 }
 static double coarse_bytes(const MGData* M) {
   const double es = (double)csz(M->cprec), n2 = 2.0 * M->g.Nv;
-  return (double)M->g.Vc * (9.0 * n2 * n2 + 0.5 * n2 * n2) * es + 2.0 * (double)M->ncoarse * es;
+  // five stored blocks and the odd-projector block read per coarse site (the backward
+  // hops come from the neighbours' forward blocks), the input and output vectors
+  return (double)M->g.Vc * (5.0 * n2 * n2 + 0.5 * n2 * n2) * es + 2.0 * (double)M->ncoarse * es;
 }
 
 // ---- coarse solve: GMRES on the device ------------------------------------
@@ -612,7 +614,7 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->cprec = prm->precision == NDTM_PREC_F64 ? P64 : P32;
   const int Nv = g.Nv, n2 = 2 * Nv;
   const size_t nP = (size_t)g.Vc * g.nloc * 12 * Nv;
-  const size_t nD = (size_t)g.Vc * 9 * n2 * n2;
+  const size_t nD = (size_t)g.Vc * 5 * n2 * n2;  // self block and the four forward hops
   const size_t nB = (size_t)g.Vc * 2 * Nv * Nv;
   M->ncoarse = (size_t)g.Vc * 2 * n2;
   M->P64 = (double2*)mg_alloc(c, M, nP * 16);
