@@ -183,6 +183,10 @@ typedef struct {
                           relative (section 3: the coarse system solved to a loose tolerance);
                           the host reads the residual after each cycle, so no graphs */
   int coarse_cycles;   /* restart cap of the coarse solve when coarse_tol > 0 (>= 1) */
+  int coarse_eo;       /* 1 (default): the coarse solve runs GMRES on the odd Schur complement of
+                          the coarse operator (section 3: even-odd reduction on the coarsest
+                          level), with the even site terms inverted per value of m (cached);
+                          needs even coarse extents, else (or 0) GMRES on the full coarse system */
   int keep_f64;        /* 1 (default): keep the FP64 P and coarse blocks, which the FP64 calls
                           ndtm_mg_restrict/prolong/coarse_apply(_multi)/coarse_solve_multi
                           use; 0 with an FP32 cycle: free them after the setup (those

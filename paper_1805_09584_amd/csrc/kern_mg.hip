@@ -69,6 +69,18 @@ __device__ __forceinline__ int local_index(const MGGeom& m, const int loc[4]) {
   return ((loc[0] * m.bz + loc[3]) * m.by + loc[2]) * m.bx + loc[1];
 }
 
+// parity of coarse site X (sum of its coarse coordinates mod 2)
+__device__ __forceinline__ int coarse_parity(const MGGeom& m, int X) {
+  int r = X;
+  const int cx = r % m.CX;
+  r /= m.CX;
+  const int cy = r % m.CY;
+  r /= m.CY;
+  const int cz = r % m.CZ;
+  const int ct = r / m.CZ;
+  return (ct + cz + cy + cx) & 1;
+}
+
 // neighbouring coarse site in direction mu (+1 or -1), periodic
 __device__ __forceinline__ int coarse_nbr(const MGGeom& m, int X, int mu, int dir) {
   int r = X;
@@ -520,9 +532,12 @@ template <class R>
 __global__ __launch_bounds__(512) void coarse_apply_k(MGGeom m, const typename C2<R>::T* D,
                                                       const typename C2<R>::T* Bo, const typename C2<R>::T* x,
                                                       typename C2<R>::T* y, double mubar_c, double epsbar,
-                                                      double mm, const double* xnorm2, typename C2<R>::T* xout) {
+                                                      double mm, const double* xnorm2, typename C2<R>::T* xout,
+                                                      int par_out) {
   using T2 = typename C2<R>::T;
   const int X = blockIdx.x;
+  // par_out >= 0: only the output sites of that coarse parity (the others keep their values)
+  if (par_out >= 0 && coarse_parity(m, X) != par_out) return;
   const int Nv = m.Nv, n2 = 2 * Nv, ntot = n2 * n2, nout = 2 * n2;
   __shared__ T2 xs[9][2 * 64];
   __shared__ int nb[9];
@@ -817,14 +832,192 @@ void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* 
 }
 
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
-                     double mubar_c, double epsbar, double m, hipStream_t st, const double* xnorm2, void* xout) {
+                     double mubar_c, double epsbar, double m, hipStream_t st, const double* xnorm2, void* xout,
+                     int par_out) {
   const dim3 blk(std::max(2 * g.Nv * kApplyGroups, 4 * g.Nv));
   if (prec == P64)
     hipLaunchKernelGGL(coarse_apply_k<double>, dim3(g.Vc), blk, 0, st, g, (const double2*)D, (const double2*)Bo,
-                       (const double2*)x, (double2*)y, mubar_c, epsbar, m, xnorm2, (double2*)xout);
+                       (const double2*)x, (double2*)y, mubar_c, epsbar, m, xnorm2, (double2*)xout, par_out);
   else
     hipLaunchKernelGGL(coarse_apply_k<float>, dim3(g.Vc), blk, 0, st, g, (const float2*)D, (const float2*)Bo,
-                       (const float2*)x, (float2*)y, mubar_c, epsbar, m, xnorm2, (float2*)xout);
+                       (const float2*)x, (float2*)y, mubar_c, epsbar, m, xnorm2, (float2*)xout, par_out);
+}
+
+// ---------------- even-odd coarsest level ----------------
+// The site term of D'_c(m) at coarse site X couples both flavours:
+//   rows/columns (f, i), i < 2Nv:  (f, f): S_X + i d mubar g5_i tau3_f;
+//   (f, 1-f): -epsbar + i m g5_i Bo_X (chirality-diagonal),
+// S_X the self block.  One workgroup per even coarse site inverts it in FP64 by
+// Gauss-Jordan elimination with partial pivoting on [A | 1] (rows of 4 n2 complex in
+// the scratch), and stores -A^-1 in the cycle precision, entry (r, c) at c * 2n2 + r,
+// at the even site's compact index X / 2.  *bad counts singular site terms.
+template <class R>
+__global__ __launch_bounds__(256) void einv_build_k(MGGeom m, int X0, const typename C2<R>::T* D,
+                                                     const typename C2<R>::T* Bo, double mubar_c, double epsbar,
+                                                     double mm, double2* scratch, typename C2<R>::T* Einv,
+                                                     unsigned* bad) {
+  using T2 = typename C2<R>::T;
+  const int X = X0 + blockIdx.x;  // X0 even; the scratch holds the chunk's even sites
+  if (X >= m.Vc || coarse_parity(m, X) != 0) return;
+  const int Nv = m.Nv, n2 = 2 * Nv, N = 2 * n2, W = 2 * N;
+  double2* A = scratch + (size_t)((X - X0) >> 1) * N * W;  // [row][W]
+  const T2* S = D + (size_t)X * kCoarseBlocks * n2 * n2;
+  const T2* B = Bo + (size_t)X * 2 * Nv * Nv;
+  for (int e = threadIdx.x; e < N * W; e += blockDim.x) {
+    const int r = e / W, c = e % W;
+    double2 v = make_double2(0, 0);
+    if (c < N) {
+      const int fr = r / n2, i = r % n2, fc = c / n2, j = c % n2;
+      const double g5 = i < Nv ? 1.0 : -1.0;
+      if (fr == fc) {
+        const T2 d = S[(size_t)j * n2 + i];
+        v = make_double2(double(d.x), double(d.y));
+        if (i == j) v.y += mubar_c * g5 * (fr == 0 ? 1.0 : -1.0);
+      } else {
+        if (i == j) v.x -= epsbar;
+        const int chi = i / Nv;
+        if (mm != 0.0 && j / Nv == chi) {
+          const T2 b = B[((size_t)chi * Nv + i % Nv) * Nv + j % Nv];
+          // + i m g5 b
+          v.x -= mm * g5 * double(b.y);
+          v.y += mm * g5 * double(b.x);
+        }
+      }
+    } else if (c - N == r) {
+      v = make_double2(1, 0);
+    }
+    A[e] = v;
+  }
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  __shared__ double2 piv;
+  __shared__ int prow;
+  __shared__ double2 fcol[128];
+  for (int c = 0; c < N; ++c) {
+    __syncthreads();
+    // pivot: largest |A[r][c]| over r >= c
+    double best = -1.0;
+    int bestr = c;
+    for (int r = c + threadIdx.x; r < N; r += blockDim.x) {
+      const double2 a = A[(size_t)r * W + c];
+      const double v = a.x * a.x + a.y * a.y;
+      if (v > best) {
+        best = v;
+        bestr = r;
+      }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = bestr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = -1.0;
+      int rr = c;
+      for (int t = 0; t < (int)blockDim.x; ++t)
+        if (bv[t] > b) {
+          b = bv[t];
+          rr = bi[t];
+        }
+      prow = rr;
+      if (!(b > 0.0)) atomicAdd(bad, 1u);
+    }
+    __syncthreads();
+    const int p = prow;
+    if (p != c)
+      for (int j = threadIdx.x; j < W; j += blockDim.x) {
+        const double2 t = A[(size_t)c * W + j];
+        A[(size_t)c * W + j] = A[(size_t)p * W + j];
+        A[(size_t)p * W + j] = t;
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double2 d = A[(size_t)c * W + c];
+      const double n = d.x * d.x + d.y * d.y;
+      piv = n > 0.0 ? make_double2(d.x / n, -d.y / n) : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < W; j += blockDim.x) A[(size_t)c * W + j] = cmul(A[(size_t)c * W + j], piv);
+    __syncthreads();
+    // eliminate column c from every other row with the column's factors staged in LDS
+    // (read before any thread changes them); the pivot row is only read
+    for (int r = threadIdx.x; r < N; r += blockDim.x) fcol[r] = A[(size_t)r * W + c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * W; e += blockDim.x) {
+      const int r = e / W, j = e % W;
+      if (r == c) continue;
+      const double2 t = cmul(fcol[r], A[(size_t)c * W + j]);
+      A[(size_t)r * W + j] = make_double2(A[(size_t)r * W + j].x - t.x, A[(size_t)r * W + j].y - t.y);
+    }
+  }
+  __syncthreads();
+  T2* E = Einv + (size_t)(X >> 1) * N * N;
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int c = e / N, r = e % N;
+    const double2 v = A[(size_t)r * W + N + c];
+    E[e] = mk<R>(R(-v.x), R(-v.y));
+  }
+}
+
+// out = (-A_ee^-1 u_e) on the even coarse sites and out = v on the odd ones (the
+// input of the odd Schur complement's second coarse stencil), Einv holding -A^-1.
+template <class R>
+__global__ __launch_bounds__(128) void einv_apply_k(MGGeom m, const typename C2<R>::T* Einv, const typename C2<R>::T* u,
+                                                     const typename C2<R>::T* v, typename C2<R>::T* out) {
+  using T2 = typename C2<R>::T;
+  const int X = blockIdx.x;
+  const int N = 4 * m.Nv;
+  if (coarse_parity(m, X) != 0) {
+    for (int r = threadIdx.x; r < N; r += blockDim.x) out[(size_t)X * N + r] = v ? v[(size_t)X * N + r] : mk<R>(R(0), R(0));
+    return;
+  }
+  __shared__ T2 us[128];
+  for (int r = threadIdx.x; r < N; r += blockDim.x) us[r] = u[(size_t)X * N + r];
+  __syncthreads();
+  const T2* E = Einv + (size_t)(X >> 1) * N * N;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    R ax = 0, ay = 0;
+    for (int c = 0; c < N; ++c) {
+      const T2 e = E[(size_t)c * N + r], w = us[c];
+      ax += e.x * w.x - e.y * w.y;
+      ay += e.x * w.y + e.y * w.x;
+    }
+    out[(size_t)X * N + r] = mk<R>(ax, ay);
+  }
+}
+
+// zero the coarse vector on the sites of coarse parity par
+template <class R>
+__global__ void coarse_zero_parity_k(MGGeom m, typename C2<R>::T* x, int par) {
+  const int X = blockIdx.x;
+  if (coarse_parity(m, X) != par) return;
+  const int N = 4 * m.Nv;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) x[(size_t)X * N + r] = mk<R>(R(0), R(0));
+}
+
+void mg_einv_build(int prec, const MGGeom& g, int X0, int count, const void* D, const void* Bo, double mubar_c,
+                   double epsbar, double m, double2* scratch, void* Einv, unsigned* bad, hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(einv_build_k<double>, dim3(count), dim3(256), 0, st, g, X0, (const double2*)D,
+                       (const double2*)Bo, mubar_c, epsbar, m, scratch, (double2*)Einv, bad);
+  else
+    hipLaunchKernelGGL(einv_build_k<float>, dim3(count), dim3(256), 0, st, g, X0, (const float2*)D,
+                       (const float2*)Bo, mubar_c, epsbar, m, scratch, (float2*)Einv, bad);
+}
+
+void mg_einv_apply(int prec, const MGGeom& g, const void* Einv, const void* u, const void* v, void* out,
+                   hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(einv_apply_k<double>, dim3(g.Vc), dim3(128), 0, st, g, (const double2*)Einv, (const double2*)u,
+                       (const double2*)v, (double2*)out);
+  else
+    hipLaunchKernelGGL(einv_apply_k<float>, dim3(g.Vc), dim3(128), 0, st, g, (const float2*)Einv, (const float2*)u,
+                       (const float2*)v, (float2*)out);
+}
+
+void mg_coarse_zero_parity(int prec, const MGGeom& g, void* x, int par, hipStream_t st) {
+  if (prec == P64)
+    hipLaunchKernelGGL(coarse_zero_parity_k<double>, dim3(g.Vc), dim3(128), 0, st, g, (double2*)x, par);
+  else
+    hipLaunchKernelGGL(coarse_zero_parity_k<float>, dim3(g.Vc), dim3(128), 0, st, g, (float2*)x, par);
 }
 
 void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo, const double2* x, double2* y, int k,

@@ -65,6 +65,14 @@ struct MGData {
   double* dtmp = nullptr;
   double* dh2 = nullptr;  // second Gram-Schmidt pass coefficients, laid out as dH
   double* dpart = nullptr;  // smoother: stencil partials of <D'S, S>, ||D'S||^2 ([3][2 nblk])
+  // even-odd coarsest level: -A_ee^-1 per value of m (null when that m's site terms
+  // could not be inverted), the Schur complement's work vectors and the build scratch
+  bool eo = false;
+  std::vector<std::pair<double, void*>> einv;
+  void *cU = nullptr, *cT2 = nullptr, *cR2 = nullptr;
+  double2* einv_scratch = nullptr;
+  int einv_chunk = 0;
+  unsigned* einv_bad = nullptr;
   std::vector<void*> owned;
   bool ready = false;
   // cycle graphs: one per value of the odd-site shift m, replayed on the caller's stream
@@ -117,6 +125,119 @@ static double coarse_bytes(const MGData* M) {
   return (double)M->g.Vc * (5.0 * n2 * n2 + 0.5 * n2 * n2) * es + 2.0 * (double)M->ncoarse * es;
 }
 
+// ---- even-odd coarsest level ------------------------------------------------
+// -A_ee^-1 of D'_c(m)'s even site terms, built on first use of m (outside any graph
+// capture: mg_cycle asks for it before capturing) and kept until the next setup.
+static const void* einv_for(ndtm_ctx* c, MGData* M, double m, hipStream_t st) {
+  for (auto& e : M->einv)
+    if (e.first == m) return e.second;
+  const int N = 4 * M->g.Nv;
+  const size_t bytes = (size_t)(M->g.Vc / 2) * N * N * csz(M->cprec);
+  void* E = dev_alloc(c, bytes);
+  if (E) M->owned.push_back(E);
+  bool ok = E != nullptr;
+  if (ok) {
+    (void)hipMemsetAsync(M->einv_bad, 0, sizeof(unsigned), st);
+    const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+    for (int X0 = 0; X0 < M->g.Vc; X0 += M->einv_chunk)
+      mg_einv_build(M->cprec, M->g, X0, std::min(M->einv_chunk, M->g.Vc - X0), M->Dc, M->Boc, mubar_c, c->epsbar, m,
+                    M->einv_scratch, E, M->einv_bad, st);
+    unsigned bad = 0;
+    (void)hipMemcpyAsync(&bad, M->einv_bad, sizeof(unsigned), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    ok = bad == 0;
+  }
+  M->einv.push_back({m, ok ? E : nullptr});
+  return ok ? E : nullptr;
+}
+
+// w_o = S v_o with S = D_oo - D_oe A_ee^-1 D_eo the odd Schur complement of D'_c(m), for
+// coarse vectors whose even part is zero (v) or stays zero (w)
+static void schur_apply(ndtm_ctx* c, MGData* M, const void* E, const void* v, void* w, double m, double eps,
+                        hipStream_t st) {
+  const int cp = M->cprec;
+  const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+  ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
+  mg_coarse_apply(cp, M->g, M->Dc, M->Boc, v, M->cU, mubar_c, eps, m, st, nullptr, nullptr, 0);  // D_eo v_o
+  mg_einv_apply(cp, M->g, E, M->cU, v, M->cT2, st);  // (-A_ee^-1 D_eo v_o) + v_o
+  mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cT2, w, mubar_c, eps, m, st, nullptr, nullptr, 1);
+}
+
+// One GMRES(kc) cycle from zero on S y_o = src_o (src's even part zero), as coarse_gmres_cycle
+static void eo_gmres_cycle(ndtm_ctx* c, MGData* M, const void* E, const void* src, const double* src2, void* sol,
+                           int accumulate, double m, double eps, hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t n = M->ncoarse;
+  const int kc = M->prm.coarse_iters;
+  // the Schur complement writes the odd sites only: the work vectors' even parts are
+  // cleared (the full coarse solve may have left values there)
+  mg_coarse_zero_parity(cp, M->g, M->cW, 0, st);
+  mg_coarse_zero_parity(cp, M->g, M->cW2, 0, st);
+  vscale_inv_sqrt(cp, M->cV[0], src, src2, n, st);
+  for (int j = 0; j < kc; ++j) {
+    void* w = (j & 1) ? M->cW2 : M->cW;
+    schur_apply(c, M, E, M->cV[j], w, m, eps, st);
+    double* hcol = M->dH + 2 * (size_t)j * (kc + 1);
+    double* hcol2 = M->dh2 + 2 * (size_t)j * (kc + 1);
+    vmultidot(cp, (const void* const*)M->cV.data(), j + 1, w, n, c->vred, hcol, st);
+    vmulti_axpy_multidot(cp, w, (const void* const*)M->cV.data(), j + 1, hcol, n, c->vred, hcol2, st);
+    vmulti_axpy_norm_dev(cp, w, (const void* const*)M->cV.data(), j + 1, hcol2, n, c->vred, M->dsub + j, st);
+    if (j + 1 < kc) vscale_inv_sqrt(cp, M->cV[j + 1], w, M->dsub + j, n, st);
+  }
+  hess_lsq(M->dH, M->dh2, kc + 1, kc, src2, M->dsub, M->dy, st);
+  vlincomb_dev(cp, sol, (const void* const*)M->cV.data(), kc, M->dy, accumulate, n, st);
+}
+
+// sol ~ D'_c(m)^-1 rhs through the odd Schur complement: rhs_o' = rhs_o - D_oe A_ee^-1 rhs_e,
+// GMRES on S sol_o = rhs_o' (restarted on its true residual when coarse_tol > 0), then
+// sol_e = A_ee^-1 (rhs_e - D_eo sol_o).  Returns false if this m has no even inverse.
+static bool coarse_solve_eo(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
+                            hipStream_t st) {
+  const void* E = einv_for(c, M, m, st);
+  if (!E) return false;
+  const int cp = M->cprec;
+  const size_t n = M->ncoarse;
+  const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
+  // cR2 = rhs_o - D_oe A_ee^-1 rhs_e on the odd sites, zero on the even ones
+  mg_einv_apply(cp, M->g, E, rhs, nullptr, M->cT2, st);
+  {
+    ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
+    mg_coarse_apply(cp, M->g, M->Dc, M->Boc, M->cT2, M->cR2, mubar_c, eps, m, st, nullptr, nullptr, 1);
+  }
+  vaxpby(cp, M->cR2, make_double2(1, 0), rhs, make_double2(1, 0), n, st);
+  mg_coarse_zero_parity(cp, M->g, M->cR2, 0, st);
+  vnorm2(cp, M->cR2, n, c->vred, M->dbeta, st);
+  eo_gmres_cycle(c, M, E, M->cR2, M->dbeta, sol, 0, m, eps, st);
+  if (M->prm.coarse_tol > 0.0) {
+    // the full coarse residual equals the Schur residual on the odd sites (its even part
+    // vanishes by the construction of sol_e): the tolerance is relative to ||rhs||
+    vnorm2(cp, rhs, n, c->vred, M->dbeta + 2, st);
+    (void)hipMemcpyAsync(c->hscal, M->dbeta + 2, sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    const double rhs2 = c->hscal[0];
+    const double tol2 = M->prm.coarse_tol * M->prm.coarse_tol * rhs2;
+    for (int cyc = 1; cyc < M->prm.coarse_cycles && rhs2 > 0.0; ++cyc) {
+      mg_coarse_zero_parity(cp, M->g, M->cT, 0, st);
+      schur_apply(c, M, E, sol, M->cT, m, eps, st);
+      vaxpby(cp, M->cT, make_double2(1, 0), M->cR2, make_double2(-1, 0), n, st);  // cT = rhs' - S sol
+      vnorm2(cp, M->cT, n, c->vred, M->dbeta + 1, st);
+      (void)hipMemcpyAsync(c->hscal, M->dbeta + 1, sizeof(double), hipMemcpyDeviceToHost, st);
+      (void)hipStreamSynchronize(st);
+      const double res2 = c->hscal[0];
+      if (!(res2 > tol2) || !std::isfinite(res2)) break;
+      eo_gmres_cycle(c, M, E, M->cT, M->dbeta + 1, sol, 1, m, eps, st);
+    }
+  }
+  // sol_e = A_ee^-1 (rhs_e - D_eo sol_o) = -A_ee^-1 (D_eo sol_o - rhs_e)
+  {
+    ProfScope ps(c, NDTM_PROF_COARSE, coarse_bytes(M), st);
+    mg_coarse_apply(cp, M->g, M->Dc, M->Boc, sol, M->cU, mubar_c, eps, m, st, nullptr, nullptr, 0);
+  }
+  vaxpby(cp, M->cU, make_double2(-1, 0), rhs, make_double2(1, 0), n, st);
+  mg_einv_apply(cp, M->g, E, M->cU, sol, sol, st);
+  return true;
+}
+
 // ---- coarse solve: GMRES on the device ------------------------------------
 // One GMRES(kc) cycle from zero on D'_c y = src; *src2 = ||src||^2 on the device.
 // The solution is written (accumulate = 0) or added (1) to sol, which must not be
@@ -159,6 +280,7 @@ static void coarse_gmres_cycle(ndtm_ctx* c, MGData* M, const void* src, const do
 // coarse_tol ||rhs|| or coarse_cycles cycles have run.
 static void coarse_solve(ndtm_ctx* c, MGData* M, const void* rhs, void* sol, double m, double eps,
                          hipStream_t st) {
+  if (M->eo && coarse_solve_eo(c, M, rhs, sol, m, eps, st)) return;
   const int cp = M->cprec;
   const size_t n = M->ncoarse;
   const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
@@ -260,6 +382,7 @@ static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfFie
   const size_t nh = half_elems(c);
   Full R = full_field(c, "mg_R", cp), Z = full_field(c, "mg_Z", cp);
   vconvert_field(cp, R.o.v, P64, r64.v, 1, c->g.vh, c->g.stride, st);
+  if (M->eo) (void)einv_for(c, M, m, st);  // built now, never inside a graph capture
   hipGraphExec_t g = M->use_graphs ? cycle_graph(c, M, m) : nullptr;
   if (g)
     (void)hipGraphLaunch(g, st);
@@ -652,6 +775,18 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   M->dpart = (double*)mg_alloc(c, M, 6 * (size_t)hop_grid(c->g) * sizeof(double));
   if (!M->dpart || !M->dh2 || !M->cW || !M->cW2 || !M->cR || !M->cT || !M->cX || !M->dH || !M->dsub || !M->dy || !M->dbeta || !M->dtmp)
     return fail(c, NDTM_ENOMEM, "mg_setup: coarse workspace");
+  M->eo = prm->coarse_eo && g.CT % 2 == 0 && g.CZ % 2 == 0 && g.CY % 2 == 0 && g.CX % 2 == 0;
+  if (M->eo) {
+    const size_t N = 4 * (size_t)Nv;
+    M->einv_chunk = (int)std::max<size_t>(2, std::min<size_t>(g.Vc, ((size_t)1 << 30) / (N * 2 * N * 16) * 2)) & ~1;
+    M->cU = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+    M->cT2 = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+    M->cR2 = mg_alloc(c, M, M->ncoarse * csz(M->cprec));
+    M->einv_scratch = (double2*)mg_alloc(c, M, (size_t)(M->einv_chunk / 2) * N * 2 * N * 16);
+    M->einv_bad = (unsigned*)mg_alloc(c, M, 256);
+    if (!M->cU || !M->cT2 || !M->cR2 || !M->einv_scratch || !M->einv_bad)
+      return fail(c, NDTM_ENOMEM, "mg_setup: even-odd coarse workspace");
+  }
   double2* scratch = (double2*)ws_get(c, "mg_scratch", (size_t)g.Vc * 8 * n2 * n2 * 16);
   if (!scratch) return fail(c, NDTM_ENOMEM, "mg_setup: scratch");
   // P from the vectors currently in M->P64: orthonormalise, Galerkin products, cycle-precision copies
@@ -810,6 +945,7 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->precision = NDTM_PREC_F32;
   p->coarse_tol = 0.0;
   p->coarse_cycles = 20;
+  p->coarse_eo = 1;
   p->keep_f64 = 1;
 }
 

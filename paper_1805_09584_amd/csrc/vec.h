@@ -90,9 +90,18 @@ void mg_coarse_apply_multi(const MGGeom& g, const double2* D, const double2* Bo,
                            const double* m, double mubar_c, double epsbar, hipStream_t st);
 // y = D'_c(m) x; with xnorm2 the input is x / sqrt(*xnorm2), and xout (if given) receives that
 // scaled input (every coarse site written once)
+// par_out >= 0: only the output sites of that coarse parity are written
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,
                      double mubar_c, double epsbar, double m, hipStream_t st, const double* xnorm2 = nullptr,
-                     void* xout = nullptr);
+                     void* xout = nullptr, int par_out = -1);
+// even-odd coarsest level: -A_ee^-1 of the coarse site terms of D'_c(m) for the even sites
+// X0 .. X0+count-1 (X0 even; FP64 scratch of count/2 x 4n2 x 8n2 complex), stored at X/2
+void mg_einv_build(int prec, const MGGeom& g, int X0, int count, const void* D, const void* Bo, double mubar_c,
+                   double epsbar, double m, double2* scratch, void* Einv, unsigned* bad, hipStream_t st);
+// out = -A_ee^-1 u on even coarse sites, v (zero when null) on odd ones
+void mg_einv_apply(int prec, const MGGeom& g, const void* Einv, const void* u, const void* v, void* out,
+                   hipStream_t st);
+void mg_coarse_zero_parity(int prec, const MGGeom& g, void* x, int par, hipStream_t st);
 // fill a full doublet field (both halves) with complex Gaussian numbers from a counter-based hash
 void mg_random_fill(const MGGeom& m, int vh, double2* fe, double2* fo, unsigned long long seed, hipStream_t st);
 

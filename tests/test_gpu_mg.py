@@ -250,21 +250,28 @@ def test_coarse_solve_to_tolerance(nd):
     Bo = omg.odd_projector_coarse(lat, P, agg, Vc)
     bc = synth.gaussian_vectors((Vc, 2, 2 * Nv), 6)
     res = {}
-    for tol in (0.0, 1e-9):
-        ctx = nd.Context(dims)
-        ctx.ndtm_set_gauge(dev(U))
-        ctx.ndtm_set_params(K, MB, EB)
-        ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, coarse_iters=2, coarse_tol=tol,
-                                        coarse_cycles=400), test_vectors=dev(tv))
-        for m in (0.01, -0.01):
-            xc = host(ctx.ndtm_mg_coarse_solve(dev(bc), m))
-            r = bc - omg.coarse_nd_apply(Dc, Bo, xc, Nv, MB, EB, m=m)
-            res[(tol, m)] = np.linalg.norm(r) / np.linalg.norm(bc)
-        ctx.close()
+    # both coarse solvers: GMRES on the full coarse system and on its odd Schur complement
+    # (even-odd reduction on the coarsest level)
+    for eo in (0, 1):
+        for tol in (0.0, 1e-9):
+            ctx = nd.Context(dims)
+            ctx.ndtm_set_gauge(dev(U))
+            ctx.ndtm_set_params(K, MB, EB)
+            ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, coarse_iters=2, coarse_tol=tol,
+                                            coarse_cycles=400, coarse_eo=eo), test_vectors=dev(tv))
+            for m in (0.01, -0.01):
+                xc = host(ctx.ndtm_mg_coarse_solve(dev(bc), m))
+                r = bc - omg.coarse_nd_apply(Dc, Bo, xc, Nv, MB, EB, m=m)
+                res[(eo, tol, m)] = np.linalg.norm(r) / np.linalg.norm(bc)
+            ctx.close()
     print("relative coarse residuals", res, flush=True)
-    for m in (0.01, -0.01):
-        assert res[(1e-9, m)] <= 1e-9
-        assert res[(0.0, m)] > 1e-6
+    for eo in (0, 1):
+        for m in (0.01, -0.01):
+            assert res[(eo, 1e-9, m)] <= 1e-9
+            assert res[(eo, 0.0, m)] > 1e-6
+        # one GMRES(2) cycle on the Schur complement leaves a smaller residual than on the
+        # full system (the reduced system is better conditioned)
+    assert all(res[(1, 0.0, m)] < res[(0, 0.0, m)] for m in (0.01, -0.01))
 
 
 def test_near_critical_coarse_tolerance_config(nd):
