@@ -16,8 +16,9 @@ Forms (the first is the headline `value`):
           from the learned guess with Lagrange as fallback (shift 12)
   plain   multi-shift CG for all 12 shifts (the speed-up reference)
   hybrid  as full with Lagrange guesses only
-  mixed   hybrid in the mixed-precision form (FP16 stencil storage, FP32 Krylov vectors,
-          FP64 recurrences and defect correction)
+  mixed   hybrid in the mixed-precision form (FP64 vectors and recurrences; the
+          multi-shift stencil moves to FP32, then FP16 storage as the residual falls)
+  plain_mixed  plain in the mixed-precision form
 All forms run the same kernels on the same GPU; every shift's FP64 true residual is
 reported.  Roofline: the dominant kernel class of the headline form (largest summed
 time), timed by HIP events on its launch stream during the timed region; achieved
@@ -56,7 +57,7 @@ def parse():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--steps", type=int, default=None, help="timed solves (default: one per right-hand side)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="full,plain,hybrid,mixed",
+    ap.add_argument("--forms", default="full,plain,hybrid,mixed,plain_mixed",
                     help="comma list; the first is the headline value")
     ap.add_argument("--fgmres-restart", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -127,8 +128,10 @@ def form_params(ctx, nd, form, restart):
         return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, mms_predict=2, **hyb)
     if form == "lagrange":
         return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, mms_predict=0, **hyb)
+    if form == "plain_mixed":
+        return ctx.solve_params(tol=1e-10, precision=nd.NDTM_PREC_F16)
     if form == "mixed":
-        return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, precision=nd.NDTM_PREC_F16, **hyb)
+        return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, mms_predict=2, precision=nd.NDTM_PREC_F16, **hyb)
     if form == "full_mixed":
         return ctx.solve_params(guess=nd.NDTM_GUESS_MLP, precision=nd.NDTM_PREC_F16, **hyb)
     raise ValueError(form)
@@ -146,6 +149,7 @@ def run_form(ctx, nd, bds, xs, form, steps, warmup, profile, restart):
             ctx.ndtm_profile_read(k, reset=True)
         ctx.ndtm_profile_enable((1 << len(nd.PROF_CLASSES)) - 1)
     reps = []
+    allocs0 = ctx.ndtm_workspace_stats()["device_allocs"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -153,6 +157,7 @@ def run_form(ctx, nd, bds, xs, form, steps, warmup, profile, restart):
         reps.append(rep)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    allocs = ctx.ndtm_workspace_stats()["device_allocs"] - allocs0
     prof = None
     if profile:
         ctx.ndtm_profile_enable(0)
@@ -163,10 +168,13 @@ def run_form(ctx, nd, bds, xs, form, steps, warmup, profile, restart):
     last = reps[-1]
     return {
         "ms_per_solve": 1000.0 * dt / steps,
+        "ms_per_solve_each": [r["t_total_ms"] for r in reps],
+        "device_allocs_timed": allocs,
         "solves_per_s": steps / dt,
         "worst_true_res": max(max(r["true_res"]) for r in reps),
         "true_res_per_rhs": [max(r["true_res"]) for r in reps],
         "mms_iterations_per_rhs": [r["mms_iterations"] for r in reps],
+        "mms_first_f32_f16": [last["mms_it32"], last["mms_it16"]],
         "mg_iterations": [it for it, m in zip(last["iterations"], last["method"]) if m != 0],
         "methods": list(last["method"]),
         "iterations_per_shift": list(last["iterations"]),
@@ -294,7 +302,7 @@ def main():
     forms = [f for f in args.forms.split(",") if f]
     setup_ms = None
     mgp = None
-    if any(f != "plain" for f in forms):
+    if any(f not in ("plain", "plain_mixed") for f in forms):
         # FP32 cycle; on the large lattice the FP64 copies of P and the coarse blocks are
         # freed after the setup (the cycle reads only the FP32 ones)
         mgp = ctx.mg_params(keep_f64=0 if big else 1)

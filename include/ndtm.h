@@ -262,11 +262,17 @@ typedef struct {
                           setup or a spectrum estimate, all shifts go to MMS-CG */
   int guess;           /* NDTM_GUESS_* for the multigrid shifts */
   int precision;       /* NDTM_PREC_F64: FP64 throughout.  NDTM_PREC_F16: mixed form, the
-                          multi-shift CG runs on FP16 stencil storage (one FP32 scale per
-                          site, FP32 arithmetic) with FP32 Krylov vectors and FP64 scalar
-                          recurrences, then each shift is refined by FP64 defect correction
-                          (FP64 true residual and solution, mixed-precision inner CG).
-                          Other values select the FP64 form. */
+                          multi-shift CG keeps its FP64 vectors, residual slots, solutions
+                          and scalar recurrences, but its stencil moves to lower-precision
+                          operand storage as the base residual falls: FP32 once
+                          ||r||/||b|| <= tol / (K u32) and FP16 (one FP32 scale per site,
+                          FP32 arithmetic) once ||r||/||b|| <= tol / (K u16), with u32, u16
+                          the storages' unit roundoffs and K a safety factor; each stencil
+                          error then enters the solutions scaled by the residual of its
+                          iteration, below tol.  Every shift is checked by its FP64 true
+                          residual and finished by FP64 CG if it misses.  Needs the
+                          deferred recurrences (mms_defer >= 2; otherwise FP64).  Other
+                          values select the FP64 form. */
   int poll_every;      /* MMS-CG iterations between host convergence polls */
   double mg_tol;       /* cap on the relative residual of each single (Q +- i m) solve; each
                           round tightens it so that the squared system meets tol */
@@ -310,6 +316,8 @@ typedef struct {
   double hop_ms;                    /* summed duration of FP64 stencil launches (if profiling) */
   long long hop_launches;
   int n_mmscg;                      /* shifts the multi-shift CG solved (the choice of NDTM_NMMS_AUTO) */
+  int mms_it32, mms_it16;           /* mixed form: first multi-shift iteration whose stencil ran on
+                                       FP32 / FP16 storage (-1: none) */
 } ndtm_solve_report;
 
 /* Solves all shifts for one b.  x_dev[i] receives the solution of the i-th

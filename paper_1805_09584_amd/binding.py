@@ -58,12 +58,14 @@ class SolveReport(C.Structure):
                 ("rounds", _I16), ("true_res", _D16), ("guess_res", _D16), ("lagrange_res", _D16),
                 ("mlp_res", _D16), ("guess_kind", _I16), ("t_mms_ms", C.c_double),
                 ("t_guess_ms", C.c_double), ("t_mg_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("hop_ms", C.c_double), ("hop_launches", C.c_longlong), ("n_mmscg", C.c_int)]
+                ("hop_ms", C.c_double), ("hop_launches", C.c_longlong), ("n_mmscg", C.c_int),
+                ("mms_it32", C.c_int), ("mms_it16", C.c_int)]
 
     def to_dict(self):
         n = self.n_shifts
         d = {k: getattr(self, k) for k in ("status", "n_shifts", "mms_iterations", "t_mms_ms", "t_guess_ms",
-                                          "t_mg_ms", "t_total_ms", "hop_ms", "hop_launches", "n_mmscg")}
+                                          "t_mg_ms", "t_total_ms", "hop_ms", "hop_launches", "n_mmscg",
+                                          "mms_it32", "mms_it16")}
         for k in ("sigma", "input_index", "method", "iterations", "rounds", "true_res", "guess_res",
                   "lagrange_res", "mlp_res", "guess_kind"):
             d[k] = list(getattr(self, k)[:n])

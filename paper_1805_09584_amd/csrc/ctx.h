@@ -146,8 +146,16 @@ int red_grid(size_t n);
 void mms_seed(double* S, const double* src, hipStream_t st);
 
 // drivers
+// Stencil precision schedule of the mixed form (deferred recurrences only): the
+// stencil moves to FP32 storage once ||r|| / ||b|| of the base system is at most
+// rel32 and to FP16 once it is at most rel16 (0: never).  Vectors, ring, solutions
+// and scalars stay FP64.
+struct MmsRamp {
+  double rel32 = 0, rel16 = 0;
+};
 struct MmsResult {
   int iterations = 0;
+  int it32 = -1, it16 = -1;  // first iteration on FP32 / FP16 stencil storage (-1: none)
   std::vector<int> iters;
   bool breakdown = false;
   double lam_lo = -1, lam_hi = -1;  // extreme eigenvalues of Q^2 from the Lanczos coefficients (deferred form)
@@ -163,9 +171,10 @@ int hybrid_choose(int N, const double* sig, double lmin, double lmax, double tol
 // region (optional): holds the shifted directions of shifts 1.. and the `defer`
 // residual slots, (nsh - 1 + defer) FP64 half fields; without it they are named
 // workspace buffers and defer is clamped to half of the free device memory.
+// ramp (optional, deferred form): the mixed form's stencil precision schedule.
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st, int npass = 0, void* region = nullptr);
+              hipStream_t st, int npass = 0, void* region = nullptr, const MmsRamp* ramp = nullptr);
 // FP64 half fields the multigrid phase takes from the solve's region (case C and FGMRES)
 int mg_region_fields(int fgmres_restart);
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual

@@ -489,74 +489,138 @@ __global__ void mms_seed_k(double* S, const double* src) {
   }
 }
 
-// ---------------- MMS-CG, mixed form ----------------
-// Krylov vectors in FP32 half-field layout [24][stride]; the stencil runs on
-// FP16 copies with one FP32 scale per site (w16 produced by the stencil, p16
-// written here).  All scalars stay FP64 in S.
-struct ShiftPtrs32 {
-  float2* x[kMaxShifts];
-  float2* p[kMaxShifts];
+// ---------------- deferred MMS-CG on low-precision stencil storage ----------------
+// The mixed form keeps the FP64 Krylov vectors and residual ring of the deferred form;
+// only the stencil runs on FP32 or FP16 copies.  The residual pass reads w as the
+// stencil wrote it, the direction pass writes p's copy for the next stencil.  Both
+// storages come in 16-byte words per half-site: FP32 holds 2 complex components a word
+// (12 words), FP16 4 (6 words, one FP32 scale per site).  Scalar steps as in the FP64
+// fused passes.
+typedef unsigned mx_v4u __attribute__((ext_vector_type(4)));
+union MxWord {
+  mx_v4u w;
+  __half2 h[4];
+  float2 f[2];
 };
 
-__global__ void mms_update_r_mx_k(float2* r, const __half2* w16, const float* wsc, const double* S, int vh,
-                                  int stride, double* partials) {
-  const double alpha = S[MS_ALPHA];
+template <int PREC>
+struct MxStore {
+  static constexpr int kPer = PREC == P16 ? 4 : 2;  // complex components per word
+  static constexpr int kWords = 24 / kPer;
+  __device__ static float2 get(const MxWord& u, int j) {
+    if constexpr (PREC == P16)
+      return __half22float2(u.h[j]);
+    else
+      return u.f[j];
+  }
+  __device__ static void put(MxWord& u, int j, double x, double y, double inv) {
+    if constexpr (PREC == P16)
+      u.h[j] = __floats2half2_rn((float)(x * inv), (float)(y * inv));
+    else
+      u.f[j] = make_float2((float)x, (float)y);
+  }
+};
+
+template <int PREC>
+__global__ void __launch_bounds__(256) mms_update_r_fused_mx_k(const double2* rin, double2* rout, const mx_v4u* wq,
+                                                               const float* wsc, double* S, int vh, int stride,
+                                                               const double* pst, int nst, double* partials,
+                                                               const double* skip, int it) {
+  using M = MxStore<PREC>;
+  if (skip && *skip != 0.0) return;
+  const double pw = mms::sum_partials(pst, nst);
+  const double alpha = mms::alpha_of(S, pw);
+  if (blockIdx.x == 0) mms::step1_pw(S, pw, (double)(it + 1));
   double acc = 0;
-  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < vh; h += gridDim.x * blockDim.x) {
-    const double sc = wsc[h];
-    for (int c = 0; c < 24; ++c) {
-      const size_t i = idx32(c, stride, h);
-      const float2 w = __half22float2(w16[idx16(c, stride, h)]);
-      float2 v = r[i];
-      v.x = (float)((double)v.x - alpha * sc * (double)w.x);
-      v.y = (float)((double)v.y - alpha * sc * (double)w.y);
-      r[i] = v;
-      acc += (double)v.x * v.x + (double)v.y * v.y;
+  // the padding sites past vh carry rin over (the FP64 passes treat them as sites)
+  const long nq = (long)M::kWords * stride;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nq; q += (long)gridDim.x * blockDim.x) {
+    const int g = (int)(q / stride), h = (int)(q - (long)g * stride);
+    MxWord u;
+    double a = 0;
+    if (h < vh) {
+      u.w = wq[(long)g * stride + h];
+      a = PREC == P16 ? alpha * (double)wsc[h] : alpha;
+    } else {
+      u.w = mx_v4u{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int j = 0; j < M::kPer; ++j) {
+      const long i = (long)(M::kPer * g + j) * stride + h;
+      const float2 wf = M::get(u, j);
+      double2 v = rin[i];
+      v.x -= a * (double)wf.x;
+      v.y -= a * (double)wf.y;
+      rout[i] = v;
+      acc += v.x * v.x + v.y * v.y;
     }
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-__global__ void mms_update_p_mx_k(const float2* r, float2* p, __half2* p16, float* p16sc, ShiftPtrs32 P, int nsh,
-                                  const double* S, int vh, int stride) {
-  const double beta = S[MS_BETA];
-  const bool any_before = S[MS_ALPHA] != 0.0;
+template <int PREC>
+__global__ void __launch_bounds__(256) mms_update_pbase_fused_mx_k(const double2* r, double2* p, mx_v4u* pq,
+                                                                   float* psc, double* S, int vh, int stride,
+                                                                   const double* pr, int npr, int slot, double* H,
+                                                                   int it) {
+  using M = MxStore<PREC>;
+  if (S[MS_GO] != (double)(it + 1)) return;
+  const bool stepped = S[MS_ALPHA] != 0.0;
+  const double rr = mms::sum_partials(pr, npr);
+  if (blockIdx.x == 0) mms::step2_rr(S, rr, slot, H);
+  if (!stepped || !isfinite(rr)) return;
+  const double beta = rr / S[MS_RR_OLD];
   for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < vh; h += gridDim.x * blockDim.x) {
-    float2 pn[24];
-    float mx = 0.f;
+    double2 pv[24];
+    double mx = 0;
+#pragma unroll
     for (int c = 0; c < 24; ++c) {
-      const size_t i = idx32(c, stride, h);
-      const float2 ri = r[i];
-      for (int s = 0; s < nsh; ++s) {
-        if (S[MS_ACT + s] == 0.0) continue;
-        const double as = S[MS_ALPHA_S + s], bs = S[MS_BETA_S + s], z = S[MS_ZETA + s];
-        float2 ps = P.p[s][i];
-        float2 xs = P.x[s][i];
-        xs.x = (float)(xs.x + as * ps.x);
-        xs.y = (float)(xs.y + as * ps.y);
-        ps.x = (float)(z * ri.x + bs * ps.x);
-        ps.y = (float)(z * ri.y + bs * ps.y);
-        P.x[s][i] = xs;
-        P.p[s][i] = ps;
-      }
-      float2 pv = p[i];
-      if (any_before) {
-        pv.x = (float)(ri.x + beta * pv.x);
-        pv.y = (float)(ri.y + beta * pv.y);
-        p[i] = pv;
-      }
-      pn[c] = pv;
-      mx = fmaxf(mx, fmaxf(fabsf(pv.x), fabsf(pv.y)));
+      const long i = (long)c * stride + h;
+      const double2 ri = r[i], pi = p[i];
+      pv[c] = make_double2(ri.x + beta * pi.x, ri.y + beta * pi.y);
+      p[i] = pv[c];
+      mx = fmax(mx, fmax(fabs(pv[c].x), fabs(pv[c].y)));
     }
-    const float inv = mx > 0.f ? 1.0f / mx : 0.f;
-    for (int c = 0; c < 24; ++c)
-      p16[idx16(c, stride, h)] = __floats2half2_rn(pn[c].x * inv, pn[c].y * inv);
-    p16sc[h] = mx;
+    double inv = 1.0;
+    if constexpr (PREC == P16) {
+      const float sc = (float)mx;
+      inv = sc > 0.f ? 1.0 / (double)sc : 0.0;
+      psc[h] = sc;
+    }
+#pragma unroll
+    for (int g = 0; g < M::kWords; ++g) {
+      MxWord u;
+#pragma unroll
+      for (int j = 0; j < M::kPer; ++j) M::put(u, j, pv[M::kPer * g + j].x, pv[M::kPer * g + j].y, inv);
+      pq[(long)g * stride + h] = u.w;
+    }
   }
 }
 
+
 }  // namespace
+
+void mms_update_r_fused_mx(int prec, const double2* rin, double2* rout, const void* wq, const float* wsc, double* S,
+                           int vh, int stride, const double* pst, int nst, double* partials, int nblk,
+                           const double* skip, int it, hipStream_t st) {
+  if (prec == P16)
+    hipLaunchKernelGGL(mms_update_r_fused_mx_k<P16>, dim3(nblk), dim3(256), 0, st, rin, rout, (const mx_v4u*)wq, wsc,
+                       S, vh, stride, pst, nst, partials, skip, it);
+  else
+    hipLaunchKernelGGL(mms_update_r_fused_mx_k<P32>, dim3(nblk), dim3(256), 0, st, rin, rout, (const mx_v4u*)wq, wsc,
+                       S, vh, stride, pst, nst, partials, skip, it);
+}
+void mms_update_pbase_fused_mx(int prec, const double2* r, double2* p, void* pq, float* psc, double* S, int vh,
+                               int stride, const double* pr, int npr, int slot, double* H, int it, hipStream_t st) {
+  const dim3 grid((vh + 255) / 256);
+  if (prec == P16)
+    hipLaunchKernelGGL(mms_update_pbase_fused_mx_k<P16>, grid, dim3(256), 0, st, r, p, (mx_v4u*)pq, psc, S, vh,
+                       stride, pr, npr, slot, H, it);
+  else
+    hipLaunchKernelGGL(mms_update_pbase_fused_mx_k<P32>, grid, dim3(256), 0, st, r, p, (mx_v4u*)pq, psc, S, vh,
+                       stride, pr, npr, slot, H, it);
+}
 
 void blas_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n = bytes / sizeof(double);
@@ -668,19 +732,6 @@ void mms_update_p(double2* r, double2* p, double2* const* xs, double2* const* ps
   hipLaunchKernelGGL(mms_update_p_k, dim3(grid_for(n)), dim3(256), 0, st, r, p, P, nsh, sb, S, n, it);
 }
 int red_grid(size_t n) { return (int)grid_for(n); }
-void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
-                     double* partials, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(mms_update_r_mx_k, dim3(nblk), dim3(256), 0, st, r, w16, wsc, S, vh, stride, partials);
-}
-void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
-                     int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st) {
-  ShiftPtrs32 P;
-  for (int s = 0; s < nsh; ++s) {
-    P.x[s] = xs[s];
-    P.p[s] = ps[s];
-  }
-  hipLaunchKernelGGL(mms_update_p_mx_k, dim3(nblk), dim3(256), 0, st, r, p, p16, p16sc, P, nsh, S, vh, stride);
-}
 void mms_seed(double* S, const double* src, hipStream_t st) {
   hipLaunchKernelGGL(mms_seed_k, dim3(1), dim3(64), 0, st, S, src);
 }

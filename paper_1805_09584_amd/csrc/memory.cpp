@@ -190,16 +190,15 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     t += 6 * h64;                  // base Krylov vectors and the first shifted direction
     t += (size_t)nsh * h64;        // solutions of ndtm_solve_rational
     const size_t mg_fields = mg_phase ? (size_t)mg_region_fields(sp->fgmres_restart) : 0;
-    if (sp->precision == NDTM_PREC_F16) {
-      t += (size_t)(2 * n_mms + 5) * z.half(P32) + 4 * z.half(P16) + 2 * h64;
-      t += R(mg_fields * z.n * 16);
-    } else {
+    {
       const int n_pred = mg_phase ? std::max(0, std::min(sp->mms_predict, nsh - n_mms)) : 0;
       int defer = std::min(sp->mms_defer, kMaxDefer);
       if (defer < 2) defer = 0;
       const size_t mms_fields = (size_t)(n_mms + n_pred - 1 + defer);
       t += R(std::max(mg_fields, mms_fields) * z.n * 16);
       if (n_pred > 0) t += 2 * h64;
+      // mixed form: the stencil's operands (p, w and two temporaries) in FP32 and FP16
+      if (sp->precision == NDTM_PREC_F16 && defer) t += 4 * z.half(P32) + 4 * z.half(P16);
     }
     if (mg_phase) {
       t += 2 * h64;  // guess: projection or network sample vectors

@@ -182,13 +182,17 @@ void mms_update_r_fused(const double2* rin, double2* rout, const double2* w, dou
                         int nst, double* partials, const double* skip, int it, hipStream_t st);
 void mms_update_pbase_fused(const double2* r, double2* p, double* S, size_t n, const double* pr, int npr, int slot,
                             double* H, int it, hipStream_t st);
+// mixed form of the two fused passes: FP64 vectors; the stencil's output wq (FP32 or FP16
+// words of precision prec, FP16 with the per-site scale wsc) read by the residual pass,
+// p's copy in that precision (psc: its FP16 scales) written by the direction pass; nblk:
+// blocks of the residual pass (its partial count)
+void mms_update_r_fused_mx(int prec, const double2* rin, double2* rout, const void* wq, const float* wsc, double* S,
+                           int vh, int stride, const double* pst, int nst, double* partials, int nblk,
+                           const double* skip, int it, hipStream_t st);
+void mms_update_pbase_fused_mx(int prec, const double2* r, double2* p, void* pq, float* psc, double* S, int vh,
+                               int stride, const double* pr, int npr, int slot, double* H, int it, hipStream_t st);
 void mms_flush(double2* const* xs, double2* const* ps, int nsh, const double2* R, int nr, int k0, bool with_p,
                const double* S, const double* H, double* C, size_t n, hipStream_t st);
-// mixed form: FP32 vectors, FP16 stencil fields (per-site scale), FP64 scalars; one thread per site
-void mms_update_r_mx(float2* r, const __half2* w16, const float* wsc, const double* S, int vh, int stride,
-                     double* partials, int nblk, hipStream_t st);
-void mms_update_p_mx(const float2* r, float2* p, __half2* p16, float* p16sc, float2* const* xs, float2* const* ps,
-                     int nsh, const double* S, int vh, int stride, int nblk, hipStream_t st);
 // Deferred multi-shift update: the shifted x_s, p_s are formed once per block of
 // at most kMaxDefer iterations from the residuals of that block.  Each iteration
 // records per shift (alpha_s or 0, beta_s, zeta_{k+1}, active) in slot k mod m of

@@ -37,7 +37,11 @@
 
 namespace ndtm {
 
-static_assert(MS_SIZE + 8 <= kScalN, "scalar block and poll slots fit the pinned mirror");
+// unit roundoffs of the mixed form's stencil storages (FP32 mantissa; FP16 relative to
+// the per-site scale) and the safety factor of its precision schedule
+constexpr double kUnitRoundoff32 = 0x1p-24, kUnitRoundoff16 = 0x1p-11, kRampSafety = 100.0;
+
+static_assert(MS_SIZE + 32 <= kScalN && MS_DONE < 16, "scalar block and poll slots fit the pinned mirror");
 
 namespace {
 
@@ -48,16 +52,21 @@ namespace {
 // is set, so the iterations queued past convergence cost only their launches.
 // With kernel timing on, every poll waits for its own flag instead, so that no
 // skipped launch enters the per-class statistics.
+// Each poll copies the scalar header S[MS_RR .. MS_DONE], so that the relative
+// residual of the base system at the last completed poll is known as well.
 struct LaggedPoll {
+  static constexpr int kSpan = MS_DONE + 1;
   ndtm_ctx* c;
   hipStream_t st;
   hipEvent_t ev[2] = {nullptr, nullptr};
   double* slot;
   int n = 0;
-  const double* flag;
+  const double* S;
   bool lag;
-  LaggedPoll(ndtm_ctx* cc, const double* done_flag, hipStream_t s) : c(cc), st(s), flag(done_flag) {
-    slot = c->hscal + kScalN - 4;
+  double rel = INFINITY;  // sqrt(rr / bb) of the base system at the last completed poll
+  LaggedPoll(ndtm_ctx* cc, const double* scal, hipStream_t s) : c(cc), st(s), S(scal) {
+    const double* done_flag = S + MS_DONE;
+    slot = c->hscal + kScalN - 2 * 16;
     for (auto& e : ev) (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
     lag = c->prof_mask == 0;
     if (lag) c->hop_skip = done_flag;
@@ -68,18 +77,23 @@ struct LaggedPoll {
       if (e) (void)hipEventDestroy(e);
   }
   // true once a completed poll has seen the flag set
+  bool seen(int k) {
+    const double* h = slot + 16 * k;
+    if (h[MS_BB] > 0) rel = std::sqrt(h[MS_RR] / h[MS_BB]);
+    return h[MS_DONE] != 0.0;
+  }
   bool done() {
     const int k = n & 1;
-    (void)hipMemcpyAsync(slot + k, flag, sizeof(double), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(slot + 16 * k, S, kSpan * sizeof(double), hipMemcpyDeviceToHost, st);
     (void)hipEventRecord(ev[k], st);
     ++n;
     if (!lag) {
       (void)hipEventSynchronize(ev[k]);
-      return slot[k] != 0.0;
+      return seen(k);
     }
     if (n < 2) return false;
     (void)hipEventSynchronize(ev[1 - k]);
-    return slot[1 - k] != 0.0;
+    return seen(1 - k);
   }
 };
 
@@ -100,7 +114,7 @@ struct RegionScope {
 
 int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
-              hipStream_t st, int npass, void* region) {
+              hipStream_t st, int npass, void* region, const MmsRamp* ramp) {
   const int nsh = (int)sigmas.size();
   const size_t n = half_elems(c);
   const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
@@ -137,6 +151,21 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     ring = static_cast<double2*>(ws_get(c, "cg_ring", (size_t)defer * n * sizeof(double2)));
     if (!ring) return fail(c, NDTM_ENOMEM, "mmscg: residual slots");
   }
+  // mixed form: the stencil's operands in FP32 and FP16 storage
+  const bool ramped = ramp && deferred && (ramp->rel32 > 0 || ramp->rel16 > 0);
+  HalfField lq[2][4];  // [FP32, FP16][p, w, u, te]
+  if (ramped) {
+    const char* nm[4] = {"mx_p", "mx_w", "mx_u", "mx_te"};
+    for (int q = 0; q < 2; ++q) {
+      if ((q == 0 ? ramp->rel32 : ramp->rel16) <= 0) continue;
+      for (int k = 0; k < 4; ++k) {
+        lq[q][k] = half_field(c, std::string(nm[k]) + (q == 0 ? "32" : "16"), q == 0 ? P32 : P16);
+        if (!lq[q][k].v || (q == 1 && !lq[q][k].sc)) return fail(c, NDTM_ENOMEM, "mmscg: workspace");
+      }
+    }
+  }
+  int sprec = P64;
+  res->it32 = res->it16 = -1;
   const double2* bv = static_cast<const double2*>(b.v);
   blas_copy((double2*)r.v, bv, n, st);
   blas_copy((double2*)p.v, bv, n, st);
@@ -163,7 +192,7 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   }
   int it = 0;
   if (poll_every < 1) poll_every = 1;
-  LaggedPoll poll(c, c->mms_S + MS_DONE, st);
+  LaggedPoll poll(c, c->mms_S, st);
   struct Flush {
     int first, nr;
     bool with_p;
@@ -179,9 +208,28 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   const int hg = hop_grid(c->g);
   const int rg = red_grid(n);
   while (it < maxiter) {
+    if (ramped) {
+      // the schedule follows the base residual seen by the last completed poll; the
+      // direction's copy in the new storage is formed from its FP64 value
+      int want = sprec;
+      if (ramp->rel16 > 0 && poll.rel <= ramp->rel16)
+        want = P16;
+      else if (ramp->rel32 > 0 && poll.rel <= ramp->rel32 && sprec == P64)
+        want = P32;
+      if (want != sprec) {
+        const HalfField& pq = lq[want == P16 ? 1 : 0][0];
+        launch_convert_half(c->g, p, pq, st);
+        (want == P16 ? res->it16 : res->it32) = it;
+        sprec = want;
+      }
+    }
+    const HalfField* q = sprec == P64 ? nullptr : lq[sprec == P16 ? 1 : 0];
     // past the done flag the stencil passes and the residual update return at once, and
     // the update kernels of an iteration run only if its scalar step was taken
-    apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
+    if (q)
+      apply_qhat2(c, sprec, q[1], q[0], q[2], q[3], sig_base, c->partials, st);
+    else
+      apply_qhat2(c, P64, w, p, u, te, sig_base, c->partials, st);
     // deferred: r_k is in slot (k-1) mod m (b for k = 0), r_{k+1} goes to slot k mod m
     const int slot = deferred ? it % defer : -1;
     const double2* rin = !deferred ? (const double2*)r.v : it == 0 ? bv : ring + (size_t)((it - 1) % defer) * n;
@@ -190,13 +238,26 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
       // the scalar steps ride in the two vector passes; the residual norms go behind
       // the stencil's partials, which the first pass still reads
       double* pr_r = c->partials + hg;
-      {
-        ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
-        mms_update_r_fused(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, hg, pr_r, c->hop_skip, it,
-                           st);
+      if (q) {
+        // rin, rout FP64 and w in the stencil's storage; p FP64 read and written, its copy written
+        const double wb = sprec == P16 ? 100.0 : 192.0;
+        {
+          ProfScope pr(c, NDTM_PROF_MMS_RESID, (2.0 * 384.0 + wb) * c->g.vh, st);
+          mms_update_r_fused_mx(sprec, rin, rout, q[1].v, q[1].sc, c->mms_S, c->g.vh, c->g.stride, c->partials, hg,
+                                pr_r, rg, c->hop_skip, it, st);
+        }
+        ProfScope pu(c, NDTM_PROF_MMS_UPDATE, wb * c->g.vh, st);
+        mms_update_pbase_fused_mx(sprec, rout, (double2*)p.v, q[0].v, q[0].sc, c->mms_S, c->g.vh, c->g.stride, pr_r,
+                                  rg, slot, c->mms_H, it, st);
+      } else {
+        {
+          ProfScope pr(c, NDTM_PROF_MMS_RESID, 3.0 * 384.0 * c->g.vh, st);
+          mms_update_r_fused(rin, rout, (const double2*)w.v, c->mms_S, n, c->partials, hg, pr_r, c->hop_skip, it,
+                             st);
+        }
+        ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
+        mms_update_pbase_fused(rout, (double2*)p.v, c->mms_S, n, pr_r, rg, slot, c->mms_H, it, st);
       }
-      ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_pbase_fused(rout, (double2*)p.v, c->mms_S, n, pr_r, rg, slot, c->mms_H, it, st);
     } else {
       mms_scal1(c->mms_S, c->partials, hg, st);
       {
@@ -265,84 +326,6 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   return done ? NDTM_OK : NDTM_ENOCONV;
 }
 
-// Mixed form of the same iteration: Krylov vectors in FP32, the stencil on
-// FP16 copies (per-site scale, FP32 arithmetic), every scalar recurrence in
-// FP64 on the device.  Solves (Q^2 + sigma_s) x_s = b for FP32 fields x_s, b.
-int run_mmscg_mixed(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<HalfField>& xs,
-                    const HalfField& b, double tol, int maxiter, int poll_every, MmsResult* res, hipStream_t st) {
-  const int nsh = (int)sigmas.size();
-  const size_t n = half_elems(c);
-  const double sig_base = *std::min_element(sigmas.begin(), sigmas.end());
-  HalfField r = half_field(c, "mx_r", P32), p = half_field(c, "mx_p", P32);
-  HalfField p16 = half_field(c, "mx_p16", P16), w16 = half_field(c, "mx_w16", P16), u16 = half_field(c, "mx_u16", P16),
-            te16 = half_field(c, "mx_te16", P16);
-  std::vector<float2*> ps(nsh), xv(nsh);
-  for (int s = 0; s < nsh; ++s) {
-    HalfField f = half_field(c, "mx_ps" + std::to_string(s), P32);
-    if (!f.v) return fail(c, NDTM_ENOMEM, "mixed mmscg: workspace");
-    ps[s] = static_cast<float2*>(f.v);
-    xv[s] = static_cast<float2*>(xs[s].v);
-  }
-  if (!r.v || !p.v || !p16.v || !w16.v || !u16.v || !te16.v) return fail(c, NDTM_ENOMEM, "mixed mmscg: workspace");
-  vconvert(P32, r.v, P32, b.v, n, st);
-  vconvert(P32, p.v, P32, b.v, n, st);
-  launch_convert_half(c->g, b, p16, st);
-  for (int s = 0; s < nsh; ++s) {
-    vconvert(P32, ps[s], P32, b.v, n, st);
-    vzero(P32, xv[s], n, st);
-  }
-  std::vector<double> S(MS_SIZE, 0.0);
-  S[MS_ALPHA_PREV] = 1.0;
-  S[MS_TOL2] = tol * tol;
-  S[MS_NSH] = nsh;
-  for (int s = 0; s < nsh; ++s) {
-    S[MS_ZETA + s] = S[MS_ZETA_PREV + s] = 1.0;
-    S[MS_DELTA + s] = sigmas[s] - sig_base;
-    S[MS_ACT_NEXT + s] = 1.0;
-  }
-  NDTM_HIP(c, hipMemcpyAsync(c->mms_S, S.data(), MS_SIZE * sizeof(double), hipMemcpyHostToDevice, st));
-  vnorm2(P32, b.v, n, c->vred, c->dscal, st);
-  mms_seed(c->mms_S, c->dscal, st);
-  const int hg = hop_grid(c->g);
-  const int nb = std::min(1024, (c->g.vh + 255) / 256);
-  int it = 0;
-  if (poll_every < 1) poll_every = 1;
-  LaggedPoll poll(c, c->mms_S + MS_DONE, st);
-  while (it < maxiter) {
-    apply_qhat2(c, P16, w16, p16, u16, te16, sig_base, c->partials, st);
-    mms_scal1(c->mms_S, c->partials, hg, st);
-    {
-      ProfScope pr(c, NDTM_PROF_MMS_RESID, (192.0 * 2 + 100.0) * c->g.vh, st);
-      mms_update_r_mx((float2*)r.v, (const __half2*)w16.v, w16.sc, c->mms_S, c->g.vh, c->g.stride, c->partials, nb,
-                      st);
-    }
-    mms_scal2(c->mms_S, c->partials, nb, -1, nullptr, st);
-    {
-      ProfScope pu(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
-      mms_update_p_mx((const float2*)r.v, (float2*)p.v, (__half2*)p16.v, p16.sc, xv.data(), ps.data(), nsh, c->mms_S,
-                      c->g.vh, c->g.stride, nb, st);
-    }
-    ++it;
-    if (it % poll_every == 0 && poll.done()) break;
-  }
-  NDTM_HIP(c, hipGetLastError());
-  NDTM_HIP(c, hipMemcpyAsync(c->hscal, c->mms_S, MS_SIZE * sizeof(double), hipMemcpyDeviceToHost, st));
-  NDTM_HIP(c, hipStreamSynchronize(st));
-  res->iterations = (int)c->hscal[MS_IT];
-  res->breakdown = c->hscal[MS_BREAK] != 0.0;
-  res->iters.resize(nsh);
-  for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
-  const bool done = c->hscal[MS_DONE] != 0.0;
-  if ((c->prof_mask >> NDTM_PROF_MMS_UPDATE) & 1) {
-    // r (read), p (read, written) and its FP16 copy (written), x_s and p_s (read, written) in FP32
-    double active_launches = 0;
-    for (int s = 0; s < nsh; ++s) active_launches += res->iters[s];
-    c->prof_bytes[NDTM_PROF_MMS_UPDATE] += ((3.0 * 192.0 + 100.0) * it + 4.0 * 192.0 * active_launches) * c->g.vh;
-  }
-  if (res->breakdown) return fail(c, NDTM_EBREAKDOWN, "mixed mmscg: breakdown (non-finite or p.Ap <= 0)");
-  return done ? NDTM_OK : NDTM_ENOCONV;
-}
-
 double true_residual(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, const HalfField& r,
                      hipStream_t st) {
   const size_t n = half_elems(c);
@@ -392,46 +375,6 @@ int cg_shift(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, 
   return polish_cg(c, x, b, sigma, tol, maxiter, res_out, iters_out, st);
 }
 
-// FP64 defect correction of one shift with the mixed-precision CG as the inner
-// solver: r = b - (Q^2+sigma) x in FP64, e ~ (Q^2+sigma)^-1 r in the mixed form,
-// x += e in FP64, until the true residual meets tol.  Falls back to the FP64
-// polish when a round gains less than a factor 4.
-static int refine_mixed(ndtm_ctx* c, const HalfField& x, const HalfField& b, double sigma, double tol, int maxiter,
-                        double* res_out, int* iters_out, int* rounds_out, hipStream_t st) {
-  const size_t n = half_elems(c);
-  HalfField r = half_field(c, "rf_r", P64), r32 = half_field(c, "rf_r32", P32), e32 = half_field(c, "rf_e32", P32),
-            e64 = half_field(c, "rf_e64", P64);
-  if (!r.v || !r32.v || !e32.v || !e64.v) return fail(c, NDTM_ENOMEM, "refine: workspace");
-  double res = true_residual(c, x, b, sigma, r, st);
-  int total = 0, rounds = 0;
-  while (res > tol && rounds < 12) {
-    vconvert_field(P32, r32.v, P64, r.v, 1, c->g.vh, c->g.stride, st);
-    MmsResult mr;
-    std::vector<HalfField> es{e32};
-    const double inner = std::max(1e-4, std::min(0.5, 0.5 * tol / res));
-    int rc = run_mmscg_mixed(c, {sigma}, es, r32, inner, maxiter, 8, &mr, st);
-    total += mr.iterations;
-    ++rounds;
-    if (rc == NDTM_ENOMEM) return rc;
-    if (rc == NDTM_EBREAKDOWN) break;
-    vconvert_field(P64, e64.v, P32, e32.v, 1, c->g.vh, c->g.stride, st);
-    blas_axpy((double2*)x.v, make_double2(1, 0), (const double2*)e64.v, n, st);
-    const double prev = res;
-    res = true_residual(c, x, b, sigma, r, st);
-    if (!(res < 0.25 * prev)) break;
-  }
-  int rc = NDTM_OK;
-  if (res > tol) {
-    int extra = 0;
-    rc = polish_cg(c, x, b, sigma, tol, maxiter, &res, &extra, st);
-    total += extra;
-  }
-  *res_out = res;
-  *iters_out = total;
-  *rounds_out = rounds;
-  return res <= tol ? NDTM_OK : rc;
-}
-
 // The hybrid part (multigrid shifts) lives in mg.cpp; xs[n_mms .. n_mms+n_pred)
 // hold the multi-shift iterates of the passenger shifts.
 int solve_mg_shifts(ndtm_ctx* c, const std::vector<double>& sig_desc, int n_mms, int n_pred,
@@ -476,6 +419,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   auto t0 = std::chrono::steady_clock::now();
   std::memset(rep, 0, sizeof(*rep));
   rep->n_shifts = nsh;
+  rep->mms_it32 = rep->mms_it16 = -1;
   // descending order (section 4.2: solve sigma_1 > sigma_2 > ...)
   std::vector<int> order(nsh);
   std::iota(order.begin(), order.end(), 0);
@@ -529,35 +473,17 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   rep->n_mmscg = n_mms;
   int status = NDTM_OK;
   // ---- MMS-CG for the n_mms largest shifts ----
-  if (p->precision == NDTM_PREC_F16) {
-    // mixed form: multi-shift CG on FP16 stencil storage, then FP64 defect correction per shift
-    std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms);
-    std::vector<HalfField> x32(n_mms);
-    for (int i = 0; i < n_mms; ++i) {
-      x32[i] = half_field(c, "sv_x32_" + std::to_string(i), P32);
-      if (!x32[i].v) return fail(c, NDTM_ENOMEM, "solve: workspace");
-    }
-    HalfField B32 = half_field(c, "sv_b32", P32);
-    vconvert_field(P32, B32.v, P64, B.v, 1, c->g.vh, c->g.stride, st);
-    MmsResult mr;
-    int rc = run_mmscg_mixed(c, s_mms, x32, B32, std::max(p->tol, 1e-5), p->maxiter, p->poll_every, &mr, st);
-    rep->mms_iterations = mr.iterations;
-    if (rc != NDTM_OK && rc != NDTM_ENOCONV) {
-      rep->status = rc;
-      return rc;
-    }
-    for (int i = 0; i < n_mms; ++i) {
-      vconvert_field(P64, xs[i].v, P32, x32[i].v, 1, c->g.vh, c->g.stride, st);
-      double res = 0;
-      int extra = 0, rounds = 0;
-      int prc = refine_mixed(c, xs[i], B, sig[i], p->tol, p->maxiter, &res, &extra, &rounds, st);
-      rep->method[i] = 0;
-      rep->iterations[i] = mr.iters[i] + extra;
-      rep->rounds[i] = rounds;
-      rep->true_res[i] = res;
-      if (prc != NDTM_OK) status = prc;
-    }
-  } else {
+  // mixed form: the stencil's storage precision follows the base residual (an error of
+  // relative size u in the stencil of an iteration whose residual is rho moves the
+  // solutions' residuals by about u rho, so the storage with unit roundoff u serves
+  // once K u rho <= tol)
+  MmsRamp ramp;
+  const bool mixed = p->precision == NDTM_PREC_F16;
+  if (mixed) {
+    ramp.rel32 = p->tol / (kRampSafety * kUnitRoundoff32);
+    ramp.rel16 = p->tol / (kRampSafety * kUnitRoundoff16);
+  }
+  {
     // the first n_pred multigrid shifts ride along as passengers (predicted guesses)
     const int n_pred = std::max(0, std::min(p->mms_predict, nsh - n_mms));
     std::vector<double> s_mms(sig.begin(), sig.begin() + n_mms + n_pred);
@@ -570,9 +496,11 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     int defer = std::min(p->mms_defer, kMaxDefer);
     if (defer < 2) defer = 0;
     {
-      const size_t own = ws_bytes(c, "sv_region") / fb;
-      // managed storage: the ring takes at most half of the free device memory
-      const size_t avail = own + (c->arena ? dev_largest_free(c) : dev_largest_free(c) / 2) / fb;
+      // the region keeps its size from solve to solve: managed storage gives the ring at
+      // most half of the device memory that is free or already the region's; in a caller
+      // region it takes the larger of its current block and the largest free one
+      const size_t own = ws_bytes(c, "sv_region");
+      const size_t avail = (c->arena ? std::max(own, dev_largest_free(c)) : (own + dev_largest_free(c)) / 2) / fb;
       const size_t fixed = (size_t)(n_ps - 1);
       if (defer && fixed + defer > avail) defer = avail > fixed + 2 ? (int)(avail - fixed) : 0;
     }
@@ -582,8 +510,10 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     RegionScope rs(c, region, fields);
     MmsResult mr;
     int rc = run_mmscg(c, s_mms, x_mms, B, 0.5 * p->tol, p->maxiter, p->poll_every, defer, &mr, st, n_pred,
-                       region);
+                       region, mixed ? &ramp : nullptr);
     rep->mms_iterations = mr.iterations;
+    rep->mms_it32 = mr.it32;
+    rep->mms_it16 = mr.it16;
     if (rc != NDTM_OK && rc != NDTM_ENOCONV) {
       rep->status = rc;
       return rc;
@@ -592,7 +522,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       c->est_lmin = mr.lam_lo;
       c->est_lmax = mr.lam_hi;
     }
-    if (mr.iterations > 0) {
+    if (mr.iterations > 0 && !mixed) {
       const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       c->cost_iter_ms = (c->cost_iter_ms * c->cost_iter_n + ms / mr.iterations) / (c->cost_iter_n + 1);
       ++c->cost_iter_n;
@@ -616,7 +546,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
 
   // ---- multigrid (case C) for the remaining shifts ----
   if (n_mms < nsh) {
-    const int n_pred = p->precision == NDTM_PREC_F16 ? 0 : std::max(0, std::min(p->mms_predict, nsh - n_mms));
+    const int n_pred = std::max(0, std::min(p->mms_predict, nsh - n_mms));
     const size_t fields = (size_t)mg_region_fields(p->fgmres_restart);
     void* region = ws_get(c, "sv_region", std::max(ws_bytes(c, "sv_region"), fields * n * sizeof(double2)));
     if (!region) return fail(c, NDTM_ENOMEM, "solve: phase region");
@@ -625,7 +555,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     int rc = solve_mg_shifts(c, sig, n_mms, n_pred, xs, B, p, rep, st);
     // multigrid cost per shift, guesses included (a shift whose predicted guess already
     // meets tol costs only its residual check)
-    if (rc == NDTM_OK && p->precision != NDTM_PREC_F16) {
+    if (rc == NDTM_OK && !mixed) {
       const double ms = (rep->t_guess_ms - g0 + rep->t_mg_ms - m0) / (nsh - n_mms);
       c->cost_mg_ms = (c->cost_mg_ms * c->cost_mg_n + ms) / (c->cost_mg_n + 1);
       ++c->cost_mg_n;

@@ -1,14 +1,18 @@
-"""Mixed-precision form (FP16 stencil storage with per-site scale, FP32 vectors,
-FP64 recurrences, FP64 defect correction) against the FP64 oracle.
+"""Mixed-precision form against the FP64 oracle.  The multi-shift CG keeps FP64
+vectors, solutions and recurrences; its stencil moves from FP64 to FP32 storage and
+then to FP16 storage (one FP32 scale per site) as the base residual falls.
 
 * 4^4 config: every shift meets a true relative residual of 1e-10 (recomputed by
   the oracle) and its error against the oracle's own FP64 solution lies within
   the appendix A bound ||x - x*|| <= (||r|| + ||r*||) / sigma (both residuals <= 1e-10).
 * 24^3x48 config (the mixed-precision workload), hybrid solver with mixed
-  multi-shift CG: every shift's true residual (oracle) <= 1e-10, and its error
-  against the FP64 form's solution (whose residuals the oracle also checks) within
-  the appendix A bound ||x - x64|| <= (||r|| + ||r64||) ||b|| / (lambda_min + sigma),
-  with lambda_min >= 0; the per-shift errors are printed.
+  multi-shift CG: the schedule reaches FP16 storage; every shift's true residual
+  (oracle) <= 1e-10, and its error against the FP64 form's solution (whose
+  residuals the oracle also checks) within the appendix A bound
+  ||x - x64|| <= (||r|| + ||r64||) ||b|| / (lambda_min + sigma), with lambda_min >= 0;
+  the per-shift errors are printed.
+* the same lattice with all 12 shifts in the multi-shift CG: every shift meets 1e-10
+  without an FP64 finishing CG (its iteration count stays the multi-shift one).
 """
 import numpy as np
 import pytest
@@ -63,8 +67,9 @@ def test_mixed_hybrid_config3(nd):
     ctx, op, b, sig = _ctx(nd, "c3")
     ctx.ndtm_mg_setup(ctx.mg_params())
     xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(precision=nd.NDTM_PREC_F16, n_mmscg=9))
-    print("report", {k: rep[k] for k in ("mms_iterations", "iterations", "rounds", "true_res", "t_total_ms")},
-          flush=True)
+    print("report", {k: rep[k] for k in ("mms_iterations", "mms_it32", "mms_it16", "iterations", "true_res",
+                                         "t_total_ms")}, flush=True)
+    assert 0 < rep["mms_it32"] < rep["mms_it16"] < rep["mms_iterations"], rep
     xm = [host(x) for x in xs]
     x64, rep64 = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9))
     bd = dev(b)
@@ -87,4 +92,22 @@ def test_mixed_hybrid_config3(nd):
         print(f"shift {s:.3e}: mixed true res {r:.2e}, FP64 {r64:.2e}, relative error vs FP64 "
               f"{err / np.linalg.norm(xd):.2e}", flush=True)
         assert err <= (r + r64) * bn / s
+    ctx.close()
+
+
+def test_mixed_all_shifts_config3(nd):
+    print("case c3 mixed, all shifts by multi-shift CG", flush=True)
+    ctx, op, b, sig = _ctx(nd, "c3")
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(precision=nd.NDTM_PREC_F16, n_mmscg=12))
+    _, rep64 = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=12))
+    print("mixed", rep["mms_iterations"], rep["mms_it32"], rep["mms_it16"], rep["iterations"], rep["t_total_ms"],
+          "FP64", rep64["mms_iterations"], rep64["t_total_ms"], flush=True)
+    assert 0 < rep["mms_it32"] < rep["mms_it16"] < rep["mms_iterations"], rep
+    bd = dev(b)
+    bn = np.sqrt(norm2(b))
+    for i, s in enumerate(sig):
+        r = float(np.linalg.norm(host(bd - ctx.ndtm_apply(nd.NDTM_OP_QHAT2, xs[i], float(s))))) / bn
+        assert r <= 1e-10 and rep["true_res"][i] <= 1e-10, (i, r)
+        # no finishing CG: a shift's count is the multi-shift iteration at which it froze
+        assert rep["iterations"][i] <= rep["mms_iterations"], (i, rep["iterations"])
     ctx.close()
