@@ -10,15 +10,17 @@ before the timed region.  The multigrid setup (test vectors, prolongator, coarse
 operator) is timed separately, as it is shared by the right-hand sides.
 
 Forms (the first is the headline `value`):
-  full    hybrid of the paper's recipe: multi-shift CG for the 9 largest shifts, the
+  full    the workload's full pipeline: multi-shift CG for the 9 largest shifts, the
           two-level aggregation multigrid (case C, FGMRES, FP64 defect correction) for
           the 3 smallest, started from their multi-shift iterates (shifts 10, 11) and
-          from the learned guess with Lagrange as fallback (shift 12)
-  plain   multi-shift CG for all 12 shifts (the speed-up reference)
-  hybrid  as full with Lagrange guesses only
-  mixed   hybrid in the mixed-precision form (FP64 vectors and recurrences; the
-          multi-shift stencil moves to FP32, then FP16 storage as the residual falls)
+          from the learned guess with Lagrange as fallback (shift 12), in the
+          mixed-precision form (FP64 vectors and recurrences; the multi-shift stencil
+          moves to FP32, then FP16 storage as the residual falls; FP32 cycle)
+  full_f64  the same in FP64 (FP32 multigrid cycle inside FP64 defect correction)
+  plain   multi-shift CG for all 12 shifts in FP64 (the speed-up reference)
   plain_mixed  plain in the mixed-precision form
+  hybrid  full_f64 with Lagrange guesses only
+  mixed   hybrid in the mixed-precision form
 All forms run the same kernels on the same GPU; every shift's FP64 true residual is
 reported.  Roofline: the dominant kernel class of the headline form (largest summed
 time), timed by HIP events on its launch stream during the timed region; achieved
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--config", default="c5")
     ap.add_argument("--steps", type=int, default=None, help="timed solves (default: one per right-hand side)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="full,plain,hybrid,mixed,plain_mixed",
+    ap.add_argument("--forms", default="full,plain,full_f64,plain_mixed,hybrid",
                     help="comma list; the first is the headline value")
     ap.add_argument("--fgmres-restart", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,6 +116,9 @@ def cpu_baseline(cfg, U, b, gpu_iters, n_iter):
     return out
 
 
+MIXED_FORMS = ("full", "plain_mixed", "mixed")
+
+
 def form_params(ctx, nd, form, restart):
     # the multigrid cycle runs eagerly (use_graphs=0): a captured cycle replays bit-identically
     # but was not faster, and eager launches stay visible to the per-class event timers
@@ -123,6 +128,8 @@ def form_params(ctx, nd, form, restart):
     if form == "plain":
         return ctx.solve_params(tol=1e-10)
     if form == "full":
+        return ctx.solve_params(guess=nd.NDTM_GUESS_MLP, mms_predict=2, precision=nd.NDTM_PREC_F16, **hyb)
+    if form == "full_f64":
         return ctx.solve_params(guess=nd.NDTM_GUESS_MLP, mms_predict=2, **hyb)
     if form == "hybrid":
         return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, mms_predict=2, **hyb)
@@ -132,8 +139,6 @@ def form_params(ctx, nd, form, restart):
         return ctx.solve_params(tol=1e-10, precision=nd.NDTM_PREC_F16)
     if form == "mixed":
         return ctx.solve_params(guess=nd.NDTM_GUESS_LAGRANGE, mms_predict=2, precision=nd.NDTM_PREC_F16, **hyb)
-    if form == "full_mixed":
-        return ctx.solve_params(guess=nd.NDTM_GUESS_MLP, precision=nd.NDTM_PREC_F16, **hyb)
     raise ValueError(form)
 
 
@@ -313,11 +318,11 @@ def main():
         setup_ms = 1000.0 * (time.perf_counter() - t0)
         log(f"multigrid setup {setup_ms / 1000:.1f} s")
     weights = nd.trained_weights_path()
-    if any(f in ("full", "full_mixed") for f in forms):
+    if any(f in ("full", "full_f64") for f in forms):
         if weights and os.path.exists(weights):
             ctx.ndtm_mlp_set_weights(np.load(weights)["w"])
         else:
-            forms = [f for f in forms if f not in ("full", "full_mixed")]
+            forms = [f for f in forms if f not in ("full", "full_f64")]
 
     results = {}
     prof = None
@@ -350,7 +355,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64/f32/f16" if forms[0] in MIXED_FORMS else "f64",
         "data": "synthetic",
         "config": {"workload": f"ND twisted-mass multi-shift solves, {'x'.join(map(str, dims))} (T,Lz,Ly,Lx), "
                                f"{len(cfg['shifts'])} shifts geometric in [{cfg['shifts'][-1]:g},1], tol 1e-10, "
