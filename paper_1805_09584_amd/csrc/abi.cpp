@@ -261,6 +261,7 @@ int ndtm_create(const int dims[4], int bc_flags, int device, ndtm_ctx** out) {
       hipMalloc(&c->dscal, kScalN * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->mms_S, MS_SIZE * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->mms_H, (size_t)kMaxDefer * kMaxShifts * kHistStride * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->mms_L, (size_t)kLanczosIters * kMaxShifts * kHistStride * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->mms_C, (size_t)kMaxShifts * kCoefStride * sizeof(double)) != hipSuccess ||
 
       hipMalloc(&c->vred, kVredN * sizeof(double)) != hipSuccess || hipMemset(c->vred, 0, kVredN * sizeof(double)) != hipSuccess ||
@@ -296,6 +297,7 @@ void ndtm_destroy(ndtm_ctx* c) {
   if (c->dscal) (void)hipFree(c->dscal);
   if (c->mms_S) (void)hipFree(c->mms_S);
   if (c->mms_H) (void)hipFree(c->mms_H);
+  if (c->mms_L) (void)hipFree(c->mms_L);
   if (c->mms_C) (void)hipFree(c->mms_C);
 
   if (c->vred) (void)hipFree(c->vred);

@@ -46,6 +46,7 @@ struct ndtm_ctx {
   double* hscal = nullptr;  // pinned host mirror
   double* mms_S = nullptr;
   double* mms_H = nullptr;  // MMS-CG history of the deferred form [kMaxDefer][kMaxShifts][kHistStride]
+  double* mms_L = nullptr;  // the history of the first kLanczosIters iterations, kept for the spectrum estimate
   double* mms_C = nullptr;  // its flush coefficients [kMaxShifts][kCoefStride]
   std::map<std::string, ndtm::DevBuf> bufs;
   int prof_mask = 0;  // bit k: time kernel class k
@@ -79,6 +80,7 @@ struct ndtm_ctx {
 namespace ndtm {
 
 constexpr int kScalN = 8192;
+constexpr int kLanczosIters = 512;
 constexpr size_t kVredN = 8 + 96 * 1024;  // counter + partials of up to 48 complex sums over 1024 blocks
 
 // status helpers

@@ -511,7 +511,11 @@ static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField&
   return total;
 }
 
-static double lambda_max_estimate() { return 28.0; }  // upper estimate of the spectrum of Q^2 (free field 25.6)
+// upper estimate of the spectrum of Q^2: the context's estimate (largest Ritz value of
+// the base system's Lanczos matrix, from a multi-shift solve or ndtm_spectrum_estimate,
+// which approaches lambda_max from below) with a 10% margin; without one, 28 (the free
+// field's 25.6 with a margin)
+static double lambda_max_estimate(const ndtm_ctx* c) { return c->est_lmax > 0 ? 1.1 * c->est_lmax : 28.0; }
 
 // Solves (Q^2 + sigma) x = b for one multigrid shift by case C with FP64 defect
 // correction, starting from x (initial guess).  Returns NDTM_OK when the true
@@ -527,7 +531,7 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
   if (!r.v || !cr.v || !ep.v || !em.v || !xb.v) return fail(c, NDTM_ENOMEM, "multigrid shift: workspace");
   double res = true_residual(c, x, b, sigma, r, st);
   *guess_res = res;
-  const double amp = m / std::sqrt(lambda_max_estimate() + sigma);
+  const double amp = m / std::sqrt(lambda_max_estimate(c) + sigma);
   int it_total = 0, rd = 0;
   while (res > p->tol && rd < p->max_rounds) {
     blas_copy((double2*)xb.v, (const double2*)x.v, n, st);

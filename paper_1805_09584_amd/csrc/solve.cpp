@@ -204,6 +204,12 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
     ProfScope pf(c, NDTM_PROF_MMS_UPDATE, 0.0, st);
     mms_flush(xv.data(), ps.data(), nsh, ring, nr, it - nr, with_p, c->mms_S, c->mms_H, c->mms_C, n, st);
     flushes.push_back({it - nr, nr, with_p});
+    // the record of the first iterations stays for the spectrum estimate
+    const int k0 = it - nr, keep = std::min(nr, kLanczosIters - k0);
+    const size_t per = (size_t)kMaxShifts * kHistStride;
+    if (keep > 0)
+      (void)hipMemcpyAsync(c->mms_L + (size_t)k0 * per, c->mms_H, keep * per * sizeof(double),
+                           hipMemcpyDeviceToDevice, st);
   };
   const int hg = hop_grid(c->g);
   const int rg = red_grid(n);
@@ -282,12 +288,13 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
   res->iters.resize(nsh);
   for (int s = 0; s < nsh; ++s) res->iters[s] = (int)c->hscal[MS_ITERS + s];
   bool done = c->hscal[MS_DONE] != 0.0;
-  if (deferred && res->iterations >= 2 && res->iterations <= defer && !res->breakdown) {
-    // the base system's alpha_k, beta_k are in the record of the single block
-    std::vector<double> h((size_t)res->iterations * kMaxShifts * kHistStride);
-    NDTM_HIP(c, hipMemcpy(h.data(), c->mms_H, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (deferred && res->iterations >= 2 && !res->breakdown) {
+    // the base system's alpha_k, beta_k of the first iterations (Lanczos coefficients)
+    const int nk = std::min(res->iterations, kLanczosIters);
+    std::vector<double> h((size_t)nk * kMaxShifts * kHistStride);
+    NDTM_HIP(c, hipMemcpy(h.data(), c->mms_L, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     std::vector<double> al, be;
-    for (int k = 0; k < res->iterations; ++k) {
+    for (int k = 0; k < nk; ++k) {
       const double* hk = &h[((size_t)k * kMaxShifts + sb) * kHistStride];
       if (hk[3] == 0.0) break;
       al.push_back(hk[0]);
