@@ -70,7 +70,9 @@ typedef enum {
 #define NDTM_NMMS_AUTO (-1)
 
 /* Precision of the stencil / multigrid inner work. */
-enum { NDTM_PREC_F64 = 0, NDTM_PREC_F32 = 1, NDTM_PREC_F16 = 2 };
+enum { NDTM_PREC_F64 = 0, NDTM_PREC_F32 = 1, NDTM_PREC_F16 = 2, NDTM_PREC_F32_H16 = 3 };
+/* NDTM_PREC_F32_H16 (ndtm_apply only): FP32 fields and arithmetic on the FP16 links, the
+ * stencil of the multigrid cycle in its FP16-storage form */
 
 /* Operators of ndtm_apply. */
 enum {
@@ -176,7 +178,10 @@ typedef struct {
   int coarse_iters;    /* GMRES iterations of the coarse solve per cycle (default 12) */
   double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
   unsigned long long seed; /* seed of the random initial test vectors */
-  int precision;       /* NDTM_PREC_F64 or NDTM_PREC_F32 for P, coarse ops and the cycle */
+  int precision;       /* the cycle's precision: NDTM_PREC_F64; NDTM_PREC_F32 (FP32 P, coarse
+                          operator, fields and stencil); NDTM_PREC_F16 (FP16 storage: P in FP16
+                          with one FP32 scale per fine site and the smoother's stencil on the
+                          FP16 links, FP32 fields, coarse operator and arithmetic) */
   double coarse_tol;   /* 0: the coarse solve is coarse_iters GMRES iterations from zero (a fixed
                           sequence, which the cycle graphs capture).  > 0: GMRES(coarse_iters)
                           restarted on the true coarse residual until it is below coarse_tol
@@ -211,6 +216,12 @@ long long ndtm_mg_coarse_volume(const ndtm_ctx* ctx);
 int ndtm_mg_restrict(ndtm_ctx* ctx, void* vc_dev, const void* v_dev, void* stream);
 /* v = (P x I2) vc. */
 int ndtm_mg_prolong(ndtm_ctx* ctx, void* v_dev, const void* vc_dev, void* stream);
+/* The restriction (dir 0: out = (P x I2)^dag in, in full-lattice canonical, out coarse) or
+ * prolongation (dir 1: out = (P x I2) in) as the cycle runs it: the input is rounded to
+ * the cycle's field precision, P read in the cycle's storage (FP64, FP32, or FP16 with
+ * per-site scales), the output returned in complex128.  Works without the FP64 copies
+ * (keep_f64 = 0).  ESTATE without a setup; EINVAL for another dir or equal pointers. */
+int ndtm_mg_transfer_cycle(ndtm_ctx* ctx, int dir, void* out_dev, const void* in_dev, void* stream);
 /* yc = D'_c(m) xc = (D_W,c x I2 + i d mubar Gamma5_c x tau3 - epsbar tau1
  *                     + i m C_o x tau1) xc   (eq:non-degenerate_coarse). */
 int ndtm_mg_coarse_apply(ndtm_ctx* ctx, void* yc_dev, const void* xc_dev, double m, void* stream);

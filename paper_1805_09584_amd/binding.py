@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 NDTM_OK = 0
-NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16 = 0, 1, 2
+NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16, NDTM_PREC_F32_H16 = 0, 1, 2, 3
 (NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
  NDTM_OP_HOP_OE) = range(6)
 NDTM_NMMS_AUTO = -1
@@ -103,6 +103,7 @@ def load_library():
         "ndtm_mg_coarse_volume": (C.c_longlong, [vp]),
         "ndtm_mg_restrict": (i, [vp, vp, vp, vp]),
         "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
+        "ndtm_mg_transfer_cycle": (i, [vp, i, vp, vp, vp]),
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
@@ -301,6 +302,16 @@ class Context:
     def ndtm_mg_prolong(self, vc):
         out = torch.empty((self.V, 2, 4, 3), dtype=torch.complex128, device=vc.device)
         self._check(self.lib.ndtm_mg_prolong(self.h, _ptr(out), _ptr(vc), _stream()))
+        return out
+
+    def ndtm_mg_transfer_cycle(self, direction, x):
+        """direction 0: restriction of a full-lattice field; 1: prolongation of a coarse one,
+        both as the cycle runs them (its precision and storage of P)."""
+        if direction == 0:
+            out = torch.empty((self.Vc, 2, 2 * self.n_vec), dtype=torch.complex128, device=x.device)
+        else:
+            out = torch.empty((self.V, 2, 4, 3), dtype=torch.complex128, device=x.device)
+        self._check(self.lib.ndtm_mg_transfer_cycle(self.h, int(direction), _ptr(out), _ptr(x), _stream()))
         return out
 
     def ndtm_mg_coarse_apply(self, xc, m=0.0):

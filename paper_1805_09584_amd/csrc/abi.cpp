@@ -112,7 +112,9 @@ ProfScope::~ProfScope() {
 // input and one output doublet spinor, each read or written once.  The fused site
 // epilogues also read one or two site vectors; those bytes count as moved, not as
 // the pass's algorithmic bytes.
-static const double kHopBase[3] = {1920.0, 960.0, 488.0}, kHopVec[3] = {384.0, 192.0, 100.0};
+// strict bytes per output site (8 links with two rows, the input and output spinors) and
+// per extra epilogue vector; P32H: FP16 links with FP32 fields
+static const double kHopBase[4] = {1920.0, 960.0, 488.0, 672.0}, kHopVec[4] = {384.0, 192.0, 100.0, 192.0};
 static double hop_epi_vectors(int epi) {
   if (epi == EPI_QHAT || epi == EPI_SITE) return 1;
   if (epi == EPI_QHAT_SIG) return 2;
@@ -122,11 +124,13 @@ static double hop_epi_vectors(int epi) {
 void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& in, const HalfField& out,
          const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
          double* partials, hipStream_t st) {
-  ProfScope ps(c, NDTM_PROF_HOP_F64 + prec, kHopBase[prec] * c->g.vh, st,
+  // the FP32-field stencil on FP16 links times into the FP32 class
+  const int cls = prec == P32H ? P32 : prec, lp = prec == P32H ? P16 : prec;
+  ProfScope ps(c, NDTM_PROF_HOP_F64 + cls, kHopBase[prec] * c->g.vh, st,
                (kHopBase[prec] + hop_epi_vectors(epi) * kHopVec[prec]) * c->g.vh);
   OpParams op = c->op;
   op.skip = c->hop_skip;
-  launch_hop(prec, epi, red, c->g, parity, op, c->U[prec][parity], c->U[prec][1 - parity], in, out,
+  launch_hop(prec, epi, red, c->g, parity, op, c->U[lp][parity], c->U[lp][1 - parity], in, out,
              xs, zs, ms, hop_coef, sigma, partials, st);
 }
 
@@ -387,13 +391,15 @@ int ndtm_set_shifts(ndtm_ctx* c, int n, const double* sigma) {
 int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, double param, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!y_dev || !x_dev || y_dev == x_dev) return fail(c, NDTM_EINVAL, "apply: null or aliased pointers");
-  if (prec < 0 || prec > 2) return fail(c, NDTM_EINVAL, "apply: bad precision");
+  if (prec < 0 || prec > 3) return fail(c, NDTM_EINVAL, "apply: bad precision");
   if (!c->have_gauge || !c->have_params) return fail(c, NDTM_ESTATE, "apply: set_gauge and set_params first");
   NDTM_HIP(c, hipSetDevice(c->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double2* x = static_cast<const double2*>(x_dev);
   double2* y = static_cast<double2*>(y_dev);
-  HalfField X = half_field(c, "ap_x", prec), Y = half_field(c, "ap_y", prec), T = half_field(c, "ap_t", prec);
+  // NDTM_PREC_F32_H16 (= P32H): FP32 fields, the stencil on the FP16 links
+  const int fp = prec == P32H ? P32 : prec;
+  HalfField X = half_field(c, "ap_x", fp), Y = half_field(c, "ap_y", fp), T = half_field(c, "ap_t", fp);
   if (!X.v || !Y.v || !T.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
   switch (op) {
     case NDTM_OP_QHAT:
@@ -402,7 +408,7 @@ int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, do
       launch_unpack_half(c->g, Y, y, st);
       break;
     case NDTM_OP_QHAT2: {
-      HalfField U = half_field(c, "ap_u", prec);
+      HalfField U = half_field(c, "ap_u", fp);
       if (!U.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
       launch_pack_half(c->g, x, X, st);
       apply_qhat2(c, prec, Y, X, U, T, param, nullptr, st);
@@ -415,7 +421,7 @@ int ndtm_apply(ndtm_ctx* c, int op, int prec, void* y_dev, const void* x_dev, do
       launch_unpack_half(c->g, Y, y, st);
       break;
     case NDTM_OP_DFULL: {
-      HalfField Ye = half_field(c, "ap_ye", prec);
+      HalfField Ye = half_field(c, "ap_ye", fp);
       if (!Ye.v) return fail(c, NDTM_ENOMEM, "apply: workspace");
       launch_pack_full(c->g, x, T, X, st);
       apply_dfull(c, prec, Ye, Y, T, X, param, st);

@@ -266,14 +266,17 @@ __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, i
     }
     if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
     const unsigned vl = (unsigned)hl * 16u;
-    // rows 0-1 (components 0..5) always; with R12 row 2 is rebuilt in hop_compute
-    constexpr int NLG = R12 ? (6 + G - 1) / G : 8 / G;
+    // rows 0-1 (components 0..5) always; with R12 row 2 is rebuilt in hop_compute.  The
+    // links group by their own storage (FP32 links with FP32 fields, FP16 links with
+    // FP16 or FP32 fields)
+    constexpr int GL = kG<L>;
+    constexpr int NLG = R12 ? (6 + GL - 1) / GL : 8 / GL;
 #pragma unroll
     for (int g = 0; g < NLG; ++g) {
-      const Grp<L> u = ld_group<true>(U, (8 / G) * MU + g, A.stride, vl);
+      const Grp<L> u = ld_group<true>(U, (8 / GL) * MU + g, A.stride, vl);
 #pragma unroll
-      for (int q = 0; q < G; ++q)
-        if (G * g + q < 9) r.u[G * g + q] = u.e[q];
+      for (int q = 0; q < GL; ++q)
+        if (GL * g + q < 9) r.u[GL * g + q] = u.e[q];
     }
     if constexpr (!R12) r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
   } else {
@@ -788,6 +791,10 @@ void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpP
     case P32:
       launch_typed<float2, float2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
                                    sigma, partials, st);
+      break;
+    case P32H:
+      launch_typed<float2, __half2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
+                                    sigma, partials, st);
       break;
     default:
       launch_typed<__half2, __half2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,

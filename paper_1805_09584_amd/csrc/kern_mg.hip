@@ -435,11 +435,32 @@ __device__ __forceinline__ int xcd_site(int b, int nb) {
   return xcd * q + min(xcd, rem) + loc;
 }
 
-template <class R>
-__global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R>::T* P,
+// P in the cycle precision, or (PH) in FP16 with one FP32 scale per fine site (the
+// largest magnitude of the site's 12 N_v entries), read as scale * entry in FP32
+template <class R, bool PH>
+struct PStore {
+  using T = typename C2<R>::T;
+};
+template <>
+struct PStore<float, true> {
+  using T = __half2;
+};
+template <class R, bool PH>
+__device__ __forceinline__ typename C2<R>::T p_at(const typename PStore<R, PH>::T* P, long i, R sc) {
+  if constexpr (PH) {
+    const float2 f = __half22float2(P[i]);
+    return mk<R>(sc * f.x, sc * f.y);
+  } else {
+    return P[i];
+  }
+}
+
+template <class R, bool PH>
+__global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename PStore<R, PH>::T* P, const float* Psc,
                                                   const typename C2<R>::T* fe, const typename C2<R>::T* fo,
                                                   typename C2<R>::T* vc) {
   using T2 = typename C2<R>::T;
+  using PT = typename PStore<R, PH>::T;
   const int X = xcd_site(blockIdx.x, gridDim.x);
   const int Nv = m.Nv, n2 = 2 * Nv, nout = 2 * n2;
   __shared__ int ph[1024];
@@ -457,15 +478,16 @@ __global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R
   R ax = 0, ay = 0;
   if (q < kGroups) {
     const int f = t & 1, i = t >> 1, chi = i / Nv, k = i % Nv;
-    const T2* PX = P + (long)X * m.nloc * 12 * Nv;
+    const PT* PX = P + (long)X * m.nloc * 12 * Nv;
     for (int l = q; l < m.nloc; l += kGroups) {
       const int hp = ph[l];
       const T2* F = (hp & 1) ? fo : fe;
       const int h = hp >> 1;
+      const R sc = PH ? (R)Psc[(long)X * m.nloc + l] : R(1);
 #pragma unroll
       for (int rr = 0; rr < 6; ++rr) {
         const int r = 6 * chi + rr;
-        const T2 p = PX[((long)l * 12 + r) * Nv + k];
+        const T2 p = p_at<R, PH>(PX, ((long)l * 12 + r) * Nv + k, sc);
         const T2 v = F[fine_idx<R>(f * 12 + r, m.stride, h)];
         ax += p.x * v.x + p.y * v.y;
         ay += p.x * v.y - p.y * v.x;
@@ -487,11 +509,12 @@ __global__ __launch_bounds__(1024) void restrict_k(MGGeom m, const typename C2<R
   }
 }
 
-template <class R>
-__global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>::T* P,
+template <class R, bool PH>
+__global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename PStore<R, PH>::T* P, const float* Psc,
                                                  const typename C2<R>::T* vc, typename C2<R>::T* fe,
                                                  typename C2<R>::T* fo) {
   using T2 = typename C2<R>::T;
+  using PT = typename PStore<R, PH>::T;
   const int X = xcd_site(blockIdx.x, gridDim.x);
   const int Nv = m.Nv, n2 = 2 * Nv;
   __shared__ T2 cv[2 * 64];
@@ -502,13 +525,14 @@ __global__ __launch_bounds__(256) void prolong_k(MGGeom m, const typename C2<R>:
     ph[l] = (s.h << 1) | s.par;
   }
   __syncthreads();
-  const T2* PX = P + (long)X * m.nloc * 12 * Nv;
+  const PT* PX = P + (long)X * m.nloc * 12 * Nv;
   for (int e = threadIdx.x; e < m.nloc * 12; e += blockDim.x) {
     const int l = e / 12, r = e % 12, chi = r / 6;
     R a0x = 0, a0y = 0, a1x = 0, a1y = 0;
-    const T2* pr = PX + ((long)l * 12 + r) * Nv;
+    const PT* pr = PX + ((long)l * 12 + r) * Nv;
+    const R sc = PH ? (R)Psc[(long)X * m.nloc + l] : R(1);
     for (int k = 0; k < Nv; ++k) {
-      const T2 p = pr[k];
+      const T2 p = p_at<R, PH>(pr, k, sc);
       const T2 c0 = cv[chi * Nv + k], c1 = cv[n2 + chi * Nv + k];
       a0x += p.x * c0.x - p.y * c0.y;
       a0y += p.x * c0.y + p.y * c0.x;
@@ -812,23 +836,50 @@ void mg_galerkin_clover(const MGGeom& m, const double2* P, const double* Me, con
   hipLaunchKernelGGL(galerkin_clover_k, dim3(m.Vc), dim3(256), 0, st, m, P, Me, Mo, a, D);
 }
 
-void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
+void mg_restrict(int prec, const MGGeom& m, const void* P, const float* Psc, const void* fe, const void* fo, void* vc,
                  hipStream_t st) {
+  const dim3 grid(m.Vc), blk(4 * m.Nv * kGroups);
   if (prec == P64)
-    hipLaunchKernelGGL(restrict_k<double>, dim3(m.Vc), dim3(4 * m.Nv * kGroups), 0, st, m, (const double2*)P, (const double2*)fe,
-                       (const double2*)fo, (double2*)vc);
-  else
-    hipLaunchKernelGGL(restrict_k<float>, dim3(m.Vc), dim3(4 * m.Nv * kGroups), 0, st, m, (const float2*)P, (const float2*)fe,
+    hipLaunchKernelGGL((restrict_k<double, false>), grid, blk, 0, st, m, (const double2*)P, nullptr,
+                       (const double2*)fe, (const double2*)fo, (double2*)vc);
+  else if (Psc)
+    hipLaunchKernelGGL((restrict_k<float, true>), grid, blk, 0, st, m, (const __half2*)P, Psc, (const float2*)fe,
                        (const float2*)fo, (float2*)vc);
+  else
+    hipLaunchKernelGGL((restrict_k<float, false>), grid, blk, 0, st, m, (const float2*)P, nullptr,
+                       (const float2*)fe, (const float2*)fo, (float2*)vc);
 }
 
-void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* fe, void* fo, hipStream_t st) {
+void mg_prolong(int prec, const MGGeom& m, const void* P, const float* Psc, const void* vc, void* fe, void* fo,
+                hipStream_t st) {
   if (prec == P64)
-    hipLaunchKernelGGL(prolong_k<double>, dim3(m.Vc), dim3(256), 0, st, m, (const double2*)P, (const double2*)vc,
-                       (double2*)fe, (double2*)fo);
+    hipLaunchKernelGGL((prolong_k<double, false>), dim3(m.Vc), dim3(256), 0, st, m, (const double2*)P, nullptr,
+                       (const double2*)vc, (double2*)fe, (double2*)fo);
+  else if (Psc)
+    hipLaunchKernelGGL((prolong_k<float, true>), dim3(m.Vc), dim3(256), 0, st, m, (const __half2*)P, Psc,
+                       (const float2*)vc, (float2*)fe, (float2*)fo);
   else
-    hipLaunchKernelGGL(prolong_k<float>, dim3(m.Vc), dim3(256), 0, st, m, (const float2*)P, (const float2*)vc,
-                       (float2*)fe, (float2*)fo);
+    hipLaunchKernelGGL((prolong_k<float, false>), dim3(m.Vc), dim3(256), 0, st, m, (const float2*)P, nullptr,
+                       (const float2*)vc, (float2*)fe, (float2*)fo);
+}
+
+// P (FP64, [aggregate][site][row][k]) to FP16 entries with one FP32 scale per fine site
+__global__ void p_to_half_k(long nsites, int per, const double2* P, __half2* P16, float* Psc) {
+  const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (s >= nsites) return;
+  const double2* src = P + s * per;
+  double mx = 0;
+  for (int i = 0; i < per; ++i) mx = fmax(mx, fmax(fabs(src[i].x), fabs(src[i].y)));
+  const float sc = (float)mx;
+  const double inv = sc > 0.f ? 1.0 / (double)sc : 0.0;
+  for (int i = 0; i < per; ++i) P16[s * per + i] = __floats2half2_rn((float)(src[i].x * inv), (float)(src[i].y * inv));
+  Psc[s] = sc;
+}
+
+void mg_p_to_half(const MGGeom& m, const void* P64, void* P16, float* Psc, hipStream_t st) {
+  const long ns = (long)m.Vc * m.nloc;
+  hipLaunchKernelGGL(p_to_half_k, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, 12 * m.Nv,
+                     (const double2*)P64, (__half2*)P16, Psc);
 }
 
 void mg_coarse_apply(int prec, const MGGeom& g, const void* D, const void* Bo, const void* x, void* y,

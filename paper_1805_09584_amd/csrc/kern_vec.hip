@@ -28,8 +28,18 @@ struct StridedBasis {
 };
 
 // reductions: at most 256 blocks (the completion of each block costs a release
-// fence and an atomic on one counter, which grows with the block count)
+// fence and an atomic on one counter, which grows with the block count), 1024 on
+// vectors of 2^23 elements or more, where one block per CU kept too few loads in
+// flight (a 12-vector multi-dot at 96x48^3 reached 2.4 TB/s); the reduction
+// workspace holds 48 complex sums over 1024 blocks
 inline unsigned rgrid(size_t n) {
+  size_t g = (n + kVB - 1) / kVB;
+  const size_t cap = n >= ((size_t)1 << 23) ? 1024 : 256;
+  if (g > cap) g = cap;
+  return (unsigned)(g ? g : 1);
+}
+// the batched (k-system) reductions size their workspaces for 256 blocks
+inline unsigned rgrid_sys(size_t n) {
   size_t g = (n + kVB - 1) / kVB;
   if (g > 256) g = 256;
   return (unsigned)(g ? g : 1);
@@ -628,7 +638,7 @@ static void by_km(int cnt, F f) {
 void vmultidot_sys(const double2* V, size_t ldv, int cnt, const double2* w, size_t n, int k, double* ws, size_t wss,
                    double* dst, size_t ds, hipStream_t st) {
   const SysArgs a{ldv, wss, 0, ds};
-  const dim3 g(rgrid(n), k);
+  const dim3 g(rgrid_sys(n), k);
   by_km(cnt, [&](auto km) {
     hipLaunchKernelGGL((multidot_sys_k<decltype(km)::value>), g, dim3(kVB), 0, st, V, cnt, w, n, ws, dst, a);
   });
@@ -636,7 +646,7 @@ void vmultidot_sys(const double2* V, size_t ldv, int cnt, const double2* w, size
 void vmulti_axpy_multidot_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs,
                               size_t n, int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st) {
   const SysArgs a{ldv, wss, cs, ds};
-  const dim3 g(rgrid(n), k);
+  const dim3 g(rgrid_sys(n), k);
   by_km(cnt, [&](auto km) {
     hipLaunchKernelGGL((multi_axpy_dot_sys_k<decltype(km)::value>), g, dim3(kVB), 0, st, w, V, cnt, coef, n, ws, dst,
                        a);
@@ -645,7 +655,7 @@ void vmulti_axpy_multidot_sys(double2* w, const double2* V, size_t ldv, int cnt,
 void vmulti_axpy_norm_sys(double2* w, const double2* V, size_t ldv, int cnt, const double* coef, size_t cs, size_t n,
                           int k, double* ws, size_t wss, double* dst, size_t ds, hipStream_t st) {
   const SysArgs a{ldv, wss, cs, ds};
-  hipLaunchKernelGGL(multi_axpy_norm_sys_k, dim3(rgrid(n), k), dim3(kVB), 0, st, w, V, cnt, coef, n, ws, dst, a);
+  hipLaunchKernelGGL(multi_axpy_norm_sys_k, dim3(rgrid_sys(n), k), dim3(kVB), 0, st, w, V, cnt, coef, n, ws, dst, a);
 }
 void vscale_inv_sqrt_sys(double2* y, const double2* x, const double* nrm2, size_t ds, size_t n, int k,
                          hipStream_t st) {

@@ -217,10 +217,12 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     if (mg->n_vec < 2 || mg->n_vec > 32 || mg->coarse_iters < 1 || mg->coarse_iters > 32) return NDTM_EINVAL;
     const size_t Vc = (size_t)c->V / nloc, Nv = (size_t)mg->n_vec, n2 = 2 * Nv, kc = (size_t)mg->coarse_iters;
     const int cp = mg->precision == NDTM_PREC_F64 ? P64 : P32;
+    const bool f16 = mg->precision == NDTM_PREC_F16;
     const size_t cs = cp == P64 ? 16 : 8;
     const size_t nP = Vc * nloc * 12 * Nv, nD = Vc * 5 * n2 * n2, nB = Vc * 2 * Nv * Nv, nc = Vc * 2 * n2;
     t += R(nP * 16) + R(nD * 16) + R(nB * 16);
-    if (cp == P32) t += R(nP * 8) + R(nD * 8) + R(nB * 8);
+    // cycle copies: P in FP32, or in FP16 with one scale per fine site
+    if (cp == P32) t += R(nP * (f16 ? 4 : 8)) + R(nD * 8) + R(nB * 8) + (f16 ? R(Vc * nloc * 4) : 0);
     t += (kc + 1 + 5) * R(nc * cs) + 2 * R(2 * (kc + 1) * (kc + 1) * 8) + R((kc + 1) * 8) + R(2 * (kc + 1) * 8) +
          R(64) + R(128) + R(6 * (size_t)hop_grid(c->g) * 8);
     t += 4 * z.full(cp);  // cycle vectors
@@ -228,7 +230,7 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     t += R(Vc * 8 * n2 * n2 * 16) + ((Nv + 1) / 2 + 6) * z.full(P64) + 2 * z.full(cp);
     // the multigrid calls of the ABI: a full FP64 field, the batched coarse solve of 8 systems
     const size_t per = 2 * (2 * (kc + 1) * (kc + 1)) + 3 * (kc + 1) + 2;
-    t += z.full(P64) + R((kc + 1) * 8 * nc * 16) + 2 * R(8 * nc * 16) + R(8 * per * 8) +
+    t += z.full(P64) + z.full(cp) + R((kc + 1) * 8 * nc * 16) + 2 * R(8 * nc * 16) + R(8 * per * 8) +
          R(8 * (8 + 2 * (kc + 1) * 256) * 8);
   }
   // first-fit slack: two half fields

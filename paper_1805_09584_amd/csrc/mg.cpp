@@ -44,7 +44,9 @@ namespace ndtm {
 struct MGData {
   MGGeom g{};
   ndtm_mg_params prm{};
-  int cprec = P32;  // precision of the cycle
+  int cprec = P32;  // precision of the cycle's fields and coarse operator
+  int sprec = P32;  // precision of its stencil: cprec, or P32H (FP32 fields on FP16 links)
+  float* Psc = nullptr;  // FP16-storage cycle: Pc holds FP16 entries with these per-site scales
   double2* P64 = nullptr;
   double2* D64 = nullptr;
   double2* Bo64 = nullptr;
@@ -116,7 +118,9 @@ static Full full_field(ndtm_ctx* c, const std::string& name, int prec) {
 static double transfer_bytes(const MGData* M) {
   const double es = (double)csz(M->cprec), Nv = M->g.Nv;
   const double V = (double)M->g.Vc * M->g.nloc;
-  return V * (12.0 * Nv + 24.0) * es + (double)M->ncoarse * es;
+  // FP16 storage of P: 4 bytes an entry and one scale per site
+  const double pb = M->Psc ? 12.0 * Nv * 4.0 + 4.0 : 12.0 * Nv * es;
+  return V * (pb + 24.0 * es) + (double)M->ncoarse * es;
 }
 static double coarse_bytes(const MGData* M) {
   const double es = (double)csz(M->cprec), n2 = 2.0 * M->g.Nv;
@@ -328,22 +332,22 @@ static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
   Full S = full_field(c, "mg_S", cp), Tt = full_field(c, "mg_T", cp);
   {
     ProfScope ps(c, NDTM_PROF_RESTRICT, transfer_bytes(M), st);
-    mg_restrict(cp, M->g, M->Pc, R.e.v, R.o.v, M->cR, st);
+    mg_restrict(cp, M->g, M->Pc, M->Psc, R.e.v, R.o.v, M->cR, st);
   }
   coarse_solve(c, M, M->cR, M->cX, m, eps, st);
   {
     ProfScope ps(c, NDTM_PROF_PROLONG, transfer_bytes(M), st);
-    mg_prolong(cp, M->g, M->Pc, M->cX, Z.e.v, Z.o.v, st);
+    mg_prolong(cp, M->g, M->Pc, M->Psc, M->cX, Z.e.v, Z.o.v, st);
   }
   // post-smoothing: minimal residual steps on D' z = r
   const int nu = M->prm.smooth_iters;
   if (nu > 0) {
-    dprime(c, cp, S, Z, m, st);
+    dprime(c, M->sprec, S, Z, m, st);
     vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
     for (int it = 0; it < nu; ++it) {
       // T = D' S with <T, S>, ||T||^2 reduced in the stencil epilogue; the update
       // kernel forms omega from those partials
-      dprime_mr(c, cp, Tt, S, m, M->dpart, st);
+      dprime_mr(c, M->sprec, Tt, S, m, M->dpart, st);
       vmr_update_part(cp, Z.base, S.base, Tt.base, M->dpart, 2 * hop_grid(c->g), it + 1 < nu, 2 * nh, st);
     }
   }
@@ -739,6 +743,10 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
   g.Nv = prm->n_vec;
   g.stride = c->g.stride;
   M->cprec = prm->precision == NDTM_PREC_F64 ? P64 : P32;
+  // FP16 storage: the cycle's stencil reads the FP16 links and P is kept in FP16 with
+  // one scale per fine site; fields, coarse operator and arithmetic stay FP32
+  const bool f16 = prm->precision == NDTM_PREC_F16;
+  M->sprec = f16 ? P32H : M->cprec;
   const int Nv = g.Nv, n2 = 2 * Nv;
   const size_t nP = (size_t)g.Vc * g.nloc * 12 * Nv;
   const size_t nD = (size_t)g.Vc * 5 * n2 * n2;  // self block and the four forward hops
@@ -754,10 +762,11 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     M->Dc = M->D64;
     M->Boc = M->Bo64;
   } else {
-    M->Pc = mg_alloc(c, M, nP * 8);
+    M->Pc = mg_alloc(c, M, nP * (f16 ? 4 : 8));
     M->Dc = mg_alloc(c, M, nD * 8);
     M->Boc = mg_alloc(c, M, nB * 8);
-    if (!M->Pc || !M->Dc || !M->Boc) return fail(c, NDTM_ENOMEM, "mg_setup: FP32 copies");
+    if (f16) M->Psc = (float*)mg_alloc(c, M, (size_t)g.Vc * g.nloc * sizeof(float));
+    if (!M->Pc || !M->Dc || !M->Boc || (f16 && !M->Psc)) return fail(c, NDTM_ENOMEM, "mg_setup: cycle copies");
   }
   const int kc = prm->coarse_iters;
   M->cV.resize(kc + 1);
@@ -801,7 +810,10 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     if (c->op.clover)
       mg_galerkin_clover(g, M->P64, (const double*)c->clv_m[0][0], (const double*)c->clv_m[0][1], c->op.a, M->D64, st);
     if (M->cprec != P64) {
-      vconvert(P32, M->Pc, P64, M->P64, nP, st);
+      if (M->Psc)
+        mg_p_to_half(g, M->P64, M->Pc, M->Psc, st);
+      else
+        vconvert(P32, M->Pc, P64, M->P64, nP, st);
       vconvert(P32, M->Dc, P64, M->D64, nD, st);
       vconvert(P32, M->Boc, P64, M->Bo64, nB, st);
     }
@@ -972,8 +984,8 @@ int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* st
     return fail(c, NDTM_EINVAL, "mg_setup: coarse_tol >= 0 and coarse_cycles >= 1");
   if (p->smooth_iters < 0 || p->setup_iters < 0 || p->setup_smooth < 1 || p->setup_refine < 0 || !(p->coarse_mu_factor >= 1.0))
     return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
-  if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32)
-    return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64 or F32");
+  if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32 && p->precision != NDTM_PREC_F16)
+    return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64, F32 or F16");
   NDTM_HIP(c, hipSetDevice(c->device));
   const int rc = mg_build(c, p, tv, static_cast<hipStream_t>(stream));
   if (rc != NDTM_OK) ndtm_mg_free(c);
@@ -990,7 +1002,7 @@ int ndtm_mg_restrict(ndtm_ctx* c, void* vc, const void* v, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   Full F = full_field(c, "ab_f", P64);
   launch_pack_full(c->g, static_cast<const double2*>(v), F.e, F.o, st);
-  mg_restrict(P64, c->mg->g, c->mg->P64, F.e.v, F.o.v, vc, st);
+  mg_restrict(P64, c->mg->g, c->mg->P64, nullptr, F.e.v, F.o.v, vc, st);
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }
@@ -1002,8 +1014,33 @@ int ndtm_mg_prolong(ndtm_ctx* c, void* v, const void* vc, void* stream) {
   if (!vc || !v) return fail(c, NDTM_EINVAL, "mg_prolong: null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Full F = full_field(c, "ab_f", P64);
-  mg_prolong(P64, c->mg->g, c->mg->P64, vc, F.e.v, F.o.v, st);
+  mg_prolong(P64, c->mg->g, c->mg->P64, nullptr, vc, F.e.v, F.o.v, st);
   launch_unpack_full(c->g, F.e, F.o, static_cast<double2*>(v), st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_mg_transfer_cycle(ndtm_ctx* c, int dir, void* out, const void* in, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_transfer_cycle: no multigrid setup");
+  if (!out || !in || out == in || (dir != 0 && dir != 1))
+    return fail(c, NDTM_EINVAL, "mg_transfer_cycle: dir 0 or 1, distinct pointers");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MGData* M = c->mg;
+  const int cp = M->cprec;
+  Full F64 = full_field(c, "ab_f", P64), Fc = full_field(c, "ab_fc", cp);
+  if (!F64.e.v || !Fc.e.v) return fail(c, NDTM_ENOMEM, "mg_transfer_cycle: workspace");
+  if (dir == 0) {
+    launch_pack_full(c->g, static_cast<const double2*>(in), F64.e, F64.o, st);
+    vconvert_field(cp, Fc.base, P64, F64.base, 2, c->g.vh, c->g.stride, st);
+    mg_restrict(cp, M->g, M->Pc, M->Psc, Fc.e.v, Fc.o.v, M->cR, st);
+    vconvert(P64, out, cp, M->cR, M->ncoarse, st);
+  } else {
+    vconvert(cp, M->cX, P64, in, M->ncoarse, st);
+    mg_prolong(cp, M->g, M->Pc, M->Psc, M->cX, Fc.e.v, Fc.o.v, st);
+    vconvert_field(P64, F64.base, cp, Fc.base, 2, c->g.vh, c->g.stride, st);
+    launch_unpack_full(c->g, F64.e, F64.o, static_cast<double2*>(out), st);
+  }
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }

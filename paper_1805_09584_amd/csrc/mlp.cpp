@@ -133,14 +133,14 @@ static int mlp_prepare(ndtm_ctx* c, const std::vector<double>& nodes, const std:
   std::vector<const void*> B(K + 1);
   B[0] = b.v;
   for (int i = 0; i < K; ++i) B[1 + i] = xs[i].v;
-  double* d = c->dscal + 1024;  // (K+1) Gram rows + the r_L overlaps, complex
-  for (int j = 0; j <= K; ++j) vmultidot(P64, B.data(), K + 1, B[j], n, c->vred, d + 2 * (K + 1) * j, st);
+  double* d = c->dscal + 1024;  // (K+1) Gram columns (i <= j) + the r_L overlaps, complex
+  for (int j = 0; j <= K; ++j) vmultidot(P64, B.data(), j + 1, B[j], n, c->vred, d + 2 * (K + 1) * j, st);
   vmultidot(P64, B.data(), K + 1, rl.v, n, c->vred, d + 2 * (K + 1) * (K + 1), st);
   NDTM_HIP(c, hipMemcpyAsync(c->hscal, d, 2 * (K + 1) * (K + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
   NDTM_HIP(c, hipStreamSynchronize(st));
   const double* h = c->hscal;
-  // M[i][j] = <B_i, B_j>: column j holds <B_i, B_j> for all i
-  auto Mre = [&](int i, int j) { return h[2 * ((K + 1) * j + i)]; };
+  // M[i][j] = <B_i, B_j>: column j holds <B_i, B_j> for i <= j; the real part is symmetric
+  auto Mre = [&](int i, int j) { return i <= j ? h[2 * ((K + 1) * j + i)] : h[2 * ((K + 1) * i + j)]; };
   auto hre = [&](int i) { return h[2 * ((K + 1) * (K + 1) + i)]; };
   S->bb = Mre(0, 0);
   S->rL2 = rel * rel * S->bb;

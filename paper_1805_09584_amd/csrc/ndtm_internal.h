@@ -37,7 +37,9 @@ struct Geom {
   int antiperiodic;
 };
 
-enum Prec { P64 = 0, P32 = 1, P16 = 2 };
+// P32H: a stencil precision only, FP32 fields with the FP16 links (the multigrid cycle's
+// FP16-storage form); fields and buffers are P64, P32 or P16
+enum Prec { P64 = 0, P32 = 1, P16 = 2, P32H = 3 };
 
 __host__ __device__ inline long idx32(int c, int stride, long h) {
   return ((long)(c >> 1) * stride + h) * 2 + (c & 1);

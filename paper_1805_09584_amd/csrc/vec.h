@@ -79,10 +79,13 @@ void mg_galerkin(const MGGeom& m, const double2* U64e, const double2* U64o, int 
 // clover part of the Galerkin self blocks from the fine site blocks M = a + C of both parities
 void mg_galerkin_clover(const MGGeom& m, const double2* P, const double* Me, const double* Mo, double a, double2* D,
                         hipStream_t st);
-// restrict / prolong between fine full fields (even half at fe, odd half at fo) and coarse [X][2][2Nv]
-void mg_restrict(int prec, const MGGeom& m, const void* P, const void* fe, const void* fo, void* vc,
+// restrict / prolong between fine full fields (even half at fe, odd half at fo) and coarse [X][2][2Nv];
+// Psc (FP32 fields only): P is FP16 with one FP32 scale per fine site (mg_p_to_half)
+void mg_restrict(int prec, const MGGeom& m, const void* P, const float* Psc, const void* fe, const void* fo, void* vc,
                  hipStream_t st);
-void mg_prolong(int prec, const MGGeom& m, const void* P, const void* vc, void* fe, void* fo, hipStream_t st);
+void mg_prolong(int prec, const MGGeom& m, const void* P, const float* Psc, const void* vc, void* fe, void* fo,
+                hipStream_t st);
+void mg_p_to_half(const MGGeom& m, const void* P64, void* P16, float* Psc, hipStream_t st);
 // coarse doublet operator y = D'_c(m) x
 // k <= kMultiMax FP64 coarse systems y_r = D'_c(m_r) x_r at once on MFMA; x, y: [k][Vc][2][2Nv]
 constexpr int kMultiMax = 8;

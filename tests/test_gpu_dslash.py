@@ -18,7 +18,8 @@ from tests.gpu_util import dev, host, rel_err, site_err
 pytestmark = pytest.mark.gpu
 
 K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
-TOL = {0: 1e-12, 1: 2e-6, 2: 5e-3}
+# FP64; FP32; FP16 (2^-11 per component over 8 hops); FP32 fields on FP16 links
+TOL = {0: 1e-12, 1: 2e-6, 2: 5e-3, 3: 5e-3}
 
 CASES = [((2, 2, 2, 2), False), ((2, 2, 2, 2), True), ((6, 4, 2, 10), True), ((4, 4, 4, 4), False),
          ((32, 16, 16, 16), False)]
@@ -101,7 +102,7 @@ def test_tiled_traversal_every_operator(nd, dims, tile, ap):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 10)])
 def test_low_precision_operators(nd, dims, prec):
     print(f"case dims={dims} prec={prec}", flush=True)
@@ -114,6 +115,8 @@ def test_low_precision_operators(nd, dims, prec):
         got = host(ctx.ndtm_apply(opcode, xd, par, prec=prec))
         want = ref(x)
         assert rel_err(got, want) < TOL[prec], (opcode, rel_err(got, want))
+        if prec == 3:  # the FP16 links are really read (their rounding is visible)
+            assert rel_err(got, want) > 1e-6
     xf = synth.gaussian_spinor(dims, 8, "full")
     got = host(ctx.ndtm_apply(nd.NDTM_OP_DFULL, dev(xf), 0.03, prec=prec))
     want = op.D_full(xf.reshape(dims + (2, 4, 3)), odd_shift=0.03).reshape(xf.shape)
@@ -136,7 +139,7 @@ def test_errors_and_state(nd):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_non_su3_links_use_all_rows(nd, prec):
     """Links multiplied by a random U(1) phase per link are unitary but not SU(3):
     their third row is not conj(row 0 x row 1), so the stencil must load all
