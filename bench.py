@@ -15,8 +15,10 @@ Forms (the first is the headline `value`):
           the 3 smallest, started from their multi-shift iterates (shifts 10, 11) and
           from the learned guess with Lagrange as fallback (shift 12), in the
           mixed-precision form (FP64 vectors and recurrences; the multi-shift stencil
-          moves to FP32, then FP16 storage as the residual falls; FP32 cycle)
-  full_f64  the same in FP64 (FP32 multigrid cycle inside FP64 defect correction)
+          moves to FP32, then FP16 storage as the residual falls)
+The multigrid setup (shared by all forms) builds the cycle in FP16 storage: P and the
+smoother's links in FP16, fields, coarse operator and arithmetic in FP32.
+  full_f64  the same in FP64 (the multigrid cycle inside FP64 FGMRES and defect correction)
   plain   multi-shift CG for all 12 shifts in FP64 (the speed-up reference)
   plain_mixed  plain in the mixed-precision form
   hybrid  full_f64 with Lagrange guesses only
@@ -308,9 +310,10 @@ def main():
     setup_ms = None
     mgp = None
     if any(f not in ("plain", "plain_mixed") for f in forms):
-        # FP32 cycle; on the large lattice the FP64 copies of P and the coarse blocks are
-        # freed after the setup (the cycle reads only the FP32 ones)
-        mgp = ctx.mg_params(keep_f64=0 if big else 1)
+        # cycle in FP16 storage (FP16 P and links, FP32 fields and arithmetic); on the large
+        # lattice the FP64 copies of P and the coarse blocks are freed after the setup (the
+        # cycle reads only its own copies)
+        mgp = ctx.mg_params(keep_f64=0 if big else 1, precision=nd.NDTM_PREC_F16)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.ndtm_mg_setup(mgp)

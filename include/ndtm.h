@@ -196,6 +196,12 @@ typedef struct {
                           ndtm_mg_restrict/prolong/coarse_apply(_multi)/coarse_solve_multi
                           use; 0 with an FP32 cycle: free them after the setup (those
                           calls then return NDTM_ESTATE), about 2/3 of the multigrid storage */
+  int pair_signs;      /* 1 (default): case C runs the FGMRES solves of +m and -m in lock-step, and
+                          each of their cycles solves the two coarse systems D'_c(+m), D'_c(-m)
+                          together by the batched coarse solve on the matrix cores (section 3.2:
+                          several coarse systems share the coarse blocks; FP64 coarse GMRES on the
+                          full coarse system).  Needs the FP64 coarse blocks (keep_f64 = 1); without
+                          them, or with 0, one sign after the other */
 } ndtm_mg_params;
 
 /* Fills *p with the defaults (4^4 aggregates, 24 vectors, ...). */

@@ -37,7 +37,7 @@ class MGParams(C.Structure):
                 ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
                 ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int), ("coarse_eo", C.c_int),
-                ("keep_f64", C.c_int)]
+                ("keep_f64", C.c_int), ("pair_signs", C.c_int)]
 
 
 class SolveParams(C.Structure):

@@ -178,7 +178,8 @@ int run_mmscg(ndtm_ctx* c, const std::vector<double>& sigmas, const std::vector<
               const HalfField& b, double tol, int maxiter, int poll_every, int defer, MmsResult* res,
               hipStream_t st, int npass = 0, void* region = nullptr, const MmsRamp* ramp = nullptr);
 // FP64 half fields the multigrid phase takes from the solve's region (case C and FGMRES)
-int mg_region_fields(int fgmres_restart);
+int mg_region_fields(int fgmres_restart, bool pair = false);
+bool mg_pairs_signs(const ndtm_ctx* c);  // the setup runs case C's two signs in lock-step
 // true relative residual ||b - (Q^2+sigma) x|| / ||b|| (FP64); r receives the residual
 // Gram matrix <B_i, B_j> of B = [b, x_1, x_2, ...] (row-major 17 x 17), filled
 // for the first `count` vectors; kept across the multigrid targets of one solve

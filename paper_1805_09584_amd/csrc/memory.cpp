@@ -189,7 +189,7 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     t += 5 * h64;                  // true residual, its Q^2 temporaries, CG polish
     t += 6 * h64;                  // base Krylov vectors and the first shifted direction
     t += (size_t)nsh * h64;        // solutions of ndtm_solve_rational
-    const size_t mg_fields = mg_phase ? (size_t)mg_region_fields(sp->fgmres_restart) : 0;
+    const size_t mg_fields = mg_phase ? (size_t)mg_region_fields(sp->fgmres_restart, mg && mg->pair_signs) : 0;
     {
       const int n_pred = mg_phase ? std::max(0, std::min(sp->mms_predict, nsh - n_mms)) : 0;
       int defer = std::min(sp->mms_defer, kMaxDefer);
@@ -226,6 +226,8 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     t += (kc + 1 + 5) * R(nc * cs) + 2 * R(2 * (kc + 1) * (kc + 1) * 8) + R((kc + 1) * 8) + R(2 * (kc + 1) * 8) +
          R(64) + R(128) + R(6 * (size_t)hop_grid(c->g) * 8);
     t += 4 * z.full(cp);  // cycle vectors
+    // paired signs: the second system's cycle vectors and the FP64 coarse pair
+    if (mg->pair_signs) t += 2 * z.full(cp) + 2 * R(2 * nc * 16);
     // setup temporaries: partial self blocks, test vectors and the inverse-iteration CG
     t += R(Vc * 8 * n2 * n2 * 16) + ((Nv + 1) / 2 + 6) * z.full(P64) + 2 * z.full(cp);
     // the multigrid calls of the ABI: a full FP64 field, the batched coarse solve of 8 systems

@@ -99,6 +99,10 @@ struct Full {
   void* base = nullptr;
 };
 
+// k FP64 coarse systems D'_c(m_r) x_r = b_r at once (x, b: [k][Vc][2][2Nv]); the batched
+// solve of ndtm_mg_coarse_solve_multi (FP64 coarse blocks)
+int coarse_solve_multi(ndtm_ctx* c, MGData* M, void* xc, const void* bc, int k, const double* m, hipStream_t st);
+
 static Full full_field(ndtm_ctx* c, const std::string& name, int prec) {
   Full f;
   const size_t n = half_elems(c);
@@ -326,10 +330,28 @@ static void dprime_mr(ndtm_ctx* c, int prec, const Full& y, const Full& x, doubl
 // Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
 // smooth_iters minimal-residual steps.  The fine operator is the one in c->op
 // (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
-static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, double eps, hipStream_t st) {
+// post-smoothing: smooth_iters minimal-residual steps on D'(m) z = r from the coarse correction in Z
+static void mg_smooth(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, hipStream_t st) {
   const int cp = M->cprec;
   const size_t nh = half_elems(c);
+  const int nu = M->prm.smooth_iters;
+  if (nu <= 0) return;
   Full S = full_field(c, "mg_S", cp), Tt = full_field(c, "mg_T", cp);
+  dprime(c, M->sprec, S, Z, m, st);
+  vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
+  for (int it = 0; it < nu; ++it) {
+    // T = D' S with <T, S>, ||T||^2 reduced in the stencil epilogue; the update
+    // kernel forms omega from those partials
+    dprime_mr(c, M->sprec, Tt, S, m, M->dpart, st);
+    vmr_update_part(cp, Z.base, S.base, Tt.base, M->dpart, 2 * hop_grid(c->g), it + 1 < nu, 2 * nh, st);
+  }
+}
+
+// Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
+// smooth_iters minimal-residual steps.  The fine operator is the one in c->op
+// (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
+static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, double eps, hipStream_t st) {
+  const int cp = M->cprec;
   {
     ProfScope ps(c, NDTM_PROF_RESTRICT, transfer_bytes(M), st);
     mg_restrict(cp, M->g, M->Pc, M->Psc, R.e.v, R.o.v, M->cR, st);
@@ -339,18 +361,7 @@ static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
     ProfScope ps(c, NDTM_PROF_PROLONG, transfer_bytes(M), st);
     mg_prolong(cp, M->g, M->Pc, M->Psc, M->cX, Z.e.v, Z.o.v, st);
   }
-  // post-smoothing: minimal residual steps on D' z = r
-  const int nu = M->prm.smooth_iters;
-  if (nu > 0) {
-    dprime(c, M->sprec, S, Z, m, st);
-    vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
-    for (int it = 0; it < nu; ++it) {
-      // T = D' S with <T, S>, ||T||^2 reduced in the stencil epilogue; the update
-      // kernel forms omega from those partials
-      dprime_mr(c, M->sprec, Tt, S, m, M->dpart, st);
-      vmr_update_part(cp, Z.base, S.base, Tt.base, M->dpart, 2 * hop_grid(c->g), it + 1 < nu, 2 * nh, st);
-    }
-  }
+  mg_smooth(c, M, R, Z, m, st);
 }
 
 // z_o ~ S'^-1 r_o : the cycle for D'(m) applied to (0, r_o), odd part; FP64 in/out
@@ -395,11 +406,47 @@ static void mg_cycle(ndtm_ctx* c, MGData* M, const HalfField& r64, const HalfFie
   vconvert_field(P64, z64.v, cp, Z.o.v, 1, c->g.vh, c->g.stride, st);
 }
 
+// The cycles of D'(+m) and D'(-m) side by side (case C's two signs): both residuals
+// restricted, the two coarse systems solved together by the batched FP64 coarse solve
+// (one matrix-core stencil launch per Arnoldi step for both), each correction
+// prolonged and smoothed with its own sign.  FP64 in/out on the odd sites.
+static bool mg_cycle_pair(ndtm_ctx* c, MGData* M, const HalfField* r64, const HalfField* z64, double m, hipStream_t st) {
+  const int cp = M->cprec;
+  const size_t nc = M->ncoarse;
+  Full R[2] = {full_field(c, "mg_R", cp), full_field(c, "mg_R2", cp)};
+  Full Z[2] = {full_field(c, "mg_Z", cp), full_field(c, "mg_Z2", cp)};
+  double2* B = static_cast<double2*>(ws_get(c, "mp_B", 2 * nc * sizeof(double2)));
+  double2* X = static_cast<double2*>(ws_get(c, "mp_X", 2 * nc * sizeof(double2)));
+  if (!R[1].base || !Z[1].base || !B || !X) return false;
+  for (int s = 0; s < 2; ++s) {
+    // the even halves of R stay zero (the second pair's from its allocation)
+    vconvert_field(cp, R[s].o.v, P64, r64[s].v, 1, c->g.vh, c->g.stride, st);
+    ProfScope ps(c, NDTM_PROF_RESTRICT, transfer_bytes(M), st);
+    mg_restrict(cp, M->g, M->Pc, M->Psc, R[s].e.v, R[s].o.v, M->cR, st);
+    vconvert(P64, B + s * nc, cp, M->cR, nc, st);
+  }
+  const double ms[2] = {m, -m};
+  if (coarse_solve_multi(c, M, X, B, 2, ms, st) != NDTM_OK) return false;
+  for (int s = 0; s < 2; ++s) {
+    vconvert(cp, M->cX, P64, X + s * nc, nc, st);
+    {
+      ProfScope ps(c, NDTM_PROF_PROLONG, transfer_bytes(M), st);
+      mg_prolong(cp, M->g, M->Pc, M->Psc, M->cX, Z[s].e.v, Z[s].o.v, st);
+    }
+    mg_smooth(c, M, R[s], Z[s], ms[s], st);
+    vconvert_field(P64, z64[s].v, cp, Z[s].o.v, 1, c->g.vh, c->g.stride, st);
+  }
+  return true;
+}
+
 // FGMRES in FP64 for (S + i m Gamma5 tau1) x = rhs, x starting from zero.
 // Stops when the recursive residual <= tol * ||rhs||.  Returns iterations.
 // Case C takes 5 FP64 half fields of the solve's phase region, FGMRES(k) 2k + 4 more.
 static int fgmres_restart_clamp(int restart) { return std::max(2, std::min(restart, 32)); }
-int mg_region_fields(int fgmres_restart) { return 5 + 2 * fgmres_restart_clamp(fgmres_restart) + 4; }
+// case C's five fields, then FGMRES(k)'s 2k + 4 (twice with the signs paired)
+int mg_region_fields(int fgmres_restart, bool pair) {
+  return 5 + (pair ? 2 : 1) * (2 * fgmres_restart_clamp(fgmres_restart) + 4);
+}
 
 // FP64 half field j of the solve's phase region, else the named workspace buffer
 static HalfField region_field(ndtm_ctx* c, size_t j, const std::string& name) {
@@ -515,6 +562,171 @@ static int fgmres(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField&
   return total;
 }
 
+// The FGMRES solves of (S + i m Gamma5 tau1) x_+ = rhs and (S - i m Gamma5 tau1) x_- = rhs
+// in lock-step: while both are inside an Arnoldi cycle their preconditioner steps run as
+// one paired cycle (mg_cycle_pair); a system that has converged (or whose cycle ended)
+// waits, and the other continues with single cycles.  Each system follows the single
+// fgmres exactly otherwise (same restarts, same stopping rule on its own ||rhs||).
+// Returns the iterations of both (its[0] for +m, its[1] for -m), -1 without workspace.
+static int fgmres_pair(ndtm_ctx* c, MGData* M, const HalfField& rhs, const HalfField* x, double m, double tol,
+                       int restart, int maxiter, double* res_out, int* its, hipStream_t st) {
+  const size_t n = half_elems(c);
+  restart = fgmres_restart_clamp(restart);
+  const int per = 2 * restart + 4;
+  struct Sys {
+    std::vector<HalfField> V, Z;
+    HalfField W, te, r;
+    std::vector<const void*> Vp, Zp;
+    std::vector<std::complex<double>> H, cs, sn, g;
+    double sgn = 1, res = 0;
+    int total = 0, k = 0;
+    bool done = false, in_cycle = false;
+  } S[2];
+  for (int s = 0; s < 2; ++s) {
+    Sys& y = S[s];
+    y.sgn = s == 0 ? 1.0 : -1.0;
+    size_t j0 = 5 + (size_t)s * per;
+    y.V.resize(restart + 1);
+    y.Z.resize(restart);
+    bool have = true;
+    for (int j = 0; j <= restart; ++j) have &= (y.V[j] = region_field(c, j0++, "fp_v" + std::to_string(s) + "_" + std::to_string(j))).v != nullptr;
+    for (int j = 0; j < restart; ++j) have &= (y.Z[j] = region_field(c, j0++, "fp_z" + std::to_string(s) + "_" + std::to_string(j))).v != nullptr;
+    y.W = region_field(c, j0, "fp_w" + std::to_string(s));
+    y.te = region_field(c, j0 + 1, "fp_te" + std::to_string(s));
+    y.r = region_field(c, j0 + 2, "fp_r" + std::to_string(s));
+    if (!have || !y.W.v || !y.te.v || !y.r.v) {
+      res_out[0] = res_out[1] = INFINITY;
+      return -1;
+    }
+    for (auto& f : y.V) y.Vp.push_back(f.v);
+    for (auto& f : y.Z) y.Zp.push_back(f.v);
+    blas_zero(x[s].v, n * sizeof(double2), st);
+  }
+  const double bn = std::sqrt(norm2_host(c, (const double2*)rhs.v, n, st));
+  if (bn == 0) {
+    res_out[0] = res_out[1] = 0;
+    its[0] = its[1] = 0;
+    return 0;
+  }
+  // per system: [0, 2 restart) h, [2 restart, 4 restart) second pass, 4 restart: norm2,
+  // [6 restart, 8 restart): the update coefficients
+  auto dh = [&](int s) { return c->dscal + (size_t)s * 8 * (restart + 1); };
+  while (!(S[0].done && S[1].done)) {
+    // start a cycle for every system that is not done: r = rhs - A x, V_0 = r / beta
+    for (int s = 0; s < 2; ++s) {
+      Sys& y = S[s];
+      if (y.done) continue;
+      if (y.total >= maxiter) {
+        y.done = true;
+        continue;
+      }
+      apply_sshift(c, P64, y.r, x[s], y.te, y.sgn * m, st);
+      blas_axpby((double2*)y.r.v, make_double2(1, 0), (const double2*)rhs.v, make_double2(-1, 0), n, st);
+      const double beta = std::sqrt(norm2_host(c, (const double2*)y.r.v, n, st));
+      y.res = beta;
+      if (beta <= tol * bn) {
+        y.done = true;
+        continue;
+      }
+      blas_axpby((double2*)y.V[0].v, make_double2(1.0 / beta, 0), (const double2*)y.r.v, make_double2(0, 0), n, st);
+      y.H.assign((size_t)(restart + 1) * restart, 0.0);
+      y.cs.assign(restart, 0.0);
+      y.sn.assign(restart, 0.0);
+      y.g.assign(restart + 1, 0.0);
+      y.g[0] = beta;
+      y.k = 0;
+      y.in_cycle = true;
+    }
+    if (S[0].done && S[1].done) break;
+    // Arnoldi steps, paired while both systems are inside a cycle
+    while (S[0].in_cycle || S[1].in_cycle) {
+      if (S[0].in_cycle && S[1].in_cycle) {
+        const HalfField rv[2] = {S[0].V[S[0].k], S[1].V[S[1].k]}, zv[2] = {S[0].Z[S[0].k], S[1].Z[S[1].k]};
+        if (!mg_cycle_pair(c, M, rv, zv, m, st)) {
+          res_out[0] = res_out[1] = INFINITY;
+          return -1;
+        }
+      } else {
+        const int s = S[0].in_cycle ? 0 : 1;
+        mg_cycle(c, M, S[s].V[S[s].k], S[s].Z[S[s].k], S[s].sgn * m, st);
+      }
+      for (int s = 0; s < 2; ++s) {
+        Sys& y = S[s];
+        if (!y.in_cycle) continue;
+        const int k = y.k;
+        apply_sshift(c, P64, y.W, y.Z[k], y.te, y.sgn * m, st);
+        vmultidot(P64, y.Vp.data(), k + 1, y.W.v, n, c->vred, dh(s), st);
+        vmulti_axpy_multidot(P64, y.W.v, y.Vp.data(), k + 1, dh(s), n, c->vred, dh(s) + 2 * restart, st);
+        vmulti_axpy_norm_dev(P64, y.W.v, y.Vp.data(), k + 1, dh(s) + 2 * restart, n, c->vred, dh(s) + 4 * restart,
+                             st);
+        vscale_inv_sqrt(P64, y.V[k + 1].v, y.W.v, dh(s) + 4 * restart, n, st);
+        (void)hipMemcpyAsync(c->hscal + (size_t)s * 8 * (restart + 1), dh(s), (4 * restart + 1) * sizeof(double),
+                             hipMemcpyDeviceToHost, st);
+      }
+      (void)hipStreamSynchronize(st);
+      for (int s = 0; s < 2; ++s) {
+        Sys& y = S[s];
+        if (!y.in_cycle) continue;
+        const int k = y.k;
+        const double* hs = c->hscal + (size_t)s * 8 * (restart + 1);
+        ++y.total;
+        auto Hk = [&](int i) -> std::complex<double>& { return y.H[(size_t)k * (restart + 1) + i]; };
+        for (int i = 0; i <= k; ++i)
+          Hk(i) = std::complex<double>(hs[2 * i] + hs[2 * restart + 2 * i], hs[2 * i + 1] + hs[2 * restart + 2 * i + 1]);
+        const double hn = std::sqrt(std::max(0.0, hs[4 * restart]));
+        Hk(k + 1) = hn;
+        for (int i = 0; i < k; ++i) {
+          const auto t = std::conj(y.cs[i]) * Hk(i) + std::conj(y.sn[i]) * Hk(i + 1);
+          Hk(i + 1) = -y.sn[i] * Hk(i) + y.cs[i] * Hk(i + 1);
+          Hk(i) = t;
+        }
+        const double den = std::sqrt(std::norm(Hk(k)) + std::norm(Hk(k + 1)));
+        bool stop = false;
+        if (!(den > 0) || !std::isfinite(den)) {
+          stop = true;  // breakdown: the cycle ends with the columns before this one
+        } else {
+          y.cs[k] = Hk(k) / den;
+          y.sn[k] = Hk(k + 1) / den;
+          Hk(k) = den;
+          Hk(k + 1) = 0;
+          y.g[k + 1] = -y.sn[k] * y.g[k];
+          y.g[k] = std::conj(y.cs[k]) * y.g[k];
+          y.res = std::abs(y.g[k + 1]);
+          y.k = k + 1;
+          stop = y.res <= tol * bn || hn == 0 || y.k == restart || y.total >= maxiter;
+        }
+        if (stop) {
+          y.in_cycle = false;
+          // x += Z y with y = R^-1 g over the columns of this cycle
+          const int kk = y.k;
+          std::vector<std::complex<double>> yy(kk);
+          for (int i = kk - 1; i >= 0; --i) {
+            auto sum = y.g[i];
+            for (int j = i + 1; j < kk; ++j) sum -= y.H[(size_t)j * (restart + 1) + i] * yy[j];
+            yy[i] = sum / y.H[(size_t)i * (restart + 1) + i];
+          }
+          std::vector<double> yc(2 * kk);
+          for (int i = 0; i < kk; ++i) {
+            yc[2 * i] = yy[i].real();
+            yc[2 * i + 1] = yy[i].imag();
+          }
+          if (kk > 0) {
+            (void)hipMemcpyAsync(dh(s) + 6 * restart, yc.data(), 2 * kk * sizeof(double), hipMemcpyHostToDevice, st);
+            vlincomb_dev(P64, x[s].v, y.Zp.data(), kk, dh(s) + 6 * restart, 1, n, st);
+            // the host buffer yc must outlive the copy
+            (void)hipStreamSynchronize(st);
+          }
+        }
+      }
+    }
+  }
+  for (int s = 0; s < 2; ++s) {
+    res_out[s] = S[s].res / bn;
+    its[s] = S[s].total;
+  }
+  return its[0] + its[1];
+}
+
 // upper estimate of the spectrum of Q^2: the context's estimate (largest Ritz value of
 // the base system's Lanczos matrix, from a multi-shift solve or ndtm_spectrum_estimate,
 // which approaches lambda_max from below) with a 10% margin; without one, 28 (the free
@@ -544,11 +756,20 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
     rho = std::max(1e-14, std::min(rho, p->mg_tol));
     launch_g5t1(c->g, (const double2*)r.v, (double2*)cr.v, st);
     double rp = 0, rm = 0;
-    const int ip = fgmres(c, M, cr, ep, +m, rho, p->fgmres_restart, p->fgmres_maxiter, &rp, st);
-    if (ip < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
-    const int im = fgmres(c, M, cr, em, -m, rho, p->fgmres_restart, p->fgmres_maxiter, &rm, st);
-    if (im < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
-    it_total += ip + im;
+    if (mg_pairs_signs(c)) {
+      const HalfField xe[2] = {ep, em};
+      double rr[2];
+      int its[2];
+      if (fgmres_pair(c, M, cr, xe, m, rho, p->fgmres_restart, p->fgmres_maxiter, rr, its, st) < 0)
+        return fail(c, NDTM_ENOMEM, "multigrid shift: paired FGMRES workspace");
+      it_total += its[0] + its[1];
+    } else {
+      const int ip = fgmres(c, M, cr, ep, +m, rho, p->fgmres_restart, p->fgmres_maxiter, &rp, st);
+      if (ip < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
+      const int im = fgmres(c, M, cr, em, -m, rho, p->fgmres_restart, p->fgmres_maxiter, &rm, st);
+      if (im < 0) return fail(c, NDTM_ENOMEM, "multigrid shift: FGMRES workspace");
+      it_total += ip + im;
+    }
     // x += (i/2m)(e_+ - e_-)
     blas_axpy((double2*)x.v, make_double2(0, 0.5 / m), (const double2*)ep.v, n, st);
     blas_axpy((double2*)x.v, make_double2(0, -0.5 / m), (const double2*)em.v, n, st);
@@ -569,6 +790,7 @@ static int case_c_solve(ndtm_ctx* c, MGData* M, const HalfField& x, const HalfFi
 }
 
 bool mg_ready(const ndtm_ctx* c) { return c->mg && c->mg->ready; }
+bool mg_pairs_signs(const ndtm_ctx* c) { return c->mg && c->mg->ready && c->mg->prm.pair_signs && c->mg->D64; }
 
 // Lagrange coefficients l_i(target) over the nodes (section 4.2, appendix B).
 static std::vector<double> lagrange(const std::vector<double>& nodes, double t) {
@@ -962,6 +1184,7 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->coarse_tol = 0.0;
   p->coarse_cycles = 20;
   p->coarse_eo = 1;
+  p->pair_signs = 1;
   p->keep_f64 = 1;
 }
 
@@ -1099,8 +1322,14 @@ int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, con
   if (!c->mg->P64) return fail(c, NDTM_ESTATE, "mg_coarse_solve_multi: FP64 operators not kept (keep_f64 = 0)");
   if (!xc || !bc || !m || xc == bc) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: null or aliased pointer");
   if (k < 1 || k > kMultiMax) return fail(c, NDTM_EINVAL, "mg_coarse_solve_multi: 1 <= k <= 8");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  MGData* M = c->mg;
+  return coarse_solve_multi(c, c->mg, xc, bc, k, m, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace ndtm {
+
+int coarse_solve_multi(ndtm_ctx* c, MGData* M, void* xc, const void* bc, int k, const double* m, hipStream_t st) {
   const size_t n = M->ncoarse;
   const int kc = M->prm.coarse_iters;
   const double mubar_c = M->prm.coarse_mu_factor * c->mubar;
@@ -1173,4 +1402,4 @@ int ndtm_mg_coarse_solve_multi(ndtm_ctx* c, void* xc, const void* bc, int k, con
   return NDTM_OK;
 }
 
-}  // extern "C"
+}  // namespace ndtm

@@ -499,7 +499,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
     // the multigrid phase's vectors; the ring gets what the region can hold beyond them
     const int n_ps = n_mms + n_pred;
     const size_t fb = n * sizeof(double2);
-    const size_t mg_fields = n_mms < nsh ? (size_t)mg_region_fields(p->fgmres_restart) : 0;
+    const size_t mg_fields = n_mms < nsh ? (size_t)mg_region_fields(p->fgmres_restart, mg_pairs_signs(c)) : 0;
     int defer = std::min(p->mms_defer, kMaxDefer);
     if (defer < 2) defer = 0;
     {
@@ -554,7 +554,7 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
   // ---- multigrid (case C) for the remaining shifts ----
   if (n_mms < nsh) {
     const int n_pred = std::max(0, std::min(p->mms_predict, nsh - n_mms));
-    const size_t fields = (size_t)mg_region_fields(p->fgmres_restart);
+    const size_t fields = (size_t)mg_region_fields(p->fgmres_restart, mg_pairs_signs(c));
     void* region = ws_get(c, "sv_region", std::max(ws_bytes(c, "sv_region"), fields * n * sizeof(double2)));
     if (!region) return fail(c, NDTM_ENOMEM, "solve: phase region");
     RegionScope rs(c, region, fields);

@@ -130,6 +130,21 @@ def test_hybrid_config2(nd):
     ctx.close()
 
 
+def test_paired_signs_config2(nd):
+    """Case C with the two signs in lock-step, each paired cycle solving its two coarse
+    systems by the batched matrix-core coarse solve: every shift meets 1e-10 by the
+    oracle's residual, the multigrid shifts by multigrid (no CG fallback)."""
+    print("case c2 hybrid, paired signs", flush=True)
+    _, _, _, _, _, rep1 = _hybrid(nd, "c2", 9, dict())
+    ctx, op, b, sig, xs, rep = _hybrid(nd, "c2", 9, dict(pair_signs=1))
+    print("unpaired", rep1["iterations"][9:], rep1["t_mg_ms"], "paired", rep["iterations"][9:], rep["t_mg_ms"],
+          flush=True)
+    for i in range(12):
+        assert rel_residual(op, host(xs[i]), b, sig[i]) <= 1e-10, i
+        assert rep["method"][i] == (1 if i >= 9 else 0), rep["method"]
+    ctx.close()
+
+
 def test_graph_replay_matches_eager(nd):
     """The multigrid cycle replayed from captured HIP graphs (many replays, with
     eager FGMRES work between them) gives bitwise the same solutions as eager launches."""
