@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--dslash-reps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--mg-pair", type=int, default=1, help="case C's two signs in lock-step (needs FP64 coarse blocks)")
+    ap.add_argument("--mg-prec", type=int, default=2, help="multigrid cycle precision (2: FP16 storage)")
+    ap.add_argument("--mg-eo", type=int, default=1, help="even-odd coarsest level in the single-sign cycles")
     return ap.parse_args()
 
 
@@ -313,7 +316,8 @@ def main():
         # cycle in FP16 storage (FP16 P and links, FP32 fields and arithmetic); on the large
         # lattice the FP64 copies of P and the coarse blocks are freed after the setup (the
         # cycle reads only its own copies)
-        mgp = ctx.mg_params(keep_f64=0 if big else 1, precision=nd.NDTM_PREC_F16)
+        mgp = ctx.mg_params(keep_f64=0 if big else 1, precision=args.mg_prec, pair_signs=args.mg_pair,
+                            coarse_eo=args.mg_eo)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.ndtm_mg_setup(mgp)
@@ -377,6 +381,7 @@ def main():
         "forms": results,
         "speedup_vs_plain": speedup,
         "mg_setup_ms": setup_ms,
+        "mg_cycle": {"precision": args.mg_prec, "pair_signs": args.mg_pair, "coarse_eo": args.mg_eo},
         "fgmres_restart": restart or 16,
         "set_gauge_ms": set_gauge_ms,
         "device_storage_gb": {"live": mem["live"] / 1e9, "peak": mem["peak"] / 1e9},

@@ -1010,9 +1010,15 @@ __global__ __launch_bounds__(256) void einv_build_k(MGGeom m, int X0, const type
 
 // out = (-A_ee^-1 u_e) on the even coarse sites and out = v on the odd ones (the
 // input of the odd Schur complement's second coarse stencil), Einv holding -A^-1.
+// The N x N product of each even site is split over kEinvGroups thread groups, each
+// summing a quarter of the columns (a row's dependent chain of loads and FMAs is a
+// quarter as long), then the groups' partial rows are added in LDS in a fixed order.
+constexpr int kEinvGroups = 4;
 template <class R>
-__global__ __launch_bounds__(128) void einv_apply_k(MGGeom m, const typename C2<R>::T* Einv, const typename C2<R>::T* u,
-                                                     const typename C2<R>::T* v, typename C2<R>::T* out) {
+__global__ __launch_bounds__(128 * kEinvGroups) void einv_apply_k(MGGeom m, const typename C2<R>::T* Einv,
+                                                                  const typename C2<R>::T* u,
+                                                                  const typename C2<R>::T* v,
+                                                                  typename C2<R>::T* out) {
   using T2 = typename C2<R>::T;
   const int X = blockIdx.x;
   const int N = 4 * m.Nv;
@@ -1021,17 +1027,31 @@ __global__ __launch_bounds__(128) void einv_apply_k(MGGeom m, const typename C2<
     return;
   }
   __shared__ T2 us[128];
+  __shared__ R part[kEinvGroups][2][128];
   for (int r = threadIdx.x; r < N; r += blockDim.x) us[r] = u[(size_t)X * N + r];
   __syncthreads();
   const T2* E = Einv + (size_t)(X >> 1) * N * N;
-  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+  const int r = threadIdx.x & 127, q = threadIdx.x >> 7;
+  const int c0 = q * N / kEinvGroups, c1 = (q + 1) * N / kEinvGroups;
+  if (r < N) {
     R ax = 0, ay = 0;
-    for (int c = 0; c < N; ++c) {
+    for (int c = c0; c < c1; ++c) {
       const T2 e = E[(size_t)c * N + r], w = us[c];
       ax += e.x * w.x - e.y * w.y;
       ay += e.x * w.y + e.y * w.x;
     }
-    out[(size_t)X * N + r] = mk<R>(ax, ay);
+    part[q][0][r] = ax;
+    part[q][1][r] = ay;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    R sx = 0, sy = 0;
+#pragma unroll
+    for (int g = 0; g < kEinvGroups; ++g) {
+      sx += part[g][0][threadIdx.x];
+      sy += part[g][1][threadIdx.x];
+    }
+    out[(size_t)X * N + threadIdx.x] = mk<R>(sx, sy);
   }
 }
 
@@ -1057,10 +1077,10 @@ void mg_einv_build(int prec, const MGGeom& g, int X0, int count, const void* D, 
 void mg_einv_apply(int prec, const MGGeom& g, const void* Einv, const void* u, const void* v, void* out,
                    hipStream_t st) {
   if (prec == P64)
-    hipLaunchKernelGGL(einv_apply_k<double>, dim3(g.Vc), dim3(128), 0, st, g, (const double2*)Einv, (const double2*)u,
+    hipLaunchKernelGGL(einv_apply_k<double>, dim3(g.Vc), dim3(128 * kEinvGroups), 0, st, g, (const double2*)Einv, (const double2*)u,
                        (const double2*)v, (double2*)out);
   else
-    hipLaunchKernelGGL(einv_apply_k<float>, dim3(g.Vc), dim3(128), 0, st, g, (const float2*)Einv, (const float2*)u,
+    hipLaunchKernelGGL(einv_apply_k<float>, dim3(g.Vc), dim3(128 * kEinvGroups), 0, st, g, (const float2*)Einv, (const float2*)u,
                        (const float2*)v, (float2*)out);
 }
 

@@ -135,7 +135,7 @@ def test_paired_signs_config2(nd):
     systems by the batched matrix-core coarse solve: every shift meets 1e-10 by the
     oracle's residual, the multigrid shifts by multigrid (no CG fallback)."""
     print("case c2 hybrid, paired signs", flush=True)
-    _, _, _, _, _, rep1 = _hybrid(nd, "c2", 9, dict())
+    _, _, _, _, _, rep1 = _hybrid(nd, "c2", 9, dict(pair_signs=0))
     ctx, op, b, sig, xs, rep = _hybrid(nd, "c2", 9, dict(pair_signs=1))
     print("unpaired", rep1["iterations"][9:], rep1["t_mg_ms"], "paired", rep["iterations"][9:], rep["t_mg_ms"],
           flush=True)
