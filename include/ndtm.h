@@ -392,9 +392,11 @@ int ndtm_hybrid_split(int n_shifts, const double* sigma_desc, double lambda_min,
                       double ms_per_iteration, double ms_per_mg_shift, int* n_out);
 
 /* Extreme eigenvalues of Q^2 estimated from the Lanczos matrix of the base system
- * of the last FP64 multi-shift solve on this context that fitted one block of the
- * deferred form (Ritz values: inside the spectrum).  They bound the spectrum for
- * ndtm_hybrid_split and for the interval of ndtm_solve_rational.  ESTATE before one. */
+ * (its CG coefficients over the first 512 iterations) of the last multi-shift solve on
+ * this context that used the deferred form (Ritz values: inside the spectrum, the
+ * largest close to lambda_max after a few dozen iterations).  They bound the spectrum
+ * for ndtm_hybrid_split, the automatic split, case C's tolerance and the interval of
+ * ndtm_solve_rational.  ESTATE before one. */
 int ndtm_spectrum_estimate(const ndtm_ctx* ctx, double* lambda_min, double* lambda_max);
 
 /* ---- rational approximation (section "Rational approximation") ---------- */
