@@ -121,6 +121,12 @@ static double hop_epi_vectors(int epi) {
   return 0;
 }
 
+// smallest |U01|^2 + |U02|^2 of every link for the eight-parameter form: the rebuild
+// divides by it (its numerators are of the same order, so the rebuilt entries keep FP64
+// accuracy down to tiny norms; the bound only keeps out links whose first row is
+// (u, 0, 0) to within rounding, such as unit links)
+constexpr double kR8MinNorm = 1e-20;
+
 void hop(ndtm_ctx* c, int prec, int epi, int red, int parity, const HalfField& in, const HalfField& out,
          const HalfField* xs, const HalfField* zs, double ms, double hop_coef, double sigma,
          double* partials, hipStream_t st) {
@@ -290,6 +296,7 @@ void ndtm_destroy(ndtm_ctx* c) {
   c->bufs.clear();
   for (int p = 0; p < 3; ++p)
     for (int q = 0; q < 2; ++q) dev_free(c, c->U[p][q]);
+  for (int q = 0; q < 2; ++q) dev_free(c, c->U8[q]);
   for (int q = 0; q < 2; ++q) {
     dev_free(c, c->clv_m[q][0]);
     dev_free(c, c->clv_m[q][1]);
@@ -351,6 +358,24 @@ int ndtm_set_gauge(ndtm_ctx* c, const void* U_dev, void* stream) {
     for (double v : part) dev = std::isfinite(v) ? std::max(dev, v) : 1e300;
     c->op.recon12 = dev <= 1e-14 ? 1 : 0;
     c->su3_dev = dev;
+  }
+  // SU(3) fields: the FP64 stencil reads eight parameters per link, unless some link's
+  // first row is too close to (u, 0, 0) for the rebuild's division (unit links, for one)
+  c->op.u8[0] = c->op.u8[1] = nullptr;
+  if (c->op.recon12) {
+    const size_t n8 = (size_t)16 * c->g.stride * sizeof(double2);
+    double mn = 1.0;
+    for (int q = 0; q < 2; ++q) {
+      if (!c->U8[q]) c->U8[q] = dev_alloc(c, n8);
+      if (!c->U8[q]) return fail(c, NDTM_ENOMEM, "set_gauge: link storage");
+      const int nb = launch_pack_r8(c->g, (const double2*)c->U[P64][q], (double2*)c->U8[q], c->partials, st);
+      std::vector<double> part(nb);
+      NDTM_HIP(c, hipMemcpyAsync(part.data(), c->partials, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+      NDTM_HIP(c, hipStreamSynchronize(st));
+      for (double v : part) mn = std::isfinite(v) ? std::min(mn, v) : 0.0;
+    }
+    if (mn >= kR8MinNorm)
+      for (int q = 0; q < 2; ++q) c->op.u8[q] = static_cast<const double2*>(c->U8[q]);
   }
   c->have_gauge = true;
   ndtm_mg_free(c);

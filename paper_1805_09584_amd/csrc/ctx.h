@@ -34,6 +34,7 @@ struct ndtm_ctx {
   double su3_dev = 0;  // max deviation of the stored links from SU(3) row structure
   std::vector<double> shifts;
   void* U[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
+  void* U8[2] = {nullptr, nullptr};  // FP64 links in eight parameters (SU(3) fields), [parity]
   // clover term (eq:Wilson): c_sw and the site blocks [FP64, FP32][parity], even inverse
   double csw = 0;
   void* clv_m[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};

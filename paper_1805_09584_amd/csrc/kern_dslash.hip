@@ -241,6 +241,38 @@ __device__ __forceinline__ void herm6(const CT* base, int stride, int h, int com
     }
 }
 
+// sin and cos of an angle in [-pi, pi] in FP64, for the eight-parameter links: the
+// angle is reduced by the nearest multiple k of pi/2 (pi/2 split in two parts, so
+// the remainder |r| <= pi/4 is exact to rounding), then the Taylor series of sin r
+// (to r^15) and cos r (to r^16), whose truncation errors stay below 1e-16 at pi/4,
+// and the quadrant k mod 4 selects and signs them.  Small in registers, unlike a
+// general-purpose sincos with its reduction for large arguments.
+__device__ __forceinline__ void sincos_pi(double x, double* sn, double* cs) {
+  const double k = rint(x * 0.63661977236758134308);
+  const double r = fma(-k, 6.123233995736766e-17, fma(-k, 1.5707963267948966, x));
+  const double r2 = r * r;
+  // coefficients (-1)^n / (2n+1)! and (-1)^n / (2n)!, n >= 1
+  const double ps = fma(fma(fma(fma(fma(fma(-7.647163731819816e-13, r2, 1.6059043836821613e-10), r2, -2.505210838544172e-08), r2, 2.7557319223985893e-06), r2, -0.0001984126984126984), r2, 0.008333333333333333), r2, -0.16666666666666666);
+  const double pc = fma(fma(fma(fma(fma(fma(fma(4.779477332387385e-14, r2, -1.1470745597729725e-11), r2, 2.08767569878681e-09), r2, -2.755731922398589e-07), r2, 2.48015873015873e-05), r2, -0.001388888888888889), r2, 0.041666666666666664), r2, -0.5);
+  const double sr = fma(r * r2, ps, r), cr = fma(r2, pc, 1.0);
+  const int q = (int)k & 3;
+  *sn = q == 0 ? sr : q == 1 ? cr : q == 2 ? -sr : -cr;
+  *cs = q == 0 ? cr : q == 1 ? -sr : q == 2 ? -cr : sr;
+}
+
+// sin and cos of the two phases of one eight-parameter link.  Kept out of line: inlined
+// into the eight hops, the compiler scheduled all sixteen evaluations together and the
+// FP64 stencil spilled to scratch at one wave per SIMD; as a call it runs at three.
+struct SinCos2 {
+  double s0, c0, s1, c1;
+};
+__device__ __noinline__ SinCos2 sincos_pair(double x0, double x1) {
+  SinCos2 r;
+  sincos_pi(x0, &r.s0, &r.c0);
+  sincos_pi(x1, &r.s1, &r.c1);
+  return r;
+}
+
 // Raw operands of one hop in storage precision: the neighbour spinor of the
 // lane's flavour (12 complex), its scale (FP16 only) and the link (9 complex).
 // Loading them is split from the arithmetic so that the loads of the next
@@ -252,7 +284,9 @@ struct Raw {
   float sc;
 };
 
-template <int MU, bool R12, class S, class L>
+// R8 (FP64, SU(3) links): U points at the eight-parameter link arrays, four complex
+// words per link (see launch_pack_r8)
+template <int MU, bool R12, bool R8, class S, class L>
 __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
                                          int hl) {
   if constexpr (kGrouped<S>) {
@@ -284,15 +318,20 @@ __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, i
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
     const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
+    if constexpr (R8) {
 #pragma unroll
-    for (int k = 0; k < (R12 ? 6 : 9); ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+      for (int k = 0; k < 4; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 4 + k) * A.stride, vl));
+    } else {
+#pragma unroll
+      for (int k = 0; k < (R12 ? 6 : 9); ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
+    }
   }
 }
 
 // One of the eight hops: project, colour-multiply, reconstruct, accumulate.
 // SIGN: the hop carries the sign sg of an antiperiodic time boundary; the
 // FP16 spinor scale and sg multiply the colour products once, at the end.
-template <int MU, bool FWD, bool SIGN, bool R12, class S, class L, class R>
+template <int MU, bool FWD, bool SIGN, bool R12, bool R8, class S, class L, class R>
 __device__ __forceinline__ void hop_compute(cx<R> (&acc)[4][3], const Raw<S, L>& raw, R sg) {
   cx<R> p[4][3];
 #pragma unroll
@@ -317,11 +356,41 @@ __device__ __forceinline__ void hop_compute(cx<R> (&acc)[4][3], const Raw<S, L>&
     }
   }
   cx<R> u[3][3];
+  if constexpr (R8) {
+    // eight parameters: a = (U01, U02) and the kept first-column entry exactly, the
+    // phases of U00 and of the other first-column entry (+8 marks that U20 was kept);
+    // |U00| and the other entry's magnitude from the row and column norms (both equal
+    // 1 - |a|^2 off the corner), and with c = (U10, U20)^T, u = U00, n = |a|^2 the
+    // unitarity and det U = 1 relations give the lower 2x2 block
+    //   B = -(1/n) [ (conj c2, -conj c1)^T (conj a2, -conj a1) + conj(u) c a ]
+    auto cj = [](cx<R> z) { return cx<R>{z.x, -z.y}; };
+    const cx<R> a1 = cvt(raw.u[0]), a2 = cvt(raw.u[1]), ks = cvt(raw.u[2]), th = cvt(raw.u[3]);
+    const bool k20 = th.y > R(4);
+    const R tho = k20 ? th.y - R(8) : th.y;
+    const R n = a1.x * a1.x + a1.y * a1.y + a2.x * a2.x + a2.y * a2.y;
+    const R mu = sqrt(fmax(R(1) - n, R(0)));
+    const R mo = sqrt(fmax(n - (ks.x * ks.x + ks.y * ks.y), R(0)));
+    const SinCos2 sc = sincos_pair(th.x, tho);
+    const cx<R> u0 = {mu * sc.c0, mu * sc.s0}, oth = {mo * sc.c1, mo * sc.s1};
+    const cx<R> c1 = k20 ? oth : ks, c2 = k20 ? ks : oth;
+    const cx<R> uc = cj(u0);
+    const R in = R(1) / n;
+    u[0][0] = u0;
+    u[0][1] = a1;
+    u[0][2] = a2;
+    u[1][0] = c1;
+    u[2][0] = c2;
+    u[1][1] = (-in) * (cj(mul(c2, a2)) + mul(uc, mul(c1, a1)));
+    u[1][2] = in * (cj(mul(c2, a1)) - mul(uc, mul(c1, a2)));
+    u[2][1] = in * (cj(mul(c1, a2)) - mul(uc, mul(c2, a1)));
+    u[2][2] = (-in) * (cj(mul(c1, a1)) + mul(uc, mul(c2, a2)));
+  } else {
 #pragma unroll
   for (int r = 0; r < (R12 ? 2 : 3); ++r)
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[r][c] = cvt(raw.u[r * 3 + c]);
-  if constexpr (R12) {
+  }
+  if constexpr (R12 && !R8) {
     // SU(3): row 2 = conj(row 0 x row 1)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -416,7 +485,7 @@ __device__ __forceinline__ void block_reduce_store3(double v0, double v1, double
   }
 }
 
-template <class S, class L, int EPI, int RED, bool R12, bool CLV>
+template <class S, class L, int EPI, int RED, bool R12, bool CLV, bool R8 = false>
 __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
   using R = typename RealOf<S>::T;
   if (A.skip && *A.skip != 0.0) return;
@@ -482,40 +551,40 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
       // FP64: the operands of one hop already take ~90 registers; a second
       // buffer would leave one wave per SIMD, so hops are loaded one at a time
       Raw<S, L> r;
-      load_raw<0, R12>(r, A, f, ht_p, A.Uo, h);
-      hop_compute<0, true, true, R12>(acc, r, sg_tp);
-      load_raw<0, R12>(r, A, f, ht_m, A.Ui, ht_m);
-      hop_compute<0, false, true, R12>(acc, r, sg_tm);
-      load_raw<1, R12>(r, A, f, hx_p, A.Uo, h);
-      hop_compute<1, true, false, R12>(acc, r, R(1));
-      load_raw<1, R12>(r, A, f, hx_m, A.Ui, hx_m);
-      hop_compute<1, false, false, R12>(acc, r, R(1));
-      load_raw<2, R12>(r, A, f, hy_p, A.Uo, h);
-      hop_compute<2, true, false, R12>(acc, r, R(1));
-      load_raw<2, R12>(r, A, f, hy_m, A.Ui, hy_m);
-      hop_compute<2, false, false, R12>(acc, r, R(1));
-      load_raw<3, R12>(r, A, f, hz_p, A.Uo, h);
-      hop_compute<3, true, false, R12>(acc, r, R(1));
-      load_raw<3, R12>(r, A, f, hz_m, A.Ui, hz_m);
-      hop_compute<3, false, false, R12>(acc, r, R(1));
+      load_raw<0, R12, R8>(r, A, f, ht_p, A.Uo, h);
+      hop_compute<0, true, true, R12, R8>(acc, r, sg_tp);
+      load_raw<0, R12, R8>(r, A, f, ht_m, A.Ui, ht_m);
+      hop_compute<0, false, true, R12, R8>(acc, r, sg_tm);
+      load_raw<1, R12, R8>(r, A, f, hx_p, A.Uo, h);
+      hop_compute<1, true, false, R12, R8>(acc, r, R(1));
+      load_raw<1, R12, R8>(r, A, f, hx_m, A.Ui, hx_m);
+      hop_compute<1, false, false, R12, R8>(acc, r, R(1));
+      load_raw<2, R12, R8>(r, A, f, hy_p, A.Uo, h);
+      hop_compute<2, true, false, R12, R8>(acc, r, R(1));
+      load_raw<2, R12, R8>(r, A, f, hy_m, A.Ui, hy_m);
+      hop_compute<2, false, false, R12, R8>(acc, r, R(1));
+      load_raw<3, R12, R8>(r, A, f, hz_p, A.Uo, h);
+      hop_compute<3, true, false, R12, R8>(acc, r, R(1));
+      load_raw<3, R12, R8>(r, A, f, hz_m, A.Ui, hz_m);
+      hop_compute<3, false, false, R12, R8>(acc, r, R(1));
     } else {
     Raw<S, L> ra, rb;
-    load_raw<0, R12>(ra, A, f, ht_p, A.Uo, h);
-    load_raw<0, R12>(rb, A, f, ht_m, A.Ui, ht_m);
-    hop_compute<0, true, true, R12>(acc, ra, sg_tp);
-    load_raw<1, R12>(ra, A, f, hx_p, A.Uo, h);
-    hop_compute<0, false, true, R12>(acc, rb, sg_tm);
-    load_raw<1, R12>(rb, A, f, hx_m, A.Ui, hx_m);
-    hop_compute<1, true, false, R12>(acc, ra, R(1));
-    load_raw<2, R12>(ra, A, f, hy_p, A.Uo, h);
-    hop_compute<1, false, false, R12>(acc, rb, R(1));
-    load_raw<2, R12>(rb, A, f, hy_m, A.Ui, hy_m);
-    hop_compute<2, true, false, R12>(acc, ra, R(1));
-    load_raw<3, R12>(ra, A, f, hz_p, A.Uo, h);
-    hop_compute<2, false, false, R12>(acc, rb, R(1));
-    load_raw<3, R12>(rb, A, f, hz_m, A.Ui, hz_m);
-    hop_compute<3, true, false, R12>(acc, ra, R(1));
-    hop_compute<3, false, false, R12>(acc, rb, R(1));
+    load_raw<0, R12, R8>(ra, A, f, ht_p, A.Uo, h);
+    load_raw<0, R12, R8>(rb, A, f, ht_m, A.Ui, ht_m);
+    hop_compute<0, true, true, R12, R8>(acc, ra, sg_tp);
+    load_raw<1, R12, R8>(ra, A, f, hx_p, A.Uo, h);
+    hop_compute<0, false, true, R12, R8>(acc, rb, sg_tm);
+    load_raw<1, R12, R8>(rb, A, f, hx_m, A.Ui, hx_m);
+    hop_compute<1, true, false, R12, R8>(acc, ra, R(1));
+    load_raw<2, R12, R8>(ra, A, f, hy_p, A.Uo, h);
+    hop_compute<1, false, false, R12, R8>(acc, rb, R(1));
+    load_raw<2, R12, R8>(rb, A, f, hy_m, A.Ui, hy_m);
+    hop_compute<2, true, false, R12, R8>(acc, ra, R(1));
+    load_raw<3, R12, R8>(ra, A, f, hz_p, A.Uo, h);
+    hop_compute<2, false, false, R12, R8>(acc, rb, R(1));
+    load_raw<3, R12, R8>(rb, A, f, hz_m, A.Ui, hz_m);
+    hop_compute<3, true, false, R12, R8>(acc, ra, R(1));
+    hop_compute<3, false, false, R12, R8>(acc, rb, R(1));
     }
   }
 
@@ -746,12 +815,21 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
   A.hop_coef = hop_coef;
   A.sigma = sigma;
   const dim3 grid(hop_grid(g)), block(kBlock);
+  // FP64 with SU(3) links in eight parameters: the link pointers go to those arrays
+  constexpr bool kF64 = std::is_same<S, double2>::value;
+  const bool r8 = kF64 && op.recon12 && op.u8[parity] && op.u8[1 - parity];
+  if (r8) {
+    A.Uo = reinterpret_cast<const L*>(op.u8[parity]);
+    A.Ui = reinterpret_cast<const L*>(op.u8[1 - parity]);
+  }
 #define NDTM_HOP(E, RD)                                                                         \
   do {                                                                                          \
     if (clv && E != EPI_PLAIN) {                                                                \
+      if constexpr (kF64) if (r8) { hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, true, true>), grid, block, 0, st, A); break; } \
       if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, true>), grid, block, 0, st, A);   \
       else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false, true>), grid, block, 0, st, A);             \
     } else {                                                                                    \
+      if constexpr (kF64) if (r8) { hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, false, true>), grid, block, 0, st, A); break; } \
       if (op.recon12) hipLaunchKernelGGL((hop_kernel<S, L, E, RD, true, false>), grid, block, 0, st, A);  \
       else hipLaunchKernelGGL((hop_kernel<S, L, E, RD, false, false>), grid, block, 0, st, A);            \
     }                                                                                           \

@@ -152,7 +152,42 @@ __global__ __launch_bounds__(256) void su3_check_k(long nlinks, const double2* U
   if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(ws[0], ws[1]), fmax(ws[2], ws[3]));
 }
 
+// SU(3) links of one parity ([mu 9 + k][stride], FP64) in eight real parameters: per
+// link four complex words [mu 4 + j][stride]: U01, U02, the smaller in magnitude of
+// U10 and U20 (kept exactly), and (arg U00, arg of the other + 8 if the kept one is U20).
+// The stencil rebuilds |U00| from the first row's norm, the other first-column entry's
+// magnitude from the column norm (the larger of the two, so no cancellation), and the
+// remaining 2x2 block from unitarity and det U = 1 (a division by |U01|^2 + |U02|^2).
+// part[block] receives the smallest |U01|^2 + |U02|^2 of the block's links.
+__global__ __launch_bounds__(256) void pack_r8_k(int vh, int stride, const double2* U, double2* U8, double* part) {
+  double mn = 1.0;
+  for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < 4L * vh; q += (long)gridDim.x * blockDim.x) {
+    const int mu = (int)(q / vh), h = (int)(q - (long)mu * vh);
+    const double2 u00 = U[(long)(mu * 9 + 0) * stride + h], u01 = U[(long)(mu * 9 + 1) * stride + h],
+                  u02 = U[(long)(mu * 9 + 2) * stride + h], u10 = U[(long)(mu * 9 + 3) * stride + h],
+                  u20 = U[(long)(mu * 9 + 6) * stride + h];
+    const double na = u01.x * u01.x + u01.y * u01.y + u02.x * u02.x + u02.y * u02.y;
+    mn = fmin(mn, na);
+    const bool keep20 = u20.x * u20.x + u20.y * u20.y < u10.x * u10.x + u10.y * u10.y;
+    const double2 kept = keep20 ? u20 : u10, other = keep20 ? u10 : u20;
+    U8[(long)(mu * 4 + 0) * stride + h] = u01;
+    U8[(long)(mu * 4 + 1) * stride + h] = u02;
+    U8[(long)(mu * 4 + 2) * stride + h] = kept;
+    U8[(long)(mu * 4 + 3) * stride + h] = make_double2(atan2(u00.y, u00.x), atan2(other.y, other.x) + (keep20 ? 8.0 : 0.0));
+  }
+  for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_down(mn, off));
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmin(fmin(ws[0], ws[1]), fmin(ws[2], ws[3]));
+}
+
 }  // namespace
+
+int launch_pack_r8(const Geom& g, const double2* U64, double2* U8, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(pack_r8_k, dim3(1024), dim3(256), 0, st, g.vh, g.stride, U64, U8, part);
+  return 1024;
+}
 
 int launch_su3_check(long V, const double2* U, double* part, hipStream_t st) {
   hipLaunchKernelGGL(su3_check_k, dim3(1024), dim3(256), 0, st, 4 * V, U, part);

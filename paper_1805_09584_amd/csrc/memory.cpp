@@ -175,6 +175,8 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
   size_t t = 0;
   // links: FP64, FP32 and FP16 copies of both parities
   for (size_t es : {16, 8, 4}) t += 2 * R(36 * z.stride * es);
+  // FP64 SU(3) links in eight parameters (four complex words per link and direction)
+  t += 2 * R(16 * z.stride * 16);
   // clover site blocks (with c_sw set): a + C on both parities and the even inverse, FP64 and FP32
   if (c->csw != 0.0)
     for (size_t es : {8, 4}) t += 2 * R(72 * z.stride * es) + R(144 * z.stride * es) + (es == 8 ? R(256) : 0);

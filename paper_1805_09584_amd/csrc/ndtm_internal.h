@@ -75,6 +75,9 @@ enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2, RED_MR = 3 };
 struct OpParams {
   double a, mubar, epsbar, inv_den;
   int recon12;  // links are SU(3): the stencil loads two rows and rebuilds the third
+  // FP64 SU(3) links in eight parameters per link, per parity (null: the FP64 stencil
+  // reads two rows, or nine components)
+  const double2* u8[2] = {nullptr, nullptr};
   // optional device flag: a stencil launch returns at once while *skip != 0 (the
   // iterations a solver runs past its done flag before the host sees it)
   const double* skip = nullptr;
@@ -116,6 +119,9 @@ void launch_pack_gauge(const Geom& g, const double2* U, double2* U64e, double2* 
 // canonical [V/2][24] (complex128) <-> internal half field (any precision)
 // max over all links of |row 2 - conj(row 0 x row 1)| of canonical links (V sites x 4),
 // per-block maxima written to part[0..nblk) (nblk = 1024); returns nblk
+// FP64 links of one parity in eight parameters (the FP64 stencil's SU(3) form); part:
+// per-block minimum of |U01|^2 + |U02|^2 (returns the block count)
+int launch_pack_r8(const Geom& g, const double2* U64, double2* U8, double* part, hipStream_t st);
 int launch_su3_check(long V, const double2* U, double* part, hipStream_t st);
 // streaming reference kernels: kind 0 copy a -> b, 1 read a, 2 write b (bytes multiple of 16)
 void launch_stream(int kind, const void* a, void* b, size_t bytes, unsigned* sink, hipStream_t st);

@@ -159,3 +159,28 @@ def test_non_su3_links_use_all_rows(nd, prec):
         want = op.Q_hat(x)
         assert rel_err(got, want) < TOL[prec], (prec, rel_err(got, want))
         ctx.close()
+
+
+def test_unit_links_and_near_unit_links(nd):
+    """The FP64 stencil reads SU(3) links in eight parameters unless some link's first
+    row is (u, 0, 0) to rounding (unit links): then it keeps the two-row form.  Both
+    paths against the oracle at 1e-12: unit links, and a field whose links are unit
+    except for one random SU(3) matrix per direction pattern (first rows far from
+    (u, 0, 0) only there)."""
+    dims = (4, 4, 2, 6)
+    print("unit and near-unit links", flush=True)
+    U1 = synth.unit_gauge(dims)
+    Ur = synth.gauge_field(dims, 29, 0.3)
+    mask = (np.arange(U1.shape[0]) % 3 == 0)
+    Um = np.where(mask[:, None, None, None], Ur, U1)
+    x = synth.gaussian_spinor(dims, 31)
+    for links in (U1, Um, Ur):
+        op = NDOperator(Lattice(dims, links), K, MB, EB)
+        ctx = nd.Context(dims)
+        ctx.ndtm_set_gauge(dev(links))
+        ctx.ndtm_set_params(K, MB, EB)
+        for opc, ref in ((nd.NDTM_OP_QHAT, op.Q_hat), (nd.NDTM_OP_HOP_EO, op.H_eo)):
+            got = host(ctx.ndtm_apply(opc, dev(x)))
+            assert rel_err(got, ref(x)) < 1e-12
+            assert site_err(got, ref(x)) < 1e-12
+        ctx.close()
