@@ -116,7 +116,7 @@ ProfScope::~ProfScope() {
 // per extra epilogue vector; P32H: FP16 links with FP32 fields
 static const double kHopBase[4] = {1920.0, 960.0, 488.0, 672.0}, kHopVec[4] = {384.0, 192.0, 100.0, 192.0};
 static double hop_epi_vectors(int epi) {
-  if (epi == EPI_QHAT || epi == EPI_SITE) return 1;
+  if (epi == EPI_QHAT || epi == EPI_SITE || epi == EPI_SITE_Q) return 1;
   if (epi == EPI_QHAT_SIG) return 2;
   return 0;
 }

@@ -666,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
         const cx<R> xo = shfl1(xv[s][c]);
         // y_f = M x_f + i mubar g5 tau3 x_f - epsbar x_{1-f} + hc acc_f (+ i ms g5 x_{1-f})
         cx<R> y = mx[s][c] + (mub * g5 * t3) * ipl(xv[s][c]) - eps * xo + hc * acc[s][c];
-        if constexpr (EPI == EPI_SITE) y = y + (ms * g5) * ipl(xo);
+        if constexpr (EPI == EPI_SITE || EPI == EPI_SITE_Q) y = y + (ms * g5) * ipl(xo);
         out[s][c] = y;
       }
     }
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void hop_kernel(HopArgs<S, L> A) {
           red_tt += valid ? ox * ox + oy * oy : 0.0;
         }
     }
-    if constexpr (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG) {
+    if constexpr (EPI == EPI_QHAT || EPI == EPI_QHAT_SIG || EPI == EPI_SITE_Q) {
       // Gamma5 tau1: out_f = g5 y_{1-f}
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -848,6 +848,9 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
     case EPI_SITE:
       if (red == RED_MR) NDTM_HOP(EPI_SITE, RED_MR);
       else NDTM_HOP(EPI_SITE, RED_NONE);
+      break;
+    case EPI_SITE_Q:
+      NDTM_HOP(EPI_SITE_Q, RED_NONE);
       break;
   }
 #undef NDTM_HOP

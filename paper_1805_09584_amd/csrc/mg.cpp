@@ -1067,18 +1067,18 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
     // (eq:g5tau1-hermiticity), then v = x / ||x||: inverse iteration towards the
     // smallest singular vectors, which span the near-null space the coarse grid
     // has to represent
-    Full Pp = full_field(c, "su_p", P64), W = full_field(c, "su_w", P64), T2 = full_field(c, "su_t2", P64);
-    if (!Pp.base || !W.base || !T2.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
+    Full Pp = full_field(c, "su_p", P64), W = full_field(c, "su_w", P64);
+    if (!Pp.base || !W.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
     const size_t nf2 = 2 * nh;
-    auto g5t1_full = [&](const Full& y, const Full& x) {
-      launch_g5t1(c->g, (const double2*)x.e.v, (double2*)y.e.v, st);
-      launch_g5t1(c->g, (const double2*)x.o.v, (double2*)y.o.v, st);
+    // y = Gamma5 tau1 D x (Hermitian), Gamma5 tau1 taken in the stencil's site epilogue;
+    // D^+ D = (Gamma5 tau1 D)^2
+    auto apply_q = [&](const Full& y, const Full& x) {
+      hop(c, P64, EPI_SITE_Q, RED_NONE, 0, x.o, y.e, &x.e, nullptr, 0.0, -0.5, 0, nullptr, st);
+      hop(c, P64, EPI_SITE_Q, RED_NONE, 1, x.e, y.o, &x.o, nullptr, 0.0, -0.5, 0, nullptr, st);
     };
     auto apply_normal = [&](const Full& w, const Full& v) {
-      apply_dfull(c, P64, Tt.e, Tt.o, v.e, v.o, 0.0, st);
-      g5t1_full(T2, Tt);
-      apply_dfull(c, P64, Tt.e, Tt.o, T2.e, T2.o, 0.0, st);
-      g5t1_full(w, Tt);
+      apply_q(Tt, v);
+      apply_q(w, Tt);
     };
     for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
       for (int i = 0; i < nf; ++i) {

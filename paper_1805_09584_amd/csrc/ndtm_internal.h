@@ -64,7 +64,8 @@ enum Epi {
   EPI_AINV = 1,    // out = A^-1 H in
   EPI_QHAT = 2,    // out = Gamma5 tau1 (A xs - 1/4 H in)
   EPI_QHAT_SIG = 3,// out = Gamma5 tau1 (A xs - 1/4 H in) + sigma zs
-  EPI_SITE = 4     // out = (A + i ms Gamma5 tau1) xs + hop_coef H in
+  EPI_SITE = 4,    // out = (A + i ms Gamma5 tau1) xs + hop_coef H in
+  EPI_SITE_Q = 5   // out = Gamma5 tau1 [(A + i ms Gamma5 tau1) xs + hop_coef H in]
 };
 // RED_MR (site epilogue): per block, <out, x> (complex) and ||out||^2 over the block's
 // sites, with x the site vector the epilogue reads; stored at partials[q * 2 nblk + b]

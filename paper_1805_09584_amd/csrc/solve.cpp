@@ -507,7 +507,9 @@ int ndtm_solve(ndtm_ctx* c, void* const* x_dev, const void* b_dev, const ndtm_so
       // most half of the device memory that is free or already the region's; in a caller
       // region it takes the larger of its current block and the largest free one
       const size_t own = ws_bytes(c, "sv_region");
-      const size_t avail = (c->arena ? std::max(own, dev_largest_free(c)) : (own + dev_largest_free(c)) / 2) / fb;
+      size_t avail = (c->arena ? std::max(own, dev_largest_free(c)) : (own + dev_largest_free(c)) / 2) / fb;
+      // the fields the region holds anyway (its current size, the multigrid phase's) are the ring's too
+      avail = std::max(avail, std::max(own / fb, mg_fields));
       const size_t fixed = (size_t)(n_ps - 1);
       if (defer && fixed + defer > avail) defer = avail > fixed + 2 ? (int)(avail - fixed) : 0;
     }
