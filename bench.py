@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--mg-pair", type=int, default=1, help="case C's two signs in lock-step (needs FP64 coarse blocks)")
     ap.add_argument("--mg-prec", type=int, default=2, help="multigrid cycle precision (2: FP16 storage)")
     ap.add_argument("--mg-eo", type=int, default=1, help="even-odd coarsest level in the single-sign cycles")
+    ap.add_argument("--mlp-weights", default=None,
+                    help="weights of the learned guess proposer (.npz, key 'w'; default: the shipped ones)")
     return ap.parse_args()
 
 
@@ -324,7 +326,7 @@ def main():
         torch.cuda.synchronize()
         setup_ms = 1000.0 * (time.perf_counter() - t0)
         log(f"multigrid setup {setup_ms / 1000:.1f} s")
-    weights = nd.trained_weights_path()
+    weights = args.mlp_weights or nd.trained_weights_path()
     if any(f in ("full", "full_f64") for f in forms):
         if weights and os.path.exists(weights):
             ctx.ndtm_mlp_set_weights(np.load(weights)["w"])
@@ -383,6 +385,7 @@ def main():
         "mg_setup_ms": setup_ms,
         "mg_cycle": {"precision": args.mg_prec, "pair_signs": args.mg_pair, "coarse_eo": args.mg_eo},
         "fgmres_restart": restart or 16,
+        "mlp_weights": os.path.basename(weights) if any(f in ("full", "full_f64") for f in forms) else None,
         "set_gauge_ms": set_gauge_ms,
         "device_storage_gb": {"live": mem["live"] / 1e9, "peak": mem["peak"] / 1e9},
     }

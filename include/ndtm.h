@@ -108,9 +108,12 @@ long long ndtm_half_volume(const ndtm_ctx* ctx);
 /* Copies and repacks the gauge field (eq:Wilson's U_mu(x)) from U_dev
  * (complex128 [V][4][3][3], device).  FP32 and FP16 copies for the mixed form
  * are made at the same time.  If every link's third row equals
- * conj(row 0 x row 1) to 1e-14 (SU(3) links), the stencil loads two rows per
- * link and rebuilds the third; otherwise it loads all three.  Any complex 3x3
- * links are accepted.  Synchronises the stream; invalidates any multigrid
+ * conj(row 0 x row 1) to 1e-14 (SU(3) links), the stencil rebuilds the third
+ * row: the FP32 and FP16 stencils load two rows per link, the FP64 stencil loads
+ * eight parameters per link (two entries of row 0, one of the first column, two
+ * phases) and rebuilds the rest, unless some |U_00|^2 + |U_0j|^2 falls below
+ * 1e-20, when it loads two rows as well.  Otherwise all three rows are loaded.
+ * Any complex 3x3 links are accepted.  Synchronises the stream; invalidates any multigrid
  * setup. */
 int ndtm_set_gauge(ndtm_ctx* ctx, const void* U_dev, void* stream);
 
