@@ -205,7 +205,19 @@ typedef struct {
                           several coarse systems share the coarse blocks; FP64 coarse GMRES on the
                           full coarse system).  Needs the FP64 coarse blocks (keep_f64 = 1); without
                           them, or with 0, one sign after the other */
+  int smoother;        /* NDTM_SMOOTH_MR (default): smooth_iters minimal-residual steps on the whole
+                          lattice.  NDTM_SMOOTH_SAP: smooth_iters sweeps of the Schwarz alternating
+                          procedure (section 3, eq:error_propagation's smoother M): the aggregates
+                          as blocks in two colours, each block system D'_B e = s_B solved by
+                          sap_mr_iters minimal-residual steps, the residual formed again after
+                          each colour.  SAP needs even aggregate extents, an even number of
+                          aggregates per direction, 64, 128 or 256 sites per aggregate, and no
+                          clover term */
+  int sap_mr_iters;    /* minimal-residual steps per block solve of SAP (default 4, >= 1) */
 } ndtm_mg_params;
+
+#define NDTM_SMOOTH_MR 0
+#define NDTM_SMOOTH_SAP 1
 
 /* Fills *p with the defaults (4^4 aggregates, 24 vectors, ...). */
 void ndtm_mg_default_params(ndtm_mg_params* p);
@@ -218,6 +230,14 @@ void ndtm_mg_default_params(ndtm_mg_params* p);
  * aggregate and chirality the vectors are orthonormalised (Gram-Schmidt in
  * vector order).  Synchronises the stream. */
 int ndtm_mg_setup(ndtm_ctx* ctx, const ndtm_mg_params* p, const void* test_vectors_dev, void* stream);
+
+/* z <- the cycle's post-smoother applied to D'(m) z = r (section 3: the smoother M of
+ * eq:error_propagation, started from z as the cycle starts it from the coarse correction),
+ * with D'(m) = D_ND + i m (Gamma5 x tau1) on odd sites: smooth_iters minimal-residual steps
+ * or SAP sweeps as the setup chose, in the cycle's precision.  z_dev, r_dev: full-lattice
+ * doublets, complex128 [V][2 flavour][4 spin][3 colour] canonical order, device, distinct;
+ * z_dev is read and overwritten.  ESTATE without a multigrid setup. */
+int ndtm_mg_smooth(ndtm_ctx* ctx, void* z_dev, const void* r_dev, double m, void* stream);
 
 /* Coarse vector layout: complex128 [Vc][2 flavour][2 N_v], dof = chi*N_v + k. */
 long long ndtm_mg_coarse_volume(const ndtm_ctx* ctx);

@@ -21,9 +21,11 @@ from .binding import (  # noqa: F401
     NDTM_OP_QHAT2,
     NDTM_OP_SHAT_SHIFT,
     NDTM_PREC_F16,
-    NDTM_PREC_F32_H16,
     NDTM_PREC_F32,
+    NDTM_PREC_F32_H16,
     NDTM_PREC_F64,
+    NDTM_SMOOTH_MR,
+    NDTM_SMOOTH_SAP,
     Context,
     NdtmError,
     PROF_CLASSES,

@@ -15,6 +15,7 @@ NDTM_PREC_F64, NDTM_PREC_F32, NDTM_PREC_F16, NDTM_PREC_F32_H16 = 0, 1, 2, 3
 (NDTM_OP_QHAT, NDTM_OP_QHAT2, NDTM_OP_SHAT_SHIFT, NDTM_OP_DFULL, NDTM_OP_HOP_EO,
  NDTM_OP_HOP_OE) = range(6)
 NDTM_NMMS_AUTO = -1
+NDTM_SMOOTH_MR, NDTM_SMOOTH_SAP = 0, 1
 NDTM_GUESS_ZERO, NDTM_GUESS_LAGRANGE, NDTM_GUESS_MLP, NDTM_GUESS_PROJECTION, NDTM_GUESS_MMS = 0, 1, 2, 3, 4
 PROF_CLASSES = ("hop_f64", "hop_f32", "hop_f16", "mms_update", "mms_resid", "restrict", "prolong",
                 "coarse")
@@ -37,7 +38,7 @@ class MGParams(C.Structure):
                 ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
                 ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int), ("coarse_eo", C.c_int),
-                ("keep_f64", C.c_int), ("pair_signs", C.c_int)]
+                ("keep_f64", C.c_int), ("pair_signs", C.c_int), ("smoother", C.c_int), ("sap_mr_iters", C.c_int)]
 
 
 class SolveParams(C.Structure):
@@ -104,6 +105,7 @@ def load_library():
         "ndtm_mg_restrict": (i, [vp, vp, vp, vp]),
         "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
         "ndtm_mg_transfer_cycle": (i, [vp, i, vp, vp, vp]),
+        "ndtm_mg_smooth": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
@@ -312,6 +314,13 @@ class Context:
         else:
             out = torch.empty((self.V, 2, 4, 3), dtype=torch.complex128, device=x.device)
         self._check(self.lib.ndtm_mg_transfer_cycle(self.h, int(direction), _ptr(out), _ptr(x), _stream()))
+        return out
+
+    def ndtm_mg_smooth(self, z, r, m=0.0):
+        """The cycle's post-smoother on D'(m) z = r from z (full-lattice doublets); returns the
+        smoothed z (a new tensor; the argument is not changed)."""
+        out = z.clone()
+        self._check(self.lib.ndtm_mg_smooth(self.h, _ptr(out), _ptr(r), float(m), _stream()))
         return out
 
     def ndtm_mg_coarse_apply(self, xc, m=0.0):

@@ -284,8 +284,37 @@ struct Raw {
   float sc;
 };
 
-// R8 (FP64, SU(3) links): U points at the eight-parameter link arrays, four complex
-// words per link (see launch_pack_r8)
+// The link of one hop in storage precision at half-site hl of link array U: rows 0-1
+// (components 0..5) always, row 2 too without R12 (then rebuilt in hop_compute); R8
+// (FP64, SU(3) links): U points at the eight-parameter arrays, four complex words per
+// link (see launch_pack_r8).  The links group by their own storage (FP32 links with FP32
+// fields, FP16 links with FP16 or FP32 fields).
+template <int MU, bool R12, bool R8, class S, class L>
+__device__ __forceinline__ void load_link(Raw<S, L>& r, const L* U, int stride, int hl) {
+  if constexpr (kGrouped<S>) {
+    const unsigned vl = (unsigned)hl * 16u;
+    constexpr int GL = kG<L>;
+    constexpr int NLG = R12 ? (6 + GL - 1) / GL : 8 / GL;
+#pragma unroll
+    for (int g = 0; g < NLG; ++g) {
+      const Grp<L> u = ld_group<true>(U, (8 / GL) * MU + g, stride, vl);
+#pragma unroll
+      for (int q = 0; q < GL; ++q)
+        if (GL * g + q < 9) r.u[GL * g + q] = u.e[q];
+    }
+    if constexpr (!R12) r.u[8] = ld_nt(at(U, (long)(32 + MU) * stride, (unsigned)hl * (unsigned)sizeof(L)));
+  } else {
+    const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
+    if constexpr (R8) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 4 + k) * stride, vl));
+    } else {
+#pragma unroll
+      for (int k = 0; k < (R12 ? 6 : 9); ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * stride, vl));
+    }
+  }
+}
+
 template <int MU, bool R12, bool R8, class S, class L>
 __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, int f, int hn, const L* U,
                                          int hl) {
@@ -299,33 +328,12 @@ __device__ __forceinline__ void load_raw(Raw<S, L>& r, const HopArgs<S, L>& A, i
       for (int q = 0; q < G; ++q) r.p[G * g + q] = u.e[q];
     }
     if constexpr (kHalf<S>) r.sc = A.in_sc[hn];
-    const unsigned vl = (unsigned)hl * 16u;
-    // rows 0-1 (components 0..5) always; with R12 row 2 is rebuilt in hop_compute.  The
-    // links group by their own storage (FP32 links with FP32 fields, FP16 links with
-    // FP16 or FP32 fields)
-    constexpr int GL = kG<L>;
-    constexpr int NLG = R12 ? (6 + GL - 1) / GL : 8 / GL;
-#pragma unroll
-    for (int g = 0; g < NLG; ++g) {
-      const Grp<L> u = ld_group<true>(U, (8 / GL) * MU + g, A.stride, vl);
-#pragma unroll
-      for (int q = 0; q < GL; ++q)
-        if (GL * g + q < 9) r.u[GL * g + q] = u.e[q];
-    }
-    if constexpr (!R12) r.u[8] = ld_nt(at(U, (long)(32 + MU) * A.stride, (unsigned)hl * (unsigned)sizeof(L)));
   } else {
     const unsigned vo = flav_off<S>(f, A.stride, hn);
 #pragma unroll
     for (int k = 0; k < 12; ++k) r.p[k] = *at(A.in, (long)k * A.stride, vo);
-    const unsigned vl = (unsigned)hl * (unsigned)sizeof(L);
-    if constexpr (R8) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) r.u[k] = ld_nt(at(U, (long)(MU * 4 + k) * A.stride, vl));
-    } else {
-#pragma unroll
-      for (int k = 0; k < (R12 ? 6 : 9); ++k) r.u[k] = ld_nt(at(U, (long)(MU * 9 + k) * A.stride, vl));
-    }
   }
+  load_link<MU, R12, R8>(r, U, A.stride, hl);
 }
 
 // One of the eight hops: project, colour-multiply, reconstruct, accumulate.
@@ -856,6 +864,235 @@ void launch_typed(int epi, int red, const Geom& g, int parity, const OpParams& o
 #undef NDTM_HOP
 }
 
+// ---- Schwarz alternating procedure (section 3's smoother): block solves of one colour ----
+// One work-group per block of the given colour, two lanes per site (one per flavour) as in
+// the stencil.  The block's residual s_B stays in LDS while mr_iters minimal-residual steps
+//   q = D'_B s_B,  w = <q, s_B> / <q, q>,  e += w s_B,  s_B -= w q
+// run on it, with D'_B the full-lattice operator D' = a + i mubar g5 tau3 - epsbar tau1 +
+// hop_coef H (+ i ms g5 tau1 on odd sites) restricted to the block: hops that leave the
+// block are dropped.  Then z += e at the block's sites.  The blocks of one colour do not
+// touch each other (the block grid has even extents), so they run side by side.
+//
+// Block extents are even, so a block starts on an even site and holds NS/2 sites of each
+// parity.  The work-group takes the even sites first, then the odd ones (local half-site
+// order, x fastest): every wavefront then serves one parity, and the link arrays and fields
+// of that parity are wave-uniform (scalar base plus a 32-bit lane offset, as in the stencil).
+
+template <class S, class L>
+struct SapArgs {
+  const S* s[2];  // residual, parity halves
+  S* z[2];        // iterate, parity halves
+  const L* U[2];  // links per parity (nine components, or two rows with R12)
+  int Lz, Ly, Lx, stride;
+  int bt, bz, by, bx;
+  int nbz, nby, nbxh;  // blocks per direction in z and y; half the blocks in x
+  int colour, mr_iters;
+  double a, mubar, epsbar, ms, hop_coef;
+};
+
+template <class R, class S>
+__device__ __forceinline__ S to_store(cx<R> v) {
+  if constexpr (std::is_same<S, double2>::value) return make_double2(v.x, v.y);
+  else return make_float2(v.x, v.y);
+}
+
+// one hop of the block operator: the neighbour's s_B from LDS, the link from memory
+template <int MU, bool FWD, bool R12, int NS, class S, class L, class R>
+__device__ __forceinline__ void sap_hop(cx<R> (&acc)[4][3], const S* ls, int f, int jn, const L* U, int stride,
+                                        int hl) {
+  Raw<S, L> raw;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) raw.p[k] = ls[(f * 12 + k) * NS + jn];
+  raw.sc = 1.0f;
+  load_link<MU, R12, false>(raw, U, stride, hl);
+  hop_compute<MU, FWD, false, R12, false>(acc, raw, R(1));
+}
+
+template <class S, class L, bool R12, int NS>
+__global__ __launch_bounds__(2 * NS) void sap_block_kernel(SapArgs<S, L> A) {
+  using R = typename RealOf<S>::T;
+  // s_B: component k of flavour f at local site j in ls[(f * 12 + k) * NS + j]
+  __shared__ S ls[24 * NS];
+  __shared__ double wred[3][2 * NS / 64];
+  const int f = threadIdx.x & 1, j = threadIdx.x >> 1;
+  // the work-group's block among those of this colour, x fastest
+  int rest = blockIdx.x;
+  const int jx = rest % A.nbxh;
+  rest /= A.nbxh;
+  const int By = rest % A.nby;
+  rest /= A.nby;
+  const int Bz = rest % A.nbz, Bt = rest / A.nbz;
+  const int Bx = 2 * jx + ((A.colour + Bt + Bz + By) & 1);
+  // this lane's site: parity (uniform over the wavefront), then local half-site order
+  constexpr int NH = NS / 2;
+  const int par = __builtin_amdgcn_readfirstlane(j / NH);
+  const int bxh = A.bx >> 1;
+  const int jh = j - par * NH;
+  const int lxh = jh % bxh, ly = (jh / bxh) % A.by, lz = (jh / (bxh * A.by)) % A.bz;
+  const int lt = jh / (bxh * A.by * A.bz);
+  const int lx = 2 * lxh + ((lt + lz + ly + par) & 1);
+  const int t = Bt * A.bt + lt, z = Bz * A.bz + lz, y = By * A.by + ly, x = Bx * A.bx + lx;
+  const int Lxh = A.Lx >> 1;
+  auto half = [&](int tt, int zz, int yy, int xx) { return ((tt * A.Lz + zz) * A.Ly + yy) * Lxh + (xx >> 1); };
+  const int h = half(t, z, y, x);
+  // neighbours inside the block: local index in the other parity's half (-1 outside)
+  const int op = (1 - par) * NH;
+  auto loc = [&](int a, int b, int c, int d) { return op + ((a * A.bz + b) * A.by + c) * bxh + (d >> 1); };
+  const int jtp = lt + 1 < A.bt ? loc(lt + 1, lz, ly, lx) : -1, jtm = lt > 0 ? loc(lt - 1, lz, ly, lx) : -1;
+  const int jxp = lx + 1 < A.bx ? loc(lt, lz, ly, lx + 1) : -1, jxm = lx > 0 ? loc(lt, lz, ly, lx - 1) : -1;
+  const int jyp = ly + 1 < A.by ? loc(lt, lz, ly + 1, lx) : -1, jym = ly > 0 ? loc(lt, lz, ly - 1, lx) : -1;
+  const int jzp = lz + 1 < A.bz ? loc(lt, lz + 1, ly, lx) : -1, jzm = lz > 0 ? loc(lt, lz - 1, ly, lx) : -1;
+  const int htm = lt > 0 ? half(t - 1, z, y, x) : 0, hxm = lx > 0 ? half(t, z, y, x - 1) : 0;
+  const int hym = ly > 0 ? half(t, z, y - 1, x) : 0, hzm = lz > 0 ? half(t, z - 1, y, x) : 0;
+  const L* Uo = par ? A.U[1] : A.U[0];
+  const L* Ui = par ? A.U[0] : A.U[1];
+  const S* sv = par ? A.s[1] : A.s[0];
+  S* zp = par ? A.z[1] : A.z[0];
+
+  cx<R> r[4][3], e[4][3];
+  load_flav<S, R>(r, sv, nullptr, f, A.stride, h);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e[sp][c] = {0, 0};
+      ls[(f * 12 + sp * 3 + c) * NS + j] = to_store<R, S>(r[sp][c]);
+    }
+  const R a = R(A.a), mub = R(A.mubar), eps = R(A.epsbar), hc = R(A.hop_coef);
+  const R ms = par ? R(A.ms) : R(0);
+  const R t3 = f == 0 ? R(1) : R(-1);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int it = 0; it < A.mr_iters; ++it) {
+    __syncthreads();
+    cx<R> acc[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[sp][c] = {0, 0};
+    if (jtp >= 0) sap_hop<0, true, R12, NS>(acc, ls, f, jtp, Uo, A.stride, h);
+    if (jtm >= 0) sap_hop<0, false, R12, NS>(acc, ls, f, jtm, Ui, A.stride, htm);
+    if (jxp >= 0) sap_hop<1, true, R12, NS>(acc, ls, f, jxp, Uo, A.stride, h);
+    if (jxm >= 0) sap_hop<1, false, R12, NS>(acc, ls, f, jxm, Ui, A.stride, hxm);
+    if (jyp >= 0) sap_hop<2, true, R12, NS>(acc, ls, f, jyp, Uo, A.stride, h);
+    if (jym >= 0) sap_hop<2, false, R12, NS>(acc, ls, f, jym, Ui, A.stride, hym);
+    if (jzp >= 0) sap_hop<3, true, R12, NS>(acc, ls, f, jzp, Uo, A.stride, h);
+    if (jzm >= 0) sap_hop<3, false, R12, NS>(acc, ls, f, jzm, Ui, A.stride, hzm);
+    // site terms, then <q, s_B> and <q, q>
+    cx<R> q[4][3];
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+      const R g5 = sp < 2 ? R(1) : R(-1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cx<R> xo = shfl1(r[sp][c]);
+        q[sp][c] = a * r[sp][c] + (mub * g5 * t3) * ipl(r[sp][c]) - eps * xo + hc * acc[sp][c] + (ms * g5) * ipl(xo);
+        const double qx = double(q[sp][c].x), qy = double(q[sp][c].y);
+        const double rx = double(r[sp][c].x), ry = double(r[sp][c].y);
+        v0 += qx * rx + qy * ry;
+        v1 += qx * ry - qy * rx;
+        v2 += qx * qx + qy * qy;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      v0 += __shfl_xor(v0, off);
+      v1 += __shfl_xor(v1, off);
+      v2 += __shfl_xor(v2, off);
+    }
+    if (lane == 0) {
+      wred[0][wv] = v0;
+      wred[1][wv] = v1;
+      wred[2][wv] = v2;
+    }
+    __syncthreads();
+    double qs_re = 0.0, qs_im = 0.0, qq = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2 * NS / 64; ++i) {
+      qs_re += wred[0][i];
+      qs_im += wred[1][i];
+      qq += wred[2][i];
+    }
+    if (!(qq > 0.0)) break;  // the same sums in every lane: the whole work-group leaves
+    const cx<R> w = {R(qs_re / qq), R(qs_im / qq)};
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e[sp][c] = e[sp][c] + mul(w, r[sp][c]);
+        r[sp][c] = r[sp][c] - mul(w, q[sp][c]);
+        ls[(f * 12 + sp * 3 + c) * NS + j] = to_store<R, S>(r[sp][c]);
+      }
+  }
+  // z += e
+  cx<R> zv[4][3];
+  load_flav<S, R>(zv, zp, nullptr, f, A.stride, h);
+  if constexpr (kGrouped<S>) {
+    constexpr int G = kG<S>;
+    const unsigned vo = group_off<S>(f, A.stride, h);
+#pragma unroll
+    for (int g = 0; g < 12 / G; ++g) {
+      Grp<S> u;
+#pragma unroll
+      for (int qi = 0; qi < G; ++qi) {
+        const int k = G * g + qi;
+        u.e[qi] = to_store<R, S>(zv[k / 3][k % 3] + e[k / 3][k % 3]);
+      }
+      *reinterpret_cast<v4u*>(reinterpret_cast<char*>(zp + (long)g * A.stride * G) + vo) = u.w;
+    }
+  } else {
+    const unsigned vo = flav_off<S>(f, A.stride, h);
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) *at(zp, (long)(sp * 3 + c) * A.stride, vo) = to_store<R, S>(zv[sp][c] + e[sp][c]);
+  }
+}
+
+template <class S, class L, bool R12>
+void launch_sap_ns(int ns, int nblk, const SapArgs<S, L>& A, hipStream_t st) {
+  switch (ns) {
+    case 64: hipLaunchKernelGGL((sap_block_kernel<S, L, R12, 64>), dim3(nblk), dim3(128), 0, st, A); break;
+    case 128: hipLaunchKernelGGL((sap_block_kernel<S, L, R12, 128>), dim3(nblk), dim3(256), 0, st, A); break;
+    default: hipLaunchKernelGGL((sap_block_kernel<S, L, R12, 256>), dim3(nblk), dim3(512), 0, st, A); break;
+  }
+}
+
+template <class S, class L>
+void launch_sap_typed(const Geom& g, const int block[4], int colour, int mr_iters, const OpParams& op,
+                      const void* U0, const void* U1, const HalfField& s_e, const HalfField& s_o,
+                      const HalfField& z_e, const HalfField& z_o, double ms, double hop_coef, hipStream_t st) {
+  SapArgs<S, L> A;
+  A.s[0] = static_cast<const S*>(s_e.v);
+  A.s[1] = static_cast<const S*>(s_o.v);
+  A.z[0] = static_cast<S*>(z_e.v);
+  A.z[1] = static_cast<S*>(z_o.v);
+  A.U[0] = static_cast<const L*>(U0);
+  A.U[1] = static_cast<const L*>(U1);
+  A.Lz = g.Lz;
+  A.Ly = g.Ly;
+  A.Lx = g.Lx;
+  A.stride = g.stride;
+  A.bt = block[0];
+  A.bz = block[1];
+  A.by = block[2];
+  A.bx = block[3];
+  A.nbz = g.Lz / block[1];
+  A.nby = g.Ly / block[2];
+  A.nbxh = g.Lx / block[3] / 2;
+  A.colour = colour;
+  A.mr_iters = mr_iters;
+  A.a = op.a;
+  A.mubar = op.mubar;
+  A.epsbar = op.epsbar;
+  A.ms = ms;
+  A.hop_coef = hop_coef;
+  const int ns = block[0] * block[1] * block[2] * block[3];
+  const int nblk = (g.T / block[0]) * A.nbz * A.nby * A.nbxh;
+  if (op.recon12) launch_sap_ns<S, L, true>(ns, nblk, A, st);
+  else launch_sap_ns<S, L, false>(ns, nblk, A, st);
+}
+
 }  // namespace
 
 int hop_grid(const Geom& g) { return (g.vh + kSitesPerBlock - 1) / kSitesPerBlock; }
@@ -880,6 +1117,37 @@ void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpP
     default:
       launch_typed<__half2, __half2>(epi, red, g, parity, op, Uo, Ui, in, out, xs, zs, ms, hop_coef,
                                      sigma, partials, st);
+      break;
+  }
+}
+
+bool sap_block_ok(const Geom& g, const int block[4]) {
+  const int ext[4] = {g.T, g.Lz, g.Ly, g.Lx};
+  int n = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    // even block extents (blocks start on even sites) and an even number of blocks
+    if (block[mu] < 2 || block[mu] % 2 != 0 || ext[mu] % block[mu] != 0 || (ext[mu] / block[mu]) % 2 != 0)
+      return false;
+    n *= block[mu];
+  }
+  // 64, 128 or 256 sites: each parity fills whole wavefronts
+  return n == 64 || n == 128 || n == 256;
+}
+
+void launch_sap_block(int prec, const Geom& g, const int block[4], int colour, int mr_iters, const OpParams& op,
+                      const void* U0, const void* U1, const HalfField& s_e, const HalfField& s_o,
+                      const HalfField& z_e, const HalfField& z_o, double ms, double hop_coef, hipStream_t st) {
+  switch (prec) {
+    case P64:
+      launch_sap_typed<double2, double2>(g, block, colour, mr_iters, op, U0, U1, s_e, s_o, z_e, z_o, ms, hop_coef, st);
+      break;
+    case P32:
+      launch_sap_typed<float2, float2>(g, block, colour, mr_iters, op, U0, U1, s_e, s_o, z_e, z_o, ms, hop_coef, st);
+      break;
+    case P32H:
+      launch_sap_typed<float2, __half2>(g, block, colour, mr_iters, op, U0, U1, s_e, s_o, z_e, z_o, ms, hop_coef, st);
+      break;
+    default:
       break;
   }
 }

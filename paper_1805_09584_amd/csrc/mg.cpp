@@ -331,6 +331,9 @@ static void dprime_mr(ndtm_ctx* c, int prec, const Full& y, const Full& x, doubl
 // smooth_iters minimal-residual steps.  The fine operator is the one in c->op
 // (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
 // post-smoothing: smooth_iters minimal-residual steps on D'(m) z = r from the coarse correction in Z
+// With SAP (section 3's smoother): smooth_iters sweeps; in each, the blocks of colour 0 and
+// then of colour 1 solve D'_B e = s_B by minimal-residual steps in the block kernel, with the
+// residual S = R - D'Z formed again before each colour but the first.
 static void mg_smooth(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, hipStream_t st) {
   const int cp = M->cprec;
   const size_t nh = half_elems(c);
@@ -339,6 +342,19 @@ static void mg_smooth(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
   Full S = full_field(c, "mg_S", cp), Tt = full_field(c, "mg_T", cp);
   dprime(c, M->sprec, S, Z, m, st);
   vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);  // S = R - D'Z
+  if (M->prm.smoother == NDTM_SMOOTH_SAP) {
+    const int lp = M->sprec == P32H ? P16 : M->sprec;
+    for (int sw = 0; sw < nu; ++sw)
+      for (int col = 0; col < 2; ++col) {
+        if (sw + col > 0) {
+          dprime(c, M->sprec, S, Z, m, st);
+          vaxpby(cp, S.base, make_double2(1, 0), R.base, make_double2(-1, 0), 2 * nh, st);
+        }
+        launch_sap_block(M->sprec, c->g, M->prm.block, col, M->prm.sap_mr_iters, c->op, c->U[lp][0], c->U[lp][1],
+                         S.e, S.o, Z.e, Z.o, m, -0.5, st);
+      }
+    return;
+  }
   for (int it = 0; it < nu; ++it) {
     // T = D' S with <T, S>, ||T||^2 reduced in the stencil epilogue; the update
     // kernel forms omega from those partials
@@ -1186,6 +1202,8 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->coarse_eo = 1;
   p->pair_signs = 1;
   p->keep_f64 = 1;
+  p->smoother = NDTM_SMOOTH_MR;
+  p->sap_mr_iters = 4;
 }
 
 int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* stream) {
@@ -1209,6 +1227,16 @@ int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* st
     return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
   if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32 && p->precision != NDTM_PREC_F16)
     return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64, F32 or F16");
+  if (p->smoother != NDTM_SMOOTH_MR && p->smoother != NDTM_SMOOTH_SAP)
+    return fail(c, NDTM_EINVAL, "mg_setup: smoother must be MR or SAP");
+  if (p->smoother == NDTM_SMOOTH_SAP) {
+    if (p->sap_mr_iters < 1) return fail(c, NDTM_EINVAL, "mg_setup: sap_mr_iters >= 1");
+    if (!sap_block_ok(c->g, p->block))
+      return fail(c, NDTM_EINVAL,
+                  "mg_setup: SAP needs even aggregate extents, an even number of aggregates per direction "
+                  "and 64, 128 or 256 sites per aggregate");
+    if (c->op.clover) return fail(c, NDTM_EINVAL, "mg_setup: SAP blocks without the clover term only");
+  }
   NDTM_HIP(c, hipSetDevice(c->device));
   const int rc = mg_build(c, p, tv, static_cast<hipStream_t>(stream));
   if (rc != NDTM_OK) ndtm_mg_free(c);
@@ -1264,6 +1292,26 @@ int ndtm_mg_transfer_cycle(ndtm_ctx* c, int dir, void* out, const void* in, void
     vconvert_field(P64, F64.base, cp, Fc.base, 2, c->g.vh, c->g.stride, st);
     launch_unpack_full(c->g, F64.e, F64.o, static_cast<double2*>(out), st);
   }
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
+int ndtm_mg_smooth(ndtm_ctx* c, void* z, const void* r, double m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_smooth: no multigrid setup");
+  if (!z || !r || z == r) return fail(c, NDTM_EINVAL, "mg_smooth: null or aliased pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MGData* M = c->mg;
+  const int cp = M->cprec;
+  Full F64 = full_field(c, "ab_f", P64), Rc = full_field(c, "ab_fc", cp), Zc = full_field(c, "ab_fz", cp);
+  if (!F64.e.v || !Rc.e.v || !Zc.e.v) return fail(c, NDTM_ENOMEM, "mg_smooth: workspace");
+  launch_pack_full(c->g, static_cast<const double2*>(r), F64.e, F64.o, st);
+  vconvert_field(cp, Rc.base, P64, F64.base, 2, c->g.vh, c->g.stride, st);
+  launch_pack_full(c->g, static_cast<const double2*>(z), F64.e, F64.o, st);
+  vconvert_field(cp, Zc.base, P64, F64.base, 2, c->g.vh, c->g.stride, st);
+  mg_smooth(c, M, Rc, Zc, m, st);
+  vconvert_field(P64, F64.base, cp, Zc.base, 2, c->g.vh, c->g.stride, st);
+  launch_unpack_full(c->g, F64.e, F64.o, static_cast<double2*>(z), st);
   NDTM_HIP(c, hipGetLastError());
   return NDTM_OK;
 }

@@ -108,6 +108,18 @@ void launch_hop(int prec, int epi, int red, const Geom& g, int parity, const OpP
                 double sigma, double* partials, hipStream_t st);
 int hop_grid(const Geom& g);
 
+// Schwarz alternating procedure: the block solves of one colour (section 3's smoother).
+// Blocks of block[] sites tile the lattice with an even number per direction and hold a
+// multiple of 32 sites, at most 256 (sap_block_ok).  For every block B of colour `colour`
+// (parity of the sum of its block coordinates): mr_iters minimal-residual steps on
+// D'_B e = s_B from e = 0, D' = a + i mubar g5 tau3 - epsbar tau1 + hop_coef H (+ i ms g5 tau1
+// on odd sites) restricted to B, then z += e.  prec: P64, P32 or P32H (FP32 fields on FP16
+// links); U0, U1 the links of the even and odd sites in that stencil's storage.
+bool sap_block_ok(const Geom& g, const int block[4]);
+void launch_sap_block(int prec, const Geom& g, const int block[4], int colour, int mr_iters, const OpParams& op,
+                      const void* U0, const void* U1, const HalfField& s_e, const HalfField& s_o,
+                      const HalfField& z_e, const HalfField& z_o, double ms, double hop_coef, hipStream_t st);
+
 // Clover site blocks of one parity from the FP64 links (kern_clover.hip); Ninv only for the
 // even parity.  bad counts blocks M^2 + mubar^2 - epsbar^2 that could not be inverted.
 void launch_clover_build(const Geom& g, const double2* Ue, const double2* Uo, int parity, double a, double csw,

@@ -1,0 +1,119 @@
+"""The multigrid cycle's post-smoothers (ndtm_mg_smooth) against the oracle's
+(oracle/smoothers.py, pinned in test_oracle_smoothers.py).
+
+* Minimal-residual steps on the whole lattice and SAP sweeps (the aggregates as blocks in
+  two colours, minimal-residual block solves), each from a nonzero start z0 and for both
+  signs of the odd-site shift m, on 8^4 with 4^4 blocks and on 16^3x32: within FP64
+  rounding with the FP64 cycle (1e-12), within FP32 rounding with the FP32 cycle (2e-5),
+  and within FP16 link rounding with the FP16-storage cycle (5e-3, and visibly above FP32
+  rounding).
+* Blocks of 4x4x2x2 sites (64 per block) and 4x4x4x2 (128): the other work-group shapes.
+* A hybrid solve at 16^3x32 with the SAP smoother and the FP16-storage cycle, without
+  predicted guesses, so the three smallest shifts run through the multigrid: every shift's
+  true residual (oracle) <= 1e-10 and the multigrid shifts solved by the multigrid.
+* SAP setups the block kernel cannot serve are refused.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import smoothers as osm
+from oracle.lattice import Lattice, NDOperator, rel_residual
+from tests.gpu_util import dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+K, MB, EB = synth.KAPPA, synth.MUBAR, synth.EPSBAR
+TOL = {0: 1e-12, 1: 2e-5, 2: 5e-3}
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import paper_1805_09584_amd as nd
+    return nd
+
+
+def _run(nd, dims, block, prec, smoother, sweeps, mr, m, seed=31):
+    U = synth.gauge_field(dims, seed, 0.3)
+    V = int(np.prod(dims))
+    tv = synth.gaussian_vectors((8, V, 4, 3), seed + 1)
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=8, precision=prec, keep_f64=1, smoother=smoother,
+                                    smooth_iters=sweeps, sap_mr_iters=mr), test_vectors=dev(tv))
+    r = synth.gaussian_spinor(dims, seed + 2, "full")
+    z0 = 0.1 * synth.gaussian_spinor(dims, seed + 3, "full")
+    got = host(ctx.ndtm_mg_smooth(dev(z0), dev(r), m))
+    ctx.close()
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    sh = dims + (2, 4, 3)
+    if smoother == nd.NDTM_SMOOTH_SAP:
+        want = osm.sap_smooth_colour(op, m, r.reshape(sh), z0.reshape(sh), block, sweeps, mr)
+    else:
+        want = osm.mr_smooth(op, m, r.reshape(sh), z0.reshape(sh), sweeps)
+    return got, want.reshape(got.shape), z0
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("smoother,sweeps,mr", [(0, 3, 1), (1, 2, 4), (1, 1, 1)])
+@pytest.mark.parametrize("m", [0.07, -0.04])
+def test_smoother_parity_8x8x8x8(nd, prec, smoother, sweeps, mr, m):
+    print(f"case smoother={smoother} prec={prec} sweeps={sweeps} mr={mr} m={m}", flush=True)
+    got, want, z0 = _run(nd, (8, 8, 8, 8), (4, 4, 4, 4), prec, smoother, sweeps, mr, m)
+    e = rel_err(got, want)
+    print(f"rel err {e:.2e}", flush=True)
+    assert e < TOL[prec]
+    assert rel_err(got, z0) > 0.5  # the smoother moved z
+    if prec == 2:
+        assert e > 1e-6
+
+
+@pytest.mark.parametrize("block", [(4, 4, 2, 2), (4, 4, 4, 2)])
+def test_sap_parity_other_block_shapes(nd, block):
+    print(f"case SAP block={block}", flush=True)
+    got, want, _ = _run(nd, (8, 8, 8, 8), block, 0, 1, 2, 3, 0.05)
+    assert rel_err(got, want) < 1e-12
+
+
+def test_sap_parity_config2_shape(nd):
+    print("case SAP 16^3x32 FP32 cycle", flush=True)
+    got, want, _ = _run(nd, (32, 16, 16, 16), (4, 4, 4, 4), 1, 1, 1, 2, 0.0152)
+    e = rel_err(got, want)
+    print(f"rel err {e:.2e}", flush=True)
+    assert e < TOL[1]
+
+
+def test_sap_setup_refused(nd):
+    dims = (8, 8, 8, 8)
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(synth.gauge_field(dims, 3, 0.3)))
+    ctx.ndtm_set_params(K, MB, EB)
+    for block in [(8, 4, 4, 4), (2, 2, 2, 2), (4, 4, 4, 1)]:
+        with pytest.raises(nd.NdtmError):
+            ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=8, smoother=nd.NDTM_SMOOTH_SAP))
+    with pytest.raises(nd.NdtmError):
+        ctx.ndtm_mg_setup(ctx.mg_params(block=(4, 4, 4, 4), n_vec=8, smoother=nd.NDTM_SMOOTH_SAP, sap_mr_iters=0))
+    ctx.close()
+
+
+def test_hybrid_sap_config2(nd):
+    print("case c2 hybrid, SAP smoother, FP16-storage cycle", flush=True)
+    c = synth.CONFIGS["c2"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_set_shifts(list(c["shifts"]))
+    ctx.ndtm_mg_setup(ctx.mg_params(precision=2, smoother=nd.NDTM_SMOOTH_SAP, smooth_iters=2, sap_mr_iters=4))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=1, mms_predict=0))
+    out = [host(x) for x in xs]
+    ctx.close()
+    print("SAP cycle", rep["iterations"][9:], rep["t_mg_ms"], flush=True)
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    for i, s in enumerate(c["shifts"]):
+        assert rel_residual(op, out[i], b, s) <= 1e-10, i
+    for i in range(9, 12):
+        assert rep["method"][i] == 1, rep["method"]
