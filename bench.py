@@ -16,13 +16,17 @@ Forms (the first is the headline `value`):
           from the learned guess with Lagrange as fallback (shift 12), in the
           mixed-precision form (FP64 vectors and recurrences; the multi-shift stencil
           moves to FP32, then FP16 storage as the residual falls)
-The multigrid setup (shared by all forms) builds the cycle in FP16 storage: P and the
-smoother's links in FP16, fields, coarse operator and arithmetic in FP32.
   full_f64  the same in FP64 (the multigrid cycle inside FP64 FGMRES and defect correction)
   plain   multi-shift CG for all 12 shifts in FP64 (the speed-up reference)
   plain_mixed  plain in the mixed-precision form
   hybrid  full_f64 with Lagrange guesses only
   mixed   hybrid in the mixed-precision form
+  lagrange  hybrid without the multi-shift iterates as guesses: the three smallest shifts
+          go through the multigrid from Lagrange guesses
+The multigrid setup (shared by all forms) builds the cycle in FP16 storage (P and the
+smoothers' links in FP16; fields, coarse operator and arithmetic in FP32) with SAP
+post-smoothing: 2 sweeps over the 4^4 aggregates as blocks, 4 minimal-residual steps per
+block solve (--mg-smoother 0 for minimal-residual steps on the whole lattice).
 All forms run the same kernels on the same GPU; every shift's FP64 true residual is
 reported.  Roofline: the dominant kernel class of the headline form (largest summed
 time), timed by HIP events on its launch stream during the timed region; achieved
@@ -72,6 +76,10 @@ def parse():
     ap.add_argument("--mg-pair", type=int, default=1, help="case C's two signs in lock-step (needs FP64 coarse blocks)")
     ap.add_argument("--mg-prec", type=int, default=2, help="multigrid cycle precision (2: FP16 storage)")
     ap.add_argument("--mg-eo", type=int, default=1, help="even-odd coarsest level in the single-sign cycles")
+    ap.add_argument("--mg-smoother", type=int, default=1, help="0: minimal-residual steps; 1: SAP sweeps")
+    ap.add_argument("--mg-smooth-iters", type=int, default=None,
+                    help="post-smoothing sweeps (SAP, default 2) or steps (MR, default: the library's 8)")
+    ap.add_argument("--sap-mr-iters", type=int, default=4, help="minimal-residual steps per SAP block solve")
     ap.add_argument("--mlp-weights", default=None,
                     help="weights of the learned guess proposer (.npz, key 'w'; default: the shipped ones)")
     return ap.parse_args()
@@ -313,13 +321,19 @@ def main():
 
     forms = [f for f in args.forms.split(",") if f]
     setup_ms = None
+    smooth_iters = None
     mgp = None
     if any(f not in ("plain", "plain_mixed") for f in forms):
         # cycle in FP16 storage (FP16 P and links, FP32 fields and arithmetic); on the large
         # lattice the FP64 copies of P and the coarse blocks are freed after the setup (the
         # cycle reads only its own copies)
         mgp = ctx.mg_params(keep_f64=0 if big else 1, precision=args.mg_prec, pair_signs=args.mg_pair,
-                            coarse_eo=args.mg_eo)
+                            coarse_eo=args.mg_eo, smoother=args.mg_smoother, sap_mr_iters=args.sap_mr_iters)
+        if args.mg_smooth_iters is not None:
+            mgp.smooth_iters = args.mg_smooth_iters
+        elif args.mg_smoother == 1:
+            mgp.smooth_iters = 2
+        smooth_iters = mgp.smooth_iters
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.ndtm_mg_setup(mgp)
@@ -383,7 +397,9 @@ def main():
         "forms": results,
         "speedup_vs_plain": speedup,
         "mg_setup_ms": setup_ms,
-        "mg_cycle": {"precision": args.mg_prec, "pair_signs": args.mg_pair, "coarse_eo": args.mg_eo},
+        "mg_cycle": {"precision": args.mg_prec, "pair_signs": args.mg_pair, "coarse_eo": args.mg_eo,
+                     "smoother": "sap" if args.mg_smoother == 1 else "mr", "smooth_iters": smooth_iters,
+                     "sap_mr_iters": args.sap_mr_iters if args.mg_smoother == 1 else None},
         "fgmres_restart": restart or 16,
         "mlp_weights": os.path.basename(weights) if any(f in ("full", "full_f64") for f in forms) else None,
         "set_gauge_ms": set_gauge_ms,
