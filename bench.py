@@ -26,7 +26,8 @@ Forms (the first is the headline `value`):
 The multigrid setup (shared by all forms) builds the cycle in FP16 storage (P and the
 smoothers' links in FP16; fields, coarse operator and arithmetic in FP32) with SAP
 post-smoothing: 2 sweeps over the 4^4 aggregates as blocks, 4 minimal-residual steps per
-block solve (--mg-smoother 0 for minimal-residual steps on the whole lattice).
+block solve (--mg-smoother 0 for minimal-residual steps on the whole lattice); the setup's
+inverse iteration runs its CG in FP32 (--mg-setup-prec 0 for FP64).
 All forms run the same kernels on the same GPU; every shift's FP64 true residual is
 reported.  Roofline: the dominant kernel class of the headline form (largest summed
 time), timed by HIP events on its launch stream during the timed region; achieved
@@ -80,6 +81,8 @@ def parse():
     ap.add_argument("--mg-smooth-iters", type=int, default=None,
                     help="post-smoothing sweeps (SAP, default 2) or steps (MR, default: the library's 8)")
     ap.add_argument("--sap-mr-iters", type=int, default=4, help="minimal-residual steps per SAP block solve")
+    ap.add_argument("--mg-setup-prec", type=int, default=1,
+                    help="precision of the setup's inverse iteration (0: FP64, 1: FP32)")
     ap.add_argument("--mlp-weights", default=None,
                     help="weights of the learned guess proposer (.npz, key 'w'; default: the shipped ones)")
     return ap.parse_args()
@@ -328,7 +331,8 @@ def main():
         # lattice the FP64 copies of P and the coarse blocks are freed after the setup (the
         # cycle reads only its own copies)
         mgp = ctx.mg_params(keep_f64=0 if big else 1, precision=args.mg_prec, pair_signs=args.mg_pair,
-                            coarse_eo=args.mg_eo, smoother=args.mg_smoother, sap_mr_iters=args.sap_mr_iters)
+                            coarse_eo=args.mg_eo, smoother=args.mg_smoother, sap_mr_iters=args.sap_mr_iters,
+                            setup_prec=args.mg_setup_prec)
         if args.mg_smooth_iters is not None:
             mgp.smooth_iters = args.mg_smooth_iters
         elif args.mg_smoother == 1:
@@ -399,7 +403,8 @@ def main():
         "mg_setup_ms": setup_ms,
         "mg_cycle": {"precision": args.mg_prec, "pair_signs": args.mg_pair, "coarse_eo": args.mg_eo,
                      "smoother": "sap" if args.mg_smoother == 1 else "mr", "smooth_iters": smooth_iters,
-                     "sap_mr_iters": args.sap_mr_iters if args.mg_smoother == 1 else None},
+                     "sap_mr_iters": args.sap_mr_iters if args.mg_smoother == 1 else None,
+                     "setup_precision": "f32" if args.mg_setup_prec == 1 else "f64"},
         "fgmres_restart": restart or 16,
         "mlp_weights": os.path.basename(weights) if any(f in ("full", "full_f64") for f in forms) else None,
         "set_gauge_ms": set_gauge_ms,

@@ -214,6 +214,9 @@ typedef struct {
                           aggregates per direction, 64, 128 or 256 sites per aggregate, and no
                           clover term */
   int sap_mr_iters;    /* minimal-residual steps per block solve of SAP (default 4, >= 1) */
+  int setup_prec;      /* NDTM_PREC_F64 (default): the inverse iteration's CG in FP64;
+                          NDTM_PREC_F32: in FP32 fields and links (about half the setup time;
+                          the test vectors, P and the coarse operator are still formed in FP64) */
 } ndtm_mg_params;
 
 #define NDTM_SMOOTH_MR 0

@@ -38,7 +38,8 @@ class MGParams(C.Structure):
                 ("smooth_iters", C.c_int), ("coarse_iters", C.c_int),
                 ("coarse_mu_factor", C.c_double), ("seed", C.c_ulonglong), ("precision", C.c_int),
                 ("coarse_tol", C.c_double), ("coarse_cycles", C.c_int), ("coarse_eo", C.c_int),
-                ("keep_f64", C.c_int), ("pair_signs", C.c_int), ("smoother", C.c_int), ("sap_mr_iters", C.c_int)]
+                ("keep_f64", C.c_int), ("pair_signs", C.c_int), ("smoother", C.c_int), ("sap_mr_iters", C.c_int),
+                ("setup_prec", C.c_int)]
 
 
 class SolveParams(C.Structure):

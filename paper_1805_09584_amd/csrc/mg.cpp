@@ -11,19 +11,23 @@
 // the odd system; each preconditioner application is one two-level cycle on
 // the full lattice for D'_+- applied to (0, r_o), returning the odd part:
 //   coarse correction z = P D'_c^-1 P^+ r   (the coarse system by a fixed
-//   number of GMRES iterations on the device), then post-smoothing by minimal
-//   residual steps on D'_+-  (0 pre- and smooth_iters post-smoothing steps).
-// The cycle runs in FP32 (or FP64 when the setup asks for it).
+//   number of GMRES iterations on the device), then post-smoothing on D'_+-
+//   (0 pre- and smooth_iters post-smoothing iterations): minimal-residual steps
+//   on the whole lattice, or sweeps of the Schwarz alternating procedure (SAP)
+//   over the aggregates as blocks, each block solved by minimal-residual steps.
+// The cycle runs in FP32 (FP16 storage of P and links on request), or FP64.
 //
 // Coarse operator (eq:non-degenerate_coarse with P_ND = P x I2 and the
 // odd-site shift term): D'_c = D_W,c x I2 + i d mubar Gamma5_c x tau3
 //   - epsbar tau1 +- i m (Gamma5_c P^+ P_odd P) x tau1.
 //
-// Setup (section 3.2: the one-flavour twisted-mass setup is reused for the
-// doublet): N_v test vectors by inverse iteration with the doublet kernel at
-// epsbar = 0, so that flavour 0 of each doublet field iterates D_W + i mubar
-// Gamma5 and flavour 1 D_W - i mubar Gamma5; each sweep replaces v by a few
-// minimal-residual steps towards D^-1 v and normalises it.
+// Setup: N_v test vectors by inverse iteration; each sweep replaces v by
+// setup_smooth CG steps on the normal equations D^+ D x = v and normalises x.
+// By default (setup_nd = 1) D is the doublet operator itself and both flavour
+// components of each field become test vectors; with setup_nd = 0 the doublet
+// kernel runs at epsbar = 0, so flavour 0 iterates D_W + i mubar Gamma5 and
+// flavour 1 D_W - i mubar Gamma5 (section 3.2: the one-flavour twisted-mass
+// setup reused for the doublet).
 //
 // Case C (eq:lindif): (Q^2 + m^2)^-1 r = (i/2m)[(Q + i m)^-1 r - (Q - i m)^-1 r].
 // The squared residual of case C grows by up to sqrt(lambda_max + m^2)/m over
@@ -1096,7 +1100,52 @@ static int mg_build(ndtm_ctx* c, const ndtm_mg_params* prm, const void* tv_dev, 
       apply_q(Tt, v);
       apply_q(w, Tt);
     };
-    for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
+    if (prm->setup_prec == NDTM_PREC_F32) {
+      // the same inverse iteration with the CG in FP32 fields and links; the test vectors
+      // stay FP64 (each sweep's x is normalised into them)
+      Full X3 = full_field(c, "su_x", P32), R3 = full_field(c, "su_r", P32), T3 = full_field(c, "su_t", P32);
+      Full P3 = full_field(c, "su_p", P32), W3 = full_field(c, "su_w", P32);
+      if (!X3.base || !R3.base || !T3.base || !P3.base || !W3.base) return fail(c, NDTM_ENOMEM, "mg_setup: workspace");
+      auto apply_q32 = [&](const Full& y, const Full& x) {
+        hop(c, P32, EPI_SITE_Q, RED_NONE, 0, x.o, y.e, &x.e, nullptr, 0.0, -0.5, 0, nullptr, st);
+        hop(c, P32, EPI_SITE_Q, RED_NONE, 1, x.e, y.o, &x.o, nullptr, 0.0, -0.5, 0, nullptr, st);
+      };
+      auto to_host = [&](const double* dv, int k) {
+        (void)hipMemcpyAsync(c->hscal, dv, k * sizeof(double), hipMemcpyDeviceToHost, st);
+        (void)hipStreamSynchronize(st);
+      };
+      const size_t n32 = 2 * nh;  // complex elements of a full FP32 field
+      for (int sweep = 0; sweep < prm->setup_iters; ++sweep) {
+        for (int i = 0; i < nf; ++i) {
+          vzero(P32, X3.base, n32, st);
+          vconvert_field(P32, R3.base, P64, F[i].base, 2, c->g.vh, c->g.stride, st);
+          vconvert(P32, P3.base, P32, R3.base, n32, st);
+          vnorm2(P32, R3.base, n32, c->vred, d, st);
+          to_host(d, 1);
+          double rr = c->hscal[0];
+          for (int it = 0; it < prm->setup_smooth && rr > 0; ++it) {
+            apply_q32(T3, P3);
+            apply_q32(W3, T3);
+            vdot(P32, P3.base, W3.base, n32, c->vred, d, st);
+            to_host(d, 1);
+            const double pw = c->hscal[0];
+            if (!(pw > 0)) break;
+            const double alpha = rr / pw;
+            vaxpby(P32, X3.base, make_double2(alpha, 0), P3.base, make_double2(1, 0), n32, st);
+            vaxpby(P32, R3.base, make_double2(-alpha, 0), W3.base, make_double2(1, 0), n32, st);
+            vnorm2(P32, R3.base, n32, c->vred, d, st);
+            to_host(d, 1);
+            const double rn = c->hscal[0];
+            vaxpby(P32, P3.base, make_double2(1, 0), R3.base, make_double2(rn / rr, 0), n32, st);
+            rr = rn;
+          }
+          vconvert_field(P64, X.base, P32, X3.base, 2, c->g.vh, c->g.stride, st);
+          vnorm2(P64, X.base, nf2, c->vred, d + 6, st);
+          vscale_inv_sqrt(P64, F[i].base, X.base, d + 6, nf2, st);
+        }
+      }
+    }
+    for (int sweep = 0; sweep < (prm->setup_prec == NDTM_PREC_F32 ? 0 : prm->setup_iters); ++sweep) {
       for (int i = 0; i < nf; ++i) {
         vzero(P64, X.base, nf2, st);
         blas_copy((double2*)R.base, (const double2*)F[i].base, nf2, st);
@@ -1204,6 +1253,7 @@ void ndtm_mg_default_params(ndtm_mg_params* p) {
   p->keep_f64 = 1;
   p->smoother = NDTM_SMOOTH_MR;
   p->sap_mr_iters = 4;
+  p->setup_prec = NDTM_PREC_F64;
 }
 
 int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* stream) {
@@ -1227,6 +1277,8 @@ int ndtm_mg_setup(ndtm_ctx* c, const ndtm_mg_params* p, const void* tv, void* st
     return fail(c, NDTM_EINVAL, "mg_setup: bad iteration counts or coarse mu factor");
   if (p->precision != NDTM_PREC_F64 && p->precision != NDTM_PREC_F32 && p->precision != NDTM_PREC_F16)
     return fail(c, NDTM_EINVAL, "mg_setup: precision must be F64, F32 or F16");
+  if (p->setup_prec != NDTM_PREC_F64 && p->setup_prec != NDTM_PREC_F32)
+    return fail(c, NDTM_EINVAL, "mg_setup: setup_prec must be F64 or F32");
   if (p->smoother != NDTM_SMOOTH_MR && p->smoother != NDTM_SMOOTH_SAP)
     return fail(c, NDTM_EINVAL, "mg_setup: smoother must be MR or SAP");
   if (p->smoother == NDTM_SMOOTH_SAP) {

@@ -81,3 +81,32 @@ def test_hybrid_fp16_cycle_config2(nd):
     for i in range(9, 12):
         assert rep16["method"][i] == 1, rep16["method"]
         assert rep16["iterations"][i] <= 1.25 * rep32["iterations"][i] + 2, (rep16["iterations"], rep32["iterations"])
+
+
+def test_fp32_setup_config2(nd):
+    """The inverse iteration's CG in FP32 (setup_prec F32): every shift still meets the
+    tolerance by the oracle's residual, and the multigrid's outer iteration counts stay
+    within 25% (+2) of those with the FP64 setup."""
+    print("case c2 hybrid, FP32 and FP64 setup", flush=True)
+    c = synth.CONFIGS["c2"]
+    dims = c["dims"]
+    U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
+    b = synth.gaussian_spinor(dims, c["rhs_seed"])
+    reps, outs = [], []
+    for sp in (0, 1):
+        ctx = nd.Context(dims)
+        ctx.ndtm_set_gauge(dev(U))
+        ctx.ndtm_set_params(K, MB, EB)
+        ctx.ndtm_set_shifts(list(c["shifts"]))
+        ctx.ndtm_mg_setup(ctx.mg_params(precision=2, setup_prec=sp))
+        xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=1, mms_predict=0))
+        outs.append([host(x) for x in xs])
+        reps.append(rep)
+        ctx.close()
+    print("FP64 setup", reps[0]["iterations"][9:], "FP32 setup", reps[1]["iterations"][9:], flush=True)
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    for i, s in enumerate(c["shifts"]):
+        assert rel_residual(op, outs[1][i], b, s) <= 1e-10, i
+    for i in range(9, 12):
+        assert reps[1]["method"][i] == 1, reps[1]["method"]
+        assert reps[1]["iterations"][i] <= 1.25 * reps[0]["iterations"][i] + 2, (reps[1]["iterations"], reps[0]["iterations"])
