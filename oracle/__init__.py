@@ -16,6 +16,9 @@ Contents (each function cites the passage of the paper it follows):
                 solves identity (case C), GMRES.
 * ``mg``        aggregation prolongator, restriction/prolongation, Galerkin
                 coarse operator, the odd-site shift term on the coarse grid.
+* ``smoothers`` the cycle's post-smoothers: minimal-residual steps on the whole
+                lattice, and the Schwarz alternating procedure (SAP) over two colours
+                of blocks with minimal-residual block solves.
 * ``mlp``       FP64 forward/backward/Adam for the guess-proposer network and
                 its Gram-form loss.
 * ``fp16``      half-precision storage codec with per-site scale.
