@@ -177,7 +177,8 @@ typedef struct {
   int setup_nd;        /* 0: iterate the one-flavour operators D_W +- i mubar Gamma5
                           (section 3.2's reuse of the twisted-mass setup); 1: iterate the
                           doublet operator D_ND itself and use both flavour components */
-  int smooth_iters;    /* post-smoothing iterations per cycle (0 pre; default 8) */
+  int smooth_iters;    /* post-smoothing iterations per cycle (0 pre; default 8): minimal-residual
+                          steps, or SAP sweeps (see smoother) */
   int coarse_iters;    /* GMRES iterations of the coarse solve per cycle (default 12) */
   double coarse_mu_factor; /* d >= 1 scaling mubar on the coarse grid (d = 1 default) */
   unsigned long long seed; /* seed of the random initial test vectors */

@@ -331,13 +331,11 @@ static void dprime_mr(ndtm_ctx* c, int prec, const Full& y, const Full& x, doubl
   hop(c, prec, EPI_SITE, RED_MR, 1, x.e, y.o, &x.o, nullptr, m, -0.5, 0, part + hg, st);
 }
 
-// Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
-// smooth_iters minimal-residual steps.  The fine operator is the one in c->op
-// (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
-// post-smoothing: smooth_iters minimal-residual steps on D'(m) z = r from the coarse correction in Z
-// With SAP (section 3's smoother): smooth_iters sweeps; in each, the blocks of colour 0 and
-// then of colour 1 solve D'_B e = s_B by minimal-residual steps in the block kernel, with the
-// residual S = R - D'Z formed again before each colour but the first.
+// Post-smoothing of D'(m) z = R from the coarse correction in Z: smooth_iters
+// minimal-residual steps on the whole lattice, or with SAP (section 3's smoother)
+// smooth_iters sweeps; in each, the blocks of colour 0 and then of colour 1 solve
+// D'_B e = s_B by minimal-residual steps in the block kernel, with the residual
+// S = R - D'Z formed again before each colour but the first.
 static void mg_smooth(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, hipStream_t st) {
   const int cp = M->cprec;
   const size_t nh = half_elems(c);
@@ -367,9 +365,9 @@ static void mg_smooth(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, doub
   }
 }
 
-// Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then
-// smooth_iters minimal-residual steps.  The fine operator is the one in c->op
-// (D'(m)); eps is the flavour-mixing term the coarse operator uses with it.
+// Z ~ D'^-1 R on the full lattice (cycle precision): coarse correction then the
+// post-smoother (mg_smooth).  The fine operator is the one in c->op (D'(m)); eps
+// is the flavour-mixing term the coarse operator uses with it.
 static void mg_vcycle(ndtm_ctx* c, MGData* M, const Full& R, const Full& Z, double m, double eps, hipStream_t st) {
   const int cp = M->cprec;
   {

@@ -75,7 +75,7 @@ enum Red { RED_NONE = 0, RED_NORM = 1, RED_REDOT = 2, RED_MR = 3 };
 
 struct OpParams {
   double a, mubar, epsbar, inv_den;
-  int recon12;  // links are SU(3): the stencil loads two rows and rebuilds the third
+  int recon12;  // links are SU(3): the stencils rebuild the third row (see u8 for FP64)
   // FP64 SU(3) links in eight parameters per link, per parity (null: the FP64 stencil
   // reads two rows, or nine components)
   const double2* u8[2] = {nullptr, nullptr};
