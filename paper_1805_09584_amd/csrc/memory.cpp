@@ -232,6 +232,7 @@ int ndtm_workspace_bytes(const ndtm_ctx* c, int n_shifts, const ndtm_mg_params* 
     if (mg->pair_signs) t += 2 * z.full(cp) + 2 * R(2 * nc * 16);
     // setup temporaries: partial self blocks, test vectors and the inverse-iteration CG
     t += R(Vc * 8 * n2 * n2 * 16) + ((Nv + 1) / 2 + 6) * z.full(P64) + 2 * z.full(cp);
+    if (mg->setup_prec == NDTM_PREC_F32) t += 5 * z.full(P32);  // the FP32 inverse iteration's CG vectors
     // the multigrid calls of the ABI: a full FP64 field and two in the cycle precision, the
     // batched coarse solve of 8 systems
     const size_t per = 2 * (2 * (kc + 1) * (kc + 1)) + 3 * (kc + 1) + 2;
