@@ -908,12 +908,39 @@ __device__ __forceinline__ void sap_hop(cx<R> (&acc)[4][3], const S* ls, int f, 
   hop_compute<MU, FWD, false, R12, false>(acc, raw, R(1));
 }
 
+// the same hop with the link taken from LDS, where the work-group staged the two-row
+// links of its block's internal hops (hop d = 2 MU + backward, NLG words of 16 bytes
+// each, in lk[(d * NLG + g) * NS + j] for site j)
+template <int MU, bool FWD, bool R12, int NS, int NLG, class S, class L, class R>
+__device__ __forceinline__ void sap_hop_lds(cx<R> (&acc)[4][3], const S* ls, const v4u* lk, int f, int jn, int j) {
+  Raw<S, L> raw;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) raw.p[k] = ls[(f * 12 + k) * NS + jn];
+  raw.sc = 1.0f;
+  constexpr int GL = kG<L>, d = 2 * MU + (FWD ? 0 : 1);
+#pragma unroll
+  for (int g = 0; g < NLG; ++g) {
+    Grp<L> u;
+    u.w = lk[(d * NLG + g) * NS + j];
+#pragma unroll
+    for (int q = 0; q < GL; ++q)
+      if (GL * g + q < 9) raw.u[GL * g + q] = u.e[q];
+  }
+  hop_compute<MU, FWD, false, R12, false>(acc, raw, R(1));
+}
+
 template <class S, class L, bool R12, int NS>
 __global__ __launch_bounds__(2 * NS) void sap_block_kernel(SapArgs<S, L> A) {
   using R = typename RealOf<S>::T;
   // s_B: component k of flavour f at local site j in ls[(f * 12 + k) * NS + j]
   __shared__ S ls[24 * NS];
   __shared__ double wred[3][2 * NS / 64];
+  // FP32 fields with two-row FP32 or FP16 links: the links of the block's internal hops are
+  // read once into LDS (96 or 64 KB at 256 sites); otherwise every step reads them through
+  // the L2
+  constexpr bool kStage = kGrouped<S> && R12;
+  constexpr int NLG = kStage ? (6 + kG<L> - 1) / kG<L> : 1;
+  __shared__ v4u lk[kStage ? 8 * NLG * NS : 1];
   const int f = threadIdx.x & 1, j = threadIdx.x >> 1;
   // the work-group's block among those of this colour, x fastest
   int rest = blockIdx.x;
@@ -948,6 +975,23 @@ __global__ __launch_bounds__(2 * NS) void sap_block_kernel(SapArgs<S, L> A) {
   const L* Ui = par ? A.U[0] : A.U[1];
   const S* sv = par ? A.s[1] : A.s[0];
   S* zp = par ? A.z[1] : A.z[0];
+  if constexpr (kStage) {
+    // lane f = 0 stages the four forward links (at its own site), f = 1 the four backward
+    // ones (at the neighbours); only hops that stay inside the block are used
+    const L* U = f == 0 ? Uo : Ui;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int jn = f == 0 ? (mu == 0 ? jtp : mu == 1 ? jxp : mu == 2 ? jyp : jzp)
+                            : (mu == 0 ? jtm : mu == 1 ? jxm : mu == 2 ? jym : jzm);
+      const int hl = f == 0 ? h : (mu == 0 ? htm : mu == 1 ? hxm : mu == 2 ? hym : hzm);
+      if (jn >= 0) {
+        const int d = 2 * mu + f;
+#pragma unroll
+        for (int g = 0; g < NLG; ++g)
+          lk[(d * NLG + g) * NS + j] = ld_group<true>(U, (8 / kG<L>) * mu + g, A.stride, (unsigned)hl * 16u).w;
+      }
+    }
+  }
 
   cx<R> r[4][3], e[4][3];
   load_flav<S, R>(r, sv, nullptr, f, A.stride, h);
@@ -969,14 +1013,25 @@ __global__ __launch_bounds__(2 * NS) void sap_block_kernel(SapArgs<S, L> A) {
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[sp][c] = {0, 0};
-    if (jtp >= 0) sap_hop<0, true, R12, NS>(acc, ls, f, jtp, Uo, A.stride, h);
-    if (jtm >= 0) sap_hop<0, false, R12, NS>(acc, ls, f, jtm, Ui, A.stride, htm);
-    if (jxp >= 0) sap_hop<1, true, R12, NS>(acc, ls, f, jxp, Uo, A.stride, h);
-    if (jxm >= 0) sap_hop<1, false, R12, NS>(acc, ls, f, jxm, Ui, A.stride, hxm);
-    if (jyp >= 0) sap_hop<2, true, R12, NS>(acc, ls, f, jyp, Uo, A.stride, h);
-    if (jym >= 0) sap_hop<2, false, R12, NS>(acc, ls, f, jym, Ui, A.stride, hym);
-    if (jzp >= 0) sap_hop<3, true, R12, NS>(acc, ls, f, jzp, Uo, A.stride, h);
-    if (jzm >= 0) sap_hop<3, false, R12, NS>(acc, ls, f, jzm, Ui, A.stride, hzm);
+    if constexpr (kStage) {
+      if (jtp >= 0) sap_hop_lds<0, true, R12, NS, NLG, S, L>(acc, ls, lk, f, jtp, j);
+      if (jtm >= 0) sap_hop_lds<0, false, R12, NS, NLG, S, L>(acc, ls, lk, f, jtm, j);
+      if (jxp >= 0) sap_hop_lds<1, true, R12, NS, NLG, S, L>(acc, ls, lk, f, jxp, j);
+      if (jxm >= 0) sap_hop_lds<1, false, R12, NS, NLG, S, L>(acc, ls, lk, f, jxm, j);
+      if (jyp >= 0) sap_hop_lds<2, true, R12, NS, NLG, S, L>(acc, ls, lk, f, jyp, j);
+      if (jym >= 0) sap_hop_lds<2, false, R12, NS, NLG, S, L>(acc, ls, lk, f, jym, j);
+      if (jzp >= 0) sap_hop_lds<3, true, R12, NS, NLG, S, L>(acc, ls, lk, f, jzp, j);
+      if (jzm >= 0) sap_hop_lds<3, false, R12, NS, NLG, S, L>(acc, ls, lk, f, jzm, j);
+    } else {
+      if (jtp >= 0) sap_hop<0, true, R12, NS>(acc, ls, f, jtp, Uo, A.stride, h);
+      if (jtm >= 0) sap_hop<0, false, R12, NS>(acc, ls, f, jtm, Ui, A.stride, htm);
+      if (jxp >= 0) sap_hop<1, true, R12, NS>(acc, ls, f, jxp, Uo, A.stride, h);
+      if (jxm >= 0) sap_hop<1, false, R12, NS>(acc, ls, f, jxm, Ui, A.stride, hxm);
+      if (jyp >= 0) sap_hop<2, true, R12, NS>(acc, ls, f, jyp, Uo, A.stride, h);
+      if (jym >= 0) sap_hop<2, false, R12, NS>(acc, ls, f, jym, Ui, A.stride, hym);
+      if (jzp >= 0) sap_hop<3, true, R12, NS>(acc, ls, f, jzp, Uo, A.stride, h);
+      if (jzm >= 0) sap_hop<3, false, R12, NS>(acc, ls, f, jzm, Ui, A.stride, hzm);
+    }
     // site terms, then <q, s_B> and <q, q>
     cx<R> q[4][3];
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
