@@ -235,6 +235,15 @@ void ndtm_mg_default_params(ndtm_mg_params* p);
  * vector order).  Synchronises the stream. */
 int ndtm_mg_setup(ndtm_ctx* ctx, const ndtm_mg_params* p, const void* test_vectors_dev, void* stream);
 
+/* z = one two-level cycle for D'(m) z = r, the preconditioner of case C's FGMRES
+ * (section 3, eq:error_propagation with no pre-smoothing): the coarse correction
+ * (P x I2) D'_c(m)^-1 (P x I2)^dag r, the coarse system solved as the setup chose
+ * (coarse_iters GMRES iterations, or restarted to coarse_tol), then the post-smoother,
+ * in the cycle's precision.  D'(m) = D_ND + i m (Gamma5 x tau1) on odd sites.  z_dev,
+ * r_dev: full-lattice doublets, complex128 [V][2 flavour][4 spin][3 colour] canonical
+ * order, device, distinct; z_dev is written.  ESTATE without a multigrid setup. */
+int ndtm_mg_cycle(ndtm_ctx* ctx, void* z_dev, const void* r_dev, double m, void* stream);
+
 /* z <- the cycle's post-smoother applied to D'(m) z = r (section 3: the smoother M of
  * eq:error_propagation, started from z as the cycle starts it from the coarse correction),
  * with D'(m) = D_ND + i m (Gamma5 x tau1) on odd sites: smooth_iters minimal-residual steps

@@ -150,3 +150,38 @@ def dense_prolongator(P, agg, Vc):
     for x in range(V):
         M[x * 12:(x + 1) * 12, agg[x] * n2:(agg[x] + 1) * n2] = P[x]
     return M
+
+
+def coarse_nd_dense(op, P, agg, Vc, m, d=1.0):
+    """Dense D'_c(m) over the coarse doublet (index [X][f][dof] flattened): the columns of
+    coarse_nd_apply on every coarse unit vector."""
+    Nv = P.shape[2] // 2
+    Dc = coarse_wilson_dense(op.lat, op.a, P, agg, Vc)
+    Bo = odd_projector_coarse(op.lat, P, agg, Vc)
+    n = Vc * 2 * 2 * Nv
+    A = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        A[:, j] = coarse_nd_apply(Dc, Bo, e.reshape(Vc, 2, 2 * Nv), Nv, op.mubar, op.epsbar, m, d).reshape(-1)
+    return A
+
+
+def two_grid_cycle(op, m, r, P, agg, Vc, smoother="mr", steps=0, block=None, mr_iters=1):
+    """One two-level cycle for D'(m) z = r (section 3, eq:error_propagation with no
+    pre-smoothing): the coarse correction z0 = (P x I2) D'_c(m)^-1 (P x I2)^dag r with the
+    coarse system solved exactly (dense), then `steps` post-smoothing iterations from z0:
+    minimal-residual steps (smoother "mr") or SAP sweeps (smoother "sap", blocks `block`,
+    `mr_iters` steps per block solve).  r: full-lattice doublet of shape dims + (2, 4, 3)."""
+    from . import smoothers
+
+    dims = op.lat.dims
+    V = op.lat.V
+    Nv = P.shape[2] // 2
+    A = coarse_nd_dense(op, P, agg, Vc, m)
+    rc = restrict(P, r.reshape(V, 2, 4, 3), agg, Vc)
+    xc = np.linalg.solve(A, rc.reshape(-1)).reshape(Vc, 2, 2 * Nv)
+    z = prolong(P, xc, agg).reshape(dims + (2, 4, 3))
+    if smoother == "sap":
+        return smoothers.sap_smooth_colour(op, m, r, z, block, steps, mr_iters)
+    return smoothers.mr_smooth(op, m, r, z, steps)

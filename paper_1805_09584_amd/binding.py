@@ -107,6 +107,7 @@ def load_library():
         "ndtm_mg_prolong": (i, [vp, vp, vp, vp]),
         "ndtm_mg_transfer_cycle": (i, [vp, i, vp, vp, vp]),
         "ndtm_mg_smooth": (i, [vp, vp, vp, d, vp]),
+        "ndtm_mg_cycle": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_solve": (i, [vp, vp, vp, d, vp]),
         "ndtm_mg_coarse_apply_multi": (i, [vp, vp, vp, i, C.POINTER(C.c_double), vp]),
@@ -315,6 +316,12 @@ class Context:
         else:
             out = torch.empty((self.V, 2, 4, 3), dtype=torch.complex128, device=x.device)
         self._check(self.lib.ndtm_mg_transfer_cycle(self.h, int(direction), _ptr(out), _ptr(x), _stream()))
+        return out
+
+    def ndtm_mg_cycle(self, r, m=0.0):
+        """One two-level cycle for D'(m) z = r (full-lattice doublet); returns z."""
+        out = torch.empty_like(r)
+        self._check(self.lib.ndtm_mg_cycle(self.h, _ptr(out), _ptr(r), float(m), _stream()))
         return out
 
     def ndtm_mg_smooth(self, z, r, m=0.0):

@@ -1346,6 +1346,25 @@ int ndtm_mg_transfer_cycle(ndtm_ctx* c, int dir, void* out, const void* in, void
   return NDTM_OK;
 }
 
+int ndtm_mg_cycle(ndtm_ctx* c, void* z, const void* r, double m, void* stream) {
+  if (!c) return NDTM_EINVAL;
+  if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_cycle: no multigrid setup");
+  if (!z || !r || z == r) return fail(c, NDTM_EINVAL, "mg_cycle: null or aliased pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MGData* M = c->mg;
+  const int cp = M->cprec;
+  Full F64 = full_field(c, "ab_f", P64), Rc = full_field(c, "ab_fc", cp), Zc = full_field(c, "ab_fz", cp);
+  if (!F64.e.v || !Rc.e.v || !Zc.e.v) return fail(c, NDTM_ENOMEM, "mg_cycle: workspace");
+  launch_pack_full(c->g, static_cast<const double2*>(r), F64.e, F64.o, st);
+  vconvert_field(cp, Rc.base, P64, F64.base, 2, c->g.vh, c->g.stride, st);
+  if (M->eo) (void)einv_for(c, M, m, st);
+  mg_vcycle(c, M, Rc, Zc, m, c->epsbar, st);
+  vconvert_field(P64, F64.base, cp, Zc.base, 2, c->g.vh, c->g.stride, st);
+  launch_unpack_full(c->g, F64.e, F64.o, static_cast<double2*>(z), st);
+  NDTM_HIP(c, hipGetLastError());
+  return NDTM_OK;
+}
+
 int ndtm_mg_smooth(ndtm_ctx* c, void* z, const void* r, double m, void* stream) {
   if (!c) return NDTM_EINVAL;
   if (!c->mg || !c->mg->ready) return fail(c, NDTM_ESTATE, "mg_smooth: no multigrid setup");

@@ -11,6 +11,8 @@
 * A hybrid solve at 16^3x32 with the SAP smoother and the FP16-storage cycle, without
   predicted guesses, so the three smallest shifts run through the multigrid: every shift's
   true residual (oracle) <= 1e-10 and the multigrid shifts solved by the multigrid.
+* One whole two-level cycle (ndtm_mg_cycle) in FP64 with a tight coarse solve against the
+  oracle's two-grid cycle with an exact coarse solve, for both smoothers.
 * SAP setups the block kernel cannot serve are refused.
 """
 import numpy as np
@@ -117,3 +119,34 @@ def test_hybrid_sap_config2(nd):
         assert rel_residual(op, out[i], b, s) <= 1e-10, i
     for i in range(9, 12):
         assert rep["method"][i] == 1, rep["method"]
+
+
+@pytest.mark.parametrize("smoother,steps,mr", [(0, 3, 1), (1, 2, 3)])
+def test_cycle_parity_8x8x8x8(nd, smoother, steps, mr):
+    """One whole two-level cycle (ndtm_mg_cycle: restriction, coarse solve, prolongation,
+    post-smoothing) in the FP64 cycle with the coarse system solved to 1e-12, against the
+    oracle's cycle with an exact coarse solve, from the same test vectors."""
+    from oracle import mg as omg
+    print(f"case cycle smoother={smoother} steps={steps} mr={mr}", flush=True)
+    dims, block, Nv, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.07
+    U = synth.gauge_field(dims, 31, 0.3)
+    V = int(np.prod(dims))
+    tv = synth.gaussian_vectors((Nv, V, 4, 3), 32)
+    ctx = nd.Context(dims)
+    ctx.ndtm_set_gauge(dev(U))
+    ctx.ndtm_set_params(K, MB, EB)
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, keep_f64=1, smoother=smoother,
+                                    smooth_iters=steps, sap_mr_iters=mr, coarse_tol=1e-12, coarse_cycles=400),
+                      test_vectors=dev(tv))
+    r = synth.gaussian_spinor(dims, 33, "full")
+    got = host(ctx.ndtm_mg_cycle(dev(r), m))
+    ctx.close()
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    P = omg.build_prolongator(tv, dims, block)
+    agg = omg.aggregate_of_site(dims, block)
+    Vc = int(np.prod(omg.coarse_dims(dims, block)))
+    want = omg.two_grid_cycle(op, m, r.reshape(dims + (2, 4, 3)), P, agg, Vc,
+                              smoother="sap" if smoother == 1 else "mr", steps=steps, block=block, mr_iters=mr)
+    e = rel_err(got, want.reshape(got.shape))
+    print(f"rel err {e:.2e}", flush=True)
+    assert e < 1e-8

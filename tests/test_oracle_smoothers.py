@@ -109,3 +109,29 @@ def test_mr_steps_closed_form():
         zk = sm.mr_smooth(op, m, r, z, k)
         s = r.reshape(-1) - D @ zk.reshape(-1)
         assert abs(np.vdot(s, s).real - expect) <= 1e-10 * expect
+
+
+def test_two_grid_coarse_correction_is_galerkin_projection():
+    """With no smoothing the cycle's output z satisfies (P x I2)^dag (r - D'z) = 0 (the coarse
+    operator is the Galerkin product of D' including the odd-site shift), and applying the
+    coarse correction to the new residual changes nothing (a projection)."""
+    from oracle import mg as omg
+    dims, block, Nv = (4, 4, 2, 2), (2, 2, 1, 1), 4
+    U = synth.gauge_field(dims, 9, 0.3)
+    op = NDOperator(Lattice(dims, U), K, MB, EB)
+    V = int(np.prod(dims))
+    tv = synth.gaussian_vectors((Nv, V, 4, 3), 41)
+    P = omg.build_prolongator(tv, dims, block)
+    agg = omg.aggregate_of_site(dims, block)
+    Vc = int(np.prod(omg.coarse_dims(dims, block)))
+    m = 0.06
+    r = synth.gaussian_vectors(dims + (2, 4, 3), 42)
+    z = omg.two_grid_cycle(op, m, r, P, agg, Vc)
+    res = r - op.D_full(z, m)
+    rc = omg.restrict(P, res.reshape(V, 2, 4, 3), agg, Vc)
+    assert np.max(np.abs(rc)) <= 1e-12 * np.max(np.abs(r))
+    z2 = omg.two_grid_cycle(op, m, res, P, agg, Vc)
+    assert np.max(np.abs(z2)) <= 1e-12 * np.max(np.abs(z))
+    # with post-smoothing the output is the smoother started from the coarse correction
+    zs = omg.two_grid_cycle(op, m, r, P, agg, Vc, smoother="sap", steps=1, block=block, mr_iters=2)
+    assert np.max(np.abs(zs - sm.sap_smooth(op, m, r, z, block, 1, 2))) <= 1e-13 * np.max(np.abs(zs))
