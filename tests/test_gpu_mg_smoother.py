@@ -121,13 +121,15 @@ def test_hybrid_sap_config2(nd):
         assert rep["method"][i] == 1, rep["method"]
 
 
-@pytest.mark.parametrize("smoother,steps,mr", [(0, 3, 1), (1, 2, 3)])
-def test_cycle_parity_8x8x8x8(nd, smoother, steps, mr):
+@pytest.mark.parametrize("prec,smoother,steps,mr", [(0, 0, 3, 1), (0, 1, 2, 3), (1, 1, 2, 4), (2, 1, 2, 4)])
+def test_cycle_parity_8x8x8x8(nd, prec, smoother, steps, mr):
     """One whole two-level cycle (ndtm_mg_cycle: restriction, coarse solve, prolongation,
-    post-smoothing) in the FP64 cycle with the coarse system solved to 1e-12, against the
-    oracle's cycle with an exact coarse solve, from the same test vectors."""
+    post-smoothing) against the oracle's cycle with an exact coarse solve, from the same test
+    vectors: the FP64 cycle with the coarse system solved to 1e-12 within 1e-8 (8e-16 and 9e-16
+    measured); the FP32 and FP16-storage cycles with it solved to 1e-5, within 1e-6 and 1e-3
+    (9e-8 and 1.1e-4 measured)."""
     from oracle import mg as omg
-    print(f"case cycle smoother={smoother} steps={steps} mr={mr}", flush=True)
+    print(f"case cycle prec={prec} smoother={smoother} steps={steps} mr={mr}", flush=True)
     dims, block, Nv, m = (8, 8, 8, 8), (4, 4, 4, 4), 8, 0.07
     U = synth.gauge_field(dims, 31, 0.3)
     V = int(np.prod(dims))
@@ -135,8 +137,9 @@ def test_cycle_parity_8x8x8x8(nd, smoother, steps, mr):
     ctx = nd.Context(dims)
     ctx.ndtm_set_gauge(dev(U))
     ctx.ndtm_set_params(K, MB, EB)
-    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=0, keep_f64=1, smoother=smoother,
-                                    smooth_iters=steps, sap_mr_iters=mr, coarse_tol=1e-12, coarse_cycles=400),
+    ctx.ndtm_mg_setup(ctx.mg_params(block=block, n_vec=Nv, precision=prec, keep_f64=1, smoother=smoother,
+                                    smooth_iters=steps, sap_mr_iters=mr, coarse_tol=1e-12 if prec == 0 else 1e-5,
+                                    coarse_cycles=400),
                       test_vectors=dev(tv))
     r = synth.gaussian_spinor(dims, 33, "full")
     got = host(ctx.ndtm_mg_cycle(dev(r), m))
@@ -149,4 +152,6 @@ def test_cycle_parity_8x8x8x8(nd, smoother, steps, mr):
                               smoother="sap" if smoother == 1 else "mr", steps=steps, block=block, mr_iters=mr)
     e = rel_err(got, want.reshape(got.shape))
     print(f"rel err {e:.2e}", flush=True)
-    assert e < 1e-8
+    assert e < {0: 1e-8, 1: 1e-6, 2: 1e-3}[prec]
+    if prec == 2:
+        assert e > 1e-6  # the FP16 storage of P and links is what the cycle reads
