@@ -7,7 +7,8 @@
   rounding with the FP64 cycle (1e-12), within FP32 rounding with the FP32 cycle (2e-5),
   and within FP16 link rounding with the FP16-storage cycle (5e-3, and visibly above FP32
   rounding).
-* Blocks of 4x4x2x2 sites (64 per block) and 4x4x4x2 (128): the other work-group shapes.
+* Blocks of 4x4x2x2 sites (64 per block) and 4x4x4x2 (128): the other work-group shapes, in
+  all three cycle precisions (the FP32 and FP16 ones stage their links in LDS).
 * A hybrid solve at 16^3x32 with the SAP smoother and the FP16-storage cycle, without
   predicted guesses, so the three smallest shifts run through the multigrid: every shift's
   true residual (oracle) <= 1e-10 and the multigrid shifts solved by the multigrid.
@@ -71,11 +72,12 @@ def test_smoother_parity_8x8x8x8(nd, prec, smoother, sweeps, mr, m):
         assert e > 1e-6
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("block", [(4, 4, 2, 2), (4, 4, 4, 2)])
-def test_sap_parity_other_block_shapes(nd, block):
-    print(f"case SAP block={block}", flush=True)
-    got, want, _ = _run(nd, (8, 8, 8, 8), block, 0, 1, 2, 3, 0.05)
-    assert rel_err(got, want) < 1e-12
+def test_sap_parity_other_block_shapes(nd, block, prec):
+    print(f"case SAP block={block} prec={prec}", flush=True)
+    got, want, _ = _run(nd, (8, 8, 8, 8), block, prec, 1, 2, 3, 0.05)
+    assert rel_err(got, want) < TOL[prec]
 
 
 def test_sap_parity_config2_shape(nd):
