@@ -101,8 +101,10 @@ def test_sap_setup_refused(nd):
     ctx.close()
 
 
-def test_hybrid_sap_config2(nd):
-    print("case c2 hybrid, SAP smoother, FP16-storage cycle", flush=True)
+@pytest.mark.parametrize("pair", [1, 0])
+def test_hybrid_sap_config2(nd, pair):
+    """pair = 0: one sign after the other, each cycle replayed from a captured HIP graph."""
+    print(f"case c2 hybrid, SAP smoother, FP16-storage cycle, pair_signs={pair}", flush=True)
     c = synth.CONFIGS["c2"]
     dims = c["dims"]
     U = synth.gauge_field(dims, c["gauge_seed"], c["amp"])
@@ -111,8 +113,9 @@ def test_hybrid_sap_config2(nd):
     ctx.ndtm_set_gauge(dev(U))
     ctx.ndtm_set_params(K, MB, EB)
     ctx.ndtm_set_shifts(list(c["shifts"]))
-    ctx.ndtm_mg_setup(ctx.mg_params(precision=2, smoother=nd.NDTM_SMOOTH_SAP, smooth_iters=2, sap_mr_iters=4))
-    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=1, mms_predict=0))
+    ctx.ndtm_mg_setup(ctx.mg_params(precision=2, smoother=nd.NDTM_SMOOTH_SAP, smooth_iters=2, sap_mr_iters=4,
+                                    pair_signs=pair))
+    xs, rep = ctx.ndtm_solve(dev(b), ctx.solve_params(n_mmscg=9, guess=1, mms_predict=0, use_graphs=1))
     out = [host(x) for x in xs]
     ctx.close()
     print("SAP cycle", rep["iterations"][9:], rep["t_mg_ms"], flush=True)
